@@ -1,0 +1,168 @@
+"""FP64 CPU reference of dense membrane-CNN inference (arXiv 1612.02120, Section 2.2).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline leg of the benchmark, never by the GPU library. See emcnn_oracle.c for
+the definitions; this module marshals numpy arrays into the C reference and adds
+its own copy of the receptive-field arithmetic.
+
+Pins (tests/test_oracle_*.py): pure-Python brute force on tiny inputs (bitwise),
+torch float64 conv2d, delta-kernel identity, constant-input closed form, exact
+translation equivariance, monotone-quantisation commutation, exhaustive bf16 /
+e4m3fn encoder checks against torch casts, central finite differences for the
+student gradient and the Adam step-one closed form.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_KIND = {"conv": 0, "pool": 1}
+_ACT = {"none": 0, "relu": 1, "sigmoid": 2}
+QMODES = {"exact": 0, "bf16": 1, "fp8": 2}
+
+
+class _Layer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("cin", ctypes.c_int32),
+                ("cout", ctypes.c_int32), ("act", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_forward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.orc_trace.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_student_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p, dp, ctypes.c_void_p]
+        L.orc_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double]
+        L.orc_bf16_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.orc_e4m3_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.orc_sigmoid.argtypes = [ctypes.c_double]
+        L.orc_sigmoid.restype = ctypes.c_double
+        L.orc_radius.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _layers(net):
+    arr = (_Layer * len(net))()
+    for i, L in enumerate(net):
+        if L["kind"] == "conv":
+            arr[i] = _Layer(0, L["k"], L["cin"], L["cout"], _ACT[L["act"]])
+        else:
+            arr[i] = _Layer(1, 2, 0, 0, 0)
+    return arr
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def radius(net) -> int:
+    """R = sum of (k-1) over convs plus 1 per 2x2 stride-1 max filter; FoV = R+1."""
+    return sum(L["k"] - 1 if L["kind"] == "conv" else 1 for L in net)
+
+
+def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=False):
+    """Dense output of ``net`` on every slice of ``vol`` (Z x H x W uint8).
+
+    Returns float64 Z x (H-R) x (W-R) probabilities, or pre-sigmoid logits of
+    the last layer when ``logits`` is true. ``act_scales`` (FP8 mode): one input
+    scale per conv layer (ignored where the layer is not FP8).
+    """
+    vol = np.ascontiguousarray(vol, dtype=np.uint8)
+    if vol.ndim == 2:
+        vol = vol[None]
+    Z, H, W = vol.shape
+    R = radius(net)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    n_conv = sum(1 for L in net if L["kind"] == "conv")
+    sc = np.zeros(n_conv) if act_scales is None else np.array(
+        [0.0 if s is None else s for s in act_scales], dtype=np.float64)
+    out = np.empty((Z, H - R, W - R), dtype=np.float64)
+    lay = _layers(net)
+    rc = lib().orc_forward(_ptr(vol), Z, H, W, lay, len(net), _ptr(params), QMODES[qmode],
+                           _ptr(sc), None if logits else _ptr(out),
+                           _ptr(out) if logits else None, int(threads))
+    if rc:
+        raise ValueError("oracle forward failed (%d)" % rc)
+    return out
+
+
+def trace(img, net, params):
+    """Every layer's output (C x h x w float64) for one slice, exact mode."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    lay = _layers(net)
+    dims = np.zeros(3 * len(net), dtype=np.int32)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    # first pass for dims: run with bufs == NULL
+    rc = lib().orc_trace(_ptr(img), H, W, lay, len(net), _ptr(params), _ptr(dims), None)
+    if rc:
+        raise ValueError("oracle trace failed (%d)" % rc)
+    bufs = [np.empty(tuple(dims[3 * l:3 * l + 3]), dtype=np.float64) for l in range(len(net))]
+    ptrs = (ctypes.c_void_p * len(net))(*[b.ctypes.data for b in bufs])
+    rc = lib().orc_trace(_ptr(img), H, W, lay, len(net), _ptr(params), _ptr(dims), ptrs)
+    if rc:
+        raise ValueError("oracle trace failed (%d)" % rc)
+    return bufs
+
+
+def student_loss_grad(patches, teacher, net, params):
+    """(mean BCE-with-logits, gradient) for a batch; see emcnn_oracle.c."""
+    patches = np.ascontiguousarray(patches, dtype=np.uint8)
+    teacher = np.ascontiguousarray(teacher, dtype=np.float64)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    B, P, _ = patches.shape
+    grad = np.zeros_like(params)
+    loss = ctypes.c_double(0.0)
+    rc = lib().orc_student_loss_grad(_ptr(patches), B, P, _ptr(teacher), _layers(net), len(net),
+                                     _ptr(params), ctypes.byref(loss), _ptr(grad))
+    if rc:
+        raise ValueError("oracle student_loss_grad failed (%d)" % rc)
+    return loss.value, grad
+
+
+def adam(theta, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (theta, m, v, g):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam(_ptr(theta), _ptr(m), _ptr(v), _ptr(g), theta.size, int(t), lr, b1, b2, eps)
+
+
+def bf16_round(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_bf16_array(_ptr(x), _ptr(out), x.size)
+    return out
+
+
+def e4m3_round(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_e4m3_array(_ptr(x), _ptr(out), x.size)
+    return out
+
+
+def sigmoid(t: float) -> float:
+    return lib().orc_sigmoid(float(t))
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

@@ -1,0 +1,422 @@
+/*
+ * emcnn_oracle.c - plain FP64 CPU reference for dense membrane-probability
+ * inference (arXiv 1612.02120, Section 2.2).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library. It shares no code, header, table
+ * or helper with the GPU library; it is written from the definitions below and
+ * is deliberately slow and direct.
+ *
+ * What it computes (Section 2.2, "Accelerating dense computation"): the dense
+ * output of a convolution / max-filter network, i.e. one membrane probability
+ * per input position whose field of view lies inside the image. Max-pooling is
+ * replaced by stride-1 max-filtering, which is what makes the output dense.
+ *
+ *   input      a0[y][x] = V[y][x] / 255                (one channel per slice)
+ *   conv k x k a'[co][y][x] = b[co] + sum_ci sum_i<k sum_j<k W[co][ci][i][j] a[ci][y+i][x+j]
+ *              (valid cross-correlation; loops ci, i, j ascending)
+ *   relu       max(0, t)
+ *   pool       m[c][y][x] = max over i, j in {0,1} of a[c][y+i][x+j]   (2x2, stride 1)
+ *   sigmoid    1/(1+e^-t) for t >= 0, e^t/(1+e^t) for t < 0; equal to the
+ *              two-class softmax whose outputs are interleaved in Section 2.2.
+ *
+ * Fake-quant modes mirror the number formats declared by the GPU forms (the
+ * paper states no precision; these are readings):
+ *   BF16: first conv uses weights bf16((float)(w/255)) against the raw uint8
+ *         value; every later conv except the 1x1 head rounds its weights and its
+ *         input activations to bf16 (round to nearest even, via float).
+ *   FP8:  first conv as BF16; later convs except the head use e4m3fn codes with
+ *         a per-output-channel weight scale sw[co] = max|W[co]| / 448 and a
+ *         per-layer input scale s: out = b + s * sw[co] * sum q(w/sw) q(a/s),
+ *         q = e4m3fn round-to-nearest-even, saturating at +-448.
+ *   The head (last layer, 1x1 to one channel) stays exact in both modes.
+ *
+ * Student training (BCE on teacher probabilities + Adam, Kingma & Ba) is the
+ * plain chain rule through the same definitions.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_CONV = 0, ORC_POOL = 1 };
+enum { ORC_ACT_NONE = 0, ORC_ACT_RELU = 1, ORC_ACT_SIGMOID = 2 };
+enum { ORC_Q_EXACT = 0, ORC_Q_BF16 = 1, ORC_Q_FP8 = 2 };
+
+typedef struct {
+  int32_t kind, k, cin, cout, act;
+} orc_layer;
+
+/* ---------------- scalar definitions ---------------- */
+
+double orc_sigmoid(double t) {
+  if (t >= 0.0) return 1.0 / (1.0 + exp(-t));
+  double e = exp(t);
+  return e / (1.0 + e);
+}
+
+/* bf16 round-to-nearest-even of the float value of x. */
+double orc_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan unchanged */
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  u &= 0xffff0000u;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+/* e4m3fn (1 sign, 4 exponent bits, bias 7, 3 mantissa bits, no infinities,
+ * largest finite 448, smallest subnormal 2^-9), round to nearest even,
+ * saturating to +-448. */
+double orc_e4m3(double x) {
+  if (x != x) return x;
+  double s = x < 0 ? -1.0 : 1.0;
+  double a = fabs(x);
+  if (a >= 448.0) return s * 448.0;
+  if (a == 0.0) return 0.0 * s;
+  int e;
+  frexp(a, &e);          /* a = f * 2^e, f in [0.5, 1): unbiased exponent e-1 */
+  int ue = e - 1;
+  if (ue < -6) ue = -6;  /* subnormal range shares the quantum of 2^-6 normals */
+  double quantum = ldexp(1.0, ue - 3);
+  double q = rint(a / quantum) * quantum; /* rint: nearest, ties to even */
+  if (q > 448.0) q = 448.0;
+  return s * q;
+}
+
+void orc_bf16_array(const double* in, double* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_bf16(in[i]);
+}
+
+void orc_e4m3_array(const double* in, double* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_e4m3(in[i]);
+}
+
+/* ---------------- layer definitions ---------------- */
+
+static void conv_valid(const double* in, int C, int H, int W, const double* w,
+                       const double* b, int K, int Co, double* out) {
+  int Ho = H - K + 1, Wo = W - K + 1;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int co = 0; co < Co; ++co)
+    for (int y = 0; y < Ho; ++y)
+      for (int x = 0; x < Wo; ++x) {
+        double s = b[co];
+        for (int ci = 0; ci < C; ++ci)
+          for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j)
+              s += w[((co * C + ci) * K + i) * K + j] * in[((int64_t)ci * H + y + i) * W + x + j];
+        out[((int64_t)co * Ho + y) * Wo + x] = s;
+      }
+}
+
+static void pool2(const double* in, int C, int H, int W, double* out) {
+  int Ho = H - 1, Wo = W - 1;
+  for (int c = 0; c < C; ++c)
+    for (int y = 0; y < Ho; ++y)
+      for (int x = 0; x < Wo; ++x) {
+        const double* p = in + ((int64_t)c * H + y) * W + x;
+        double m = p[0];
+        if (p[1] > m) m = p[1];
+        if (p[W] > m) m = p[W];
+        if (p[W + 1] > m) m = p[W + 1];
+        out[((int64_t)c * Ho + y) * Wo + x] = m;
+      }
+}
+
+static int param_count(const orc_layer* L, int nl) {
+  int n = 0;
+  for (int l = 0; l < nl; ++l)
+    if (L[l].kind == ORC_CONV) n += L[l].cout * L[l].cin * L[l].k * L[l].k + L[l].cout;
+  return n;
+}
+
+/* Forward pass of one slice.  trace (nullable) receives, for every layer, a
+ * pointer to a malloc'd buffer with that layer's output (caller frees); dims
+ * of layer l's output are trace_dims[3l..3l+2] = C, H, W. */
+static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
+                         const double* params, int qmode, const double* act_scale,
+                         double* out_prob, double* out_logit, double** trace,
+                         int32_t* trace_dims) {
+  int C = 1, h = H, w = W;
+  double* a = (double*)malloc(sizeof(double) * (size_t)H * W);
+  if (!a) return -2;
+  int first = 1;
+  for (int64_t i = 0; i < (int64_t)H * W; ++i)
+    a[i] = (qmode == ORC_Q_EXACT) ? img[i] / 255.0 : (double)img[i];
+  const double* p = params;
+  int conv_idx = 0;
+  for (int l = 0; l < nl; ++l) {
+    const orc_layer* ly = &L[l];
+    double* o = NULL;
+    if (ly->kind == ORC_CONV) {
+      int K = ly->k, Co = ly->cout;
+      if (ly->cin != C) { free(a); return -1; }
+      int nw = Co * C * K * K;
+      const double* wt = p;
+      const double* bs = p + nw;
+      p += nw + Co;
+      int Ho = h - K + 1, Wo = w - K + 1;
+      if (Ho < 1 || Wo < 1) { free(a); return -1; }
+      int is_head = (l == nl - 1) && K == 1 && Co == 1;
+      double* wq = (double*)malloc(sizeof(double) * nw);
+      double* aq = NULL;
+      double* osc = NULL; /* per-output-channel rescale (FP8) */
+      memcpy(wq, wt, sizeof(double) * nw);
+      const double* ain = a;
+      if (qmode != ORC_Q_EXACT && !is_head) {
+        if (first) {
+          for (int i = 0; i < nw; ++i) wq[i] = orc_bf16(wt[i] / 255.0);
+        } else if (qmode == ORC_Q_BF16) {
+          for (int i = 0; i < nw; ++i) wq[i] = orc_bf16(wt[i]);
+          aq = (double*)malloc(sizeof(double) * (size_t)C * h * w);
+          for (int64_t i = 0; i < (int64_t)C * h * w; ++i) aq[i] = orc_bf16(a[i]);
+          ain = aq;
+        } else { /* FP8 */
+          double s = act_scale[conv_idx];
+          osc = (double*)malloc(sizeof(double) * Co);
+          int per = C * K * K;
+          for (int co = 0; co < Co; ++co) {
+            double mx = 0.0;
+            for (int i = 0; i < per; ++i) {
+              double v = fabs(wt[co * per + i]);
+              if (v > mx) mx = v;
+            }
+            double sw = mx > 0 ? mx / 448.0 : 1.0;
+            for (int i = 0; i < per; ++i) wq[co * per + i] = orc_e4m3(wt[co * per + i] / sw);
+            osc[co] = s * sw;
+          }
+          aq = (double*)malloc(sizeof(double) * (size_t)C * h * w);
+          for (int64_t i = 0; i < (int64_t)C * h * w; ++i) aq[i] = orc_e4m3(a[i] / s);
+          ain = aq;
+        }
+      } else if (first && qmode != ORC_Q_EXACT) {
+        /* exact head on a raw-uint8 input cannot happen for a 1-layer net we use;
+           keep the /255 definition */
+        for (int i = 0; i < nw; ++i) wq[i] = wt[i] / 255.0;
+      }
+      o = (double*)malloc(sizeof(double) * (size_t)Co * Ho * Wo);
+      if (osc) {
+        double* zb = (double*)calloc(Co, sizeof(double));
+        conv_valid(ain, C, h, w, wq, zb, K, Co, o);
+        free(zb);
+        for (int co = 0; co < Co; ++co)
+          for (int64_t i = 0; i < (int64_t)Ho * Wo; ++i)
+            o[(int64_t)co * Ho * Wo + i] = bs[co] + osc[co] * o[(int64_t)co * Ho * Wo + i];
+      } else {
+        conv_valid(ain, C, h, w, wq, bs, K, Co, o);
+      }
+      free(wq);
+      free(aq);
+      free(osc);
+      first = 0;
+      ++conv_idx;
+      C = Co;
+      h = Ho;
+      w = Wo;
+      if (l == nl - 1 && out_logit) memcpy(out_logit, o, sizeof(double) * (size_t)h * w);
+      for (int64_t i = 0; i < (int64_t)C * h * w; ++i) {
+        if (ly->act == ORC_ACT_RELU) o[i] = o[i] > 0.0 ? o[i] : 0.0;
+        else if (ly->act == ORC_ACT_SIGMOID) o[i] = orc_sigmoid(o[i]);
+      }
+    } else if (ly->kind == ORC_POOL) {
+      if (h < 2 || w < 2) { free(a); return -1; }
+      o = (double*)malloc(sizeof(double) * (size_t)C * (h - 1) * (w - 1));
+      pool2(a, C, h, w, o);
+      h -= 1;
+      w -= 1;
+    } else {
+      free(a);
+      return -1;
+    }
+    free(a);
+    a = o;
+    if (trace) {
+      trace[l] = (double*)malloc(sizeof(double) * (size_t)C * h * w);
+      memcpy(trace[l], a, sizeof(double) * (size_t)C * h * w);
+      trace_dims[3 * l] = C;
+      trace_dims[3 * l + 1] = h;
+      trace_dims[3 * l + 2] = w;
+    }
+  }
+  if (C != 1) { free(a); return -1; }
+  if (out_prob) memcpy(out_prob, a, sizeof(double) * (size_t)h * w);
+  free(a);
+  return 0;
+}
+
+/* Receptive radius R = sum over convs of (k-1) plus 1 per 2x2/s1 pool. */
+int orc_radius(const orc_layer* L, int nl) {
+  int R = 0;
+  for (int l = 0; l < nl; ++l) R += (L[l].kind == ORC_CONV) ? L[l].k - 1 : 1;
+  return R;
+}
+
+/* vol: Z x H x W uint8; prob (nullable), logit (nullable): Z x (H-R) x (W-R). */
+int orc_forward(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int nl,
+                const double* params, int qmode, const double* act_scale, double* prob,
+                double* logit, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  int R = orc_radius(L, nl);
+  int Ho = H - R, Wo = W - R;
+  if (Ho < 1 || Wo < 1) return -1;
+  for (int z = 0; z < Z; ++z) {
+    int rc = forward_slice(vol + (int64_t)z * H * W, H, W, L, nl, params, qmode, act_scale,
+                           prob ? prob + (int64_t)z * Ho * Wo : NULL,
+                           logit ? logit + (int64_t)z * Ho * Wo : NULL, NULL, NULL);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+/* Every layer's output for one slice; bufs[l] must hold dims given by a first
+ * call with bufs == NULL (dims only). */
+int orc_trace(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
+              const double* params, int32_t* dims, double** bufs) {
+  double** tr = (double**)calloc(nl, sizeof(double*));
+  int rc = forward_slice(img, H, W, L, nl, params, ORC_Q_EXACT, NULL, NULL, NULL, tr, dims);
+  for (int l = 0; l < nl; ++l) {
+    if (bufs && tr[l])
+      memcpy(bufs[l], tr[l], sizeof(double) * (size_t)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2]);
+    free(tr[l]);
+  }
+  free(tr);
+  return rc;
+}
+
+/* ---------------- student training ---------------- */
+
+/* Mean BCE-with-logits over all outputs of a batch of patches against teacher
+ * probabilities, and its gradient w.r.t. every parameter.
+ * Net: convs only (no pooling); ReLU on all but the last conv, whose output is
+ * the logit z.  L = (1/N) sum softplus(z) - t z, dL/dz = (sigmoid(z) - t) / N.
+ * patches: B x P x P uint8; teacher: B x (P-R) x (P-R). grad has the parameter
+ * layout (per conv: W[co][ci][i][j], then b[co]). */
+int orc_student_loss_grad(const uint8_t* patches, int B, int P, const double* teacher,
+                          const orc_layer* L, int nl, const double* params, double* loss,
+                          double* grad) {
+  for (int l = 0; l < nl; ++l)
+    if (L[l].kind != ORC_CONV) return -1;
+  int R = orc_radius(L, nl);
+  int Po = P - R;
+  int64_t N = (int64_t)B * Po * Po;
+  int np = param_count(L, nl);
+  memset(grad, 0, sizeof(double) * np);
+  double total = 0.0;
+  /* per-layer geometry */
+  int* hs = (int*)malloc(sizeof(int) * (nl + 1));
+  int* cs = (int*)malloc(sizeof(int) * (nl + 1));
+  int* poff = (int*)malloc(sizeof(int) * nl);
+  hs[0] = P;
+  cs[0] = 1;
+  int off = 0;
+  for (int l = 0; l < nl; ++l) {
+    if (L[l].cin != cs[l]) { free(hs); free(cs); free(poff); return -1; }
+    hs[l + 1] = hs[l] - L[l].k + 1;
+    cs[l + 1] = L[l].cout;
+    poff[l] = off;
+    off += L[l].cout * L[l].cin * L[l].k * L[l].k + L[l].cout;
+  }
+  double** act = (double**)calloc(nl + 1, sizeof(double*)); /* post-activation */
+  double** pre = (double**)calloc(nl + 1, sizeof(double*)); /* pre-activation */
+  for (int l = 0; l <= nl; ++l) {
+    act[l] = (double*)malloc(sizeof(double) * (size_t)cs[l] * hs[l] * hs[l]);
+    pre[l] = (double*)malloc(sizeof(double) * (size_t)cs[l] * hs[l] * hs[l]);
+  }
+  for (int bi = 0; bi < B; ++bi) {
+    const uint8_t* img = patches + (int64_t)bi * P * P;
+    for (int64_t i = 0; i < (int64_t)P * P; ++i) act[0][i] = img[i] / 255.0;
+    for (int l = 0; l < nl; ++l) {
+      const double* wt = params + poff[l];
+      const double* bs = wt + L[l].cout * L[l].cin * L[l].k * L[l].k;
+      conv_valid(act[l], cs[l], hs[l], hs[l], wt, bs, L[l].k, cs[l + 1], pre[l + 1]);
+      int64_t n = (int64_t)cs[l + 1] * hs[l + 1] * hs[l + 1];
+      for (int64_t i = 0; i < n; ++i) {
+        double v = pre[l + 1][i];
+        act[l + 1][i] = (l == nl - 1) ? v : (v > 0.0 ? v : 0.0);
+      }
+    }
+    /* loss and dL/dz at the head */
+    const double* t = teacher + (int64_t)bi * Po * Po;
+    double* d = (double*)malloc(sizeof(double) * (size_t)Po * Po);
+    for (int64_t i = 0; i < (int64_t)Po * Po; ++i) {
+      double z = pre[nl][i];
+      double sp = (z > 0 ? z : 0.0) + log1p(exp(-fabs(z)));
+      total += sp - t[i] * z;
+      d[i] = (orc_sigmoid(z) - t[i]) / (double)N;
+    }
+    /* back through the convs */
+    for (int l = nl - 1; l >= 0; --l) {
+      int K = L[l].k, Ci = cs[l], Co = cs[l + 1], Hi = hs[l], Ho = hs[l + 1];
+      const double* wt = params + poff[l];
+      double* gw = grad + poff[l];
+      double* gb = gw + Co * Ci * K * K;
+      for (int co = 0; co < Co; ++co)
+        for (int y = 0; y < Ho; ++y)
+          for (int x = 0; x < Ho; ++x) {
+            double g = d[((int64_t)co * Ho + y) * Ho + x];
+            gb[co] += g;
+            for (int ci = 0; ci < Ci; ++ci)
+              for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j)
+                  gw[((co * Ci + ci) * K + i) * K + j] +=
+                      g * act[l][((int64_t)ci * Hi + y + i) * Hi + x + j];
+          }
+      if (l == 0) { free(d); break; }
+      double* dn = (double*)calloc((size_t)Ci * Hi * Hi, sizeof(double));
+      for (int co = 0; co < Co; ++co)
+        for (int y = 0; y < Ho; ++y)
+          for (int x = 0; x < Ho; ++x) {
+            double g = d[((int64_t)co * Ho + y) * Ho + x];
+            for (int ci = 0; ci < Ci; ++ci)
+              for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j)
+                  dn[((int64_t)ci * Hi + y + i) * Hi + x + j] += wt[((co * Ci + ci) * K + i) * K + j] * g;
+          }
+      for (int64_t i = 0; i < (int64_t)Ci * Hi * Hi; ++i)
+        if (!(pre[l][i] > 0.0)) dn[i] = 0.0; /* ReLU gradient: 0 where pre-activation <= 0 */
+      free(d);
+      d = dn;
+    }
+  }
+  *loss = total / (double)N;
+  for (int l = 0; l <= nl; ++l) { free(act[l]); free(pre[l]); }
+  free(act); free(pre); free(hs); free(cs); free(poff);
+  return 0;
+}
+
+/* One Adam step (Kingma & Ba) at step count t >= 1. */
+void orc_adam(double* theta, double* m, double* v, const double* g, int64_t n, int t, double lr,
+              double b1, double b2, double eps) {
+  double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    double mh = m[i] / c1, vh = v[i] / c2;
+    theta[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
+#else
+  return 1;
+#endif
+}
