@@ -1,0 +1,209 @@
+/*
+ * emcnn.h - C ABI of an MI355X (gfx950) library for dense membrane-probability
+ * inference: a uint8 electron-microscopy stack goes in, one membrane
+ * probability per voxel comes out (arXiv 1612.02120, Section 2.1 "Membrane
+ * classification": EM images are mapped to per-pixel membrane probability maps
+ * by a CNN; Section 2.2 "Accelerating dense computation": all pixel labels are
+ * produced in one dense pass, with max-pooling replaced by stride-1 max
+ * filtering).
+ *
+ * Conventions for every entry point:
+ *  - Return CNN_OK (0) or a negative CNN_E* code; cnn_last_error() gives a
+ *    thread-local message for the last failure on the calling thread.
+ *  - Arguments are validated before anything is enqueued: a failed call leaves
+ *    the stream untouched. Nothing is printed, nothing aborts, no C++ exception
+ *    crosses the ABI.
+ *  - Volume, output, patch and teacher pointers are DEVICE pointers owned by the
+ *    caller. Weight arrays and tile descriptor arrays are HOST memory, copied
+ *    during the call (the caller may free them on return).
+ *  - `stream` is a hipStream_t (NULL = legacy default stream). Inference and
+ *    training calls only enqueue work and return; faults of enqueued kernels
+ *    surface at the caller's next synchronisation of that stream.
+ *  - A handle owns device workspace: do not use one handle on two streams
+ *    concurrently.
+ *  - Dense geometry: a net with receptive radius R (sum of k-1 over convs plus
+ *    1 per 2x2/s1 max filter; field of view R+1) maps a Z x H x W volume to a
+ *    Z x (H-R) x (W-R) float32 map, C order; output (z, y, x) is centred on
+ *    input (z, y + R/2, x + R/2). Slices are independent (2-D nets).
+ *  - Input scaling: the network sees V/255; the library folds 1/255 into the
+ *    first convolution.
+ */
+#ifndef EMCNN_H
+#define EMCNN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CNN_OK 0
+#define CNN_EINVAL (-1)       /* null pointer, bad size, dims < field of view, bad spec */
+#define CNN_ENOMEM (-2)       /* device or pinned-host allocation failed */
+#define CNN_EHIP (-3)         /* a HIP runtime call failed (text in cnn_last_error) */
+#define CNN_EUNSUPPORTED (-4) /* valid request outside what the kernels implement */
+
+enum cnn_layer_kind { CNN_LAYER_CONV = 0, CNN_LAYER_MAXPOOL = 1 };
+enum cnn_act { CNN_ACT_NONE = 0, CNN_ACT_RELU = 1, CNN_ACT_SIGMOID = 2 };
+enum cnn_precision { CNN_PREC_FP32 = 0, CNN_PREC_BF16 = 1, CNN_PREC_FP8 = 2 };
+
+/* One layer of the network (Section 2.2: alternating convolution and max
+ * pooling; pooling is evaluated densely as a 2x2 stride-1 max filter).
+ *  kind      CNN_LAYER_CONV (valid k x k cross-correlation, bias, activation) or
+ *            CNN_LAYER_MAXPOOL (2x2 window, stride 1; k must be 2, other fields 0).
+ *  act_scale FP8 nets only: the per-tensor scale s of this conv's INPUT
+ *            activation (codes are e4m3fn(a / s)); ignored for the first conv,
+ *            the head and other precisions. */
+typedef struct cnn_layer {
+  int32_t kind;
+  int32_t k;
+  int32_t cin;
+  int32_t cout;
+  int32_t act;
+  float act_scale;
+} cnn_layer;
+
+typedef struct cnn_layer_spec {
+  int32_t n_layers;
+  const cnn_layer* layers; /* host array of n_layers entries */
+  int32_t precision;       /* enum cnn_precision */
+} cnn_layer_spec;
+
+typedef struct cnn_net cnn_net;
+
+/* Build a network on the current HIP device.
+ * weights: host float64, for each conv in order W[cout][cin][k][k] (C order)
+ *   followed by b[cout]; n_weights must equal that total. Copied, then packed
+ *   and quantised once here:
+ *     FP32: all products in FP32 with FP32 accumulation;
+ *     BF16: every conv but the 1x1 head takes bf16 weights and bf16 input
+ *           activations (round to nearest even), FP32 accumulation;
+ *     FP8:  the first conv as BF16; later convs except the head take e4m3fn
+ *           weights with per-output-channel scale max|W[co]|/448 and e4m3fn
+ *           input codes with the layer's act_scale, FP32 accumulation,
+ *           dequantised in the epilogue as acc * s * sw[co] + b[co].
+ *   The head (last layer, 1x1 conv to one channel with sigmoid) is FP32 in
+ *   every precision.
+ * Supported shape: conv(k=5, 1 -> 16 or 48, ReLU) [pool], then one or more
+ *   conv(k in {3,5}, C -> C, ReLU) [pool] with C = 16 (FP32) or 48, then the
+ *   head conv(1x1, C -> 1, sigmoid) with no pool before it. Other valid specs
+ *   return CNN_EUNSUPPORTED.
+ * On success *out owns device memory until cnn_destroy. */
+int cnn_create(const double* weights, int64_t n_weights, const cnn_layer_spec* spec,
+               cnn_net** out);
+
+/* Release a network and its device memory (synchronises the device first).
+ * NULL is accepted. */
+int cnn_destroy(cnn_net* net);
+
+/* Receptive radius R and field of view R+1 (either pointer may be NULL). */
+int cnn_geometry(const cnn_net* net, int32_t* R, int32_t* fov);
+
+/* Dense inference of a whole volume (Section 2.2: every pixel label in one
+ * pass, no per-patch recomputation).
+ * volume_u8: device, Z x H x W uint8, C order (x fastest).
+ * dims: host {Z, H, W}; H and W must be >= R+1, Z >= 1, each < 2^31.
+ * prob_out: device, Z x (H-R) x (W-R) float32, fully overwritten.
+ * Grows the handle's workspace with hipMalloc when needed (the only allocation
+ * it may make). */
+int cnn_infer(cnn_net* net, const uint8_t* volume_u8, const int64_t dims[3], float* prob_out,
+              void* stream);
+
+/* One block of a volume with its halo of input context (Section 2.1, "Block
+ * merging": blocks are processed independently).
+ * in:  device, z x h x w uint8 (the block plus `halo` pixels on every side).
+ * out: device, z x (h - 2 halo) x (w - 2 halo) float32, the block's interior;
+ *      out (t, y, x) is the probability centred on in (t, y + halo, x + halo).
+ * halo must be >= R/2 and h, w > 2 halo. */
+typedef struct cnn_tile {
+  const uint8_t* in;
+  int64_t z, h, w;
+  int32_t halo;
+  float* out;
+} cnn_tile;
+
+/* Many uneven blocks in one submission: the descriptors are copied to the
+ * device and every layer runs as ONE persistent kernel over the work items of
+ * all blocks; the submission is captured once as a HIP graph and replayed on
+ * later calls with the same structure. tiles: host array of n descriptors.
+ * Results equal per-block cnn_infer on each block's input, bit for bit. */
+int cnn_infer_batch(cnn_net* net, const cnn_tile* tiles, int32_t n, void* stream);
+
+/* Pick, per layer, the fastest compiled tile shape for H x W slices by timing
+ * every candidate on the device (synchronous). Each candidate's output must be
+ * bitwise equal to the default's or it is rejected. cache_path (nullable): a
+ * text file of earlier choices, read first and updated. */
+int cnn_autotune(cnn_net* net, int64_t H, int64_t W, const char* cache_path, void* stream);
+
+/* Describe the current tile choice (for logs); writes a NUL-terminated string. */
+int cnn_describe(const cnn_net* net, char* buf, int32_t buf_len);
+
+/* ------------------------------------------------------------------------
+ * Student network and fallback (Section 1 / 2: a fast pass everywhere and
+ * extra effort only where errors are likely). The student is a thinner net,
+ * conv5x5 1->8 ReLU, conv3x3 8->8 ReLU, conv1x1 8->1 sigmoid (R = 6), trained
+ * on the GPU by distillation from the plain net's probability maps.
+ * ---------------------------------------------------------------------- */
+typedef struct cnn_student cnn_student;
+
+typedef struct cnn_adam {
+  float lr, beta1, beta2, eps;
+} cnn_adam;
+
+/* w_init: host float64 parameters in the cnn_create layout (801 values).
+ * precision: CNN_PREC_FP32 or CNN_PREC_BF16 (forward and backward operands
+ * rounded to bf16, FP32 accumulation, FP32 master weights and Adam state). */
+int student_create(const double* w_init, int64_t n_weights, int32_t precision,
+                   cnn_student** out);
+int student_destroy(cnn_student* s);
+
+/* Copy the FP32 master parameters (as float64) / Adam moments / step count to
+ * host. Any pointer may be NULL. Synchronous. */
+int student_get_state(cnn_student* s, double* w_out, double* m_out, double* v_out,
+                      int64_t* step_out);
+/* Restore a saved state (resume). Synchronous. */
+int student_set_state(cnn_student* s, const double* w, const double* m, const double* v,
+                      int64_t step);
+
+/* Gradient of the mean BCE-with-logits L = mean(softplus(z) - t z) over
+ * batch x (P-6) x (P-6) outputs. patches: device batch x P x P uint8;
+ * teacher_prob: device batch x (P-6) x (P-6) float32 targets in [0,1].
+ * grad_out: device float32[801]; loss_out: device float64 scalar (nullable).
+ * The loss and gradient reductions are deterministic (fixed order). */
+int student_grad(cnn_student* s, const uint8_t* patches, const float* teacher_prob,
+                 int32_t batch, int32_t patch, float* grad_out, double* loss_out, void* stream);
+
+/* One training step: forward, loss (FP64 sum), backward, FP64 squared gradient
+ * norm, Adam update (Kingma & Ba, bias-corrected) of the FP32 master weights.
+ * loss_out, gnorm_out: device float64 scalars (nullable); gnorm is ||g||_2. */
+int student_train_step(cnn_student* s, const uint8_t* patches, const float* teacher_prob,
+                       int32_t batch, int32_t patch, const cnn_adam* hp, double* loss_out,
+                       double* gnorm_out, void* stream);
+
+/* Student inference: volume Z x H x W -> Z x (H-6) x (W-6) float32. */
+int student_infer(cnn_student* s, const uint8_t* volume_u8, const int64_t dims[3],
+                  float* prob_out, void* stream);
+
+/* Student inference aligned to the teacher's output frame, with per-tile
+ * fallback to the teacher (a multi-pass scheme: cheap pass everywhere,
+ * expensive pass where sampled disagreement is high).
+ * prob_out: Z x (H-R) x (W-R) with R the teacher's radius (the student map
+ * cropped by (R-6)/2 per side). The output is split into tiles of tile x tile
+ * pixels per slice; in each tile n_samples windows of 16 x 16 outputs (seeded
+ * by `seed`) are recomputed by the teacher; when the fraction of sampled
+ * voxels whose 0.5-threshold decision differs exceeds tau, the whole tile is
+ * recomputed by the teacher. All decisions stay on the device.
+ * stats_out (device int32[2], nullable): {tiles flagged, tiles total}. */
+int student_infer_with_fallback(cnn_student* s, cnn_net* teacher, const uint8_t* volume_u8,
+                                const int64_t dims[3], float* prob_out, float tau,
+                                int32_t tile, int32_t n_samples, uint64_t seed,
+                                int32_t* stats_out, void* stream);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* cnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMCNN_H */

@@ -1,0 +1,352 @@
+"""Python binding of libemcnn (include/emcnn.h): dense membrane-probability
+inference of a uint8 EM stack on an MI355X (arXiv 1612.02120, Section 2.2).
+
+The functions keep the C names and only marshal arguments: torch CUDA tensors
+provide device memory and streams, numpy arrays provide host weights. All
+computation happens in the library's HIP kernels. If the library is not built
+the import fails; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libemcnn.so")
+
+CNN_OK, CNN_EINVAL, CNN_ENOMEM, CNN_EHIP, CNN_EUNSUPPORTED = 0, -1, -2, -3, -4
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+_ACT = {"none": 0, "relu": 1, "sigmoid": 2}
+
+
+class CnnError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__("%s failed (%d): %s" % (fn, code, msg))
+        self.code = code
+
+
+class _Layer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("cin", ctypes.c_int32),
+                ("cout", ctypes.c_int32), ("act", ctypes.c_int32), ("act_scale", ctypes.c_float)]
+
+
+class _Spec(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("layers", ctypes.POINTER(_Layer)),
+                ("precision", ctypes.c_int32)]
+
+
+class _Tile(ctypes.Structure):
+    _fields_ = [("inp", ctypes.c_void_p), ("z", ctypes.c_int64), ("h", ctypes.c_int64),
+                ("w", ctypes.c_int64), ("halo", ctypes.c_int32), ("out", ctypes.c_void_p)]
+
+
+class _Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+EXPORTS = [
+    "cnn_create", "cnn_destroy", "cnn_geometry", "cnn_infer", "cnn_infer_batch", "cnn_autotune",
+    "cnn_describe", "cnn_set_batch_graph", "cnn_set_workspace_limit", "student_create",
+    "student_destroy", "student_get_state", "student_set_state", "student_grad",
+    "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libemcnn.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    sig = {
+        "cnn_create": [vp, i64, vp, vp],
+        "cnn_destroy": [vp],
+        "cnn_geometry": [vp, vp, vp],
+        "cnn_infer": [vp, vp, vp, vp, vp],
+        "cnn_infer_batch": [vp, vp, i32, vp],
+        "cnn_autotune": [vp, i64, i64, ctypes.c_char_p, vp],
+        "cnn_describe": [vp, ctypes.c_char_p, i32],
+        "cnn_set_batch_graph": [vp, i32],
+        "cnn_set_workspace_limit": [vp, i64],
+        "student_create": [vp, i64, i32, vp],
+        "student_destroy": [vp],
+        "student_get_state": [vp, vp, vp, vp, vp],
+        "student_set_state": [vp, vp, vp, vp, i64],
+        "student_grad": [vp, vp, vp, i32, i32, vp, vp, vp],
+        "student_train_step": [vp, vp, vp, i32, i32, vp, vp, vp, vp],
+        "student_infer": [vp, vp, vp, vp, vp],
+        "student_infer_with_fallback": [vp, vp, vp, vp, vp, f32, i32, i32, ctypes.c_uint64, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.cnn_last_error.argtypes = []
+    L.cnn_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def cnn_last_error() -> str:
+    return _lib.cnn_last_error().decode()
+
+
+def _check(rc, fn):
+    if rc != CNN_OK:
+        raise CnnError(rc, fn, cnn_last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dims(t):
+    return (ctypes.c_int64 * 3)(*[int(s) for s in t.shape])
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def radius_of(net) -> int:
+    """Receptive radius of a layer list: sum of (k-1) over convs, +1 per 2x2/s1 pool."""
+    return sum(L["k"] - 1 if L["kind"] == "conv" else 1 for L in net)
+
+
+class Net:
+    """Owning handle of a cnn_net."""
+
+    def __init__(self, ptr, R):
+        self.ptr = ptr
+        self.R = R
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.cnn_destroy(self.ptr)
+            self.ptr = None
+
+    def close(self):
+        self.__del__()
+
+
+def cnn_create(weights, net, precision="fp32", act_scales=None) -> Net:
+    """weights: float64 vector (per conv W[cout][cin][k][k] then b[cout]);
+    net: list of layer dicts; act_scales: per-conv FP8 input scales (None allowed)."""
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    arr = (_Layer * len(net))()
+    ci = 0
+    for i, L in enumerate(net):
+        if L["kind"] == "conv":
+            s = 0.0
+            if act_scales is not None and act_scales[ci] is not None:
+                s = float(act_scales[ci])
+            arr[i] = _Layer(0, L["k"], L["cin"], L["cout"], _ACT[L["act"]], s)
+            ci += 1
+        else:
+            arr[i] = _Layer(1, 2, 0, 0, 0, 0.0)
+    spec = _Spec(len(net), arr, PRECISIONS[precision])
+    out = ctypes.c_void_p()
+    _check(_lib.cnn_create(w.ctypes.data_as(ctypes.c_void_p), w.size, ctypes.byref(spec),
+                           ctypes.byref(out)), "cnn_create")
+    R = ctypes.c_int32()
+    _check(_lib.cnn_geometry(out, ctypes.byref(R), None), "cnn_geometry")
+    return Net(out, R.value)
+
+
+def cnn_destroy(net: Net):
+    net.close()
+
+
+def cnn_geometry(net: Net):
+    R, fov = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.cnn_geometry(net.ptr, ctypes.byref(R), ctypes.byref(fov)), "cnn_geometry")
+    return R.value, fov.value
+
+
+def cnn_infer(net: Net, volume, out=None, stream=None):
+    """volume: CUDA uint8 Z x H x W; returns (or fills) CUDA float32 Z x (H-R) x (W-R)."""
+    import torch
+    _require_cuda(volume, torch.uint8, "volume")
+    if volume.dim() != 3:
+        raise ValueError("volume must be Z x H x W")
+    Z, H, W = volume.shape
+    if out is None:
+        out = torch.empty((Z, max(H - net.R, 0), max(W - net.R, 0)), dtype=torch.float32,
+                          device=volume.device)
+    _require_cuda(out, torch.float32, "out")
+    if tuple(out.shape) != (Z, H - net.R, W - net.R):
+        raise ValueError("out must be Z x (H-R) x (W-R)")
+    _check(_lib.cnn_infer(net.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
+           "cnn_infer")
+    return out
+
+
+def cnn_infer_batch(net: Net, tiles, stream=None):
+    """tiles: list of (input uint8 CUDA tensor z x h x w, halo, output float32 CUDA tensor
+    z x (h-2 halo) x (w-2 halo))."""
+    import torch
+    arr = (_Tile * len(tiles))()
+    for i, (inp, halo, out) in enumerate(tiles):
+        _require_cuda(inp, torch.uint8, "tile input")
+        _require_cuda(out, torch.float32, "tile output")
+        z, h, w = inp.shape
+        if tuple(out.shape) != (z, h - 2 * halo, w - 2 * halo):
+            raise ValueError("tile %d: output must be z x (h-2 halo) x (w-2 halo)" % i)
+        arr[i] = _Tile(inp.data_ptr(), z, h, w, int(halo), out.data_ptr())
+    _check(_lib.cnn_infer_batch(net.ptr, arr, len(tiles), _stream(stream)), "cnn_infer_batch")
+
+
+def cnn_autotune(net: Net, H: int, W: int, cache_path=None, stream=None):
+    _check(_lib.cnn_autotune(net.ptr, int(H), int(W),
+                             None if cache_path is None else str(cache_path).encode(),
+                             _stream(stream)), "cnn_autotune")
+
+
+def cnn_describe(net: Net) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(_lib.cnn_describe(net.ptr, buf, 4096), "cnn_describe")
+    return buf.value.decode()
+
+
+def cnn_set_batch_graph(net: Net, enable: bool):
+    _check(_lib.cnn_set_batch_graph(net.ptr, 1 if enable else 0), "cnn_set_batch_graph")
+
+
+def cnn_set_workspace_limit(net: Net, nbytes: int):
+    _check(_lib.cnn_set_workspace_limit(net.ptr, int(nbytes)), "cnn_set_workspace_limit")
+
+
+# ---------------------------------------------------------------- student
+
+STUDENT_R = 6
+STUDENT_PARAMS = 801
+
+
+class Student:
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.student_destroy(self.ptr)
+            self.ptr = None
+
+    def close(self):
+        self.__del__()
+
+
+def student_create(w_init, precision="bf16") -> Student:
+    w = np.ascontiguousarray(w_init, dtype=np.float64)
+    out = ctypes.c_void_p()
+    _check(_lib.student_create(w.ctypes.data_as(ctypes.c_void_p), w.size, PRECISIONS[precision],
+                               ctypes.byref(out)), "student_create")
+    return Student(out)
+
+
+def student_destroy(s: Student):
+    s.close()
+
+
+def student_get_state(s: Student):
+    w, m, v = (np.zeros(STUDENT_PARAMS) for _ in range(3))
+    t = ctypes.c_int64()
+    _check(_lib.student_get_state(s.ptr, w.ctypes.data_as(ctypes.c_void_p),
+                                  m.ctypes.data_as(ctypes.c_void_p),
+                                  v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)),
+           "student_get_state")
+    return w, m, v, t.value
+
+
+def student_set_state(s: Student, w, m, v, step: int):
+    w, m, v = (np.ascontiguousarray(a, dtype=np.float64) for a in (w, m, v))
+    _check(_lib.student_set_state(s.ptr, w.ctypes.data_as(ctypes.c_void_p),
+                                  m.ctypes.data_as(ctypes.c_void_p),
+                                  v.ctypes.data_as(ctypes.c_void_p), int(step)),
+           "student_set_state")
+
+
+def _check_patches(patches, teacher):
+    import torch
+    _require_cuda(patches, torch.uint8, "patches")
+    _require_cuda(teacher, torch.float32, "teacher_prob")
+    B, P, P2 = patches.shape
+    if P != P2 or tuple(teacher.shape) != (B, P - STUDENT_R, P - STUDENT_R):
+        raise ValueError("patches B x P x P and teacher B x (P-6) x (P-6) expected")
+    return B, P
+
+
+def student_grad(s: Student, patches, teacher, grad_out=None, loss_out=None, stream=None):
+    import torch
+    B, P = _check_patches(patches, teacher)
+    dev = patches.device
+    if grad_out is None:
+        grad_out = torch.empty(STUDENT_PARAMS, dtype=torch.float32, device=dev)
+    if loss_out is None:
+        loss_out = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(_lib.student_grad(s.ptr, _ptr(patches), _ptr(teacher), B, P, _ptr(grad_out),
+                             _ptr(loss_out), _stream(stream)), "student_grad")
+    return grad_out, loss_out
+
+
+def student_train_step(s: Student, patches, teacher, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                       loss_out=None, gnorm_out=None, stream=None):
+    import torch
+    B, P = _check_patches(patches, teacher)
+    dev = patches.device
+    if loss_out is None:
+        loss_out = torch.empty(1, dtype=torch.float64, device=dev)
+    if gnorm_out is None:
+        gnorm_out = torch.empty(1, dtype=torch.float64, device=dev)
+    hp = _Adam(lr, beta1, beta2, eps)
+    _check(_lib.student_train_step(s.ptr, _ptr(patches), _ptr(teacher), B, P, ctypes.byref(hp),
+                                   _ptr(loss_out), _ptr(gnorm_out), _stream(stream)),
+           "student_train_step")
+    return loss_out, gnorm_out
+
+
+def student_infer(s: Student, volume, out=None, stream=None):
+    import torch
+    _require_cuda(volume, torch.uint8, "volume")
+    Z, H, W = volume.shape
+    if out is None:
+        out = torch.empty((Z, H - STUDENT_R, W - STUDENT_R), dtype=torch.float32, device=volume.device)
+    _require_cuda(out, torch.float32, "out")
+    _check(_lib.student_infer(s.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
+           "student_infer")
+    return out
+
+
+def student_infer_with_fallback(s: Student, teacher: Net, volume, tau=0.01, tile=512, n_samples=4,
+                                seed=0, out=None, stats=None, stream=None):
+    import torch
+    _require_cuda(volume, torch.uint8, "volume")
+    Z, H, W = volume.shape
+    R = teacher.R
+    if out is None:
+        out = torch.empty((Z, H - R, W - R), dtype=torch.float32, device=volume.device)
+    if stats is None:
+        stats = torch.zeros(2, dtype=torch.int32, device=volume.device)
+    _check(_lib.student_infer_with_fallback(s.ptr, teacher.ptr, _ptr(volume), _dims(volume),
+                                            _ptr(out), float(tau), int(tile), int(n_samples),
+                                            int(seed), _ptr(stats), _stream(stream)),
+           "student_infer_with_fallback")
+    return out, stats

@@ -1,0 +1,88 @@
+// Internal types shared by the library's host runtime and its kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace emcnn {
+
+enum Prec : int { F32 = 0, BF16 = 1, FP8 = 2 };
+
+// One 3-D activation volume processed by one layer launch.
+//
+// Activations between layers are NHWC: element (z, y, x, c) of a C-channel
+// tensor lives at ((z * zs) + y * rs + x) * C + c, with rs / zs in pixels.
+// The first layer reads the caller's uint8 volume with the same addressing
+// (C = 1); the head layer writes float32 probabilities (C = 1).
+//
+// (hin, win) are the dims of the STORED input. When the layer pools its input
+// (a 2x2 stride-1 max filter sits between the previous conv and this one) the
+// layer sees a (hin-1) x (win-1) input. (hout, wout) are this layer's conv
+// output dims.
+struct LayerJob {
+  const void* in;
+  void* out;
+  int64_t in_rs, in_zs;
+  int64_t out_rs, out_zs;
+  int64_t item0;  // index of this job's first work item across the launch
+  const int32_t* gate;  // device flag; the job's items are skipped when *gate == 0 (nullptr: always run)
+  int32_t z, hin, win, hout, wout;
+  int32_t tiles_x, tiles_y;
+  int32_t pad_;
+};
+
+// Work description of one layer launch: either a single job passed by value,
+// or a device table of jobs (batched submissions).
+struct JobSet {
+  const LayerJob* table;  // device; nullptr -> use `single`
+  int32_t njobs;
+  int32_t pad_;
+  int64_t total_items;
+  LayerJob single;
+};
+
+struct ConvParams {
+  const void* wpack;     // packed B fragments (layout decided by the kernel variant)
+  const float* bias;     // [cout]
+  const float* oscale;   // [cout] epilogue multiplier, nullptr = 1
+  const float* head_w;   // [cout] head weights (head variants)
+  float head_b;
+  float out_inv_scale;   // FP8 output codes: e4m3(v * out_inv_scale)
+};
+
+struct FirstParams {
+  const float* w;     // [cout][k][k], with 1/255 folded in (bf16 values in BF16/FP8 nets)
+  const float* bias;  // [cout]
+  float out_inv_scale;
+  float pad_;
+};
+
+// Compile-time description of a conv-kernel variant (also used on the host to
+// pack weights in the layout the variant reads).
+struct VariantInfo {
+  int prec, cin, cout, ks, pool_in, head;
+  int ty, tx, mw;       // output tile rows / cols, m-blocks per wave
+  int threads;
+  int cb;               // channels staged per LDS pass
+  int chb;              // channels per 16-byte chunk
+  int u;                // chunks per lane per MFMA
+  int ngs;              // group-steps per channel block
+  int lds_bytes;
+  const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
+  const char* name;
+};
+
+struct FirstInfo {
+  int prec_out, cout, ks;
+  int ty, tx, threads;
+  int lds_bytes;
+  const void* fn;
+  const char* name;
+};
+
+// Registries implemented in conv_kernels.hip.
+int conv_variant_count();
+const VariantInfo* conv_variant(int i);
+int first_variant_count();
+const FirstInfo* first_variant(int i);
+
+}  // namespace emcnn

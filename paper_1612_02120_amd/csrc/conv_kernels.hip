@@ -1,0 +1,510 @@
+// Dense convolution kernels for gfx950 (CDNA4).
+//
+// The network (arXiv 1612.02120, Section 2.2) alternates valid convolutions
+// with 2x2 max pooling; the dense per-pixel output is obtained by evaluating
+// every pooling as a stride-1 max filter, so every layer is a stride-1 valid
+// convolution over the whole slice and no pixel is computed twice.
+//
+// Kernels here:
+//   conv_first  - the 1-channel first layer on the VALU, reading the caller's
+//                 uint8 volume (1/255 is folded into its weights on the host).
+//   conv_mfma   - every later conv as an implicit GEMM on MFMA: M = output
+//                 pixels (16 consecutive pixels of a row per m-block), N = output
+//                 channels (16 per n-block), K = (tap, input channel).
+//                 The input tile plus halo is staged in LDS, the preceding 2x2
+//                 stride-1 max filter is applied while staging, and bias, ReLU and
+//                 the output cast (or the 1x1 head and sigmoid) are fused into the
+//                 epilogue.
+//
+// Both are persistent: a grid of a multiple of 8 workgroups walks the work
+// items (z, tile_y, tile_x) of one or many jobs. Workgroups are dispatched to
+// the 8 XCDs round-robin, so workgroup b works on the b%8-th eighth of the item
+// range: neighbouring tiles, which share halo rows, meet in the same L2.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace emcnn {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned char u8x16 __attribute__((ext_vector_type(16)));
+
+template <int P>
+struct PT;
+template <>
+struct PT<F32> {
+  static constexpr int CHB = 4, U = 1, BYTES = 4, CB = 16;
+};
+template <>
+struct PT<BF16> {
+  static constexpr int CHB = 8, U = 1, BYTES = 2, CB = 24;
+};
+template <>
+struct PT<FP8> {
+  static constexpr int CHB = 16, U = 2, BYTES = 1, CB = 48;
+};
+
+// Smallest word count >= w that is 4 mod 8: consecutive pixels then start on
+// distinct 4-bank groups, so 8 lanes reading 16 B each hit all 32 banks once.
+__host__ __device__ constexpr int pad_words(int w) {
+  return (w % 8 == 4) ? w : w + ((12 - (w % 8)) % 8);
+}
+
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW>
+struct Cfg {
+  using T = PT<P>;
+  static constexpr int CB = (T::CB < CIN) ? T::CB : CIN;
+  static_assert(CIN % CB == 0, "channel block must divide CIN");
+  static constexpr int NCB = CIN / CB;
+  static constexpr int NCHB = CB / T::CHB;  // 16-byte chunks per pixel per block
+  static_assert(NCHB * T::CHB == CB, "block must be whole chunks");
+  static constexpr int NCHK = KS * KS * NCHB;  // chunks of K per block
+  static constexpr int SLOTS = 4 * T::U;       // chunks consumed per group-step
+  static constexpr int NGS = (NCHK + SLOTS - 1) / SLOTS;
+  static constexpr int NB = COUT / 16;
+  static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
+  static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
+  static constexpr int LDS = LR * LC * PSB;
+  static constexpr int MBLK = TY * TX / 16;
+  static_assert(TX % 16 == 0, "TX must be a multiple of 16");
+  static_assert(MBLK % MW == 0, "m-blocks must split evenly over waves");
+  static constexpr int WAVES = MBLK / MW;
+  static constexpr int THREADS = WAVES * 64;
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ float relu(float v) { return v > 0.0f ? v : 0.0f; }  // +0 for v <= 0
+
+__device__ __forceinline__ float sigmoid_f(float t) {
+  if (t >= 0.0f) return 1.0f / (1.0f + expf(-t));
+  float e = expf(t);
+  return e / (1.0f + e);
+}
+
+__device__ __forceinline__ unsigned char to_e4m3(float v) {
+  // v >= 0 here (post-ReLU); saturate at the largest finite e4m3fn value.
+  v = fminf(v, 448.0f);
+  int packed = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false);
+  return (unsigned char)(packed & 0xff);
+}
+
+template <int P>
+__device__ __forceinline__ void store_act(void* base, int64_t idx, float v, float inv);
+template <>
+__device__ __forceinline__ void store_act<F32>(void* base, int64_t idx, float v, float) {
+  reinterpret_cast<float*>(base)[idx] = v;
+}
+template <>
+__device__ __forceinline__ void store_act<BF16>(void* base, int64_t idx, float v, float) {
+  reinterpret_cast<__bf16*>(base)[idx] = (__bf16)v;
+}
+template <>
+__device__ __forceinline__ void store_act<FP8>(void* base, int64_t idx, float v, float inv) {
+  reinterpret_cast<unsigned char*>(base)[idx] = to_e4m3(v * inv);
+}
+
+// Elementwise max of two 16-byte chunks of non-negative activations. For
+// non-negative bf16 and e4m3fn values the bit patterns are ordered like the
+// values, so an unsigned integer max is the float max.
+template <int P>
+__device__ __forceinline__ i4v chunk_max(i4v a, i4v b);
+template <>
+__device__ __forceinline__ i4v chunk_max<F32>(i4v a, i4v b) {
+  f4 x = __builtin_bit_cast(f4, a), y = __builtin_bit_cast(f4, b);
+  f4 r;
+  r[0] = fmaxf(x[0], y[0]);
+  r[1] = fmaxf(x[1], y[1]);
+  r[2] = fmaxf(x[2], y[2]);
+  r[3] = fmaxf(x[3], y[3]);
+  return __builtin_bit_cast(i4v, r);
+}
+template <>
+__device__ __forceinline__ i4v chunk_max<BF16>(i4v a, i4v b) {
+  u16x8 x = __builtin_bit_cast(u16x8, a), y = __builtin_bit_cast(u16x8, b);
+  return __builtin_bit_cast(i4v, __builtin_elementwise_max(x, y));
+}
+template <>
+__device__ __forceinline__ i4v chunk_max<FP8>(i4v a, i4v b) {
+  u8x16 x = __builtin_bit_cast(u8x16, a), y = __builtin_bit_cast(u8x16, b);
+  return __builtin_bit_cast(i4v, __builtin_elementwise_max(x, y));
+}
+
+template <int P>
+struct Frag;
+template <>
+struct Frag<F32> {
+  f4 v;
+};
+template <>
+struct Frag<BF16> {
+  bf16x8 v;
+};
+template <>
+struct Frag<FP8> {
+  i8v v;
+};
+
+template <int P>
+__device__ __forceinline__ void mma(f4& acc, const Frag<P>& a, const Frag<P>& b);
+template <>
+__device__ __forceinline__ void mma<F32>(f4& acc, const Frag<F32>& a, const Frag<F32>& b) {
+  // one 16-byte chunk = 4 channels = 4 MFMA k-steps of 4 (one channel per lane group)
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[0], b.v[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[1], b.v[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[2], b.v[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[3], b.v[3], acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void mma<BF16>(f4& acc, const Frag<BF16>& a, const Frag<BF16>& b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void mma<FP8>(f4& acc, const Frag<FP8>& a, const Frag<FP8>& b) {
+  // format 0 = e4m3 for both operands; unit block scales (E8M0 127 = 2^0)
+  acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, acc, 0, 0, 0, 127, 0, 127);
+}
+
+template <int P>
+__device__ __forceinline__ void load_frag(Frag<P>& f, const unsigned char* p0, const unsigned char* p1);
+template <>
+__device__ __forceinline__ void load_frag<F32>(Frag<F32>& f, const unsigned char* p0, const unsigned char*) {
+  f.v = *reinterpret_cast<const f4*>(p0);
+}
+template <>
+__device__ __forceinline__ void load_frag<BF16>(Frag<BF16>& f, const unsigned char* p0, const unsigned char*) {
+  f.v = *reinterpret_cast<const bf16x8*>(p0);
+}
+template <>
+__device__ __forceinline__ void load_frag<FP8>(Frag<FP8>& f, const unsigned char* p0, const unsigned char* p1) {
+  i4v lo = *reinterpret_cast<const i4v*>(p0);
+  i4v hi = *reinterpret_cast<const i4v*>(p1);
+  f.v = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// Persistent work distribution: workgroup b serves XCD b % 8 (hardware
+// round-robin) and walks the matching eighth of the item range.
+struct ItemRange {
+  int64_t begin, end, step;
+};
+
+__device__ __forceinline__ ItemRange item_range(int64_t total) {
+  const int64_t G = gridDim.x;
+  const int64_t b = blockIdx.x;
+  if ((G & 7) != 0) return {b, total, G};
+  const int64_t per = (total + 7) >> 3;
+  const int64_t begin = (b & 7) * per;
+  int64_t end = begin + per;
+  if (end > total) end = total;
+  return {begin + (b >> 3), end, G >> 3};
+}
+
+__device__ __forceinline__ int find_job(const LayerJob* t, int n, int64_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (t[mid].item0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- first layer
+
+template <int PO, int COUT, int KS, int TY, int TX>
+__global__ __launch_bounds__((TY * TX)) void conv_first(JobSet js, FirstParams prm) {
+  constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  __shared__ float tile[LR * LC];
+  const int tid = threadIdx.x;
+  const int ty = tid / TX, tx = tid % TX;
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    LayerJob J;
+    if (js.table) {
+      while (cur + 1 < js.njobs && js.table[cur + 1].item0 <= item) ++cur;
+      J = js.table[cur];
+    } else {
+      J = js.single;
+    }
+    if (J.gate && *J.gate == 0) continue;
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int by = (int)(t2 % J.tiles_y);
+    const int zz = (int)(t2 / J.tiles_y);
+    const int y0 = by * TY, x0 = bx * TX;
+    const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs;
+    __syncthreads();
+    for (int t = tid; t < LR * LC; t += TY * TX) {
+      int r = t / LC, c = t % LC;
+      int y = min(y0 + r, J.hin - 1), x = min(x0 + c, J.win - 1);
+      tile[t] = (float)in[(int64_t)y * J.in_rs + x];
+    }
+    __syncthreads();
+    float acc[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = prm.bias[co];
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int j = 0; j < KS; ++j) {
+        const float xv = tile[(ty + i) * LC + tx + j];
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) acc[co] = fmaf(prm.w[(co * KS + i) * KS + j], xv, acc[co]);
+      }
+    const int y = y0 + ty, x = x0 + tx;
+    if (y < J.hout && x < J.wout) {
+      const int64_t pix = (int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x;
+      if constexpr (PO == F32) {
+        f4* o = reinterpret_cast<f4*>(reinterpret_cast<float*>(J.out) + pix * COUT);
+#pragma unroll
+        for (int q = 0; q < COUT / 4; ++q)
+          o[q] = f4{relu(acc[4 * q]), relu(acc[4 * q + 1]), relu(acc[4 * q + 2]), relu(acc[4 * q + 3])};
+      } else if constexpr (PO == BF16) {
+        bf16x8* o = reinterpret_cast<bf16x8*>(reinterpret_cast<__bf16*>(J.out) + pix * COUT);
+#pragma unroll
+        for (int q = 0; q < COUT / 8; ++q) {
+          bf16x8 v;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (__bf16)relu(acc[8 * q + e]);
+          o[q] = v;
+        }
+      } else {
+        i4v* o = reinterpret_cast<i4v*>(reinterpret_cast<unsigned char*>(J.out) + pix * COUT);
+#pragma unroll
+        for (int q = 0; q < COUT / 16; ++q) {
+          u8x16 v;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) v[e] = to_e4m3(relu(acc[16 * q + e]) * prm.out_inv_scale);
+          o[q] = __builtin_bit_cast(i4v, v);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- MFMA conv
+
+// Packed weights: for channel block cb, group-step s, n-block nb, lane l,
+// U chunks of 16 bytes. Lane l (n = l % 16, lane group g = l / 16) holds for
+// chunk slot c = (4 s + g) U + uu the CHB input channels of tap (i, j), chunk
+// cg, where c -> (i, j, cg) row-major over (KS, KS, NCHB). The A side decodes
+// the same slot the same way, so the MFMA contracts matching K indices
+// whatever order the instruction uses inside a lane's operand bytes.
+template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int MW>
+__global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS)) void conv_mfma(JobSet js, ConvParams prm) {
+  using C = Cfg<P, CIN, COUT, KS, TY, TX, MW>;
+  using T = PT<P>;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  constexpr int MCOLS = TX / 16;
+  constexpr int ELB = CIN * T::BYTES;  // bytes per stored input pixel
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    LayerJob J;
+    if (js.table) {
+      while (cur + 1 < js.njobs && js.table[cur + 1].item0 <= item) ++cur;
+      J = js.table[cur];
+    } else {
+      J = js.single;
+    }
+    if (J.gate && *J.gate == 0) continue;
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int by = (int)(t2 % J.tiles_y);
+    const int zz = (int)(t2 / J.tiles_y);
+    const int y0 = by * TY, x0 = bx * TX;
+    const int hp = J.hin - (POOL ? 1 : 0), wp = J.win - (POOL ? 1 : 0);  // logical input dims
+    const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs * ELB;
+    const int64_t rowb = J.in_rs * ELB;
+
+    f4 acc[MW][C::NB];
+#pragma unroll
+    for (int u = 0; u < MW; ++u)
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) acc[u][nb] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int cb = 0; cb < C::NCB; ++cb) {
+      __syncthreads();
+      // ---- stage the (TY+KS-1) x (TX+KS-1) input tile of this channel block
+      constexpr int NST = C::LR * C::LC * C::NCHB;
+      for (int t = tid; t < NST; t += C::THREADS) {
+        const int cg = t % C::NCHB;
+        const int pix = t / C::NCHB;
+        const int r = pix / C::LC, c = pix % C::LC;
+        const int y = min(y0 + r, hp - 1), x = min(x0 + c, wp - 1);
+        const unsigned char* src = in + (int64_t)y * rowb + (int64_t)x * ELB + (cb * C::CB + cg * T::CHB) * T::BYTES;
+        i4v v = *reinterpret_cast<const i4v*>(src);
+        if constexpr (POOL) {
+          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + ELB));
+          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb));
+          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb + ELB));
+        }
+        *reinterpret_cast<i4v*>(lds + pix * C::PSB + cg * 16) = v;
+      }
+      __syncthreads();
+      // ---- implicit GEMM over this block's (tap, chunk) slots
+      const unsigned char* wb = reinterpret_cast<const unsigned char*>(prm.wpack) +
+                                (size_t)cb * C::NGS * C::NB * 64 * T::U * 16;
+#pragma unroll 2
+      for (int s = 0; s < C::NGS; ++s) {
+        Frag<P> bfr[C::NB];
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const unsigned char* p = wb + ((size_t)(s * C::NB + nb) * 64 + lane) * (T::U * 16);
+          load_frag<P>(bfr[nb], p, p + 16);
+        }
+        int off[T::U];
+#pragma unroll
+        for (int uu = 0; uu < T::U; ++uu) {
+          int c = (4 * s + g) * T::U + uu;
+          c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
+          const int i = c / (KS * C::NCHB);
+          const int rem = c % (KS * C::NCHB);
+          const int j = rem / C::NCHB, cg = rem % C::NCHB;
+          off[uu] = (i * C::LC + j) * C::PSB + cg * 16;
+        }
+#pragma unroll
+        for (int u = 0; u < MW; ++u) {
+          const int mb = wave * MW + u;
+          const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+          const unsigned char* a0 = lds + (mrow * C::LC + mcol * 16 + n16) * C::PSB;
+          Frag<P> afr;
+          load_frag<P>(afr, a0 + off[0], a0 + off[T::U - 1]);
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[u][nb], afr, bfr[nb]);
+        }
+      }
+    }
+
+    // ---- epilogue: lane holds D[m = 4 g + k][n = n16] of each (m-block, n-block)
+    float bias[C::NB], osc[C::NB], hw[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) {
+      bias[nb] = prm.bias[nb * 16 + n16];
+      osc[nb] = prm.oscale ? prm.oscale[nb * 16 + n16] : 1.0f;
+      if constexpr (HEAD) hw[nb] = prm.head_w[nb * 16 + n16];
+    }
+#pragma unroll
+    for (int u = 0; u < MW; ++u) {
+      const int mb = wave * MW + u;
+      const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+      const int y = y0 + mrow;
+      const int xb = x0 + mcol * 16 + 4 * g;
+      if constexpr (HEAD) {
+        float part[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float p = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) p = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], p);
+          p += __shfl_xor(p, 1);
+          p += __shfl_xor(p, 2);
+          p += __shfl_xor(p, 4);
+          p += __shfl_xor(p, 8);
+          part[k] = p;
+        }
+        if (n16 < 4) {
+          const int x = xb + n16;
+          const float z = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
+          if (y < J.hout && x < J.wout)
+            reinterpret_cast<float*>(J.out)[(int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x] = sigmoid_f(z);
+        }
+      } else {
+        if (y < J.hout) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x = xb + k;
+            if (x < J.wout) {
+              const int64_t pix = (int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x;
+#pragma unroll
+              for (int nb = 0; nb < C::NB; ++nb) {
+                const float v = relu(fmaf(acc[u][nb][k], osc[nb], bias[nb]));
+                store_act<P>(J.out, pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- registry
+
+#define EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW)                                          \
+  VariantInfo{P,                                                                                      \
+              CIN,                                                                                    \
+              COUT,                                                                                   \
+              KS,                                                                                     \
+              POOL,                                                                                   \
+              HEAD,                                                                                   \
+              TY,                                                                                     \
+              TX,                                                                                     \
+              MW,                                                                                     \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS,                                             \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW>::CB,                                                  \
+              PT<P>::CHB,                                                                             \
+              PT<P>::U,                                                                               \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW>::NGS,                                                 \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW>::LDS,                                                 \
+              reinterpret_cast<const void*>(&conv_mfma<P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW>), \
+              "conv_mfma<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #MW ">"}
+
+// Tile shapes per layer signature; the first of each signature is the default,
+// the rest are autotuner candidates.
+#define EMCNN_SHAPES(P, CIN, COUT, KS, POOL, HEAD)                                             \
+  EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 4, 64, 4), \
+      EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
+
+static const VariantInfo kConv[] = {
+    // net B body: 48 -> 48, 5x5 after a pool; 3x3 after a pool with the head fused
+    EMCNN_SHAPES(F32, 48, 48, 5, true, false),
+    EMCNN_SHAPES(F32, 48, 48, 3, true, true),
+    EMCNN_SHAPES(BF16, 48, 48, 5, true, false),
+    EMCNN_SHAPES(BF16, 48, 48, 3, true, true),
+    EMCNN_SHAPES(FP8, 48, 48, 5, true, false),
+    EMCNN_SHAPES(FP8, 48, 48, 3, true, true),
+    // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
+    EMCNN_SHAPES(F32, 16, 16, 5, false, true),
+    // same layer shapes without the pool / with the head elsewhere (generic specs)
+    EMCNN_CONV(F32, 48, 48, 5, false, false, 8, 32, 4),
+    EMCNN_CONV(F32, 48, 48, 3, false, true, 8, 32, 4),
+    EMCNN_CONV(F32, 48, 48, 5, false, true, 8, 32, 4),
+    EMCNN_CONV(BF16, 48, 48, 5, false, false, 8, 32, 4),
+    EMCNN_CONV(BF16, 48, 48, 3, false, true, 8, 32, 4),
+    EMCNN_CONV(FP8, 48, 48, 5, false, false, 8, 32, 4),
+    EMCNN_CONV(FP8, 48, 48, 3, false, true, 8, 32, 4),
+    EMCNN_CONV(F32, 16, 16, 5, true, true, 8, 32, 4),
+    EMCNN_CONV(F32, 16, 16, 5, false, false, 8, 32, 4),
+};
+
+#define EMCNN_FIRST(PO, COUT, KS, TY, TX)                                                            \
+  FirstInfo{PO, COUT, KS, TY, TX, TY * TX, (TY + KS - 1) * (TX + KS - 1) * 4,                        \
+            reinterpret_cast<const void*>(&conv_first<PO, COUT, KS, TY, TX>),                         \
+            "conv_first<" #PO "," #COUT "," #KS "," #TY "," #TX ">"}
+
+static const FirstInfo kFirst[] = {
+    EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 8, 32), EMCNN_FIRST(FP8, 48, 5, 8, 32),
+    EMCNN_FIRST(F32, 16, 5, 8, 32),  EMCNN_FIRST(F32, 48, 5, 16, 16), EMCNN_FIRST(BF16, 48, 5, 16, 16),
+    EMCNN_FIRST(FP8, 48, 5, 16, 16),
+};
+
+int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }
+const VariantInfo* conv_variant(int i) { return &kConv[i]; }
+int first_variant_count() { return (int)(sizeof(kFirst) / sizeof(kFirst[0])); }
+const FirstInfo* first_variant(int i) { return &kFirst[i]; }
+
+}  // namespace emcnn

@@ -1,0 +1,631 @@
+// Work planning and launches for cnn_infer / cnn_infer_batch and the
+// teacher passes of the student fallback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "../../include/emcnn.h"
+#include "common.h"
+#include "runtime.h"
+
+namespace emcnn {
+
+static int act_bytes_of(int prec) { return prec == F32 ? 4 : prec == BF16 ? 2 : 1; }
+
+Dims layer_dims(const Net* net, int h, int w) {
+  Dims d;
+  for (const auto& L : net->layers) {
+    d.hin.push_back(h);
+    d.win.push_back(w);
+    h = h - L.pool_in - L.ks + 1;
+    w = w - L.pool_in - L.ks + 1;
+    d.hout.push_back(h);
+    d.wout.push_back(w);
+  }
+  return d;
+}
+
+// Bytes per slice of each layer's stored output (0 for the head layer).
+static std::vector<size_t> layer_bytes(const Net* net, const Dims& d) {
+  std::vector<size_t> b;
+  const int nl = (int)net->layers.size();
+  for (int l = 0; l < nl; ++l)
+    b.push_back(l == nl - 1 ? 0
+                            : (size_t)d.hout[l] * d.wout[l] * net->layers[l].cout * act_bytes_of(net->prec));
+  return b;
+}
+
+int ensure_ws(Net* net, size_t need) {
+  if (need <= net->ws_bytes) return CNN_OK;
+  hipError_t e;
+  if (net->ws) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "workspace grow: sync");
+    hipFree(net->ws);
+    net->ws = nullptr;
+    net->ws_bytes = 0;
+  }
+  need = (need + (1 << 20) - 1) & ~(size_t)((1 << 20) - 1);
+  if ((e = hipMalloc(&net->ws, need)) != hipSuccess) {
+    net->ws = nullptr;
+    return fail(CNN_ENOMEM, std::string("workspace hipMalloc(") + std::to_string(need) + "): " + hipGetErrorString(e));
+  }
+  net->ws_bytes = need;
+  return CNN_OK;
+}
+
+static LayerJob make_job(const ExecLayer& L, const void* in, void* out, int z, int hin, int win, int64_t in_rs,
+                         int64_t in_zs, int hout, int wout, int64_t out_rs, int64_t out_zs, int64_t item0,
+                         const int32_t* gate) {
+  LayerJob j;
+  std::memset(&j, 0, sizeof(j));
+  j.in = in;
+  j.out = out;
+  j.z = z;
+  j.hin = hin;
+  j.win = win;
+  j.in_rs = in_rs;
+  j.in_zs = in_zs;
+  j.hout = hout;
+  j.wout = wout;
+  j.out_rs = out_rs;
+  j.out_zs = out_zs;
+  j.tiles_x = (wout + layer_tx(L) - 1) / layer_tx(L);
+  j.tiles_y = (hout + layer_ty(L) - 1) / layer_ty(L);
+  j.item0 = item0;
+  j.gate = gate;
+  return j;
+}
+
+static int64_t job_items(const LayerJob& j) { return (int64_t)j.z * j.tiles_y * j.tiles_x; }
+
+int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st) {
+  (void)net;
+  const void* fn = layer_fn(L);
+  hipError_t e;
+  if (L.first) {
+    FirstParams p;
+    p.w = reinterpret_cast<const float*>(L.wpack);
+    p.bias = L.bias;
+    p.out_inv_scale = L.out_inv_scale;
+    p.pad_ = 0.f;
+    void* args[] = {(void*)&js, (void*)&p};
+    e = hipLaunchKernel(fn, dim3(grid), dim3(layer_threads(L)), args, 0, st);
+  } else {
+    ConvParams p;
+    p.wpack = L.wpack;
+    p.bias = L.bias;
+    p.oscale = L.oscale;
+    p.head_w = L.head_w;
+    p.head_b = L.head_b;
+    p.out_inv_scale = L.out_inv_scale;
+    void* args[] = {(void*)&js, (void*)&p};
+    e = hipLaunchKernel(fn, dim3(grid), dim3(layer_threads(L)), args, 0, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, layer_name(L));
+  return CNN_OK;
+}
+
+// A whole volume: slabs of slices sized so the two inter-layer buffers stay
+// within the workspace budget; one persistent launch per layer per slab.
+int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, float* prob, hipStream_t st) {
+  const Dims d = layer_dims(net, (int)H, (int)W);
+  const std::vector<size_t> lb = layer_bytes(net, d);
+  const int nl = (int)net->layers.size();
+  size_t b0 = 0, b1 = 0;
+  for (int l = 0; l < nl; ++l) (l % 2 ? b1 : b0) = std::max((l % 2 ? b1 : b0), lb[l]);
+  const size_t per = std::max<size_t>(1, b0 + b1);
+  int64_t zs = std::max<int64_t>(1, std::min<int64_t>(Z, (int64_t)(net->ws_budget / per)));
+  int rc = ensure_ws(net, zs * (b0 + b1));
+  if (rc) return rc;
+  unsigned char* buf[2] = {reinterpret_cast<unsigned char*>(net->ws),
+                           reinterpret_cast<unsigned char*>(net->ws) + zs * b0};
+  const int Ho = d.hout[nl - 1], Wo = d.wout[nl - 1];
+  for (int64_t z0 = 0; z0 < Z; z0 += zs) {
+    const int zc = (int)std::min<int64_t>(zs, Z - z0);
+    for (int l = 0; l < nl; ++l) {
+      const ExecLayer& L = net->layers[l];
+      const void* in = (l == 0) ? (const void*)(vol + z0 * H * W) : (const void*)buf[(l - 1) % 2];
+      void* out = (l == nl - 1) ? (void*)(prob + z0 * (int64_t)Ho * Wo) : (void*)buf[l % 2];
+      LayerJob j = make_job(L, in, out, zc, d.hin[l], d.win[l], d.win[l], (int64_t)d.hin[l] * d.win[l], d.hout[l],
+                            d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
+      JobSet js;
+      std::memset(&js, 0, sizeof(js));
+      js.njobs = 1;
+      js.total_items = job_items(j);
+      js.single = j;
+      rc = launch_layer(net, L, js, persistent_grid(net, L, js.total_items), st);
+      if (rc) return rc;
+    }
+  }
+  return CNN_OK;
+}
+
+// ------------------------------------------------------------------ regions
+
+// Wait until earlier submissions no longer read the pinned job-table arena,
+// then make the arena hold `njobs` jobs (host and device copies).
+int arena_reserve(Net* net, size_t njobs) {
+  hipError_t e;
+  if (net->done_pending) {
+    if ((e = hipEventSynchronize(net->done)) != hipSuccess) return hip_fail(e, "wait previous submission");
+    net->done_pending = false;
+  }
+  const size_t bytes = std::max<size_t>(1, njobs) * sizeof(LayerJob);
+  if (net->tab_host_bytes < bytes) {
+    if (net->tab_host) hipHostFree(net->tab_host);
+    net->tab_host = nullptr;
+    net->tab_host_bytes = 0;
+    if ((e = hipHostMalloc(&net->tab_host, bytes)) != hipSuccess) return fail(CNN_ENOMEM, "pinned job table");
+    net->tab_host_bytes = bytes;
+  }
+  if (net->tab_dev_bytes < bytes) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "job table grow: sync");
+    if (net->tab_dev) hipFree(net->tab_dev);
+    net->tab_dev = nullptr;
+    net->tab_dev_bytes = 0;
+    if ((e = hipMalloc(&net->tab_dev, bytes)) != hipSuccess) return fail(CNN_ENOMEM, "device job table");
+    net->tab_dev_bytes = bytes;
+    if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
+    net->graph_exec = nullptr;
+    net->graph_key.clear();
+  }
+  if (!net->done) {
+    if ((e = hipEventCreateWithFlags(&net->done, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+  }
+  return CNN_OK;
+}
+
+// Split regions whose slices alone exceed the budget, then group regions so a
+// group's inter-layer buffers fit the workspace budget. Writes one job per
+// (group, layer, region) into the arena from `job_off` on and appends the
+// launches. Returns the workspace bytes needed in ws_need.
+int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off, std::vector<Launch>& launches,
+                 size_t& njobs_used, size_t& ws_need) {
+  const int nl = (int)net->layers.size();
+  // per-region geometry; regions with too many slices are split by z
+  std::vector<Region> regs;
+  std::vector<Dims> dims;
+  std::vector<std::vector<size_t>> lbs;
+  for (const Region& r0 : in_regions) {
+    Dims d = layer_dims(net, r0.h, r0.w);
+    std::vector<size_t> lb = layer_bytes(net, d);
+    size_t per = 0;
+    for (size_t x : lb) per += x;
+    int64_t zmax = std::max<int64_t>(1, (int64_t)(net->ws_budget / std::max<size_t>(per, 1)));
+    for (int z0 = 0; z0 < r0.z; z0 += (int)zmax) {
+      Region r = r0;
+      r.z = (int)std::min<int64_t>(zmax, r0.z - z0);
+      r.in = r0.in + (int64_t)z0 * r0.in_zs;
+      r.out = r0.out + (int64_t)z0 * r0.out_zs;
+      regs.push_back(r);
+      dims.push_back(d);
+      lbs.push_back(lb);
+    }
+  }
+  const int n = (int)regs.size();
+  std::vector<size_t> b0(n), b1(n);
+  for (int t = 0; t < n; ++t) {
+    b0[t] = b1[t] = 0;
+    for (int l = 0; l < nl; ++l) (l % 2 ? b1[t] : b0[t]) += lbs[t][l] * regs[t].z;
+  }
+  std::vector<std::pair<int, int>> groups;
+  ws_need = 0;
+  {
+    int g0 = 0;
+    size_t s0 = 0, s1 = 0;
+    for (int t = 0; t < n; ++t) {
+      if (t > g0 && s0 + s1 + b0[t] + b1[t] > net->ws_budget) {
+        groups.push_back({g0, t});
+        ws_need = std::max(ws_need, s0 + s1);
+        g0 = t;
+        s0 = s1 = 0;
+      }
+      s0 += b0[t];
+      s1 += b1[t];
+    }
+    groups.push_back({g0, n});
+    ws_need = std::max(ws_need, s0 + s1);
+  }
+  const size_t need_jobs = job_off + (size_t)n * nl;
+  if (need_jobs * sizeof(LayerJob) > net->tab_host_bytes) return fail(CNN_EINVAL, "internal: job arena too small");
+  int rc = ensure_ws(net, ws_need);
+  if (rc) return rc;
+  LayerJob* tab = reinterpret_cast<LayerJob*>(net->tab_host);
+  size_t pos = job_off;
+  for (auto& G : groups) {
+    size_t half0 = 0;
+    for (int t = G.first; t < G.second; ++t) half0 += b0[t];
+    unsigned char* base0 = reinterpret_cast<unsigned char*>(net->ws);
+    unsigned char* base1 = base0 + half0;
+    std::vector<unsigned char*> r0(n), r1(n);
+    {
+      size_t a = 0, b = 0;
+      for (int t = G.first; t < G.second; ++t) {
+        r0[t] = base0 + a;
+        r1[t] = base1 + b;
+        a += b0[t];
+        b += b1[t];
+      }
+    }
+    for (int l = 0; l < nl; ++l) {
+      const ExecLayer& L = net->layers[l];
+      const size_t first = pos;
+      int64_t item0 = 0;
+      for (int t = G.first; t < G.second; ++t) {
+        const Region& R = regs[t];
+        const Dims& d = dims[t];
+        // output of layer q lives in half q % 2 after earlier layers of that parity
+        auto buf_of = [&](int q) -> unsigned char* {
+          size_t off = 0;
+          for (int p = q % 2; p < q; p += 2) off += lbs[t][p] * R.z;
+          return (q % 2 ? r1[t] : r0[t]) + off;
+        };
+        const void* in;
+        int64_t in_rs, in_zs;
+        if (l == 0) {
+          in = R.in;
+          in_rs = R.in_rs;
+          in_zs = R.in_zs;
+        } else {
+          in = buf_of(l - 1);
+          in_rs = d.win[l];
+          in_zs = (int64_t)d.hin[l] * d.win[l];
+        }
+        void* out;
+        int64_t out_rs, out_zs;
+        if (l == nl - 1) {
+          out = R.out;
+          out_rs = R.out_rs;
+          out_zs = R.out_zs;
+        } else {
+          out = buf_of(l);
+          out_rs = d.wout[l];
+          out_zs = (int64_t)d.hout[l] * d.wout[l];
+        }
+        LayerJob j = make_job(L, in, out, R.z, d.hin[l], d.win[l], in_rs, in_zs, d.hout[l], d.wout[l], out_rs, out_zs,
+                              item0, R.gate);
+        item0 += job_items(j);
+        tab[pos++] = j;
+      }
+      Launch la;
+      la.layer = l;
+      std::memset(&la.js, 0, sizeof(la.js));
+      la.js.table = reinterpret_cast<const LayerJob*>(net->tab_dev) + first;
+      la.js.njobs = (int)(pos - first);
+      la.js.total_items = item0;
+      la.grid = persistent_grid(net, L, (int64_t)1 << 40);  // full persistent grid: structure-stable
+      launches.push_back(la);
+    }
+  }
+  njobs_used = pos - job_off;
+  return CNN_OK;
+}
+
+size_t count_region_jobs(const Net* net, const std::vector<Region>& regs) {
+  // upper bound of the jobs plan_regions writes (regions may split by z)
+  const int nl = (int)net->layers.size();
+  size_t n = 0;
+  for (const Region& r : regs) {
+    Dims d = layer_dims(net, r.h, r.w);
+    std::vector<size_t> lb = layer_bytes(net, d);
+    size_t per = 0;
+    for (size_t x : lb) per += x;
+    int64_t zmax = std::max<int64_t>(1, (int64_t)(net->ws_budget / std::max<size_t>(per, 1)));
+    n += (size_t)((r.z + zmax - 1) / zmax) * nl;
+  }
+  return n;
+}
+
+// Upload the arena's first `njobs` jobs and run the launches, either directly on
+// `st` or through a captured graph that is replayed while the structure holds.
+int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t njobs, hipStream_t st, bool graph) {
+  hipError_t e;
+  const size_t tab_bytes = std::max<size_t>(1, njobs) * sizeof(LayerJob);
+  void* dsrc = reinterpret_cast<LayerJob*>(net->tab_dev) + job_off;
+  const void* hsrc = reinterpret_cast<const LayerJob*>(net->tab_host) + job_off;
+  if (!graph) {
+    if ((e = hipMemcpyAsync(dsrc, hsrc, tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+      return hip_fail(e, "job table upload");
+    for (auto& la : launches) {
+      int rc = launch_layer(net, net->layers[la.layer], la.js, la.grid, st);
+      if (rc) return rc;
+    }
+  } else {
+    std::vector<unsigned char> key;
+    auto put = [&key](const void* p, size_t b) {
+      const unsigned char* c = reinterpret_cast<const unsigned char*>(p);
+      key.insert(key.end(), c, c + b);
+    };
+    put(&tab_bytes, sizeof(tab_bytes));
+    put(&job_off, sizeof(job_off));
+    for (auto& la : launches) {
+      put(&la.layer, sizeof(int));
+      put(&la.grid, sizeof(int));
+      put(&la.js.table, sizeof(void*));
+      put(&la.js.njobs, sizeof(int));
+      put(&la.js.total_items, sizeof(int64_t));
+      const int v = net->layers[la.layer].variant;
+      put(&v, sizeof(int));
+    }
+    if (!net->graph_exec || key != net->graph_key) {
+      if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
+      net->graph_exec = nullptr;
+      net->graph_key.clear();
+      if (!net->cap_stream) {
+        if ((e = hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+          return hip_fail(e, "hipStreamCreate");
+      }
+      if ((e = hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+      int crc = CNN_OK;
+      if ((e = hipMemcpyAsync(dsrc, hsrc, tab_bytes, hipMemcpyHostToDevice, net->cap_stream)) != hipSuccess)
+        crc = hip_fail(e, "capture: job table upload");
+      for (auto& la : launches) {
+        if (crc) break;
+        crc = launch_layer(net, net->layers[la.layer], la.js, la.grid, net->cap_stream);
+      }
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(net->cap_stream, &g);
+      if (crc) {
+        if (g) hipGraphDestroy(g);
+        return crc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&net->graph_exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        net->graph_exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      net->graph_key = key;
+    }
+    if ((e = hipGraphLaunch(net->graph_exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  if ((e = hipEventRecord(net->done, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  net->done_pending = true;
+  return CNN_OK;
+}
+
+int check_device(const Net* net) {
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != net->device)
+    return fail(CNN_EINVAL, "handle was created on device " + std::to_string(net->device) + ", current is " +
+                                std::to_string(dev));
+  return CNN_OK;
+}
+
+}  // namespace emcnn
+
+using namespace emcnn;
+
+extern "C" int cnn_infer(cnn_net* h, const uint8_t* vol, const int64_t dims[3], float* prob, void* stream) {
+  clear_error();
+  if (!h || !vol || !dims || !prob) return fail(CNN_EINVAL, "cnn_infer: null argument");
+  Net* net = reinterpret_cast<Net*>(h);
+  const int64_t Z = dims[0], H = dims[1], W = dims[2];
+  if (Z < 1 || H < net->R + 1 || W < net->R + 1)
+    return fail(CNN_EINVAL, "cnn_infer: dims smaller than the field of view (" + std::to_string(net->R + 1) + ")");
+  if (H >= (1ll << 30) || W >= (1ll << 30) || Z >= (1ll << 30))
+    return fail(CNN_EINVAL, "cnn_infer: dims must be < 2^30");
+  int rc = check_device(net);
+  if (rc) return rc;
+  return run_volume(net, vol, Z, H, W, prob, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int cnn_set_batch_graph(cnn_net* h, int32_t enable) {
+  clear_error();
+  if (!h) return fail(CNN_EINVAL, "cnn_set_batch_graph: null net");
+  reinterpret_cast<Net*>(h)->use_graph = enable ? 1 : 0;
+  return CNN_OK;
+}
+
+extern "C" int cnn_set_workspace_limit(cnn_net* h, int64_t bytes) {
+  clear_error();
+  if (!h || bytes < (1 << 20)) return fail(CNN_EINVAL, "cnn_set_workspace_limit: null net or limit < 1 MiB");
+  reinterpret_cast<Net*>(h)->ws_budget = (size_t)bytes;
+  return CNN_OK;
+}
+
+extern "C" int cnn_infer_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, void* stream) {
+  clear_error();
+  if (!h || !tiles || n < 1) return fail(CNN_EINVAL, "cnn_infer_batch: null argument or n < 1");
+  Net* net = reinterpret_cast<Net*>(h);
+  int rc = check_device(net);
+  if (rc) return rc;
+  if (net->R % 2) return fail(CNN_EUNSUPPORTED, "cnn_infer_batch: odd receptive radius");
+  const int R2 = net->R / 2;
+  std::vector<Region> regs(n);
+  for (int t = 0; t < n; ++t) {
+    const cnn_tile& T = tiles[t];
+    if (!T.in || !T.out) return fail(CNN_EINVAL, "cnn_infer_batch: tile " + std::to_string(t) + " has a null pointer");
+    if (T.z < 1 || T.halo < R2 || T.h <= 2 * (int64_t)T.halo || T.w <= 2 * (int64_t)T.halo || T.h >= (1 << 30) ||
+        T.w >= (1 << 30) || T.z >= (1 << 30))
+      return fail(CNN_EINVAL, "cnn_infer_batch: tile " + std::to_string(t) + " has bad dims or halo < R/2");
+    // drop the halo surplus beyond R/2: the tile's interior is then exactly the valid output
+    const int e = T.halo - R2;
+    Region& r = regs[t];
+    r.in = T.in + (int64_t)e * T.w + e;
+    r.in_rs = T.w;
+    r.in_zs = T.h * T.w;
+    r.z = (int)T.z;
+    r.h = (int)(T.h - 2 * e);
+    r.w = (int)(T.w - 2 * e);
+    r.out = T.out;
+    r.out_rs = T.w - 2 * T.halo;
+    r.out_zs = (T.h - 2 * T.halo) * (T.w - 2 * T.halo);
+    r.gate = nullptr;
+  }
+  rc = arena_reserve(net, count_region_jobs(net, regs));
+  if (rc) return rc;
+  std::vector<Launch> launches;
+  size_t used = 0, ws_need = 0;
+  rc = plan_regions(net, regs, 0, launches, used, ws_need);
+  if (rc) return rc;
+  return submit(net, launches, 0, used, reinterpret_cast<hipStream_t>(stream), net->use_graph != 0);
+}
+
+// ------------------------------------------------------------------ autotuner
+
+namespace emcnn {
+
+static std::string layer_sig(const Net* net, const ExecLayer& L) {
+  return net->arch + "|p" + std::to_string(net->prec) + "|f" + std::to_string(L.first) + "|" + std::to_string(L.cin) +
+         "x" + std::to_string(L.cout) + "k" + std::to_string(L.ks) + "p" + std::to_string(L.pool_in) + "h" +
+         std::to_string(L.head);
+}
+
+static int candidate_name_index(const ExecLayer& L, const std::string& name) {
+  for (int c : L.candidates) {
+    const char* n = L.first ? first_variant(c)->name : conv_variant(c)->name;
+    if (name == n) return c;
+  }
+  return -1;
+}
+
+// One launch of layer l over a single H x W slice region.
+static int run_one_layer(Net* net, int l, const void* in, void* out, const Dims& d, hipStream_t st) {
+  const ExecLayer& L = net->layers[l];
+  LayerJob j = make_job(L, in, out, 1, d.hin[l], d.win[l], d.win[l], (int64_t)d.hin[l] * d.win[l], d.hout[l],
+                        d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
+  JobSet js;
+  std::memset(&js, 0, sizeof(js));
+  js.njobs = 1;
+  js.total_items = job_items(j);
+  js.single = j;
+  return launch_layer(net, L, js, persistent_grid(net, L, js.total_items), st);
+}
+
+}  // namespace emcnn
+
+extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_path, void* stream) {
+  clear_error();
+  if (!h) return fail(CNN_EINVAL, "cnn_autotune: null net");
+  Net* net = reinterpret_cast<Net*>(h);
+  if (H < net->R + 1 || W < net->R + 1 || H > 16384 || W > 16384)
+    return fail(CNN_EINVAL, "cnn_autotune: need R+1 <= H, W <= 16384");
+  int rc = check_device(net);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int nl = (int)net->layers.size();
+  const std::string shape = std::to_string(H) + "x" + std::to_string(W);
+  // cached choices
+  std::vector<std::string> lines;
+  std::vector<int> chosen(nl, -1);
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      lines.push_back(line);
+      for (int l = 0; l < nl; ++l) {
+        const std::string pre = layer_sig(net, net->layers[l]) + "|" + shape + "|";
+        if (line.rfind(pre, 0) == 0) chosen[l] = candidate_name_index(net->layers[l], line.substr(pre.size()));
+      }
+    }
+  }
+  bool all = true;
+  for (int l = 0; l < nl; ++l)
+    if (net->layers[l].candidates.size() > 1 && chosen[l] < 0) all = false;
+  if (all) {
+    for (int l = 0; l < nl; ++l)
+      if (chosen[l] >= 0) net->layers[l].variant = chosen[l];
+    return CNN_OK;
+  }
+  // synthetic slice (fixed LCG pattern) and per-layer buffers
+  const Dims d = layer_dims(net, (int)H, (int)W);
+  std::vector<uint8_t> host_in((size_t)H * W);
+  uint32_t s = 12345u;
+  for (auto& b : host_in) {
+    s = s * 1664525u + 1013904223u;
+    b = (uint8_t)(s >> 24);
+  }
+  const int eb = net->prec == F32 ? 4 : net->prec == BF16 ? 2 : 1;
+  std::vector<size_t> ob(nl);
+  for (int l = 0; l < nl; ++l)
+    ob[l] = (l == nl - 1) ? (size_t)d.hout[l] * d.wout[l] * 4 : (size_t)d.hout[l] * d.wout[l] * net->layers[l].cout * eb;
+  std::vector<void*> bufs(nl + 2, nullptr);
+  hipError_t e;
+  size_t maxb = 0;
+  for (size_t b : ob) maxb = std::max(maxb, b);
+  bool okm = hipMalloc(&bufs[0], host_in.size()) == hipSuccess && hipMalloc(&bufs[nl + 1], maxb) == hipSuccess;
+  for (int l = 0; l < nl && okm; ++l) okm = hipMalloc(&bufs[l + 1], ob[l]) == hipSuccess;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : bufs)
+      if (p) hipFree(p);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (!okm) {
+    cleanup();
+    return fail(CNN_ENOMEM, "cnn_autotune: buffers");
+  }
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipMemcpy(bufs[0], host_in.data(), host_in.size(), hipMemcpyHostToDevice);
+  // reference pass with the default variants
+  for (int l = 0; l < nl && !rc; ++l) rc = run_one_layer(net, l, bufs[l], bufs[l + 1], d, st);
+  if (!rc && (e = hipStreamSynchronize(st)) != hipSuccess) rc = hip_fail(e, "cnn_autotune: reference pass");
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  for (int l = 0; l < nl && !rc; ++l) {
+    ExecLayer& L = net->layers[l];
+    if (chosen[l] >= 0) {
+      L.variant = chosen[l];
+      continue;
+    }
+    if (L.candidates.size() < 2) continue;
+    std::vector<unsigned char> ref(ob[l]), got(ob[l]);
+    hipMemcpy(ref.data(), bufs[l + 1], ob[l], hipMemcpyDeviceToHost);
+    const int def = L.variant;
+    int best = def;
+    float best_ms = 1e30f;
+    for (int c : L.candidates) {
+      L.variant = c;
+      rc = run_one_layer(net, l, bufs[l], bufs[nl + 1], d, st);  // warm-up, also the checked output
+      if (rc) break;
+      hipEventRecord(e0, st);
+      const int reps = 5;
+      for (int r = 0; r < reps && !rc; ++r) rc = run_one_layer(net, l, bufs[l], bufs[nl + 1], d, st);
+      hipEventRecord(e1, st);
+      if (rc) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        rc = hip_fail(e, "cnn_autotune: timing");
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      hipMemcpy(got.data(), bufs[nl + 1], ob[l], hipMemcpyDeviceToHost);
+      const bool same = std::memcmp(got.data(), ref.data(), ob[l]) == 0;
+      if (same && ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    L.variant = rc ? def : best;
+    chosen[l] = L.variant;
+  }
+  cleanup();
+  if (rc) return rc;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::trunc);
+    for (const std::string& line : lines) {
+      bool replaced = false;
+      for (int l = 0; l < nl; ++l)
+        if (line.rfind(layer_sig(net, net->layers[l]) + "|" + shape + "|", 0) == 0) replaced = true;
+      if (!replaced) f << line << "\n";
+    }
+    for (int l = 0; l < nl; ++l)
+      if (net->layers[l].candidates.size() > 1)
+        f << layer_sig(net, net->layers[l]) << "|" << shape << "|" << layer_name(net->layers[l]) << "\n";
+  }
+  return CNN_OK;
+}

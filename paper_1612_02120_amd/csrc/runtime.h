@@ -1,0 +1,103 @@
+// Host-side objects of the library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace emcnn {
+
+// One executed conv layer. A 2x2/s1 max filter before it is folded into its
+// staging (pool_in); the 1x1 sigmoid head after the last body conv is folded
+// into that conv's epilogue (head).
+struct ExecLayer {
+  int first = 0;  // 1: the uint8 first layer (conv_first kernel)
+  int cin = 0, cout = 0, ks = 0;
+  int pool_in = 0, head = 0;
+  int in_off = 0;  // receptive radius consumed by earlier layers
+  int variant = -1;
+  std::vector<int> candidates;
+  void* wpack = nullptr;
+  float* bias = nullptr;
+  float* oscale = nullptr;
+  float* head_w = nullptr;
+  float head_b = 0.f;
+  float out_inv_scale = 1.f;
+};
+
+struct Net {
+  int device = 0;
+  int prec = 0;
+  int R = 0;
+  int num_cus = 256;
+  std::string arch;
+  std::vector<ExecLayer> layers;
+  // workspace for inter-layer activations (grown on demand)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_budget = (size_t)24 << 30;
+  // batched submissions
+  void* tab_dev = nullptr;
+  size_t tab_dev_bytes = 0;
+  void* tab_host = nullptr;  // pinned
+  size_t tab_host_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> graph_key;
+  hipEvent_t done = nullptr;
+  bool done_pending = false;
+  int use_graph = 1;
+};
+
+// Conv output dims of every executed layer for an input region of h x w.
+struct Dims {
+  std::vector<int> hin, win, hout, wout;
+};
+
+// A 3-D input region of a uint8 volume (strided) and where its dense output
+// goes. h, w are the input dims; the output is (h-R) x (w-R) per slice.
+struct Region {
+  const uint8_t* in;
+  int64_t in_rs, in_zs;
+  int z, h, w;
+  float* out;
+  int64_t out_rs, out_zs;
+  const int32_t* gate;
+};
+
+struct Launch {
+  int layer;
+  int grid;
+  JobSet js;
+};
+
+Dims layer_dims(const Net* net, int h, int w);
+int ensure_ws(Net* net, size_t need);
+int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, float* prob, hipStream_t st);
+int arena_reserve(Net* net, size_t njobs);
+size_t count_region_jobs(const Net* net, const std::vector<Region>& regs);
+int plan_regions(Net* net, const std::vector<Region>& regs, size_t job_off, std::vector<Launch>& launches,
+                 size_t& njobs_used, size_t& ws_need);
+int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t njobs, hipStream_t st, bool graph);
+int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st);
+int check_device(const Net* net);
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+void clear_error();
+const char* last_error();
+
+float bf16_rne(float x);
+uint8_t e4m3_code(double x);
+
+int layer_threads(const ExecLayer& L);
+int layer_ty(const ExecLayer& L);
+int layer_tx(const ExecLayer& L);
+const void* layer_fn(const ExecLayer& L);
+const char* layer_name(const ExecLayer& L);
+int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items);
+
+}  // namespace emcnn

@@ -1,0 +1,431 @@
+// Host runtime behind include/emcnn.h: network object, weight packing and
+// quantisation, work planning, persistent launches, batched submissions with
+// HIP graphs, and the tile-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/emcnn.h"
+#include "common.h"
+#include "runtime.h"
+
+namespace emcnn {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return CNN_EHIP;
+}
+
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ number formats
+
+float bf16_rne(float x) {
+  // nearest bf16 value; on a tie the one whose last kept bit is 0
+  if (!std::isfinite(x)) return x;
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  uint32_t lo = u & 0xffff0000u;
+  uint32_t hi = lo + 0x10000u;
+  float flo, fhi;
+  std::memcpy(&flo, &lo, 4);
+  std::memcpy(&fhi, &hi, 4);
+  double dlo = std::fabs((double)x - (double)flo), dhi = std::fabs((double)fhi - (double)x);
+  if (dlo < dhi) return flo;
+  if (dhi < dlo) return fhi;
+  return ((lo >> 16) & 1u) ? fhi : flo;
+}
+
+// All 127 non-negative finite e4m3fn values, ascending (code = index).
+static const std::vector<double>& e4m3_table() {
+  static std::vector<double> t = [] {
+    std::vector<double> v;
+    for (int code = 0; code < 127; ++code) {
+      int e = (code >> 3) & 15, m = code & 7;
+      v.push_back(e == 0 ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7));
+    }
+    return v;
+  }();
+  return t;
+}
+
+// e4m3fn code of x: nearest representable value, ties to the even code,
+// magnitudes beyond 448 saturate to 448.
+uint8_t e4m3_code(double x) {
+  const auto& t = e4m3_table();
+  uint8_t sign = (x < 0) ? 0x80 : 0;
+  double a = std::fabs(x);
+  if (a >= 448.0) return sign | 126;
+  size_t hi = std::lower_bound(t.begin(), t.end(), a) - t.begin();  // t[hi] >= a
+  if (t[hi] == a) return sign | (uint8_t)hi;
+  size_t lo = hi - 1;
+  double dl = a - t[lo], dh = t[hi] - a;
+  size_t pick = dl < dh ? lo : dh < dl ? hi : ((lo & 1) ? hi : lo);
+  return sign | (uint8_t)pick;
+}
+
+// ------------------------------------------------------------------ spec parsing
+
+static int act_bytes(int prec) { return prec == F32 ? 4 : prec == BF16 ? 2 : 1; }
+
+static int find_first_variant(int prec, int cout, int ks) {
+  for (int i = 0; i < first_variant_count(); ++i) {
+    const FirstInfo* f = first_variant(i);
+    if (f->prec_out == prec && f->cout == cout && f->ks == ks) return i;
+  }
+  return -1;
+}
+
+static std::vector<int> find_conv_variants(int prec, int cin, int cout, int ks, int pool, int head) {
+  std::vector<int> v;
+  for (int i = 0; i < conv_variant_count(); ++i) {
+    const VariantInfo* c = conv_variant(i);
+    if (c->prec == prec && c->cin == cin && c->cout == cout && c->ks == ks && c->pool_in == pool &&
+        c->head == head)
+      v.push_back(i);
+  }
+  return v;
+}
+
+static int pack_conv(ExecLayer& L, const double* w, const double* b, const double* hw, double hb,
+                     double in_scale, double next_scale) {
+  const VariantInfo* v = conv_variant(L.variant);
+  const int cin = v->cin, cout = v->cout, ks = v->ks, cb = v->cb, chb = v->chb, u = v->u, ngs = v->ngs;
+  const int ncb = cin / cb, nchb = cb / chb, nchk = ks * ks * nchb, nb = cout / 16;
+  const int esz = act_bytes(v->prec);
+  const size_t bytes = (size_t)ncb * ngs * nb * 64 * u * 16;
+  std::vector<uint8_t> pk(bytes, 0);
+  // quantised weights, [co][ci][i][j]
+  const size_t nw = (size_t)cout * cin * ks * ks;
+  std::vector<double> wq(nw);
+  std::vector<float> osc(cout, 1.0f);
+  if (v->prec == F32) {
+    for (size_t i = 0; i < nw; ++i) wq[i] = (float)w[i];
+  } else if (v->prec == BF16) {
+    for (size_t i = 0; i < nw; ++i) wq[i] = bf16_rne((float)w[i]);
+  } else {
+    const size_t per = (size_t)cin * ks * ks;
+    for (int co = 0; co < cout; ++co) {
+      double mx = 0.0;
+      for (size_t i = 0; i < per; ++i) mx = std::max(mx, std::fabs(w[co * per + i]));
+      double sw = mx > 0 ? mx / 448.0 : 1.0;
+      for (size_t i = 0; i < per; ++i) wq[co * per + i] = (double)e4m3_code(w[co * per + i] / sw);  // code
+      osc[co] = (float)(in_scale * sw);
+    }
+  }
+  for (int c0 = 0; c0 < ncb; ++c0)
+    for (int s = 0; s < ngs; ++s)
+      for (int n_b = 0; n_b < nb; ++n_b)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int n = lane & 15, g = lane >> 4, co = n_b * 16 + n;
+          for (int uu = 0; uu < u; ++uu) {
+            const int c = (4 * s + g) * u + uu;
+            if (c >= nchk) continue;
+            const int i = c / (ks * nchb), rem = c % (ks * nchb), j = rem / nchb, cg = rem % nchb;
+            uint8_t* dst = pk.data() + ((((size_t)(c0 * ngs + s) * nb + n_b) * 64 + lane) * u + uu) * 16;
+            for (int t = 0; t < chb; ++t) {
+              const int ci = c0 * cb + cg * chb + t;
+              const double val = wq[(((size_t)co * cin + ci) * ks + i) * ks + j];
+              if (v->prec == F32) {
+                float f = (float)val;
+                std::memcpy(dst + t * esz, &f, 4);
+              } else if (v->prec == BF16) {
+                float f = (float)val;
+                uint32_t bits;
+                std::memcpy(&bits, &f, 4);
+                uint16_t h = (uint16_t)(bits >> 16);
+                std::memcpy(dst + t * esz, &h, 2);
+              } else {
+                dst[t] = (uint8_t)val;
+              }
+            }
+          }
+        }
+  std::vector<float> bias(b, b + cout);
+  hipError_t e;
+  if ((e = hipMalloc(&L.wpack, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(weights)");
+  if ((e = hipMemcpy(L.wpack, pk.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(weights)");
+  if ((e = hipMalloc(&L.bias, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(bias)");
+  hipMemcpy(L.bias, bias.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+  if (v->prec == FP8) {
+    if ((e = hipMalloc(&L.oscale, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(scale)");
+    hipMemcpy(L.oscale, osc.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (v->head) {
+    std::vector<float> h(hw, hw + cout);
+    if ((e = hipMalloc(&L.head_w, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(head)");
+    hipMemcpy(L.head_w, h.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+    L.head_b = (float)hb;
+  }
+  L.out_inv_scale = next_scale > 0 ? (float)(1.0 / next_scale) : 1.0f;
+  return CNN_OK;
+}
+
+static int pack_first(ExecLayer& L, const double* w, const double* b, double next_scale) {
+  const FirstInfo* f = first_variant(L.variant);
+  const int n = f->cout * f->ks * f->ks;
+  std::vector<float> wf(n);
+  for (int i = 0; i < n; ++i) {
+    float v = (float)(w[i] / 255.0);
+    wf[i] = (f->prec_out == F32) ? v : bf16_rne(v);
+  }
+  std::vector<float> bf(b, b + f->cout);
+  hipError_t e;
+  if ((e = hipMalloc(&L.wpack, n * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(w1)");
+  hipMemcpy(L.wpack, wf.data(), n * sizeof(float), hipMemcpyHostToDevice);
+  if ((e = hipMalloc(&L.bias, f->cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(b1)");
+  hipMemcpy(L.bias, bf.data(), f->cout * sizeof(float), hipMemcpyHostToDevice);
+  L.out_inv_scale = next_scale > 0 ? (float)(1.0 / next_scale) : 1.0f;
+  return CNN_OK;
+}
+
+static void free_layer(ExecLayer& L) {
+  if (L.wpack) hipFree(L.wpack);
+  if (L.bias) hipFree(L.bias);
+  if (L.oscale) hipFree(L.oscale);
+  if (L.head_w) hipFree(L.head_w);
+  L.wpack = nullptr;
+  L.bias = L.oscale = L.head_w = nullptr;
+}
+
+int layer_threads(const ExecLayer& L) {
+  return L.first ? first_variant(L.variant)->threads : conv_variant(L.variant)->threads;
+}
+int layer_ty(const ExecLayer& L) { return L.first ? first_variant(L.variant)->ty : conv_variant(L.variant)->ty; }
+int layer_tx(const ExecLayer& L) { return L.first ? first_variant(L.variant)->tx : conv_variant(L.variant)->tx; }
+const void* layer_fn(const ExecLayer& L) {
+  return L.first ? first_variant(L.variant)->fn : conv_variant(L.variant)->fn;
+}
+const char* layer_name(const ExecLayer& L) {
+  return L.first ? first_variant(L.variant)->name : conv_variant(L.variant)->name;
+}
+
+int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items) {
+  int per_cu = 0;
+  const void* fn = layer_fn(L);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, layer_threads(L), 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int64_t cap = (int64_t)net->num_cus * per_cu;
+  cap = std::max<int64_t>(8, cap / 8 * 8);
+  int64_t want = (total_items + 7) / 8 * 8;
+  return (int)std::max<int64_t>(8, std::min(cap, want));
+}
+
+}  // namespace emcnn
+
+using namespace emcnn;
+
+// ------------------------------------------------------------------ C ABI: create / destroy
+
+extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_layer_spec* spec, cnn_net** out) {
+  clear_error();
+  if (!weights || !spec || !out || !spec->layers || spec->n_layers < 2)
+    return fail(CNN_EINVAL, "cnn_create: null argument or fewer than 2 layers");
+  *out = nullptr;
+  const int prec = spec->precision;
+  if (prec != CNN_PREC_FP32 && prec != CNN_PREC_BF16 && prec != CNN_PREC_FP8)
+    return fail(CNN_EINVAL, "cnn_create: unknown precision");
+  // structural validation
+  int64_t expect = 0;
+  int R = 0;
+  int C = 1;
+  for (int i = 0; i < spec->n_layers; ++i) {
+    const cnn_layer& l = spec->layers[i];
+    if (l.kind == CNN_LAYER_CONV) {
+      if (l.k < 1 || l.cin != C || l.cout < 1 || (l.act < 0 || l.act > 2))
+        return fail(CNN_EINVAL, "cnn_create: bad conv layer " + std::to_string(i));
+      expect += (int64_t)l.cout * l.cin * l.k * l.k + l.cout;
+      R += l.k - 1;
+      C = l.cout;
+    } else if (l.kind == CNN_LAYER_MAXPOOL) {
+      if (l.k != 2 || i == 0) return fail(CNN_EINVAL, "cnn_create: maxpool must be 2x2 and follow a conv");
+      R += 1;
+    } else {
+      return fail(CNN_EINVAL, "cnn_create: bad layer kind at " + std::to_string(i));
+    }
+  }
+  if (expect != n_weights)
+    return fail(CNN_EINVAL, "cnn_create: n_weights " + std::to_string(n_weights) + " != " + std::to_string(expect));
+  if (C != 1) return fail(CNN_EINVAL, "cnn_create: last layer must have one output channel");
+  // supported shape: first conv(5, 1->C, relu) [pool], body convs (relu) [pool], head conv(1, C->1, sigmoid)
+  const cnn_layer* Lr = spec->layers;
+  const int nl = spec->n_layers;
+  if (Lr[0].kind != CNN_LAYER_CONV || Lr[0].cin != 1 || Lr[0].act != CNN_ACT_RELU)
+    return fail(CNN_EUNSUPPORTED, "cnn_create: first layer must be a ReLU conv on one channel");
+  const cnn_layer& hd = Lr[nl - 1];
+  if (hd.kind != CNN_LAYER_CONV || hd.k != 1 || hd.cout != 1 || hd.act != CNN_ACT_SIGMOID)
+    return fail(CNN_EUNSUPPORTED, "cnn_create: last layer must be a 1x1 conv to one channel with sigmoid");
+  if (Lr[nl - 2].kind != CNN_LAYER_CONV)
+    return fail(CNN_EUNSUPPORTED, "cnn_create: no pooling directly before the head");
+
+  int dev = 0;
+  hipGetDevice(&dev);
+  Net* net = new Net();
+  net->device = dev;
+  net->prec = prec;
+  net->R = R;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete net;
+    return fail(CNN_EHIP, "cnn_create: hipGetDeviceProperties failed");
+  }
+  net->num_cus = prop.multiProcessorCount;
+  net->arch = prop.gcnArchName;
+  if (net->arch.rfind("gfx950", 0) != 0) {
+    delete net;
+    return fail(CNN_EUNSUPPORTED, "cnn_create: kernels are built for gfx950, device is " + std::string(prop.gcnArchName));
+  }
+  if (const char* s = std::getenv("EMCNN_WORKSPACE_MB")) net->ws_budget = (size_t)std::atoll(s) << 20;
+
+  // build executed layers; weights pointer walks convs in order
+  const double* wp = weights;
+  int pending_pool = 0;
+  int conv_i = 0;
+  int rc = CNN_OK;
+  // next FP8 input scale of the conv following layer i
+  auto next_conv_scale = [&](int i) -> double {
+    for (int k = i + 1; k < nl; ++k)
+      if (Lr[k].kind == CNN_LAYER_CONV) {
+        const bool is_head = (k == nl - 1);
+        return (prec == CNN_PREC_FP8 && !is_head) ? (double)Lr[k].act_scale : 0.0;
+      }
+    return 0.0;
+  };
+  for (int i = 0; i < nl && rc == CNN_OK; ++i) {
+    const cnn_layer& l = Lr[i];
+    if (l.kind == CNN_LAYER_MAXPOOL) {
+      if (pending_pool || Lr[i - 1].act != CNN_ACT_RELU) {
+        rc = fail(CNN_EUNSUPPORTED, "cnn_create: pooling must follow a ReLU conv, one at a time");
+        break;
+      }
+      pending_pool = 1;
+      continue;
+    }
+    const int64_t nwl = (int64_t)l.cout * l.cin * l.k * l.k;
+    const double* w = wp;
+    const double* b = wp + nwl;
+    wp += nwl + l.cout;
+    if (i == nl - 1) break;  // head: fused into the previous conv
+    ExecLayer E;
+    E.cin = l.cin;
+    E.cout = l.cout;
+    E.ks = l.k;
+    E.pool_in = pending_pool;
+    pending_pool = 0;
+    const double nxt = next_conv_scale(i);
+    if (conv_i == 0) {
+      E.first = 1;
+      E.variant = find_first_variant(prec, l.cout, l.k);
+      if (E.variant < 0) {
+        rc = fail(CNN_EUNSUPPORTED, "cnn_create: no first-layer kernel for this shape/precision");
+        break;
+      }
+      for (int q = 0; q < first_variant_count(); ++q) {
+        const FirstInfo* f = first_variant(q);
+        if (f->prec_out == prec && f->cout == l.cout && f->ks == l.k) E.candidates.push_back(q);
+      }
+      rc = pack_first(E, w, b, nxt);
+    } else {
+      const bool fuse_head = (i == nl - 2);
+      if (l.act != CNN_ACT_RELU) {
+        rc = fail(CNN_EUNSUPPORTED, "cnn_create: body convs must use ReLU");
+        break;
+      }
+      E.head = fuse_head;
+      E.candidates = find_conv_variants(prec, l.cin, l.cout, l.k, E.pool_in, fuse_head);
+      if (E.candidates.empty()) {
+        rc = fail(CNN_EUNSUPPORTED, "cnn_create: no MFMA kernel for conv " + std::to_string(i));
+        break;
+      }
+      E.variant = E.candidates[0];
+      const double in_scale = (prec == CNN_PREC_FP8) ? (double)l.act_scale : 1.0;
+      if (prec == CNN_PREC_FP8 && !(in_scale > 0)) {
+        rc = fail(CNN_EINVAL, "cnn_create: FP8 conv " + std::to_string(i) + " needs act_scale > 0");
+        break;
+      }
+      const double* hw = nullptr;
+      double hb = 0;
+      if (fuse_head) {
+        hw = wp;
+        hb = wp[hd.cin];
+      }
+      rc = pack_conv(E, w, b, hw, hb, in_scale, fuse_head ? 0.0 : nxt);
+    }
+    net->layers.push_back(E);
+    ++conv_i;
+  }
+  if (rc == CNN_OK && (net->layers.size() < 2 || !net->layers.back().head))
+    rc = fail(CNN_EUNSUPPORTED, "cnn_create: need at least one body conv to carry the head");
+  if (rc != CNN_OK) {
+    for (auto& E : net->layers) free_layer(E);
+    delete net;
+    return rc;
+  }
+  // storage precision of each layer's output and stored dims offsets
+  int off = 0;
+  for (auto& E : net->layers) {
+    E.in_off = off;  // radius consumed before this layer
+    off += E.pool_in + E.ks - 1;
+  }
+  *out = reinterpret_cast<cnn_net*>(net);
+  return CNN_OK;
+}
+
+extern "C" int cnn_destroy(cnn_net* h) {
+  clear_error();
+  if (!h) return CNN_OK;
+  Net* net = reinterpret_cast<Net*>(h);
+  hipDeviceSynchronize();
+  for (auto& E : net->layers) free_layer(E);
+  if (net->ws) hipFree(net->ws);
+  if (net->tab_dev) hipFree(net->tab_dev);
+  if (net->tab_host) hipHostFree(net->tab_host);
+  if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
+  if (net->cap_stream) hipStreamDestroy(net->cap_stream);
+  if (net->done) hipEventDestroy(net->done);
+  delete net;
+  return CNN_OK;
+}
+
+extern "C" int cnn_geometry(const cnn_net* h, int32_t* R, int32_t* fov) {
+  clear_error();
+  if (!h) return fail(CNN_EINVAL, "cnn_geometry: null net");
+  const Net* net = reinterpret_cast<const Net*>(h);
+  if (R) *R = net->R;
+  if (fov) *fov = net->R + 1;
+  return CNN_OK;
+}
+
+extern "C" const char* cnn_last_error(void) { return last_error(); }
+
+extern "C" int cnn_describe(const cnn_net* h, char* buf, int32_t len) {
+  clear_error();
+  if (!h || !buf || len < 1) return fail(CNN_EINVAL, "cnn_describe: bad argument");
+  const Net* net = reinterpret_cast<const Net*>(h);
+  std::string s;
+  for (auto& E : net->layers) {
+    if (!s.empty()) s += " | ";
+    s += layer_name(E);
+  }
+  std::snprintf(buf, len, "%s", s.c_str());
+  return CNN_OK;
+}

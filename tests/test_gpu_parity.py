@@ -1,0 +1,135 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU reference.
+
+Tolerances (max abs probability error): FP32 1e-5; BF16 2e-2 and FP8 6e-2
+against the exact reference; BF16 / FP8 against the reference's fake-quant form
+of the same number formats 2e-3 (rare one-ulp flips of an intermediate rounding
+may move a probability by ~1e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import em_volume
+from synth.nets import NET_A, NET_B, calibrated_params, fp8_act_scales, random_bias_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def emcnn():
+    import paper_1612_02120_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(emcnn, h, vol):
+    out = emcnn.cnn_infer(h, _dev(vol))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _scales():
+    return fp8_act_scales("B")
+
+
+def test_tiny_net_a_fp32_full_slice(emcnn):
+    vol = em_volume(1, 1, 256, 256)
+    p = calibrated_params("A")
+    h = emcnn.cnn_create(p, NET_A, "fp32")
+    got = _run(emcnn, h, vol)
+    ref = oracle.forward(vol, NET_A, p)
+    assert got.shape == (1, 248, 248)
+    err = np.abs(got - ref).max()
+    print("net A fp32 256^2 max err", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(2, 75, 83), (1, 13, 13), (1, 40, 200), (3, 33, 47)])
+def test_net_b_fp32_random_bias(emcnn, shape):
+    vol = em_volume(20 + shape[1], *shape)
+    p = random_bias_params(NET_B, 200, 21)
+    h = emcnn.cnn_create(p, NET_B, "fp32")
+    got = _run(emcnn, h, vol)
+    ref = oracle.forward(vol, NET_B, p)
+    err = np.abs(got - ref).max()
+    print("net B fp32", shape, "max err", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol_fq,tol_exact", [("bf16", 2e-3, 2e-2), ("fp8", 2e-3, 6e-2)])
+def test_net_b_low_precision(emcnn, prec, tol_fq, tol_exact):
+    vol = em_volume(31, 2, 70, 90)
+    p = calibrated_params("B")
+    sc = _scales() if prec == "fp8" else None
+    h = emcnn.cnn_create(p, NET_B, prec, act_scales=sc)
+    got = _run(emcnn, h, vol)
+    fq = oracle.forward(vol, NET_B, p, qmode=prec, act_scales=sc)
+    ex = oracle.forward(vol, NET_B, p)
+    e_fq, e_ex = np.abs(got - fq).max(), np.abs(got - ex).max()
+    print(prec, "max err vs fake-quant", e_fq, "vs exact", e_ex, "mean vs exact", np.abs(got - ex).mean())
+    assert e_fq <= tol_fq
+    assert e_ex <= tol_exact
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_translation_equivariance_bitwise(emcnn, prec):
+    vol = em_volume(41, 1, 90, 100)
+    p = calibrated_params("B")
+    h = emcnn.cnn_create(p, NET_B, prec, act_scales=_scales() if prec == "fp8" else None)
+    full = _run(emcnn, h, vol)
+    for dy, dx in [(1, 0), (0, 5), (9, 17)]:
+        sh = _run(emcnn, h, vol[:, dy:, dx:])
+        assert np.array_equal(sh, full[:, dy:, dx:]), (prec, dy, dx)
+
+
+def test_run_twice_deterministic(emcnn):
+    vol = em_volume(42, 2, 120, 130)
+    h = emcnn.cnn_create(calibrated_params("B"), NET_B, "bf16")
+    a, b = _run(emcnn, h, vol), _run(emcnn, h, vol)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_matches_per_tile_and_oracle(emcnn, graph):
+    p = calibrated_params("B")
+    h = emcnn.cnn_create(p, NET_B, "fp32")
+    emcnn.cnn_set_batch_graph(h, graph)
+    rng = np.random.default_rng(5)
+    tiles, vols = [], []
+    for t in range(7):
+        L = int(rng.integers(5, 70))
+        z = int(rng.integers(1, 4))
+        halo = int(rng.choice([6, 8]))
+        v = em_volume(500 + t, z, L + 2 * halo, L + 7 + 2 * halo)
+        vols.append((v, halo))
+        tiles.append((_dev(v), halo, torch.empty((z, L, L + 7), dtype=torch.float32, device="cuda")))
+    for rep in range(3):  # replays of the captured graph
+        for _, _, o in tiles:
+            o.fill_(-1.0)
+        emcnn.cnn_infer_batch(h, tiles)
+        torch.cuda.synchronize()
+        for (v, halo), (_, _, o) in zip(vols, tiles):
+            e = halo - 6
+            single = _run(emcnn, h, v[:, e:v.shape[1] - e, e:v.shape[2] - e])
+            assert np.array_equal(o.cpu().numpy().astype(np.float64), single)
+    v, halo = vols[0]
+    e = halo - 6
+    ref = oracle.forward(v[:, e:v.shape[1] - e, e:v.shape[2] - e], NET_B, p)
+    assert np.abs(tiles[0][2].cpu().numpy() - ref).max() <= 1e-5
+
+
+def test_invalid_arguments_leave_stream_untouched(emcnn):
+    h = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")
+    small = _dev(np.zeros((1, 12, 40), np.uint8))
+    with pytest.raises(emcnn.CnnError) as ei:
+        emcnn.cnn_infer(h, small, out=torch.empty((1, 0, 28), device="cuda"))
+    assert ei.value.code == emcnn.CNN_EINVAL
+    t = _dev(np.zeros((1, 30, 30), np.uint8))
+    with pytest.raises(emcnn.CnnError) as ei:
+        emcnn.cnn_infer_batch(h, [(t, 5, torch.empty((1, 20, 20), device="cuda"))])  # halo < R/2
+    assert ei.value.code == emcnn.CNN_EINVAL
