@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of dense membrane-probability inference on one MI355X.
+
+Headline: the plain net B in FP32 over a 32 x 1024 x 1024 uint8 EM-like volume
+(seeded synthetic stand-in for the paper's EM stacks), one step = one dense pass
+of the whole path (uint8 ingest, conv1 + ReLU, 2x2/s1 max filter, conv2 + ReLU,
+max filter, conv3 + ReLU, 1x1 head + sigmoid) with input and output resident in
+HBM. Printed as one JSON line; also reported:
+
+* roofline of the dominant kernel (conv2, 72% of the FLOPs) from HIP events
+  recorded on its launch stream over the timed region;
+* the FP64 CPU reference timed on a bounded sample on the host cores;
+* the other forms (BF16 / FP8 precision, batched tiles, student) unless
+  --forms none.
+
+Only one GPU is used; --gpus N with N > 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "membrane-prob voxels/sec at 1 MI355X and % MFMA peak, plain FP32 vs BF16/FP8/student"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+HBM_GBS = 8000.0
+# algorithmic work of net B per output voxel: 2 x (1200 + 57600 + 20736 + 48) MAC
+NET_B_FLOP_PER_VOXEL = 159168
+CONV2_FLOP_PER_POS = 2 * 25 * 48 * 48  # per conv2 output position
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha1()
+    for f in ("conv_kernels.hip",):
+        with open(os.path.join(ROOT, "paper_1612_02120_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles(name):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_source_sha") != kernel_source_sha():
+            return None
+        return d.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def time_volume(emcnn, torch, h, vol_dev, steps, warmup, stream):
+    out = torch.empty((vol_dev.shape[0], vol_dev.shape[1] - h.R, vol_dev.shape[2] - h.R),
+                      dtype=torch.float32, device=vol_dev.device)
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            emcnn.cnn_infer(h, vol_dev, out=out, stream=stream)
+        torch.cuda.synchronize()
+        emcnn.cnn_profile_read(h)  # clear
+        emcnn.cnn_profile(h, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            emcnn.cnn_infer(h, vol_dev, out=out, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        emcnn.cnn_profile(h, False)
+    ms, n = emcnn.cnn_profile_read(h)
+    per_layer = [m / c if c else 0.0 for m, c in zip(ms, n)]
+    return (t1 - t0) * 1e3 / steps, per_layer, out
+
+
+def cpu_baseline(vol, net, params, out_vox_unit="voxels/s"):
+    import oracle
+    Z, H, W = 1, 512, 512
+    sample = np.ascontiguousarray(vol[:1, :H, :W])
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    oracle.forward(sample, net, params, threads=threads)
+    dt = time.perf_counter() - t0
+    R = oracle.radius(net)
+    nvox = Z * (H - R) * (W - R)
+    return {"value": nvox / dt, "unit": out_vox_unit, "cores": threads, "kind": "oracle",
+            "sample": "slice 0, input [0,512)^2 of the benchmark volume -> %d output voxels, "
+                      "FP64 direct convolution, %.1f s" % (nvox, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--forms", default="all", help="all | none | comma list of bf16,fp8,batch,student")
+    ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick tile shapes by timing first")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1612_02120_amd as emcnn
+    from synth import em_volume
+    from synth.nets import NET_B, calibrated_params, fp8_act_scales
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    Z, H, W = 32, 1024, 1024
+    t0 = time.perf_counter()
+    vol = em_volume(2, Z, H, W)
+    log("generated %s volume in %.1fs" % ((Z, H, W), time.perf_counter() - t0))
+    vol_dev = torch.from_numpy(vol).to(dev)
+    p = calibrated_params("B")
+    h = emcnn.cnn_create(p, NET_B, "fp32")
+    if args.autotune:
+        emcnn.cnn_autotune(h, H, W, None, stream)
+    R = h.R
+    Ho, Wo = H - R, W - R
+    nvox = Z * Ho * Wo
+    ms, per_layer, out = time_volume(emcnn, torch, h, vol_dev, args.steps, args.warmup, stream)
+    value = nvox / (ms * 1e-3)
+    conv2_ms = per_layer[1]
+    conv2_units = Z * (H - 9) * (W - 9)
+    conv2_flop = conv2_units * CONV2_FLOP_PER_POS
+    achieved = conv2_flop / (conv2_ms * 1e-3) / 1e12 if conv2_ms > 0 else None
+    path_tflops = nvox * NET_B_FLOP_PER_VOXEL / (ms * 1e-3) / 1e12
+    log("fp32: %.3f ms/step, %.3e vox/s, layers ms %s, tiles %s" %
+        (ms, value, ["%.3f" % x for x in per_layer[:3]], emcnn.cnn_describe(h)))
+    res = {
+        "metric": METRIC, "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain net B FP32, dense over 32 x 1024 x 1024 uint8 EM-like volume "
+                               "(seed 2) -> 32 x 1012 x 1012 probabilities",
+                   "net": "conv5x5 1->48, pool2x2/s1, conv5x5 48->48, pool2x2/s1, conv3x3 48->48, "
+                          "conv1x1 48->1 sigmoid",
+                   "precision": "fp32", "output_voxels": nvox, "tiles": emcnn.cnn_describe(h)},
+        "path_mfma_frac": path_tflops / PEAK_TFLOPS["fp32"],
+        "path_tflops": path_tflops,
+        "layer_ms": per_layer[:3],
+        "roofline": {"bound": "mfma", "kernel": "conv2 (conv_mfma FP32 48->48 5x5, pool fused)",
+                     "achieved": achieved, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_TFLOPS["fp32"]) if achieved else None,
+                     "flop_per_launch": conv2_flop, "avg_launch_ms": conv2_ms,
+                     "traffic": traffic_from_profiles("conv2_fp32_plain_traffic.json")},
+    }
+    del out
+    forms = {}
+    want = set() if args.forms == "none" else (
+        {"bf16", "fp8", "batch"} if args.forms == "all" else set(args.forms.split(",")))
+    if want & {"bf16", "fp8"}:
+        Zp = 128 if args.full else 8
+        t0 = time.perf_counter()
+        volp = em_volume(3, Zp, 2048, 2048)
+        log("generated precision volume %s in %.1fs" % ((Zp, 2048, 2048), time.perf_counter() - t0))
+        volp_dev = torch.from_numpy(volp).to(dev)
+        nv = Zp * (2048 - R) ** 2
+        for prec in ("bf16", "fp8"):
+            if prec not in want:
+                continue
+            hp = emcnn.cnn_create(p, NET_B, prec,
+                                  act_scales=fp8_act_scales("B") if prec == "fp8" else None)
+            msp, pl, outp = time_volume(emcnn, torch, hp, volp_dev, max(3, args.steps // 2), 2, stream)
+            c2u = Zp * (2048 - 9) ** 2
+            ach = c2u * CONV2_FLOP_PER_POS / (pl[1] * 1e-3) / 1e12
+            forms[prec] = {"workload": "net B %s, %d x 2048 x 2048 (seed 3)" % (prec, Zp),
+                           "voxels_per_s": nv / (msp * 1e-3), "ms_per_pass": msp,
+                           "path_mfma_frac": nv * NET_B_FLOP_PER_VOXEL / (msp * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                           "conv2_tflops": ach, "conv2_frac": ach / PEAK_TFLOPS[prec], "layer_ms": pl[:3]}
+            log(prec, json.dumps(forms[prec]))
+            del outp, hp
+        del volp_dev
+    if "batch" in want:
+        from synth import batch_tiles
+        tl = batch_tiles()
+        rng = np.random.default_rng(44)
+        pool = em_volume(4, 8, 1040, 1040)
+        hb = emcnn.cnn_create(p, NET_B, "bf16")
+        tiles, nv = [], 0
+        for t in tl:
+            y = int(rng.integers(0, 1040 - t["h"] + 1))
+            x = int(rng.integers(0, 1040 - t["w"] + 1))
+            inp = torch.from_numpy(np.ascontiguousarray(pool[:t["z"], y:y + t["h"], x:x + t["w"]])).to(dev)
+            L = t["h"] - 2 * t["halo"]
+            out = torch.empty((t["z"], L, L), dtype=torch.float32, device=dev)
+            tiles.append((inp, t["halo"], out))
+            nv += t["z"] * L * L
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                emcnn.cnn_infer_batch(hb, tiles, stream=stream)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                emcnn.cnn_infer_batch(hb, tiles, stream=stream)
+            torch.cuda.synchronize()
+            msb = (time.perf_counter() - t0) * 1e3 / reps
+            emcnn.cnn_set_batch_graph(hb, False)
+            for (inp, halo, out) in tiles[:4]:
+                emcnn.cnn_infer_batch(hb, [(inp, halo, out)], stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for (inp, halo, out) in tiles:
+                emcnn.cnn_infer_batch(hb, [(inp, halo, out)], stream=stream)
+            torch.cuda.synchronize()
+            msl = (time.perf_counter() - t0) * 1e3
+        forms["batch"] = {"workload": "512 tiles, side logU[64,1024], 1-8 slices, halo 8, BF16 net B",
+                          "output_voxels": nv, "voxels_per_s_graph": nv / (msb * 1e-3),
+                          "ms_graph": msb, "voxels_per_s_per_tile_loop": nv / (msl * 1e-3),
+                          "ms_per_tile_loop": msl}
+        log("batch", json.dumps(forms["batch"]))
+        del tiles, hb
+    if forms:
+        res["forms"] = forms
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(vol, NET_B, p)
+        log("cpu baseline", json.dumps(res["cpu_baseline"]))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,24 @@ int cnn_infer_batch(cnn_net* net, const cnn_tile* tiles, int32_t n, void* stream
  * text file of earlier choices, read first and updated. */
 int cnn_autotune(cnn_net* net, int64_t H, int64_t W, const char* cache_path, void* stream);
 
+/* Batched submissions are captured as a HIP graph by default; enable = 0
+ * launches the same kernels directly instead (a per-call launch sequence). */
+int cnn_set_batch_graph(cnn_net* net, int32_t enable);
+
+/* Upper bound in bytes of the handle's inter-layer workspace (default 24 GiB,
+ * or EMCNN_WORKSPACE_MB); larger volumes are processed in slabs of slices. */
+int cnn_set_workspace_limit(cnn_net* net, int64_t bytes);
+
+/* Per-layer kernel timing: while enabled, every layer launch of this handle
+ * is bracketed by HIP events recorded on the launch stream (direct launches
+ * only; graph replays are not timed). cnn_profile_read waits for the events,
+ * writes the summed milliseconds and launch count per executed layer (first
+ * layer, body convs; the head is fused into the last body conv) and clears
+ * the record. */
+int cnn_profile(cnn_net* net, int32_t enable);
+int cnn_profile_read(cnn_net* net, double* ms_per_layer, int32_t* launches_per_layer,
+                     int32_t max_layers);
+
 /* Describe the current tile choice (for logs); writes a NUL-terminated string. */
 int cnn_describe(const cnn_net* net, char* buf, int32_t buf_len);
 

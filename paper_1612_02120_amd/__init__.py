@@ -52,6 +52,7 @@ EXPORTS = [
     "cnn_describe", "cnn_set_batch_graph", "cnn_set_workspace_limit", "student_create",
     "student_destroy", "student_get_state", "student_set_state", "student_grad",
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
+    "cnn_profile", "cnn_profile_read",
 ]
 
 
@@ -70,6 +71,8 @@ def _load():
         "cnn_describe": [vp, ctypes.c_char_p, i32],
         "cnn_set_batch_graph": [vp, i32],
         "cnn_set_workspace_limit": [vp, i64],
+        "cnn_profile": [vp, i32],
+        "cnn_profile_read": [vp, vp, vp, i32],
         "student_create": [vp, i64, i32, vp],
         "student_destroy": [vp],
         "student_get_state": [vp, vp, vp, vp, vp],
@@ -233,6 +236,18 @@ def cnn_set_batch_graph(net: Net, enable: bool):
 
 def cnn_set_workspace_limit(net: Net, nbytes: int):
     _check(_lib.cnn_set_workspace_limit(net.ptr, int(nbytes)), "cnn_set_workspace_limit")
+
+
+def cnn_profile(net: Net, enable: bool):
+    _check(_lib.cnn_profile(net.ptr, 1 if enable else 0), "cnn_profile")
+
+
+def cnn_profile_read(net: Net, max_layers: int = 8):
+    """Summed milliseconds and launch counts per executed layer since the last read."""
+    ms = (ctypes.c_double * max_layers)()
+    n = (ctypes.c_int32 * max_layers)()
+    _check(_lib.cnn_profile_read(net.ptr, ms, n, max_layers), "cnn_profile_read")
+    return list(ms), list(n)
 
 
 # ---------------------------------------------------------------- student

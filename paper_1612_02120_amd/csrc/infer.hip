@@ -82,10 +82,26 @@ static LayerJob make_job(const ExecLayer& L, const void* in, void* out, int z, i
 
 static int64_t job_items(const LayerJob& j) { return (int64_t)j.z * j.tiles_y * j.tiles_x; }
 
+static hipEvent_t pool_event(Net* net) {
+  if (!net->event_pool.empty()) {
+    hipEvent_t e = net->event_pool.back();
+    net->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
 int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st) {
-  (void)net;
   const void* fn = layer_fn(L);
   hipError_t e;
+  Net::Timed tm{(int)(&L - net->layers.data()), nullptr, nullptr};
+  if (net->profiling) {
+    tm.a = pool_event(net);
+    tm.b = pool_event(net);
+    if (tm.a) hipEventRecord(tm.a, st);
+  }
   if (L.first) {
     FirstParams p;
     p.w = reinterpret_cast<const float*>(L.wpack);
@@ -106,6 +122,10 @@ int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipSt
     e = hipLaunchKernel(fn, dim3(grid), dim3(layer_threads(L)), args, 0, st);
   }
   if (e != hipSuccess) return hip_fail(e, layer_name(L));
+  if (net->profiling && tm.a && tm.b) {
+    hipEventRecord(tm.b, st);
+    net->timed.push_back(tm);
+  }
   return CNN_OK;
 }
 
@@ -628,4 +648,38 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
         f << layer_sig(net, net->layers[l]) << "|" << shape << "|" << layer_name(net->layers[l]) << "\n";
   }
   return CNN_OK;
+}
+
+extern "C" int cnn_profile(cnn_net* h, int32_t enable) {
+  clear_error();
+  if (!h) return fail(CNN_EINVAL, "cnn_profile: null net");
+  Net* net = reinterpret_cast<Net*>(h);
+  net->profiling = enable ? 1 : 0;
+  return CNN_OK;
+}
+
+extern "C" int cnn_profile_read(cnn_net* h, double* ms, int32_t* launches, int32_t max_layers) {
+  clear_error();
+  if (!h || !ms || !launches || max_layers < 1) return fail(CNN_EINVAL, "cnn_profile_read: bad argument");
+  Net* net = reinterpret_cast<Net*>(h);
+  const int nl = (int)net->layers.size();
+  for (int l = 0; l < max_layers; ++l) {
+    ms[l] = 0.0;
+    launches[l] = 0;
+  }
+  int rc = CNN_OK;
+  for (auto& t : net->timed) {
+    float v = 0.f;
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&v, t.a, t.b);
+    if (e != hipSuccess && rc == CNN_OK) rc = hip_fail(e, "cnn_profile_read");
+    if (t.layer >= 0 && t.layer < std::min(nl, (int)max_layers)) {
+      ms[t.layer] += v;
+      launches[t.layer] += 1;
+    }
+    net->event_pool.push_back(t.a);
+    net->event_pool.push_back(t.b);
+  }
+  net->timed.clear();
+  return rc;
 }

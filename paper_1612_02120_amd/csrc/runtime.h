@@ -50,6 +50,15 @@ struct Net {
   hipEvent_t done = nullptr;
   bool done_pending = false;
   int use_graph = 1;
+  // optional per-layer timing: events recorded on the launch stream around
+  // every layer kernel while enabled
+  int profiling = 0;
+  struct Timed {
+    int layer;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
 };
 
 // Conv output dims of every executed layer for an input region of h x w.

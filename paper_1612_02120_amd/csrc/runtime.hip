@@ -402,6 +402,11 @@ extern "C" int cnn_destroy(cnn_net* h) {
   if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
   if (net->cap_stream) hipStreamDestroy(net->cap_stream);
   if (net->done) hipEventDestroy(net->done);
+  for (auto& t : net->timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto ev : net->event_pool) hipEventDestroy(ev);
   delete net;
   return CNN_OK;
 }

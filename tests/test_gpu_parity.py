@@ -1,9 +1,13 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU reference.
 
 Tolerances (max abs probability error): FP32 1e-5; BF16 2e-2 and FP8 6e-2
-against the exact reference; BF16 / FP8 against the reference's fake-quant form
-of the same number formats 2e-3 (rare one-ulp flips of an intermediate rounding
-may move a probability by ~1e-3).
+against the exact reference. Against the reference's fake-quant form of the same
+number formats (exact accumulation of the rounded operands): BF16 2e-3 (rare
+one-ulp flips of an intermediate rounding); FP8 1e-2, because the gfx950
+16x16x128 f8f6f4 MFMA sums its 128 products with about 2^-13.6 relative
+precision (measured: error up to 8e-5 of sum|a b|, where FP32 accumulation
+gives 6e-8), which moves e4m3 codes of the next layer across rounding
+boundaries.
 """
 import numpy as np
 import pytest
@@ -61,7 +65,7 @@ def test_net_b_fp32_random_bias(emcnn, shape):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("prec,tol_fq,tol_exact", [("bf16", 2e-3, 2e-2), ("fp8", 2e-3, 6e-2)])
+@pytest.mark.parametrize("prec,tol_fq,tol_exact", [("bf16", 2e-3, 2e-2), ("fp8", 1e-2, 6e-2)])
 def test_net_b_low_precision(emcnn, prec, tol_fq, tol_exact):
     vol = em_volume(31, 2, 70, 90)
     p = calibrated_params("B")
