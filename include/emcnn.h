@@ -102,7 +102,7 @@ int cnn_geometry(const cnn_net* net, int32_t* R, int32_t* fov);
 /* Dense inference of a whole volume (Section 2.2: every pixel label in one
  * pass, no per-patch recomputation).
  * volume_u8: device, Z x H x W uint8, C order (x fastest).
- * dims: host {Z, H, W}; H and W must be >= R+1, Z >= 1, each < 2^31.
+ * dims: host {Z, H, W}; H and W must be >= R+1, Z >= 1, each < 2^30.
  * prob_out: device, Z x (H-R) x (W-R) float32, fully overwritten.
  * Grows the handle's workspace with hipMalloc when needed (the only allocation
  * it may make). */
@@ -209,8 +209,10 @@ int student_infer(cnn_student* s, const uint8_t* volume_u8, const int64_t dims[3
  * cropped by (R-6)/2 per side). The output is split into tiles of tile x tile
  * pixels per slice; in each tile n_samples windows of 16 x 16 outputs (seeded
  * by `seed`) are recomputed by the teacher; when the fraction of sampled
- * voxels whose 0.5-threshold decision differs exceeds tau, the whole tile is
- * recomputed by the teacher. All decisions stay on the device.
+ * voxels whose 0.5-threshold decision (p >= 0.5) differs exceeds tau, the
+ * whole tile is recomputed by the teacher (tau < 0: every tile; tau >= 1: no
+ * tile). All decisions stay on the device; the call returns after the work
+ * completes (it synchronises `stream`).
  * stats_out (device int32[2], nullable): {tiles flagged, tiles total}. */
 int student_infer_with_fallback(cnn_student* s, cnn_net* teacher, const uint8_t* volume_u8,
                                 const int64_t dims[3], float* prob_out, float tau,

@@ -667,8 +667,8 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
   if (R < 6 || (R - 6) % 2) return fail(CNN_EUNSUPPORTED, "fallback: teacher radius must be even and >= 6");
   if (Z < 1 || Z > 65535 || H < R + 1 || W < R + 1 || H >= (1 << 30) || W >= (1 << 30))
     return fail(CNN_EINVAL, "fallback: bad dims");
-  if (tile < 16 || n_samples < 1 || n_samples > 64 || !(tau >= 0.0f))
-    return fail(CNN_EINVAL, "fallback: tile >= 16, 1 <= n_samples <= 64, tau >= 0 required");
+  if (tile < 16 || n_samples < 1 || n_samples > 64 || tau != tau)
+    return fail(CNN_EINVAL, "fallback: tile >= 16, 1 <= n_samples <= 64, tau not NaN required");
   int rc = check_device(net);
   if (rc) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

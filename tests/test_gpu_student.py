@@ -1,0 +1,171 @@
+"""GPU student path: forward, loss/gradient and Adam against the FP64 reference;
+reproducibility, checkpoint resume and the fallback endpoints.
+
+Gradient bars: FP32 mode max|g_gpu - g_ref| <= 1e-4 max|g_ref|; BF16 mode cosine
+>= 0.999 and relative L2 <= 3e-2 (bf16 operands, FP32 accumulation).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import em_volume
+from synth.nets import NET_B, NET_S, calibrated_params, he_normal_params, random_bias_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def emcnn():
+    import paper_1612_02120_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _batch(seed, B, P):
+    rng = np.random.default_rng(seed)
+    patches = em_volume(seed, B, P, P)
+    t = rng.uniform(0, 1, size=(B, P - 6, P - 6))
+    return patches, t
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_student_forward_vs_reference(emcnn, prec):
+    vol = em_volume(61, 2, 53, 71)
+    p = random_bias_params(NET_S, 300, 62, sigma=0.1)
+    s = emcnn.student_create(p, prec)
+    out = emcnn.student_infer(s, _dev(vol))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ex = oracle.forward(vol, NET_S, p)
+    if prec == "fp32":
+        assert np.abs(got - ex).max() <= 1e-5
+    else:
+        fq = oracle.forward(vol, NET_S, p, qmode="bf16")
+        assert np.abs(got - fq).max() <= 2e-3
+        assert np.abs(got - ex).max() <= 2e-2
+
+
+@pytest.mark.parametrize("B,P", [(2, 20), (3, 37)])
+def test_student_gradient_fp32_vs_reference(emcnn, B, P):
+    patches, t = _batch(70 + P, B, P)
+    p = random_bias_params(NET_S, 301, 71, sigma=0.1)
+    s = emcnn.student_create(p, "fp32")
+    g, loss = emcnn.student_grad(s, _dev(patches), _dev(t.astype(np.float32)))
+    torch.cuda.synchronize()
+    # the reference sees the float32 targets the GPU sees
+    lref, gref = oracle.student_loss_grad(patches, t.astype(np.float32).astype(np.float64), NET_S, p)
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - lref) <= 1e-6 * abs(lref)
+    assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max()
+
+
+def test_student_gradient_bf16_cosine(emcnn):
+    patches, t = _batch(80, 4, 40)
+    p = random_bias_params(NET_S, 302, 81, sigma=0.1)
+    s = emcnn.student_create(p, "bf16")
+    g, loss = emcnn.student_grad(s, _dev(patches), _dev(t.astype(np.float32)))
+    torch.cuda.synchronize()
+    lref, gref = oracle.student_loss_grad(patches, t.astype(np.float32).astype(np.float64), NET_S, p)
+    g = g.cpu().numpy().astype(np.float64)
+    cos = g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref))
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print("bf16 grad cosine", cos, "rel L2", rel, "loss", loss.item(), lref)
+    assert cos >= 0.999 and rel <= 3e-2
+    assert abs(loss.item() - lref) <= 1e-2 * abs(lref)
+
+
+def test_adam_step_matches_reference(emcnn):
+    patches, t = _batch(90, 2, 24)
+    p = random_bias_params(NET_S, 303, 91, sigma=0.1)
+    s = emcnn.student_create(p, "fp32")
+    t32 = t.astype(np.float32)
+    loss, gnorm = emcnn.student_train_step(s, _dev(patches), _dev(t32), lr=1e-3)
+    w, m, v, step = emcnn.student_get_state(s)
+    _, gref = oracle.student_loss_grad(patches, t32.astype(np.float64), NET_S, p)
+    th, mr, vr = p.astype(np.float32).astype(np.float64), np.zeros_like(p), np.zeros_like(p)
+    oracle.adam(th, mr, vr, gref, 1, lr=1e-3)
+    assert step == 1
+    assert gnorm.item() == pytest.approx(np.linalg.norm(gref), rel=1e-4)
+    # step one moves every weight by about lr * sign(g); FP32 state
+    assert np.abs(w - th).max() <= 2e-6
+    assert np.allclose(m, mr, rtol=1e-3, atol=1e-9)
+
+
+def _teacher_maps(emcnn, vols):
+    h = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")
+    maps = [emcnn.cnn_infer(h, _dev(v)) for v in vols]
+    torch.cuda.synchronize()
+    return maps
+
+
+def _train(emcnn, s, vols_dev, maps, steps, seed, B=8, P=64):
+    rng = np.random.default_rng(seed)
+    losses = []
+    for it in range(steps):
+        v = rng.integers(0, len(vols_dev), size=B)
+        zz = rng.integers(0, vols_dev[0].shape[0], size=B)
+        Hm = vols_dev[0].shape[1]
+        ys = rng.integers(3, Hm - P - 3 + 1, size=B)
+        xs = rng.integers(3, Hm - P - 3 + 1, size=B)
+        pt = torch.stack([vols_dev[a][b, y:y + P, x:x + P] for a, b, y, x in zip(v, zz, ys, xs)]).contiguous()
+        tt = torch.stack([maps[a][b, y - 3:y - 3 + P - 6, x - 3:x - 3 + P - 6]
+                          for a, b, y, x in zip(v, zz, ys, xs)]).contiguous()
+        loss, _ = emcnn.student_train_step(s, pt, tt, lr=3e-3)
+        losses.append(loss)
+    torch.cuda.synchronize()
+    return [l.item() for l in losses]
+
+
+def test_training_reduces_loss_reproducible_and_resumes(emcnn):
+    vols = [em_volume(5000 + i, 2, 160, 160) for i in range(2)]
+    maps = _teacher_maps(emcnn, vols)
+    vols_dev = [_dev(v) for v in vols]
+    p0 = he_normal_params(NET_S, 300)
+    s1 = emcnn.student_create(p0, "bf16")
+    l1 = _train(emcnn, s1, vols_dev, maps, 60, seed=1)
+    assert np.mean(l1[-10:]) < np.mean(l1[:10])
+    s2 = emcnn.student_create(p0, "bf16")
+    l2 = _train(emcnn, s2, vols_dev, maps, 60, seed=1)
+    w1, m1, v1, t1 = emcnn.student_get_state(s1)
+    w2, _, _, _ = emcnn.student_get_state(s2)
+    assert l1 == l2 and np.array_equal(w1, w2)  # bitwise reproducible
+    # checkpoint / resume: continue s1, and restore a fresh student from s1's state
+    s3 = emcnn.student_create(p0, "bf16")
+    emcnn.student_set_state(s3, w1, m1, v1, t1)
+    la = _train(emcnn, s1, vols_dev, maps, 10, seed=7)
+    lb = _train(emcnn, s3, vols_dev, maps, 10, seed=7)
+    assert la == lb
+    assert np.array_equal(emcnn.student_get_state(s1)[0], emcnn.student_get_state(s3)[0])
+
+
+def test_fallback_endpoints(emcnn):
+    vol = em_volume(95, 2, 300, 280)
+    vd = _dev(vol)
+    teacher = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")
+    tmap = emcnn.cnn_infer(teacher, vd)
+    s = emcnn.student_create(he_normal_params(NET_S, 300), "bf16")
+    smap = emcnn.student_infer(s, vd)
+    torch.cuda.synchronize()
+    # tau < 0: every tile is recomputed by the teacher
+    out, st = emcnn.student_infer_with_fallback(s, teacher, vd, tau=-1.0, tile=128, n_samples=4, seed=3)
+    assert torch.equal(out, tmap)
+    assert st.tolist() == [2 * 3 * 3, 2 * 3 * 3]
+    # tau >= 1: no tile falls back; the output is the student map in the teacher frame
+    out, st = emcnn.student_infer_with_fallback(s, teacher, vd, tau=1.0, tile=128, n_samples=4, seed=3)
+    assert torch.equal(out, smap[:, 3:-3, 3:-3])
+    assert st.tolist()[0] == 0
+    # a constant student (all weights zero -> p = 0.5 everywhere) disagrees on about half the
+    # sampled voxels of every tile, so every tile falls back at tau = 0.01
+    z = emcnn.student_create(np.zeros(801), "bf16")
+    out, st = emcnn.student_infer_with_fallback(z, teacher, vd, tau=0.01, tile=128, n_samples=4, seed=3)
+    assert st.tolist()[0] == st.tolist()[1]
+    assert torch.equal(out, tmap)
+    # sampled windows agree with the teacher map where they were taken
+    out, st = emcnn.student_infer_with_fallback(s, teacher, vd, tau=0.05, tile=128, n_samples=4, seed=3)
+    flagged = st.tolist()[0]
+    assert 0 <= flagged <= 18
