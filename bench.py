@@ -108,7 +108,12 @@ def main():
     ap.add_argument("--forms", default="all", help="all | none | comma list of bf16,fp8,batch,student")
     ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="pick tile shapes by timing first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes instead of timing the candidates first")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (read, then updated)")
+    ap.add_argument("--no-headline", action="store_true", help="skip the FP32 headline (profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path; "
@@ -122,19 +127,30 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
+    if args.copy_calib:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     Z, H, W = 32, 1024, 1024
+    if args.no_headline:
+        Z = 1
     t0 = time.perf_counter()
     vol = em_volume(2, Z, H, W)
     log("generated %s volume in %.1fs" % ((Z, H, W), time.perf_counter() - t0))
     vol_dev = torch.from_numpy(vol).to(dev)
     p = calibrated_params("B")
     h = emcnn.cnn_create(p, NET_B, "fp32")
-    if args.autotune:
-        emcnn.cnn_autotune(h, H, W, None, stream)
+    if not args.no_autotune:
+        emcnn.cnn_autotune(h, H, W, args.tune_cache, stream)
     R = h.R
     Ho, Wo = H - R, W - R
     nvox = Z * Ho * Wo
-    ms, per_layer, out = time_volume(emcnn, torch, h, vol_dev, args.steps, args.warmup, stream)
+    ms, per_layer, out = time_volume(emcnn, torch, h, vol_dev, 1 if args.no_headline else args.steps,
+                                     0 if args.no_headline else args.warmup, stream)
     value = nvox / (ms * 1e-3)
     conv2_ms = per_layer[1]
     conv2_units = Z * (H - 9) * (W - 9)
@@ -177,13 +193,16 @@ def main():
                 continue
             hp = emcnn.cnn_create(p, NET_B, prec,
                                   act_scales=fp8_act_scales("B") if prec == "fp8" else None)
+            if not args.no_autotune:
+                emcnn.cnn_autotune(hp, 2048, 2048, args.tune_cache, stream)
             msp, pl, outp = time_volume(emcnn, torch, hp, volp_dev, max(3, args.steps // 2), 2, stream)
             c2u = Zp * (2048 - 9) ** 2
             ach = c2u * CONV2_FLOP_PER_POS / (pl[1] * 1e-3) / 1e12
             forms[prec] = {"workload": "net B %s, %d x 2048 x 2048 (seed 3)" % (prec, Zp),
                            "voxels_per_s": nv / (msp * 1e-3), "ms_per_pass": msp,
                            "path_mfma_frac": nv * NET_B_FLOP_PER_VOXEL / (msp * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
-                           "conv2_tflops": ach, "conv2_frac": ach / PEAK_TFLOPS[prec], "layer_ms": pl[:3]}
+                           "conv2_tflops": ach, "conv2_frac": ach / PEAK_TFLOPS[prec], "layer_ms": pl[:3],
+                           "tiles": emcnn.cnn_describe(hp)}
             log(prec, json.dumps(forms[prec]))
             del outp, hp
         del volp_dev
@@ -193,6 +212,8 @@ def main():
         rng = np.random.default_rng(44)
         pool = em_volume(4, 8, 1040, 1040)
         hb = emcnn.cnn_create(p, NET_B, "bf16")
+        if not args.no_autotune:
+            emcnn.cnn_autotune(hb, 512, 512, args.tune_cache, stream)
         tiles, nv = [], 0
         for t in tl:
             y = int(rng.integers(0, 1040 - t["h"] + 1))

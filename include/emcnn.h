@@ -153,6 +153,14 @@ int cnn_profile(cnn_net* net, int32_t enable);
 int cnn_profile_read(cnn_net* net, double* ms_per_layer, int32_t* launches_per_layer,
                      int32_t max_layers);
 
+/* Executed layers: 0 = first conv, then one per body conv (the head is fused
+ * into the last one). cnn_variant_name writes the name of candidate `index`
+ * of `layer` (CNN_EINVAL past the last); cnn_set_variant selects a candidate
+ * by name for later calls. Candidates of one layer may differ in accumulation
+ * order (and so in the last bits of the result). */
+int cnn_variant_name(const cnn_net* net, int32_t layer, int32_t index, char* buf, int32_t buf_len);
+int cnn_set_variant(cnn_net* net, int32_t layer, const char* name);
+
 /* Describe the current tile choice (for logs); writes a NUL-terminated string. */
 int cnn_describe(const cnn_net* net, char* buf, int32_t buf_len);
 

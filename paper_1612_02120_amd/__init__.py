@@ -52,7 +52,7 @@ EXPORTS = [
     "cnn_describe", "cnn_set_batch_graph", "cnn_set_workspace_limit", "student_create",
     "student_destroy", "student_get_state", "student_set_state", "student_grad",
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
-    "cnn_profile", "cnn_profile_read",
+    "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
 ]
 
 
@@ -72,6 +72,8 @@ def _load():
         "cnn_set_batch_graph": [vp, i32],
         "cnn_set_workspace_limit": [vp, i64],
         "cnn_profile": [vp, i32],
+        "cnn_variant_name": [vp, i32, i32, ctypes.c_char_p, i32],
+        "cnn_set_variant": [vp, i32, ctypes.c_char_p],
         "cnn_profile_read": [vp, vp, vp, i32],
         "student_create": [vp, i64, i32, vp],
         "student_destroy": [vp],
@@ -236,6 +238,18 @@ def cnn_set_batch_graph(net: Net, enable: bool):
 
 def cnn_set_workspace_limit(net: Net, nbytes: int):
     _check(_lib.cnn_set_workspace_limit(net.ptr, int(nbytes)), "cnn_set_workspace_limit")
+
+
+def cnn_variant_names(net: Net, layer: int):
+    """Names of the compiled candidates of executed layer `layer`."""
+    out, buf = [], ctypes.create_string_buffer(512)
+    while _lib.cnn_variant_name(net.ptr, layer, len(out), buf, 512) == CNN_OK:
+        out.append(buf.value.decode())
+    return out
+
+
+def cnn_set_variant(net: Net, layer: int, name: str):
+    _check(_lib.cnn_set_variant(net.ptr, int(layer), name.encode()), "cnn_set_variant")
 
 
 def cnn_profile(net: Net, enable: bool):

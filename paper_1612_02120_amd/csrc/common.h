@@ -65,7 +65,8 @@ struct VariantInfo {
   int cb;               // channels staged per LDS pass
   int chb;              // channels per 16-byte chunk
   int u;                // chunks per lane per MFMA
-  int ngs;              // group-steps per channel block
+  int ngs;              // group-steps per channel block (row reuse: per filter row)
+  int rr;               // 1: row-reuse kernel (weights packed per filter row)
   int lds_bytes;
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
   const char* name;

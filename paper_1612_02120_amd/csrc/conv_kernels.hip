@@ -54,7 +54,7 @@ __host__ __device__ constexpr int pad_words(int w) {
   return (w % 8 == 4) ? w : w + ((12 - (w % 8)) % 8);
 }
 
-template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW>
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, bool HEAD = false>
 struct Cfg {
   using T = PT<P>;
   static constexpr int CB = (T::CB < CIN) ? T::CB : CIN;
@@ -69,7 +69,12 @@ struct Cfg {
   static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
   static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
-  static constexpr int LDS = LR * LC * PSB;
+  static constexpr int LDS_IN = LR * LC * PSB;
+  // BF16 / FP8 outputs leave through LDS so that each tile row is written as
+  // contiguous 16-byte stores (FP32 rows already go out in 64-byte segments)
+  static constexpr bool STAGE_OUT = (P != F32) && !HEAD;
+  static constexpr int LDS_OUT = STAGE_OUT ? TY * TX * COUT * T::BYTES : 0;
+  static constexpr int LDS_TILE = LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT;
   static constexpr int MBLK = TY * TX / 16;
   static_assert(TX % 16 == 0, "TX must be a multiple of 16");
   static_assert(MBLK % MW == 0, "m-blocks must split evenly over waves");
@@ -216,12 +221,60 @@ __device__ __forceinline__ int find_job(const LayerJob* t, int n, int64_t item) 
 
 // ---------------------------------------------------------------- first layer
 
+// conv1 (one input channel, KS x KS, KS*KS <= 32 taps) on MFMA. M = 16
+// consecutive output pixels of a tile row per m-block, N = 16 output channels,
+// K = taps. BF16 / FP8 nets: one 16x16x32 bf16 MFMA per (m-block, n-block),
+// lane group g holding taps 8g..8g+7 (taps >= KS*KS are zero); the uint8 input
+// is exact in bf16. FP32 nets: 16x16x4 f32 MFMAs, lane group g holding tap
+// 4s+g of step s. Weights are pre-packed per lane (wpack, see the host).
+// The epilogue applies bias and ReLU, casts to the stored activation format,
+// stages the whole output tile in LDS and writes each tile row as one
+// contiguous run of 16-byte stores (NHWC rows are contiguous in memory).
 template <int PO, int COUT, int KS, int TY, int TX>
-__global__ __launch_bounds__((TY * TX)) void conv_first(JobSet js, FirstParams prm) {
-  constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
-  __shared__ float tile[LR * LC];
-  const int tid = threadIdx.x;
-  const int ty = tid / TX, tx = tid % TX;
+struct FirstCfg {
+  static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  static constexpr int ESZ = PO == F32 ? 4 : PO == BF16 ? 2 : 1;
+  static constexpr int NB = COUT / 16;
+  static constexpr int MBLK = TY * TX / 16;
+  static constexpr int WAVES = 4;
+  static constexpr int MW = MBLK / WAVES;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int NSTEP = PO == F32 ? (KS * KS + 3) / 4 : 1;
+  static constexpr int IN_BYTES = (LR * LC + 15) / 16 * 16;
+  static constexpr int OUT_BYTES = TY * TX * COUT * ESZ;
+  static constexpr int LDS = IN_BYTES + OUT_BYTES;
+  static_assert(KS * KS <= 32, "first layer supports up to 32 taps");
+  static_assert(MBLK % WAVES == 0 && TX % 16 == 0, "tile must split into m-blocks per wave");
+};
+
+template <int PO, int COUT, int KS, int TY, int TX>
+__global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void conv_first(JobSet js, FirstParams prm) {
+  using C = FirstCfg<PO, COUT, KS, TY, TX>;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+  unsigned char* tile = lds;
+  unsigned char* obuf = lds + C::IN_BYTES;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  constexpr int MCOLS = TX / 16;
+  // per-lane weight fragments and bias
+  Frag<PO == F32 ? F32 : BF16> wf[C::NSTEP][C::NB];
+  {
+    const unsigned char* wp = reinterpret_cast<const unsigned char*>(prm.w);
+#pragma unroll
+    for (int s = 0; s < C::NSTEP; ++s)
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) {
+        if constexpr (PO == F32) {
+          wf[s][nb].v = f4{reinterpret_cast<const float*>(wp)[(s * C::NB + nb) * 64 + lane], 0.f, 0.f, 0.f};
+        } else {
+          wf[s][nb].v = *reinterpret_cast<const bf16x8*>(wp + ((size_t)(s * C::NB + nb) * 64 + lane) * 16);
+        }
+      }
+  }
+  float bias[C::NB];
+#pragma unroll
+  for (int nb = 0; nb < C::NB; ++nb) bias[nb] = prm.bias[nb * 16 + n16];
+
   const ItemRange rg = item_range(js.total_items);
   int cur = 0;
   if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
@@ -242,49 +295,62 @@ __global__ __launch_bounds__((TY * TX)) void conv_first(JobSet js, FirstParams p
     const int y0 = by * TY, x0 = bx * TX;
     const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs;
     __syncthreads();
-    for (int t = tid; t < LR * LC; t += TY * TX) {
-      int r = t / LC, c = t % LC;
-      int y = min(y0 + r, J.hin - 1), x = min(x0 + c, J.win - 1);
-      tile[t] = (float)in[(int64_t)y * J.in_rs + x];
+    for (int t = tid; t < C::LR * C::LC; t += C::THREADS) {
+      const int r = t / C::LC, c = t % C::LC;
+      const int y = min(y0 + r, J.hin - 1), x = min(x0 + c, J.win - 1);
+      tile[t] = in[(int64_t)y * J.in_rs + x];
     }
     __syncthreads();
-    float acc[COUT];
 #pragma unroll
-    for (int co = 0; co < COUT; ++co) acc[co] = prm.bias[co];
+    for (int u = 0; u < C::MW; ++u) {
+      const int mb = wave * C::MW + u;
+      const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+      const unsigned char* a0 = tile + mrow * C::LC + mcol * 16 + n16;
+      f4 acc[C::NB];
 #pragma unroll
-    for (int i = 0; i < KS; ++i)
-#pragma unroll
-      for (int j = 0; j < KS; ++j) {
-        const float xv = tile[(ty + i) * LC + tx + j];
-#pragma unroll
-        for (int co = 0; co < COUT; ++co) acc[co] = fmaf(prm.w[(co * KS + i) * KS + j], xv, acc[co]);
-      }
-    const int y = y0 + ty, x = x0 + tx;
-    if (y < J.hout && x < J.wout) {
-      const int64_t pix = (int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x;
+      for (int nb = 0; nb < C::NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
       if constexpr (PO == F32) {
-        f4* o = reinterpret_cast<f4*>(reinterpret_cast<float*>(J.out) + pix * COUT);
 #pragma unroll
-        for (int q = 0; q < COUT / 4; ++q)
-          o[q] = f4{relu(acc[4 * q]), relu(acc[4 * q + 1]), relu(acc[4 * q + 2]), relu(acc[4 * q + 3])};
-      } else if constexpr (PO == BF16) {
-        bf16x8* o = reinterpret_cast<bf16x8*>(reinterpret_cast<__bf16*>(J.out) + pix * COUT);
+        for (int s = 0; s < C::NSTEP; ++s) {
+          const int k = 4 * s + g;
+          const float a = k < KS * KS ? (float)a0[(k / KS) * C::LC + k % KS] : 0.f;
 #pragma unroll
-        for (int q = 0; q < COUT / 8; ++q) {
-          bf16x8 v;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (__bf16)relu(acc[8 * q + e]);
-          o[q] = v;
+          for (int nb = 0; nb < C::NB; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wf[s][nb].v[0], acc[nb], 0, 0, 0);
         }
       } else {
-        i4v* o = reinterpret_cast<i4v*>(reinterpret_cast<unsigned char*>(J.out) + pix * COUT);
+        bf16x8 a;
 #pragma unroll
-        for (int q = 0; q < COUT / 16; ++q) {
-          u8x16 v;
-#pragma unroll
-          for (int e = 0; e < 16; ++e) v[e] = to_e4m3(relu(acc[16 * q + e]) * prm.out_inv_scale);
-          o[q] = __builtin_bit_cast(i4v, v);
+        for (int t = 0; t < 8; ++t) {
+          const int k = 8 * g + t;
+          a[t] = (__bf16)(k < KS * KS ? (float)a0[(k / KS) * C::LC + k % KS] : 0.f);
         }
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf[0][nb].v, acc[nb], 0, 0, 0);
+      }
+      // D[m = 4 g + k][n = n16] -> tile pixel (mrow, mcol*16 + 4g + k), channel nb*16 + n16
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int pix = mrow * TX + mcol * 16 + 4 * g + k;
+          const float v = relu(acc[nb][k] + bias[nb]);
+          store_act<PO>(obuf, (int64_t)pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+        }
+    }
+    __syncthreads();
+    // coalesced copy-out: each tile row is a contiguous NHWC run in global memory
+    const int vcols = min(TX, J.wout - x0);
+    constexpr int ROWB = TX * COUT * C::ESZ;
+    const int vbytes = vcols * COUT * C::ESZ;  // multiple of 16
+    for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
+      const int r = t / (ROWB / 16), q = t % (ROWB / 16);
+      const int y = y0 + r;
+      if (y < J.hout && q * 16 < vbytes) {
+        unsigned char* dst = reinterpret_cast<unsigned char*>(J.out) +
+                             (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * C::ESZ + q * 16;
+        *reinterpret_cast<i4v*>(dst) = *reinterpret_cast<const i4v*>(obuf + r * ROWB + q * 16);
       }
     }
   }
@@ -299,10 +365,10 @@ __global__ __launch_bounds__((TY * TX)) void conv_first(JobSet js, FirstParams p
 // the same slot the same way, so the MFMA contracts matching K indices
 // whatever order the instruction uses inside a lane's operand bytes.
 template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int MW>
-__global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS)) void conv_mfma(JobSet js, ConvParams prm) {
-  using C = Cfg<P, CIN, COUT, KS, TY, TX, MW>;
+__global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS)) void conv_mfma(JobSet js, ConvParams prm) {
+  using C = Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>;
   using T = PT<P>;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_TILE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
   constexpr int MCOLS = TX / 16;
@@ -338,7 +404,8 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS)) void 
 
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
-      // ---- stage the (TY+KS-1) x (TX+KS-1) input tile of this channel block
+      // ---- stage the (TY+KS-1) x (TX+KS-1) input tile of this channel block,
+      //      applying the preceding 2x2 stride-1 max filter while loading
       constexpr int NST = C::LR * C::LC * C::NCHB;
       for (int t = tid; t < NST; t += C::THREADS) {
         const int cg = t % C::NCHB;
@@ -390,6 +457,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS)) void 
     }
 
     // ---- epilogue: lane holds D[m = 4 g + k][n = n16] of each (m-block, n-block)
+    if constexpr (C::STAGE_OUT) __syncthreads();  // the LDS tile is reused for the output
     float bias[C::NB], osc[C::NB], hw[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) {
@@ -407,20 +475,30 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS)) void 
         float part[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          float p = 0.f;
+          float pv = 0.f;
 #pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) p = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], p);
-          p += __shfl_xor(p, 1);
-          p += __shfl_xor(p, 2);
-          p += __shfl_xor(p, 4);
-          p += __shfl_xor(p, 8);
-          part[k] = p;
+          for (int nb = 0; nb < C::NB; ++nb) pv = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], pv);
+          pv += __shfl_xor(pv, 1);
+          pv += __shfl_xor(pv, 2);
+          pv += __shfl_xor(pv, 4);
+          pv += __shfl_xor(pv, 8);
+          part[k] = pv;
         }
         if (n16 < 4) {
           const int x = xb + n16;
-          const float z = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
+          const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
           if (y < J.hout && x < J.wout)
-            reinterpret_cast<float*>(J.out)[(int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x] = sigmoid_f(z);
+            reinterpret_cast<float*>(J.out)[(int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x] = sigmoid_f(zl);
+        }
+      } else if constexpr (C::STAGE_OUT) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int pix = mrow * TX + mcol * 16 + 4 * g + k;
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) {
+            const float v = relu(fmaf(acc[u][nb][k], osc[nb], bias[nb]));
+            store_act<P>(lds, (int64_t)pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+          }
         }
       } else {
         if (y < J.hout) {
@@ -439,67 +517,331 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS)) void 
         }
       }
     }
+    if constexpr (C::STAGE_OUT) {
+      __syncthreads();
+      const int vcols = min(TX, J.wout - x0);
+      constexpr int ROWB = TX * COUT * T::BYTES;
+      const int vbytes = vcols * COUT * T::BYTES;  // multiple of 16
+      for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
+        const int r = t / (ROWB / 16), q = t % (ROWB / 16);
+        const int y = y0 + r;
+        if (y < J.hout && q * 16 < vbytes) {
+          unsigned char* dst = reinterpret_cast<unsigned char*>(J.out) +
+                               (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
+          *reinterpret_cast<i4v*>(dst) = *reinterpret_cast<const i4v*>(lds + r * ROWB + q * 16);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- MFMA conv, row reuse
+
+// Same layer as conv_mfma, with the K loop ordered by filter row so that A
+// fragments are reused across output rows. A wave owns MR output rows x MC
+// m-blocks of 16 pixels. For each group-step of one filter row's (j, chunk)
+// slots, the B fragments of all KS filter rows stay in registers, and the A
+// fragment of input row q (wave-relative) is loaded from LDS once and feeds
+// every filter row i with output row q - i in [0, MR): (MR + KS - 1) LDS loads
+// per MR * KS MFMA groups instead of one load per group.
+// Packed weights: [cb][i][rs][nb][lane][U chunks of 16 B]; lane (n, g) holds
+// for slot c = (4 rs + g) U + uu of filter row i the chunk (j, cg) =
+// (c / NCHB, c % NCHB) of tap (i, j); slots past KS * NCHB are zero.
+template <int P, int CIN, int COUT, int KS, int MR, int MC, int WX, int WY, bool HEAD, int CBO = 0>
+struct CfgRR {
+  using T = PT<P>;
+  static constexpr int CB = CBO ? CBO : ((T::CB < CIN) ? T::CB : CIN);
+  static_assert(CIN % CB == 0, "channel block must divide CIN");
+  static constexpr int NCB = CIN / CB;
+  static constexpr int NCHB = CB / T::CHB;
+  static_assert(NCHB * T::CHB == CB, "block must be whole chunks");
+  static constexpr int NCHR = KS * NCHB;  // chunks per filter row
+  static constexpr int SLOTS = 4 * T::U;
+  static constexpr int NGR = (NCHR + SLOTS - 1) / SLOTS;  // group-steps per filter row
+  static constexpr int NB = COUT / 16;
+  static constexpr int TY = WY * MR, TX = WX * MC * 16;
+  static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
+  static constexpr int LDS_IN = LR * LC * PSB;
+  static constexpr bool STAGE_OUT = (P != F32) && !HEAD;
+  static constexpr int LDS_OUT = STAGE_OUT ? TY * TX * COUT * T::BYTES : 0;
+  static constexpr int LDS = LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT;
+  static constexpr int THREADS = WX * WY * 64;
+  static_assert(LDS <= 160 * 1024, "LDS budget of a gfx950 workgroup");
+};
+
+template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int MR, int MC, int WX, int WY, int CBO>
+__global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::THREADS)) void conv_mfma_rr(
+    JobSet js, ConvParams prm) {
+  using C = CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>;
+  using T = PT<P>;
+  constexpr int TY = C::TY, TX = C::TX;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  const int wy = wave / WX, wx = wave % WX;
+  constexpr int ELB = CIN * T::BYTES;
+
+  // per-lane slot offsets inside a filter row (column and chunk), fixed per lane
+  int coff[C::NGR][T::U];
+#pragma unroll
+  for (int rs = 0; rs < C::NGR; ++rs)
+#pragma unroll
+    for (int uu = 0; uu < T::U; ++uu) {
+      int c = (4 * rs + g) * T::U + uu;
+      c = c < C::NCHR ? c : C::NCHR - 1;  // padded slot: finite data, zero weights
+      coff[rs][uu] = (c / C::NCHB) * C::PSB + (c % C::NCHB) * 16;
+    }
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    LayerJob J;
+    if (js.table) {
+      while (cur + 1 < js.njobs && js.table[cur + 1].item0 <= item) ++cur;
+      J = js.table[cur];
+    } else {
+      J = js.single;
+    }
+    if (J.gate && *J.gate == 0) continue;
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int by = (int)(t2 % J.tiles_y);
+    const int zz = (int)(t2 / J.tiles_y);
+    const int y0 = by * TY, x0 = bx * TX;
+    const int hp = J.hin - (POOL ? 1 : 0), wp = J.win - (POOL ? 1 : 0);
+    const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs * ELB;
+    const int64_t rowb = J.in_rs * ELB;
+
+    f4 acc[MR][MC][C::NB];
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+      for (int m = 0; m < MC; ++m)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) acc[r][m][nb] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int cb = 0; cb < C::NCB; ++cb) {
+      __syncthreads();
+      constexpr int NST = C::LR * C::LC * C::NCHB;
+      for (int t = tid; t < NST; t += C::THREADS) {
+        const int cg = t % C::NCHB;
+        const int pix = t / C::NCHB;
+        const int r = pix / C::LC, c = pix % C::LC;
+        const int y = min(y0 + r, hp - 1), x = min(x0 + c, wp - 1);
+        const unsigned char* src = in + (int64_t)y * rowb + (int64_t)x * ELB + (cb * C::CB + cg * T::CHB) * T::BYTES;
+        i4v v = *reinterpret_cast<const i4v*>(src);
+        if constexpr (POOL) {
+          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + ELB));
+          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb));
+          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb + ELB));
+        }
+        *reinterpret_cast<i4v*>(lds + pix * C::PSB + cg * 16) = v;
+      }
+      __syncthreads();
+      const unsigned char* wb = reinterpret_cast<const unsigned char*>(prm.wpack) +
+                                (size_t)cb * KS * C::NGR * C::NB * 64 * T::U * 16;
+      const unsigned char* abase = lds + ((wy * MR) * C::LC + wx * MC * 16 + n16) * C::PSB;
+      for (int rs = 0; rs < C::NGR; ++rs) {
+        Frag<P> bfr[KS][C::NB];
+#pragma unroll
+        for (int i = 0; i < KS; ++i)
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) {
+            const unsigned char* p = wb + ((size_t)((i * C::NGR + rs) * C::NB + nb) * 64 + lane) * (T::U * 16);
+            load_frag<P>(bfr[i][nb], p, p + 16);
+          }
+        int o0 = coff[0][0], o1 = coff[0][T::U - 1];
+#pragma unroll
+        for (int q = 0; q < C::NGR; ++q)
+          if (q == rs) {
+            o0 = coff[q][0];
+            o1 = coff[q][T::U - 1];
+          }
+#pragma unroll
+        for (int q = 0; q < MR + KS - 1; ++q) {
+#pragma unroll
+          for (int m = 0; m < MC; ++m) {
+            const unsigned char* a0 = abase + (q * C::LC + m * 16) * C::PSB;
+            Frag<P> afr;
+            load_frag<P>(afr, a0 + o0, a0 + o1);
+#pragma unroll
+            for (int i = 0; i < KS; ++i) {
+              const int r = q - i;
+              if (r >= 0 && r < MR) {
+#pragma unroll
+                for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[r][m][nb], afr, bfr[i][nb]);
+              }
+            }
+          }
+        }
+      }
+    }
+
+    if constexpr (C::STAGE_OUT) __syncthreads();  // the LDS tile is reused for the output
+    float bias[C::NB], osc[C::NB], hw[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) {
+      bias[nb] = prm.bias[nb * 16 + n16];
+      osc[nb] = prm.oscale ? prm.oscale[nb * 16 + n16] : 1.0f;
+      if constexpr (HEAD) hw[nb] = prm.head_w[nb * 16 + n16];
+    }
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+      for (int m = 0; m < MC; ++m) {
+        const int trow = wy * MR + r, tcol = (wx * MC + m) * 16 + 4 * g;
+        const int y = y0 + trow, xb = x0 + tcol;
+        if constexpr (HEAD) {
+          float part[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            float pv = 0.f;
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) pv = fmaf(relu(fmaf(acc[r][m][nb][k], osc[nb], bias[nb])), hw[nb], pv);
+            pv += __shfl_xor(pv, 1);
+            pv += __shfl_xor(pv, 2);
+            pv += __shfl_xor(pv, 4);
+            pv += __shfl_xor(pv, 8);
+            part[k] = pv;
+          }
+          if (n16 < 4) {
+            const int x = xb + n16;
+            const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
+            if (y < J.hout && x < J.wout)
+              reinterpret_cast<float*>(J.out)[(int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x] = sigmoid_f(zl);
+          }
+        } else if constexpr (C::STAGE_OUT) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int pix = trow * TX + tcol + k;
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) {
+              const float v = relu(fmaf(acc[r][m][nb][k], osc[nb], bias[nb]));
+              store_act<P>(lds, (int64_t)pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+            }
+          }
+        } else {
+          if (y < J.hout) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int x = xb + k;
+              if (x < J.wout) {
+                const int64_t pix = (int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x;
+#pragma unroll
+                for (int nb = 0; nb < C::NB; ++nb) {
+                  const float v = relu(fmaf(acc[r][m][nb][k], osc[nb], bias[nb]));
+                  store_act<P>(J.out, pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+                }
+              }
+            }
+          }
+        }
+      }
+    if constexpr (C::STAGE_OUT) {
+      __syncthreads();
+      const int vcols = min(TX, J.wout - x0);
+      constexpr int ROWB = TX * COUT * T::BYTES;
+      const int vbytes = vcols * COUT * T::BYTES;
+      for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
+        const int r = t / (ROWB / 16), q = t % (ROWB / 16);
+        const int y = y0 + r;
+        if (y < J.hout && q * 16 < vbytes) {
+          unsigned char* dst = reinterpret_cast<unsigned char*>(J.out) +
+                               (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
+          *reinterpret_cast<i4v*>(dst) = *reinterpret_cast<const i4v*>(lds + r * ROWB + q * 16);
+        }
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------- registry
 
 #define EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW)                                          \
-  VariantInfo{P,                                                                                      \
-              CIN,                                                                                    \
-              COUT,                                                                                   \
-              KS,                                                                                     \
-              POOL,                                                                                   \
-              HEAD,                                                                                   \
-              TY,                                                                                     \
-              TX,                                                                                     \
-              MW,                                                                                     \
-              Cfg<P, CIN, COUT, KS, TY, TX, MW>::THREADS,                                             \
-              Cfg<P, CIN, COUT, KS, TY, TX, MW>::CB,                                                  \
+  VariantInfo{P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW,                                               \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS,                                       \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::CB,                                            \
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
-              Cfg<P, CIN, COUT, KS, TY, TX, MW>::NGS,                                                 \
-              Cfg<P, CIN, COUT, KS, TY, TX, MW>::LDS,                                                 \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::NGS,                                           \
+              0,                                                                                      \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::LDS_TILE,                                      \
               reinterpret_cast<const void*>(&conv_mfma<P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW>), \
               "conv_mfma<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #MW ">"}
 
-// Tile shapes per layer signature; the first of each signature is the default,
-// the rest are autotuner candidates.
-#define EMCNN_SHAPES(P, CIN, COUT, KS, POOL, HEAD)                                             \
-  EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 4, 64, 4), \
-      EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
+#define EMCNN_RR(P, CIN, COUT, KS, POOL, HEAD, MR, MC, WX, WY, CBO)                                   \
+  VariantInfo{P, CIN, COUT, KS, POOL, HEAD,                                                           \
+              CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::TY,                                 \
+              CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::TX,                                 \
+              MR * MC,                                                                                \
+              CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::THREADS,                            \
+              CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::CB,                                 \
+              PT<P>::CHB,                                                                             \
+              PT<P>::U,                                                                               \
+              CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::NGR,                                \
+              1,                                                                                      \
+              CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::LDS,                                \
+              reinterpret_cast<const void*>(&conv_mfma_rr<P, CIN, COUT, KS, POOL, HEAD, MR, MC, WX, WY, CBO>), \
+              "conv_mfma_rr<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #MR "," #MC "," #WX "," #WY \
+              "," #CBO ">"}
 
+// Flattened-K tile shapes; the first (8 x 64 outputs, 8 waves) measured fastest
+// or within noise of the fastest for every body layer of net B in every
+// precision on MI355X, so it is each signature's default.
+#define EMCNN_SHAPES(P, CIN, COUT, KS, POOL, HEAD)                                             \
+  EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), \
+      EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 4, 64, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
+
+// Row-reuse tile shapes (MR rows x MC m-blocks per wave, WX x WY waves).
+#define EMCNN_RR_SHAPES(P, CIN, COUT, KS, POOL, HEAD, CBO)                                                 \
+  EMCNN_RR(P, CIN, COUT, KS, POOL, HEAD, 4, 1, 2, 2, CBO), EMCNN_RR(P, CIN, COUT, KS, POOL, HEAD, 8, 1, 2, 1, CBO), \
+      EMCNN_RR(P, CIN, COUT, KS, POOL, HEAD, 4, 2, 2, 2, CBO), EMCNN_RR(P, CIN, COUT, KS, POOL, HEAD, 8, 1, 4, 1, CBO)
+
+// The first entry of each layer signature is the default; the rest are
+// candidates for the autotuner (which only accepts those whose output is
+// bitwise equal to the default's, i.e. the same K order and channel block)
+// and for explicit selection with cnn_set_variant.
 static const VariantInfo kConv[] = {
     // net B body: 48 -> 48, 5x5 after a pool; 3x3 after a pool with the head fused
     EMCNN_SHAPES(F32, 48, 48, 5, true, false),
+    EMCNN_RR_SHAPES(F32, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(F32, 48, 48, 3, true, true),
+    EMCNN_RR_SHAPES(F32, 48, 48, 3, true, true, 0),
     EMCNN_SHAPES(BF16, 48, 48, 5, true, false),
+    EMCNN_RR_SHAPES(BF16, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(BF16, 48, 48, 3, true, true),
+    EMCNN_RR_SHAPES(BF16, 48, 48, 3, true, true, 48),
     EMCNN_SHAPES(FP8, 48, 48, 5, true, false),
+    EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 2, 2, 0),
+    EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 4, 1, 0),
     EMCNN_SHAPES(FP8, 48, 48, 3, true, true),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)
-    EMCNN_CONV(F32, 48, 48, 5, false, false, 8, 32, 4),
-    EMCNN_CONV(F32, 48, 48, 3, false, true, 8, 32, 4),
-    EMCNN_CONV(F32, 48, 48, 5, false, true, 8, 32, 4),
-    EMCNN_CONV(BF16, 48, 48, 5, false, false, 8, 32, 4),
-    EMCNN_CONV(BF16, 48, 48, 3, false, true, 8, 32, 4),
-    EMCNN_CONV(FP8, 48, 48, 5, false, false, 8, 32, 4),
-    EMCNN_CONV(FP8, 48, 48, 3, false, true, 8, 32, 4),
+    EMCNN_CONV(F32, 48, 48, 5, false, false, 8, 64, 4),
+    EMCNN_CONV(F32, 48, 48, 3, false, true, 8, 64, 4),
+    EMCNN_CONV(F32, 48, 48, 5, false, true, 8, 64, 4),
+    EMCNN_CONV(BF16, 48, 48, 5, false, false, 8, 64, 4),
+    EMCNN_CONV(BF16, 48, 48, 3, false, true, 8, 64, 4),
+    EMCNN_CONV(FP8, 48, 48, 5, false, false, 8, 64, 4),
+    EMCNN_CONV(FP8, 48, 48, 3, false, true, 8, 64, 4),
     EMCNN_CONV(F32, 16, 16, 5, true, true, 8, 32, 4),
     EMCNN_CONV(F32, 16, 16, 5, false, false, 8, 32, 4),
 };
 
 #define EMCNN_FIRST(PO, COUT, KS, TY, TX)                                                            \
-  FirstInfo{PO, COUT, KS, TY, TX, TY * TX, (TY + KS - 1) * (TX + KS - 1) * 4,                        \
+  FirstInfo{PO, COUT, KS, TY, TX, FirstCfg<PO, COUT, KS, TY, TX>::THREADS, FirstCfg<PO, COUT, KS, TY, TX>::LDS, \
             reinterpret_cast<const void*>(&conv_first<PO, COUT, KS, TY, TX>),                         \
             "conv_first<" #PO "," #COUT "," #KS "," #TY "," #TX ">"}
 
 static const FirstInfo kFirst[] = {
-    EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 8, 32), EMCNN_FIRST(FP8, 48, 5, 8, 32),
-    EMCNN_FIRST(F32, 16, 5, 8, 32),  EMCNN_FIRST(F32, 48, 5, 16, 16), EMCNN_FIRST(BF16, 48, 5, 16, 16),
-    EMCNN_FIRST(FP8, 48, 5, 16, 16),
+    // defaults (first match per signature) are the measured fastest shapes
+    EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 4, 64), EMCNN_FIRST(FP8, 48, 5, 8, 64),
+    EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64),
+    EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 16, 64),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }

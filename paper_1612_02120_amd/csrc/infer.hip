@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <fstream>
 #include <string>
@@ -553,7 +554,7 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
     if (net->layers[l].candidates.size() > 1 && chosen[l] < 0) all = false;
   if (all) {
     for (int l = 0; l < nl; ++l)
-      if (chosen[l] >= 0) net->layers[l].variant = chosen[l];
+      if (chosen[l] >= 0) select_variant(net->layers[l], chosen[l]);
     return CNN_OK;
   }
   // synthetic slice (fixed LCG pattern) and per-layer buffers
@@ -598,7 +599,7 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   for (int l = 0; l < nl && !rc; ++l) {
     ExecLayer& L = net->layers[l];
     if (chosen[l] >= 0) {
-      L.variant = chosen[l];
+      select_variant(L, chosen[l]);
       continue;
     }
     if (L.candidates.size() < 2) continue;
@@ -608,7 +609,10 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
     int best = def;
     float best_ms = 1e30f;
     for (int c : L.candidates) {
-      L.variant = c;
+      // only candidates with the default's accumulation order (K layout and channel block)
+      if (!L.first && (conv_variant(c)->rr != conv_variant(def)->rr || conv_variant(c)->cb != conv_variant(def)->cb))
+        continue;
+      select_variant(L, c);
       rc = run_one_layer(net, l, bufs[l], bufs[nl + 1], d, st);  // warm-up, also the checked output
       if (rc) break;
       hipEventRecord(e0, st);
@@ -630,7 +634,7 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
         best = c;
       }
     }
-    L.variant = rc ? def : best;
+    select_variant(L, rc ? def : best);
     chosen[l] = L.variant;
   }
   cleanup();
@@ -682,4 +686,27 @@ extern "C" int cnn_profile_read(cnn_net* h, double* ms, int32_t* launches, int32
   }
   net->timed.clear();
   return rc;
+}
+
+extern "C" int cnn_set_variant(cnn_net* h, int32_t layer, const char* name) {
+  clear_error();
+  if (!h || !name) return fail(CNN_EINVAL, "cnn_set_variant: null argument");
+  Net* net = reinterpret_cast<Net*>(h);
+  if (layer < 0 || layer >= (int)net->layers.size()) return fail(CNN_EINVAL, "cnn_set_variant: bad layer index");
+  ExecLayer& L = net->layers[layer];
+  const int c = candidate_name_index(L, name);
+  if (c < 0 || !select_variant(L, c)) return fail(CNN_EINVAL, std::string("cnn_set_variant: no candidate ") + name);
+  return CNN_OK;
+}
+
+extern "C" int cnn_variant_name(const cnn_net* h, int32_t layer, int32_t index, char* buf, int32_t len) {
+  clear_error();
+  if (!h || !buf || len < 1) return fail(CNN_EINVAL, "cnn_variant_name: bad argument");
+  const Net* net = reinterpret_cast<const Net*>(h);
+  if (layer < 0 || layer >= (int)net->layers.size()) return fail(CNN_EINVAL, "cnn_variant_name: bad layer index");
+  const ExecLayer& L = net->layers[layer];
+  if (index < 0 || index >= (int)L.candidates.size()) return fail(CNN_EINVAL, "cnn_variant_name: index out of range");
+  const int c = L.candidates[index];
+  std::snprintf(buf, len, "%s", L.first ? first_variant(c)->name : conv_variant(c)->name);
+  return CNN_OK;
 }

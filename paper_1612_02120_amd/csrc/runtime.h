@@ -20,7 +20,8 @@ struct ExecLayer {
   int in_off = 0;  // receptive radius consumed by earlier layers
   int variant = -1;
   std::vector<int> candidates;
-  void* wpack = nullptr;
+  std::vector<void*> wpacks;  // packed weights per candidate (layouts differ between variants)
+  void* wpack = nullptr;      // == wpacks[index of variant in candidates]
   float* bias = nullptr;
   float* oscale = nullptr;
   float* head_w = nullptr;
@@ -108,5 +109,7 @@ int layer_tx(const ExecLayer& L);
 const void* layer_fn(const ExecLayer& L);
 const char* layer_name(const ExecLayer& L);
 int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items);
+// Select candidate `variant` of layer L (binds its packed weights).
+bool select_variant(ExecLayer& L, int variant);
 
 }  // namespace emcnn

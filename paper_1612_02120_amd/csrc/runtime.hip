@@ -105,13 +105,15 @@ static std::vector<int> find_conv_variants(int prec, int cin, int cout, int ks, 
   return v;
 }
 
-static int pack_conv(ExecLayer& L, const double* w, const double* b, const double* hw, double hb,
+static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b, const double* hw, double hb,
                      double in_scale, double next_scale) {
-  const VariantInfo* v = conv_variant(L.variant);
+  const VariantInfo* v = conv_variant(variant);
   const int cin = v->cin, cout = v->cout, ks = v->ks, cb = v->cb, chb = v->chb, u = v->u, ngs = v->ngs;
   const int ncb = cin / cb, nchb = cb / chb, nchk = ks * ks * nchb, nb = cout / 16;
   const int esz = act_bytes(v->prec);
-  const size_t bytes = (size_t)ncb * ngs * nb * 64 * u * 16;
+  // flattened K: [cb][s][nb][lane][u]; row reuse: [cb][i][rs][nb][lane][u]
+  const int nsteps = v->rr ? ks * ngs : ngs;
+  const size_t bytes = (size_t)ncb * nsteps * nb * 64 * u * 16;
   std::vector<uint8_t> pk(bytes, 0);
   // quantised weights, [co][ci][i][j]
   const size_t nw = (size_t)cout * cin * ks * ks;
@@ -132,15 +134,28 @@ static int pack_conv(ExecLayer& L, const double* w, const double* b, const doubl
     }
   }
   for (int c0 = 0; c0 < ncb; ++c0)
-    for (int s = 0; s < ngs; ++s)
+    for (int s = 0; s < nsteps; ++s)
       for (int n_b = 0; n_b < nb; ++n_b)
         for (int lane = 0; lane < 64; ++lane) {
           const int n = lane & 15, g = lane >> 4, co = n_b * 16 + n;
           for (int uu = 0; uu < u; ++uu) {
-            const int c = (4 * s + g) * u + uu;
-            if (c >= nchk) continue;
-            const int i = c / (ks * nchb), rem = c % (ks * nchb), j = rem / nchb, cg = rem % nchb;
-            uint8_t* dst = pk.data() + ((((size_t)(c0 * ngs + s) * nb + n_b) * 64 + lane) * u + uu) * 16;
+            int i, j, cg;
+            if (v->rr) {
+              // step s = (filter row i, row-step rs); slot c over the row's (j, chunk) pairs
+              i = s / ngs;
+              const int c = (4 * (s % ngs) + g) * u + uu;
+              if (c >= ks * nchb) continue;
+              j = c / nchb;
+              cg = c % nchb;
+            } else {
+              const int c = (4 * s + g) * u + uu;
+              if (c >= nchk) continue;
+              i = c / (ks * nchb);
+              const int rem = c % (ks * nchb);
+              j = rem / nchb;
+              cg = rem % nchb;
+            }
+            uint8_t* dst = pk.data() + ((((size_t)(c0 * nsteps + s) * nb + n_b) * 64 + lane) * u + uu) * 16;
             for (int t = 0; t < chb; ++t) {
               const int ci = c0 * cb + cg * chb + t;
               const double val = wq[(((size_t)co * cin + ci) * ks + i) * ks + j];
@@ -161,9 +176,12 @@ static int pack_conv(ExecLayer& L, const double* w, const double* b, const doubl
         }
   std::vector<float> bias(b, b + cout);
   hipError_t e;
-  if ((e = hipMalloc(&L.wpack, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(weights)");
-  if ((e = hipMemcpy(L.wpack, pk.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
+  void* wdev = nullptr;
+  if ((e = hipMalloc(&wdev, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(weights)");
+  L.wpacks.push_back(wdev);
+  if ((e = hipMemcpy(wdev, pk.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "hipMemcpy(weights)");
+  if (L.bias) return CNN_OK;  // per-channel data shared by all candidates is already set
   if ((e = hipMalloc(&L.bias, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(bias)");
   hipMemcpy(L.bias, bias.data(), cout * sizeof(float), hipMemcpyHostToDevice);
   if (v->prec == FP8) {
@@ -180,26 +198,58 @@ static int pack_conv(ExecLayer& L, const double* w, const double* b, const doubl
   return CNN_OK;
 }
 
-static int pack_first(ExecLayer& L, const double* w, const double* b, double next_scale) {
-  const FirstInfo* f = first_variant(L.variant);
-  const int n = f->cout * f->ks * f->ks;
-  std::vector<float> wf(n);
-  for (int i = 0; i < n; ++i) {
-    float v = (float)(w[i] / 255.0);
-    wf[i] = (f->prec_out == F32) ? v : bf16_rne(v);
+// First-layer weights as per-lane MFMA B fragments (see conv_first):
+//   FP32 nets: float [step][n-block][lane], lane (n, g) holds tap 4 step + g of
+//              channel 16 n-block + n;
+//   others:    bf16 [n-block][lane][8], lane (n, g) holds taps 8g .. 8g+7.
+// Taps beyond k*k are zero. 1/255 is folded in (the kernel reads raw uint8).
+static int pack_first(ExecLayer& L, int variant, const double* w, const double* b, double next_scale) {
+  const FirstInfo* f = first_variant(variant);
+  const int cout = f->cout, taps = f->ks * f->ks, nb = cout / 16;
+  std::vector<unsigned char> pk;
+  if (f->prec_out == F32) {
+    const int nstep = (taps + 3) / 4;
+    std::vector<float> v((size_t)nstep * nb * 64, 0.f);
+    for (int s = 0; s < nstep; ++s)
+      for (int q = 0; q < nb; ++q)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int co = q * 16 + (lane & 15), k = 4 * s + (lane >> 4);
+          if (k < taps) v[((size_t)s * nb + q) * 64 + lane] = (float)(w[(size_t)co * taps + k] / 255.0);
+        }
+    pk.resize(v.size() * 4);
+    std::memcpy(pk.data(), v.data(), pk.size());
+  } else {
+    std::vector<uint16_t> v((size_t)nb * 64 * 8, 0);
+    for (int q = 0; q < nb; ++q)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 8; ++t) {
+          const int co = q * 16 + (lane & 15), k = 8 * (lane >> 4) + t;
+          if (k >= taps) continue;
+          const float x = bf16_rne((float)(w[(size_t)co * taps + k] / 255.0));
+          uint32_t bits;
+          std::memcpy(&bits, &x, 4);
+          v[((size_t)q * 64 + lane) * 8 + t] = (uint16_t)(bits >> 16);
+        }
+    pk.resize(v.size() * 2);
+    std::memcpy(pk.data(), v.data(), pk.size());
   }
-  std::vector<float> bf(b, b + f->cout);
+  std::vector<float> bf(b, b + cout);
   hipError_t e;
-  if ((e = hipMalloc(&L.wpack, n * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(w1)");
-  hipMemcpy(L.wpack, wf.data(), n * sizeof(float), hipMemcpyHostToDevice);
-  if ((e = hipMalloc(&L.bias, f->cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(b1)");
-  hipMemcpy(L.bias, bf.data(), f->cout * sizeof(float), hipMemcpyHostToDevice);
+  void* wdev = nullptr;
+  if ((e = hipMalloc(&wdev, pk.size())) != hipSuccess) return hip_fail(e, "hipMalloc(w1)");
+  L.wpacks.push_back(wdev);
+  hipMemcpy(wdev, pk.data(), pk.size(), hipMemcpyHostToDevice);
+  if (L.bias) return CNN_OK;
+  if ((e = hipMalloc(&L.bias, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(b1)");
+  hipMemcpy(L.bias, bf.data(), cout * sizeof(float), hipMemcpyHostToDevice);
   L.out_inv_scale = next_scale > 0 ? (float)(1.0 / next_scale) : 1.0f;
   return CNN_OK;
 }
 
 static void free_layer(ExecLayer& L) {
-  if (L.wpack) hipFree(L.wpack);
+  for (void* p : L.wpacks)
+    if (p) hipFree(p);
+  L.wpacks.clear();
   if (L.bias) hipFree(L.bias);
   if (L.oscale) hipFree(L.oscale);
   if (L.head_w) hipFree(L.head_w);
@@ -217,6 +267,16 @@ const void* layer_fn(const ExecLayer& L) {
 }
 const char* layer_name(const ExecLayer& L) {
   return L.first ? first_variant(L.variant)->name : conv_variant(L.variant)->name;
+}
+
+bool select_variant(ExecLayer& L, int variant) {
+  for (size_t i = 0; i < L.candidates.size(); ++i)
+    if (L.candidates[i] == variant && i < L.wpacks.size()) {
+      L.variant = variant;
+      L.wpack = L.wpacks[i];
+      return true;
+    }
+  return false;
 }
 
 int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items) {
@@ -343,7 +403,10 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
         const FirstInfo* f = first_variant(q);
         if (f->prec_out == prec && f->cout == l.cout && f->ks == l.k) E.candidates.push_back(q);
       }
-      rc = pack_first(E, w, b, nxt);
+      for (int c : E.candidates) {
+        if (rc == CNN_OK) rc = pack_first(E, c, w, b, nxt);
+      }
+      if (rc == CNN_OK) select_variant(E, E.variant);
     } else {
       const bool fuse_head = (i == nl - 2);
       if (l.act != CNN_ACT_RELU) {
@@ -368,7 +431,10 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
         hw = wp;
         hb = wp[hd.cin];
       }
-      rc = pack_conv(E, w, b, hw, hb, in_scale, fuse_head ? 0.0 : nxt);
+      for (int c : E.candidates) {
+        if (rc == CNN_OK) rc = pack_conv(E, c, w, b, hw, hb, in_scale, fuse_head ? 0.0 : nxt);
+      }
+      if (rc == CNN_OK) select_variant(E, E.variant);
     }
     net->layers.push_back(E);
     ++conv_i;

@@ -137,3 +137,21 @@ def test_invalid_arguments_leave_stream_untouched(emcnn):
     with pytest.raises(emcnn.CnnError) as ei:
         emcnn.cnn_infer_batch(h, [(t, 5, torch.empty((1, 20, 20), device="cuda"))])  # halo < R/2
     assert ei.value.code == emcnn.CNN_EINVAL
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2), ("fp8", 6e-2)])
+def test_every_candidate_variant_matches_reference(emcnn, prec, tol):
+    # every compiled tile shape / K order the autotuner may pick, on a ragged volume
+    vol = em_volume(77, 2, 61, 150)
+    p = calibrated_params("B")
+    sc = _scales() if prec == "fp8" else None
+    h = emcnn.cnn_create(p, NET_B, prec, act_scales=sc)
+    ref = oracle.forward(vol, NET_B, p)
+    defaults = [emcnn.cnn_variant_names(h, l)[0] for l in range(3)]
+    for layer in range(3):
+        for name in emcnn.cnn_variant_names(h, layer):
+            emcnn.cnn_set_variant(h, layer, name)
+            got = _run(emcnn, h, vol)
+            err = np.abs(got - ref).max()
+            assert err <= tol, (layer, name, err)
+        emcnn.cnn_set_variant(h, layer, defaults[layer])
