@@ -108,8 +108,8 @@ def main():
     ap.add_argument("--forms", default="all", help="all | none | comma list of bf16,fp8,batch,student")
     ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default tile shapes instead of timing the candidates first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate tile shapes first (the defaults are the measured best)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (read, then updated)")
     ap.add_argument("--no-headline", action="store_true", help="skip the FP32 headline (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -144,7 +144,7 @@ def main():
     vol_dev = torch.from_numpy(vol).to(dev)
     p = calibrated_params("B")
     h = emcnn.cnn_create(p, NET_B, "fp32")
-    if not args.no_autotune:
+    if args.autotune:
         emcnn.cnn_autotune(h, H, W, args.tune_cache, stream)
     R = h.R
     Ho, Wo = H - R, W - R
@@ -193,7 +193,7 @@ def main():
                 continue
             hp = emcnn.cnn_create(p, NET_B, prec,
                                   act_scales=fp8_act_scales("B") if prec == "fp8" else None)
-            if not args.no_autotune:
+            if args.autotune:
                 emcnn.cnn_autotune(hp, 2048, 2048, args.tune_cache, stream)
             msp, pl, outp = time_volume(emcnn, torch, hp, volp_dev, max(3, args.steps // 2), 2, stream)
             c2u = Zp * (2048 - 9) ** 2
@@ -212,7 +212,7 @@ def main():
         rng = np.random.default_rng(44)
         pool = em_volume(4, 8, 1040, 1040)
         hb = emcnn.cnn_create(p, NET_B, "bf16")
-        if not args.no_autotune:
+        if args.autotune:
             emcnn.cnn_autotune(hb, 512, 512, args.tune_cache, stream)
         tiles, nv = [], 0
         for t in tl:
