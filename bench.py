@@ -85,19 +85,24 @@ def time_volume(emcnn, torch, h, vol_dev, steps, warmup, stream):
     return (t1 - t0) * 1e3 / steps, per_layer, out
 
 
-def cpu_baseline(vol, net, params, out_vox_unit="voxels/s"):
+def cpu_baseline(vol, net, params, min_seconds=10.0, out_vox_unit="voxels/s"):
+    """The FP64 CPU reference on whole slices of the benchmark volume, one slice
+    after another until at least `min_seconds` of work has run."""
     import oracle
-    Z, H, W = 1, 512, 512
-    sample = np.ascontiguousarray(vol[:1, :H, :W])
     threads = oracle.num_threads()
-    t0 = time.perf_counter()
-    oracle.forward(sample, net, params, threads=threads)
-    dt = time.perf_counter() - t0
     R = oracle.radius(net)
-    nvox = Z * (H - R) * (W - R)
+    nvox, n, t0 = 0, 0, time.perf_counter()
+    while n < vol.shape[0]:
+        oracle.forward(np.ascontiguousarray(vol[n:n + 1]), net, params, threads=threads)
+        nvox += (vol.shape[1] - R) * (vol.shape[2] - R)
+        n += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    dt = time.perf_counter() - t0
     return {"value": nvox / dt, "unit": out_vox_unit, "cores": threads, "kind": "oracle",
-            "sample": "slice 0, input [0,512)^2 of the benchmark volume -> %d output voxels, "
-                      "FP64 direct convolution, %.1f s" % (nvox, dt)}
+            "sample": "%d whole slice(s) of the benchmark volume (%d x %d) -> %d output voxels, "
+                      "FP64 direct convolution, %.1f s on %d threads" % (n, vol.shape[1], vol.shape[2], nvox,
+                                                                           dt, threads)}
 
 
 def main():
