@@ -145,7 +145,7 @@ class Net:
         self.R = R
 
     def __del__(self):
-        if getattr(self, "ptr", None):
+        if getattr(self, "ptr", None) and _lib is not None:
             _lib.cnn_destroy(self.ptr)
             self.ptr = None
 
@@ -275,7 +275,7 @@ class Student:
         self.ptr = ptr
 
     def __del__(self):
-        if getattr(self, "ptr", None):
+        if getattr(self, "ptr", None) and _lib is not None:
             _lib.student_destroy(self.ptr)
             self.ptr = None
 
