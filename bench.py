@@ -105,6 +105,55 @@ def cpu_baseline(vol, net, params, min_seconds=10.0, out_vox_unit="voxels/s"):
                                                                            dt, threads)}
 
 
+def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args):
+    """Distil the student (64 volumes of 16 x 512 x 512, Adam lr 1e-3, batch 16 x
+    128^2) from the FP32 net's maps, then time student, student + fallback and
+    the plain net on a 2048^2 slab and report agreement and fallback rate."""
+    from paper_1612_02120_amd import distill
+    from synth.nets import NET_S, he_normal_params
+    steps = 20000 if args.full else 4000
+    t0 = time.perf_counter()
+    vols = [torch.from_numpy(em_volume(5000 + i, 16, 512, 512)).to(dev) for i in range(64)]
+    teacher = emcnn.cnn_create(p, NET_B, "fp32")
+    maps = distill.teacher_maps(teacher, vols)
+    s = emcnn.student_create(he_normal_params(NET_S, 300), "bf16")
+    losses, _ = distill.train(s, vols, maps, teacher.R, steps, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del vols, maps
+    Zs = 128 if args.full else 8
+    big = torch.from_numpy(em_volume(3, Zs, 2048, 2048)).to(dev)
+    tmap = emcnn.cnn_infer(teacher, big)
+    b16 = emcnn.cnn_create(p, NET_B, "bf16")
+    nv = Zs * (2048 - teacher.R) ** 2
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps
+
+    t_s = timed(lambda: emcnn.student_infer(s, big, stream=stream))
+    res = {"workload": "student conv5x5 1->8, conv3x3 8->8, 1x1 sigmoid, BF16; distilled %d steps "
+                       "(64 x 16 x 512^2, batch 16 x 128^2, lr 1e-3) from FP32 net B; eval %d x 2048^2"
+                       % (steps, Zs),
+           "train_s": t_train, "final_loss": float(losses[-200:].mean().item()),
+           "student_voxels_per_s": nv / t_s}
+    for tau in (0.01, 0.25):
+        r, out, st = distill.evaluate(s, teacher, big, tmap, tau=tau, tile=512, n_samples=4, seed=3)
+        t_f = timed(lambda: emcnn.student_infer_with_fallback(s, teacher, big, tau=tau, stream=stream), reps=2)
+        res["tau_%g" % tau] = dict(r, voxels_per_s=nv / t_f)
+    t32 = timed(lambda: emcnn.cnn_infer(teacher, big, stream=stream))
+    t16 = timed(lambda: emcnn.cnn_infer(b16, big, stream=stream))
+    res["net_b_fp32_voxels_per_s"] = nv / t32
+    res["net_b_bf16_voxels_per_s"] = nv / t16
+    res["bf16_teacher_agreement_with_fp32"] = distill.agreement(emcnn.cnn_infer(b16, big), tmap)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +234,7 @@ def main():
     del out
     forms = {}
     want = set() if args.forms == "none" else (
-        {"bf16", "fp8", "batch"} if args.forms == "all" else set(args.forms.split(",")))
+        {"bf16", "fp8", "batch", "student"} if args.forms == "all" else set(args.forms.split(",")))
     if want & {"bf16", "fp8"}:
         Zp = 128 if args.full else 8
         t0 = time.perf_counter()
@@ -253,6 +302,9 @@ def main():
                           "ms_per_tile_loop": msl}
         log("batch", json.dumps(forms["batch"]))
         del tiles, hb
+    if "student" in want:
+        forms["student"] = student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args)
+        log("student", json.dumps(forms["student"]))
     if forms:
         res["forms"] = forms
     if not args.no_cpu_baseline:
