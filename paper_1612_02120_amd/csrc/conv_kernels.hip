@@ -48,9 +48,20 @@ struct PT<FP8> {
   static constexpr int CHB = 16, U = 2, BYTES = 1, CB = 48;
 };
 
-// Smallest word count >= w that is 4 mod 8: consecutive pixels then start on
-// distinct 4-bank groups, so 8 lanes reading 16 B each hit all 32 banks once.
+// Pixel stride of an LDS operand tile, in dwords: the smallest w' >= w with
+// w' = 8 (mod 16). gfx950 serves a 16-byte LDS read per half-wave (32 lanes,
+// 512 B) from 128 dword banks (measured with SQ_LDS_BANK_CONFLICT). An A
+// fragment read has 16 consecutive pixels x 2 chunk groups (+16 B) per half
+// wave; with the stride = 8 (mod 16) the 16 pixel starts are exactly the
+// multiples of 8 dwords mod 128, the second chunk group fills the gaps, and the
+// 128 dwords hit 128 distinct banks.
 __host__ __device__ constexpr int pad_words(int w) {
+  return (w % 16 == 8) ? w : w + ((24 - (w % 16)) % 16);
+}
+// FP8 tiles keep the smaller stride = 4 (mod 8) dwords (a 2-way conflict on A
+// reads): the conflict-free stride doubles their LDS footprint, and the
+// occupancy lost costs more than the conflicts (measured).
+__host__ __device__ constexpr int pad_words_small(int w) {
   return (w % 8 == 4) ? w : w + ((12 - (w % 8)) % 8);
 }
 
@@ -68,7 +79,7 @@ struct Cfg {
   static constexpr int NB = COUT / 16;
   static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
-  static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
+  static constexpr int PSB = (P == FP8 ? pad_words_small(CB * T::BYTES / 4) : pad_words(CB * T::BYTES / 4)) * 4;
   static constexpr int LDS_IN = LR * LC * PSB;
   // BF16 / FP8 outputs leave through LDS so that each tile row is written as
   // contiguous 16-byte stores (FP32 rows already go out in 64-byte segments)
@@ -788,12 +799,17 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
               "conv_mfma_rr<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #MR "," #MC "," #WX "," #WY \
               "," #CBO ">"}
 
-// Flattened-K tile shapes; the first (8 x 64 outputs, 8 waves) measured fastest
-// or within noise of the fastest for every body layer of net B in every
-// precision on MI355X, so it is each signature's default.
-#define EMCNN_SHAPES(P, CIN, COUT, KS, POOL, HEAD)                                             \
-  EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), \
-      EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 4, 64, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
+// Flattened-K tile shapes. The first of each list is the signature's default:
+// the measured fastest on MI355X (16 x 64 outputs with 8 m-blocks per wave for
+// FP32 and BF16 -- halo overhead 1.33x; 8 x 64 with 4 m-blocks for FP8, whose
+// operand tile is half the size and whose occupancy matters more).
+#define EMCNN_SHAPES(P, CIN, COUT, KS, POOL, HEAD)                                                \
+  EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 16, 64, 8), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), \
+      EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 4, 64, 4), \
+      EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
+#define EMCNN_SHAPES_FP8(CIN, COUT, KS, POOL, HEAD)                                                \
+  EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 16, 64, 8), \
+      EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
 
 // Row-reuse tile shapes (MR rows x MC m-blocks per wave, WX x WY waves).
 #define EMCNN_RR_SHAPES(P, CIN, COUT, KS, POOL, HEAD, CBO)                                                 \
@@ -814,10 +830,10 @@ static const VariantInfo kConv[] = {
     EMCNN_RR_SHAPES(BF16, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(BF16, 48, 48, 3, true, true),
     EMCNN_RR_SHAPES(BF16, 48, 48, 3, true, true, 48),
-    EMCNN_SHAPES(FP8, 48, 48, 5, true, false),
+    EMCNN_SHAPES_FP8(48, 48, 5, true, false),
     EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 2, 2, 0),
     EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 4, 1, 0),
-    EMCNN_SHAPES(FP8, 48, 48, 3, true, true),
+    EMCNN_SHAPES_FP8(48, 48, 3, true, true),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)
