@@ -418,7 +418,15 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
       // ---- stage the (TY+KS-1) x (TX+KS-1) input tile of this channel block,
       //      applying the preceding 2x2 stride-1 max filter while loading
       constexpr int NST = C::LR * C::LC * C::NCHB;
-      for (int t = tid; t < NST; t += C::THREADS) {
+      constexpr int NIT = (NST + C::THREADS - 1) / C::THREADS;
+      // BF16: unrolled so that all of a thread's staging loads are in flight
+      // together (measured faster); FP32 / FP8 keep the rolled loop (the
+      // unrolled one costs registers and occupancy there)
+      constexpr int UNR = P == BF16 ? NIT : 1;
+#pragma unroll UNR
+      for (int k = 0; k < NIT; ++k) {
+        const int t = tid + k * C::THREADS;
+        if (t >= NST) break;
         const int cg = t % C::NCHB;
         const int pix = t / C::NCHB;
         const int r = pix / C::LC, c = pix % C::LC;
@@ -637,7 +645,15 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
       constexpr int NST = C::LR * C::LC * C::NCHB;
-      for (int t = tid; t < NST; t += C::THREADS) {
+      constexpr int NIT = (NST + C::THREADS - 1) / C::THREADS;
+      // BF16: unrolled so that all of a thread's staging loads are in flight
+      // together (measured faster); FP32 / FP8 keep the rolled loop (the
+      // unrolled one costs registers and occupancy there)
+      constexpr int UNR = P == BF16 ? NIT : 1;
+#pragma unroll UNR
+      for (int k = 0; k < NIT; ++k) {
+        const int t = tid + k * C::THREADS;
+        if (t >= NST) break;
         const int cg = t % C::NCHB;
         const int pix = t / C::NCHB;
         const int r = pix / C::LC, c = pix % C::LC;
