@@ -230,6 +230,74 @@ __device__ __forceinline__ int find_job(const LayerJob* t, int n, int64_t item) 
   return lo;
 }
 
+// Stage a LR x LC operand tile (NCHB 16-byte chunks per pixel, pixel stride
+// PSB bytes in LDS) whose pixel (r, c) is the stored input at (y0 + r, x0 + c)
+// (coordinates clamped to the logical hp x wp input; clamped values only feed
+// outputs that are never stored). With POOL the operand pixel is the 2x2
+// stride-1 max of the stored (pre-filter) input; each thread then covers a 2x2
+// block of operand pixels of one chunk and loads the 3x3 stored neighbourhood
+// once (9 loads for 4 pixels instead of 16). BF16 unrolls the loop so that all
+// of a thread's loads are in flight together (measured faster); FP32 / FP8 keep
+// it rolled (registers and occupancy).
+template <int P, int LR, int LC, int NCHB, int PSB, int THREADS, bool POOL>
+__device__ __forceinline__ void stage_tile(unsigned char* lds, const unsigned char* in, int64_t rowb, int elb,
+                                           int y0, int x0, int hp, int wp, int tid) {
+  if constexpr (!POOL) {
+    constexpr int NST = LR * LC * NCHB;
+    constexpr int NIT = (NST + THREADS - 1) / THREADS;
+    constexpr int UNR = P == BF16 ? NIT : 1;
+#pragma unroll UNR
+    for (int k = 0; k < NIT; ++k) {
+      const int t = tid + k * THREADS;
+      if (t >= NST) break;
+      const int cg = t % NCHB, pix = t / NCHB;
+      const int r = pix / LC, c = pix % LC;
+      const int y = min(y0 + r, hp - 1), x = min(x0 + c, wp - 1);
+      *reinterpret_cast<i4v*>(lds + pix * PSB + cg * 16) =
+          *reinterpret_cast<const i4v*>(in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16);
+    }
+  } else {
+    static_assert(LR % 2 == 0 && LC % 2 == 0, "2x2 staging blocks need even tile sides");
+    constexpr int BR = LR / 2, BC = LC / 2;
+    constexpr int NST = BR * BC * NCHB;
+    constexpr int NIT = (NST + THREADS - 1) / THREADS;
+    constexpr int UNR = P == BF16 ? NIT : 1;
+#pragma unroll UNR
+    for (int k = 0; k < NIT; ++k) {
+      const int t = tid + k * THREADS;
+      if (t >= NST) break;
+      const int cg = t % NCHB, blk = t / NCHB;
+      const int r = 2 * (blk / BC), c = 2 * (blk % BC);
+      // Operand pixel (r + d, c + e) is the max of stored rows Y_d, Y_d + 1 and
+      // columns X_e, X_e + 1 with Y_d = min(y0 + r + d, hp - 1) (likewise X_e).
+      // Load stored rows Y_0, Y_0 + 1, Y_1 + 1 (and the same for columns): pixel
+      // row 0 uses the first two; pixel row 1 uses the last two, which are Y_1
+      // and Y_1 + 1 whenever row r + 1 is a valid operand row (a clamped row only
+      // feeds outputs that are never stored). All indices stay <= hp (< hin).
+      int ys[3], xs[3];
+      ys[0] = min(y0 + r, hp - 1);
+      ys[1] = ys[0] + 1;
+      ys[2] = min(y0 + r + 1, hp - 1) + 1;
+      xs[0] = min(x0 + c, wp - 1);
+      xs[1] = xs[0] + 1;
+      xs[2] = min(x0 + c + 1, wp - 1) + 1;
+      i4v q[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          q[a][b] = *reinterpret_cast<const i4v*>(in + (int64_t)ys[a] * rowb + (int64_t)xs[b] * elb + cg * 16);
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          i4v v = chunk_max<P>(chunk_max<P>(q[d][e], q[d][e + 1]), chunk_max<P>(q[d + 1][e], q[d + 1][e + 1]));
+          *reinterpret_cast<i4v*>(lds + ((r + d) * LC + c + e) * PSB + cg * 16) = v;
+        }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- first layer
 
 // conv1 (one input channel, KS x KS, KS*KS <= 32 taps) on MFMA. M = 16
@@ -417,29 +485,8 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
       __syncthreads();
       // ---- stage the (TY+KS-1) x (TX+KS-1) input tile of this channel block,
       //      applying the preceding 2x2 stride-1 max filter while loading
-      constexpr int NST = C::LR * C::LC * C::NCHB;
-      constexpr int NIT = (NST + C::THREADS - 1) / C::THREADS;
-      // BF16: unrolled so that all of a thread's staging loads are in flight
-      // together (measured faster); FP32 / FP8 keep the rolled loop (the
-      // unrolled one costs registers and occupancy there)
-      constexpr int UNR = P == BF16 ? NIT : 1;
-#pragma unroll UNR
-      for (int k = 0; k < NIT; ++k) {
-        const int t = tid + k * C::THREADS;
-        if (t >= NST) break;
-        const int cg = t % C::NCHB;
-        const int pix = t / C::NCHB;
-        const int r = pix / C::LC, c = pix % C::LC;
-        const int y = min(y0 + r, hp - 1), x = min(x0 + c, wp - 1);
-        const unsigned char* src = in + (int64_t)y * rowb + (int64_t)x * ELB + (cb * C::CB + cg * T::CHB) * T::BYTES;
-        i4v v = *reinterpret_cast<const i4v*>(src);
-        if constexpr (POOL) {
-          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + ELB));
-          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb));
-          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb + ELB));
-        }
-        *reinterpret_cast<i4v*>(lds + pix * C::PSB + cg * 16) = v;
-      }
+      stage_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS, POOL>(
+          lds, in + (cb * C::CB) * T::BYTES, rowb, ELB, y0, x0, hp, wp, tid);
       __syncthreads();
       // ---- implicit GEMM over this block's (tap, chunk) slots
       const unsigned char* wb = reinterpret_cast<const unsigned char*>(prm.wpack) +
@@ -644,29 +691,8 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
-      constexpr int NST = C::LR * C::LC * C::NCHB;
-      constexpr int NIT = (NST + C::THREADS - 1) / C::THREADS;
-      // BF16: unrolled so that all of a thread's staging loads are in flight
-      // together (measured faster); FP32 / FP8 keep the rolled loop (the
-      // unrolled one costs registers and occupancy there)
-      constexpr int UNR = P == BF16 ? NIT : 1;
-#pragma unroll UNR
-      for (int k = 0; k < NIT; ++k) {
-        const int t = tid + k * C::THREADS;
-        if (t >= NST) break;
-        const int cg = t % C::NCHB;
-        const int pix = t / C::NCHB;
-        const int r = pix / C::LC, c = pix % C::LC;
-        const int y = min(y0 + r, hp - 1), x = min(x0 + c, wp - 1);
-        const unsigned char* src = in + (int64_t)y * rowb + (int64_t)x * ELB + (cb * C::CB + cg * T::CHB) * T::BYTES;
-        i4v v = *reinterpret_cast<const i4v*>(src);
-        if constexpr (POOL) {
-          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + ELB));
-          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb));
-          v = chunk_max<P>(v, *reinterpret_cast<const i4v*>(src + rowb + ELB));
-        }
-        *reinterpret_cast<i4v*>(lds + pix * C::PSB + cg * 16) = v;
-      }
+      stage_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS, POOL>(
+          lds, in + (cb * C::CB) * T::BYTES, rowb, ELB, y0, x0, hp, wp, tid);
       __syncthreads();
       const unsigned char* wb = reinterpret_cast<const unsigned char*>(prm.wpack) +
                                 (size_t)cb * KS * C::NGR * C::NB * 64 * T::U * 16;
@@ -815,17 +841,13 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
               "conv_mfma_rr<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #MR "," #MC "," #WX "," #WY \
               "," #CBO ">"}
 
-// Flattened-K tile shapes. The first of each list is the signature's default:
-// the measured fastest on MI355X (16 x 64 outputs with 8 m-blocks per wave for
-// FP32 and BF16 -- halo overhead 1.33x; 8 x 64 with 4 m-blocks for FP8, whose
-// operand tile is half the size and whose occupancy matters more).
+// Flattened-K tile shapes. The first is each signature's default: 16 x 64
+// outputs with 8 m-blocks per wave (halo overhead 1.33x) measured fastest for
+// the body convs of net B in every precision on MI355X.
 #define EMCNN_SHAPES(P, CIN, COUT, KS, POOL, HEAD)                                                \
   EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 16, 64, 8), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), \
       EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 4, 64, 4), \
       EMCNN_CONV(P, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
-#define EMCNN_SHAPES_FP8(CIN, COUT, KS, POOL, HEAD)                                                \
-  EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 8, 64, 4), EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 16, 64, 8), \
-      EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 8, 32, 4), EMCNN_CONV(FP8, CIN, COUT, KS, POOL, HEAD, 8, 32, 2)
 
 // Row-reuse tile shapes (MR rows x MC m-blocks per wave, WX x WY waves).
 #define EMCNN_RR_SHAPES(P, CIN, COUT, KS, POOL, HEAD, CBO)                                                 \
@@ -846,10 +868,10 @@ static const VariantInfo kConv[] = {
     EMCNN_RR_SHAPES(BF16, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(BF16, 48, 48, 3, true, true),
     EMCNN_RR_SHAPES(BF16, 48, 48, 3, true, true, 48),
-    EMCNN_SHAPES_FP8(48, 48, 5, true, false),
+    EMCNN_SHAPES(FP8, 48, 48, 5, true, false),
     EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 2, 2, 0),
     EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 4, 1, 0),
-    EMCNN_SHAPES_FP8(48, 48, 3, true, true),
+    EMCNN_SHAPES(FP8, 48, 48, 3, true, true),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)
