@@ -9,10 +9,13 @@ enum Prec : int { F32 = 0, BF16 = 1, FP8 = 2 };
 
 // One 3-D activation volume processed by one layer launch.
 //
-// Activations between layers are NHWC: element (z, y, x, c) of a C-channel
-// tensor lives at ((z * zs) + y * rs + x) * C + c, with rs / zs in pixels.
-// The first layer reads the caller's uint8 volume with the same addressing
-// (C = 1); the head layer writes float32 probabilities (C = 1).
+// Activations between layers: FP32 nets use NHWC, element (z, y, x, c) of a
+// C-channel tensor at ((z * zs) + y * rs + x) * C + c; BF16 / FP8 nets use the
+// channel-blocked layout, the same element at z*zs*C + (c/16)*zs*16 +
+// (y*rs + x)*16 + c%16 (rs / zs in pixels in both). A slice occupies zs*C
+// elements either way. The first layer reads the caller's uint8 volume with
+// the same addressing (C = 1); the head layer writes float32 probabilities
+// (C = 1).
 //
 // (hin, win) are the dims of the STORED input. When the layer pools its input
 // (a 2x2 stride-1 max filter sits between the previous conv and this one) the

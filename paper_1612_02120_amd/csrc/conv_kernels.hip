@@ -6,15 +6,18 @@
 // convolution over the whole slice and no pixel is computed twice.
 //
 // Kernels here:
-//   conv_first  - the 1-channel first layer on the VALU, reading the caller's
+//   conv_first  - the 1-channel first layer on MFMA, reading the caller's
 //                 uint8 volume (1/255 is folded into its weights on the host).
-//   conv_mfma   - every later conv as an implicit GEMM on MFMA: M = output
+//   conv_mfma   - every later FP32 conv as an implicit GEMM on MFMA: M = output
 //                 pixels (16 consecutive pixels of a row per m-block), N = output
 //                 channels (16 per n-block), K = (tap, input channel).
 //                 The input tile plus halo is staged in LDS, the preceding 2x2
 //                 stride-1 max filter is applied while staging, and bias, ReLU and
 //                 the output cast (or the 1x1 head and sigmoid) are fused into the
-//                 epilogue.
+//                 epilogue. conv_mfma_rr is the same layer with a row-reuse K order.
+//   conv_ws     - the BF16 / FP8 convs: the same implicit GEMM, warp-specialised
+//                 (producer waves stage the next tile while consumer waves run
+//                 MFMA) over channel-blocked activations.
 //
 // Both are persistent: a grid of a multiple of 8 workgroups walks the work
 // items (z, tile_y, tile_x) of one or many jobs. Workgroups are dispatched to
@@ -32,6 +35,34 @@ typedef int i4v __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned char u8x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
+// Global-memory access. Pointers read from job tables and parameter structs
+// are generic to the compiler, which then emits FLAT instructions; a FLAT load
+// also counts against the LDS wait counter, so every wait for an LDS read
+// would wait for it as well. Accesses through these global-address-space
+// pointers compile to global_load / global_store (vector memory counter only).
+#define EMCNN_GLOBAL __attribute__((address_space(1)))
+typedef EMCNN_GLOBAL unsigned char gbyte;
+__device__ __forceinline__ const gbyte* gin(const void* p) { return (const gbyte*)p; }
+__device__ __forceinline__ gbyte* gout(void* p) { return (gbyte*)p; }
+template <class V>
+__device__ __forceinline__ V ld(const unsigned char* p) {
+  return *reinterpret_cast<const V*>(p);
+}
+template <class V>
+__device__ __forceinline__ V ld(const gbyte* p) {
+  return *reinterpret_cast<const EMCNN_GLOBAL V*>(p);
+}
+template <class V>
+__device__ __forceinline__ void st(unsigned char* p, V v) {
+  *reinterpret_cast<V*>(p) = v;
+}
+template <class V>
+__device__ __forceinline__ void st(gbyte* p, V v) {
+  *reinterpret_cast<EMCNN_GLOBAL V*>(p) = v;
+}
+__device__ __forceinline__ float ldf(const float* p, int i) { return ld<float>(gin(p) + (int64_t)i * 4); }
 
 template <int P>
 struct PT;
@@ -110,19 +141,12 @@ __device__ __forceinline__ unsigned char to_e4m3(float v) {
   return (unsigned char)(packed & 0xff);
 }
 
-template <int P>
-__device__ __forceinline__ void store_act(void* base, int64_t idx, float v, float inv);
-template <>
-__device__ __forceinline__ void store_act<F32>(void* base, int64_t idx, float v, float) {
-  reinterpret_cast<float*>(base)[idx] = v;
-}
-template <>
-__device__ __forceinline__ void store_act<BF16>(void* base, int64_t idx, float v, float) {
-  reinterpret_cast<__bf16*>(base)[idx] = (__bf16)v;
-}
-template <>
-__device__ __forceinline__ void store_act<FP8>(void* base, int64_t idx, float v, float inv) {
-  reinterpret_cast<unsigned char*>(base)[idx] = to_e4m3(v * inv);
+// Store element idx of an activation array (LDS or global) in the layer's format.
+template <int P, class B>
+__device__ __forceinline__ void store_act(B* base, int64_t idx, float v, float inv) {
+  if constexpr (P == F32) st<float>(base + idx * 4, v);
+  else if constexpr (P == BF16) st<__bf16>(base + idx * 2, (__bf16)v);
+  else st<unsigned char>(base + idx, to_e4m3(v * inv));
 }
 
 // Elementwise max of two 16-byte chunks of non-negative activations. For
@@ -145,10 +169,21 @@ __device__ __forceinline__ i4v chunk_max<BF16>(i4v a, i4v b) {
   u16x8 x = __builtin_bit_cast(u16x8, a), y = __builtin_bit_cast(u16x8, b);
   return __builtin_bit_cast(i4v, __builtin_elementwise_max(x, y));
 }
+// e4m3fn codes of non-negative values are 0x00..0x7e (bit 7 clear), so a
+// per-byte a - b + 128 never borrows across bytes and its bit 7 is (a >= b).
+__device__ __forceinline__ uint32_t max_u7x4(uint32_t a, uint32_t b) {
+  const uint32_t hm = ((a | 0x80808080u) - b) & 0x80808080u;  // 0x80 per byte where a >= b
+  const uint32_t m = hm | (hm - (hm >> 7));                   // 0xff per byte where a >= b
+  return (a & m) | (b & ~m);
+}
 template <>
 __device__ __forceinline__ i4v chunk_max<FP8>(i4v a, i4v b) {
-  u8x16 x = __builtin_bit_cast(u8x16, a), y = __builtin_bit_cast(u8x16, b);
-  return __builtin_bit_cast(i4v, __builtin_elementwise_max(x, y));
+  i4v r;
+  r[0] = (int)max_u7x4((uint32_t)a[0], (uint32_t)b[0]);
+  r[1] = (int)max_u7x4((uint32_t)a[1], (uint32_t)b[1]);
+  r[2] = (int)max_u7x4((uint32_t)a[2], (uint32_t)b[2]);
+  r[3] = (int)max_u7x4((uint32_t)a[3], (uint32_t)b[3]);
+  return r;
 }
 
 template <int P>
@@ -186,21 +221,18 @@ __device__ __forceinline__ void mma<FP8>(f4& acc, const Frag<FP8>& a, const Frag
   acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, acc, 0, 0, 0, 127, 0, 127);
 }
 
-template <int P>
-__device__ __forceinline__ void load_frag(Frag<P>& f, const unsigned char* p0, const unsigned char* p1);
-template <>
-__device__ __forceinline__ void load_frag<F32>(Frag<F32>& f, const unsigned char* p0, const unsigned char*) {
-  f.v = *reinterpret_cast<const f4*>(p0);
-}
-template <>
-__device__ __forceinline__ void load_frag<BF16>(Frag<BF16>& f, const unsigned char* p0, const unsigned char*) {
-  f.v = *reinterpret_cast<const bf16x8*>(p0);
-}
-template <>
-__device__ __forceinline__ void load_frag<FP8>(Frag<FP8>& f, const unsigned char* p0, const unsigned char* p1) {
-  i4v lo = *reinterpret_cast<const i4v*>(p0);
-  i4v hi = *reinterpret_cast<const i4v*>(p1);
-  f.v = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+// Load an MFMA operand fragment (16 bytes per lane, FP8: two 16-byte chunks)
+// from LDS or global memory.
+template <int P, class B>
+__device__ __forceinline__ void load_frag(Frag<P>& f, const B* p0, const B* p1) {
+  if constexpr (P == F32) {
+    f.v = ld<f4>(p0);
+  } else if constexpr (P == BF16) {
+    f.v = ld<bf16x8>(p0);
+  } else {
+    const i4v lo = ld<i4v>(p0), hi = ld<i4v>(p1);
+    f.v = i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
 }
 
 // Persistent work distribution: workgroup b serves XCD b % 8 (hardware
@@ -220,7 +252,12 @@ __device__ __forceinline__ ItemRange item_range(int64_t total) {
   return {begin + (b >> 3), end, G >> 3};
 }
 
-__device__ __forceinline__ int find_job(const LayerJob* t, int n, int64_t item) {
+__device__ __forceinline__ const EMCNN_GLOBAL LayerJob* gtab(const LayerJob* t) {
+  return (const EMCNN_GLOBAL LayerJob*)t;
+}
+
+__device__ __forceinline__ int find_job(const LayerJob* table, int n, int64_t item) {
+  const EMCNN_GLOBAL LayerJob* t = gtab(table);
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -228,6 +265,23 @@ __device__ __forceinline__ int find_job(const LayerJob* t, int n, int64_t item) 
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Job of a work item: advance the cursor through the table (items ascend).
+__device__ __forceinline__ LayerJob job_at(const JobSet& js, int& cur, int64_t item) {
+  if (!js.table) return js.single;
+  const EMCNN_GLOBAL LayerJob* t = gtab(js.table);
+  while (cur + 1 < js.njobs && t[cur + 1].item0 <= item) ++cur;
+  static_assert(sizeof(LayerJob) % 16 == 0, "job copied in 16-byte chunks");
+  LayerJob J;
+  const gbyte* src = reinterpret_cast<const gbyte*>(t + cur);
+#pragma unroll
+  for (int k = 0; k < (int)sizeof(LayerJob) / 16; ++k) reinterpret_cast<i4v*>(&J)[k] = ld<i4v>(src + 16 * k);
+  return J;
+}
+
+__device__ __forceinline__ bool gated_off(const LayerJob& J) {
+  return J.gate && *(const EMCNN_GLOBAL int32_t*)J.gate == 0;
 }
 
 // Stage a LR x LC operand tile (NCHB 16-byte chunks per pixel, pixel stride
@@ -240,7 +294,7 @@ __device__ __forceinline__ int find_job(const LayerJob* t, int n, int64_t item) 
 // of a thread's loads are in flight together (measured faster); FP32 / FP8 keep
 // it rolled (registers and occupancy).
 template <int P, int LR, int LC, int NCHB, int PSB, int THREADS, bool POOL>
-__device__ __forceinline__ void stage_tile(unsigned char* lds, const unsigned char* in, int64_t rowb, int elb,
+__device__ __forceinline__ void stage_tile(unsigned char* lds, const gbyte* in, int64_t rowb, int elb,
                                            int y0, int x0, int hp, int wp, int tid) {
   if constexpr (!POOL) {
     constexpr int NST = LR * LC * NCHB;
@@ -253,8 +307,7 @@ __device__ __forceinline__ void stage_tile(unsigned char* lds, const unsigned ch
       const int cg = t % NCHB, pix = t / NCHB;
       const int r = pix / LC, c = pix % LC;
       const int y = min(y0 + r, hp - 1), x = min(x0 + c, wp - 1);
-      *reinterpret_cast<i4v*>(lds + pix * PSB + cg * 16) =
-          *reinterpret_cast<const i4v*>(in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16);
+      st<i4v>(lds + pix * PSB + cg * 16, ld<i4v>(in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16));
     }
   } else {
     static_assert(LR % 2 == 0 && LC % 2 == 0, "2x2 staging blocks need even tile sides");
@@ -286,7 +339,7 @@ __device__ __forceinline__ void stage_tile(unsigned char* lds, const unsigned ch
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-          q[a][b] = *reinterpret_cast<const i4v*>(in + (int64_t)ys[a] * rowb + (int64_t)xs[b] * elb + cg * 16);
+          q[a][b] = ld<i4v>(in + (int64_t)ys[a] * rowb + (int64_t)xs[b] * elb + cg * 16);
 #pragma unroll
       for (int d = 0; d < 2; ++d)
 #pragma unroll
@@ -308,11 +361,13 @@ __device__ __forceinline__ void stage_tile(unsigned char* lds, const unsigned ch
 // 4s+g of step s. Weights are pre-packed per lane (wpack, see the host).
 // The epilogue applies bias and ReLU, casts to the stored activation format,
 // stages the whole output tile in LDS and writes each tile row as one
-// contiguous run of 16-byte stores (NHWC rows are contiguous in memory).
+// contiguous run of 16-byte stores: FP32 output is NHWC (a tile row is one
+// run), BF16 / FP8 output is channel-blocked (one run per 16-channel plane).
 template <int PO, int COUT, int KS, int TY, int TX>
 struct FirstCfg {
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
   static constexpr int ESZ = PO == F32 ? 4 : PO == BF16 ? 2 : 1;
+  static constexpr bool BLOCKED = PO != F32;  // BF16 / FP8 activations are channel-blocked
   static constexpr int NB = COUT / 16;
   static constexpr int MBLK = TY * TX / 16;
   static constexpr int WAVES = 4;
@@ -338,41 +393,35 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
   // per-lane weight fragments and bias
   Frag<PO == F32 ? F32 : BF16> wf[C::NSTEP][C::NB];
   {
-    const unsigned char* wp = reinterpret_cast<const unsigned char*>(prm.w);
+    const gbyte* wp = gin(prm.w);
 #pragma unroll
     for (int s = 0; s < C::NSTEP; ++s)
 #pragma unroll
       for (int nb = 0; nb < C::NB; ++nb) {
         if constexpr (PO == F32) {
-          wf[s][nb].v = f4{reinterpret_cast<const float*>(wp)[(s * C::NB + nb) * 64 + lane], 0.f, 0.f, 0.f};
+          wf[s][nb].v = f4{ld<float>(wp + ((s * C::NB + nb) * 64 + lane) * 4), 0.f, 0.f, 0.f};
         } else {
-          wf[s][nb].v = *reinterpret_cast<const bf16x8*>(wp + ((size_t)(s * C::NB + nb) * 64 + lane) * 16);
+          wf[s][nb].v = ld<bf16x8>(wp + ((size_t)(s * C::NB + nb) * 64 + lane) * 16);
         }
       }
   }
   float bias[C::NB];
 #pragma unroll
-  for (int nb = 0; nb < C::NB; ++nb) bias[nb] = prm.bias[nb * 16 + n16];
+  for (int nb = 0; nb < C::NB; ++nb) bias[nb] = ldf(prm.bias, nb * 16 + n16);
 
   const ItemRange rg = item_range(js.total_items);
   int cur = 0;
   if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
   for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
-    LayerJob J;
-    if (js.table) {
-      while (cur + 1 < js.njobs && js.table[cur + 1].item0 <= item) ++cur;
-      J = js.table[cur];
-    } else {
-      J = js.single;
-    }
-    if (J.gate && *J.gate == 0) continue;
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
     const int64_t local = item - J.item0;
     const int bx = (int)(local % J.tiles_x);
     const int64_t t2 = local / J.tiles_x;
     const int by = (int)(t2 % J.tiles_y);
     const int zz = (int)(t2 / J.tiles_y);
     const int y0 = by * TY, x0 = bx * TX;
-    const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs;
+    const gbyte* in = gin(J.in) + (int64_t)zz * J.in_zs;
     __syncthreads();
     for (int t = tid; t < C::LR * C::LC; t += C::THREADS) {
       const int r = t / C::LC, c = t % C::LC;
@@ -415,21 +464,38 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
         for (int k = 0; k < 4; ++k) {
           const int pix = mrow * TX + mcol * 16 + 4 * g + k;
           const float v = relu(acc[nb][k] + bias[nb]);
-          store_act<PO>(obuf, (int64_t)pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+          const int64_t idx = C::BLOCKED ? ((int64_t)nb * TY * TX + pix) * 16 + n16 : (int64_t)pix * COUT + nb * 16 + n16;
+          store_act<PO>(obuf, idx, v, prm.out_inv_scale);
         }
     }
     __syncthreads();
-    // coalesced copy-out: each tile row is a contiguous NHWC run in global memory
+    // coalesced copy-out
     const int vcols = min(TX, J.wout - x0);
-    constexpr int ROWB = TX * COUT * C::ESZ;
-    const int vbytes = vcols * COUT * C::ESZ;  // multiple of 16
-    for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
-      const int r = t / (ROWB / 16), q = t % (ROWB / 16);
-      const int y = y0 + r;
-      if (y < J.hout && q * 16 < vbytes) {
-        unsigned char* dst = reinterpret_cast<unsigned char*>(J.out) +
-                             (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * C::ESZ + q * 16;
-        *reinterpret_cast<i4v*>(dst) = *reinterpret_cast<const i4v*>(obuf + r * ROWB + q * 16);
+    gbyte* oslice = gout(J.out) + (int64_t)zz * J.out_zs * COUT * C::ESZ;
+    if constexpr (!C::BLOCKED) {
+      // NHWC: each tile row is one contiguous run
+      constexpr int ROWB = TX * COUT * C::ESZ;
+      const int vbytes = vcols * COUT * C::ESZ;  // multiple of 16
+      for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
+        const int r = t / (ROWB / 16), q = t % (ROWB / 16);
+        const int y = y0 + r;
+        if (y < J.hout && q * 16 < vbytes) {
+          st<i4v>(oslice + ((int64_t)y * J.out_rs + x0) * COUT * C::ESZ + q * 16, ld<i4v>(obuf + r * ROWB + q * 16));
+        }
+      }
+    } else {
+      // channel-blocked: each (plane, tile row) is one contiguous run
+      constexpr int ROWB = TX * 16 * C::ESZ;
+      const int vbytes = vcols * 16 * C::ESZ;  // multiple of 16
+      const int64_t plane_b = J.out_zs * 16 * C::ESZ;
+      for (int t = tid; t < C::NB * TY * (ROWB / 16); t += C::THREADS) {
+        const int q = t % (ROWB / 16), rr = t / (ROWB / 16);
+        const int r = rr % TY, nb = rr / TY;
+        const int y = y0 + r;
+        if (y < J.hout && q * 16 < vbytes) {
+          st<i4v>(oslice + nb * plane_b + ((int64_t)y * J.out_rs + x0) * 16 * C::ESZ + q * 16,
+                  ld<i4v>(obuf + (nb * TY + r) * ROWB + q * 16));
+        }
       }
     }
   }
@@ -457,14 +523,8 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
   int cur = 0;
   if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
   for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
-    LayerJob J;
-    if (js.table) {
-      while (cur + 1 < js.njobs && js.table[cur + 1].item0 <= item) ++cur;
-      J = js.table[cur];
-    } else {
-      J = js.single;
-    }
-    if (J.gate && *J.gate == 0) continue;
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
     const int64_t local = item - J.item0;
     const int bx = (int)(local % J.tiles_x);
     const int64_t t2 = local / J.tiles_x;
@@ -472,7 +532,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
     const int zz = (int)(t2 / J.tiles_y);
     const int y0 = by * TY, x0 = bx * TX;
     const int hp = J.hin - (POOL ? 1 : 0), wp = J.win - (POOL ? 1 : 0);  // logical input dims
-    const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs * ELB;
+    const gbyte* in = gin(J.in) + (int64_t)zz * J.in_zs * ELB;
     const int64_t rowb = J.in_rs * ELB;
 
     f4 acc[MW][C::NB];
@@ -489,14 +549,14 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
           lds, in + (cb * C::CB) * T::BYTES, rowb, ELB, y0, x0, hp, wp, tid);
       __syncthreads();
       // ---- implicit GEMM over this block's (tap, chunk) slots
-      const unsigned char* wb = reinterpret_cast<const unsigned char*>(prm.wpack) +
+      const gbyte* wb = gin(prm.wpack) +
                                 (size_t)cb * C::NGS * C::NB * 64 * T::U * 16;
 #pragma unroll 2
       for (int s = 0; s < C::NGS; ++s) {
         Frag<P> bfr[C::NB];
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
-          const unsigned char* p = wb + ((size_t)(s * C::NB + nb) * 64 + lane) * (T::U * 16);
+          const gbyte* p = wb + ((size_t)(s * C::NB + nb) * 64 + lane) * (T::U * 16);
           load_frag<P>(bfr[nb], p, p + 16);
         }
         int off[T::U];
@@ -527,9 +587,9 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
     float bias[C::NB], osc[C::NB], hw[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) {
-      bias[nb] = prm.bias[nb * 16 + n16];
-      osc[nb] = prm.oscale ? prm.oscale[nb * 16 + n16] : 1.0f;
-      if constexpr (HEAD) hw[nb] = prm.head_w[nb * 16 + n16];
+      bias[nb] = ldf(prm.bias, nb * 16 + n16);
+      osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
+      if constexpr (HEAD) hw[nb] = ldf(prm.head_w, nb * 16 + n16);
     }
 #pragma unroll
     for (int u = 0; u < MW; ++u) {
@@ -554,7 +614,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
           const int x = xb + n16;
           const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
           if (y < J.hout && x < J.wout)
-            reinterpret_cast<float*>(J.out)[(int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x] = sigmoid_f(zl);
+            st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
         }
       } else if constexpr (C::STAGE_OUT) {
 #pragma unroll
@@ -576,7 +636,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
 #pragma unroll
               for (int nb = 0; nb < C::NB; ++nb) {
                 const float v = relu(fmaf(acc[u][nb][k], osc[nb], bias[nb]));
-                store_act<P>(J.out, pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+                store_act<P>(gout(J.out), pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
               }
             }
           }
@@ -592,9 +652,8 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
         const int r = t / (ROWB / 16), q = t % (ROWB / 16);
         const int y = y0 + r;
         if (y < J.hout && q * 16 < vbytes) {
-          unsigned char* dst = reinterpret_cast<unsigned char*>(J.out) +
-                               (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
-          *reinterpret_cast<i4v*>(dst) = *reinterpret_cast<const i4v*>(lds + r * ROWB + q * 16);
+          gbyte* dst = gout(J.out) + (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
+          st<i4v>(dst, ld<i4v>(lds + r * ROWB + q * 16));
         }
       }
     }
@@ -663,14 +722,8 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
   int cur = 0;
   if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
   for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
-    LayerJob J;
-    if (js.table) {
-      while (cur + 1 < js.njobs && js.table[cur + 1].item0 <= item) ++cur;
-      J = js.table[cur];
-    } else {
-      J = js.single;
-    }
-    if (J.gate && *J.gate == 0) continue;
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
     const int64_t local = item - J.item0;
     const int bx = (int)(local % J.tiles_x);
     const int64_t t2 = local / J.tiles_x;
@@ -678,7 +731,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
     const int zz = (int)(t2 / J.tiles_y);
     const int y0 = by * TY, x0 = bx * TX;
     const int hp = J.hin - (POOL ? 1 : 0), wp = J.win - (POOL ? 1 : 0);
-    const unsigned char* in = reinterpret_cast<const unsigned char*>(J.in) + (int64_t)zz * J.in_zs * ELB;
+    const gbyte* in = gin(J.in) + (int64_t)zz * J.in_zs * ELB;
     const int64_t rowb = J.in_rs * ELB;
 
     f4 acc[MR][MC][C::NB];
@@ -694,7 +747,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
       stage_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS, POOL>(
           lds, in + (cb * C::CB) * T::BYTES, rowb, ELB, y0, x0, hp, wp, tid);
       __syncthreads();
-      const unsigned char* wb = reinterpret_cast<const unsigned char*>(prm.wpack) +
+      const gbyte* wb = gin(prm.wpack) +
                                 (size_t)cb * KS * C::NGR * C::NB * 64 * T::U * 16;
       const unsigned char* abase = lds + ((wy * MR) * C::LC + wx * MC * 16 + n16) * C::PSB;
       for (int rs = 0; rs < C::NGR; ++rs) {
@@ -703,7 +756,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
         for (int i = 0; i < KS; ++i)
 #pragma unroll
           for (int nb = 0; nb < C::NB; ++nb) {
-            const unsigned char* p = wb + ((size_t)((i * C::NGR + rs) * C::NB + nb) * 64 + lane) * (T::U * 16);
+            const gbyte* p = wb + ((size_t)((i * C::NGR + rs) * C::NB + nb) * 64 + lane) * (T::U * 16);
             load_frag<P>(bfr[i][nb], p, p + 16);
           }
         int o0 = coff[0][0], o1 = coff[0][T::U - 1];
@@ -737,9 +790,9 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
     float bias[C::NB], osc[C::NB], hw[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) {
-      bias[nb] = prm.bias[nb * 16 + n16];
-      osc[nb] = prm.oscale ? prm.oscale[nb * 16 + n16] : 1.0f;
-      if constexpr (HEAD) hw[nb] = prm.head_w[nb * 16 + n16];
+      bias[nb] = ldf(prm.bias, nb * 16 + n16);
+      osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
+      if constexpr (HEAD) hw[nb] = ldf(prm.head_w, nb * 16 + n16);
     }
 #pragma unroll
     for (int r = 0; r < MR; ++r)
@@ -764,7 +817,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
             const int x = xb + n16;
             const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
             if (y < J.hout && x < J.wout)
-              reinterpret_cast<float*>(J.out)[(int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x] = sigmoid_f(zl);
+              st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
           }
         } else if constexpr (C::STAGE_OUT) {
 #pragma unroll
@@ -786,7 +839,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 #pragma unroll
                 for (int nb = 0; nb < C::NB; ++nb) {
                   const float v = relu(fmaf(acc[r][m][nb][k], osc[nb], bias[nb]));
-                  store_act<P>(J.out, pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
+                  store_act<P>(gout(J.out), pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
                 }
               }
             }
@@ -802,11 +855,419 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
         const int r = t / (ROWB / 16), q = t % (ROWB / 16);
         const int y = y0 + r;
         if (y < J.hout && q * 16 < vbytes) {
-          unsigned char* dst = reinterpret_cast<unsigned char*>(J.out) +
-                               (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
-          *reinterpret_cast<i4v*>(dst) = *reinterpret_cast<const i4v*>(lds + r * ROWB + q * 16);
+          gbyte* dst = gout(J.out) + (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
+          st<i4v>(dst, ld<i4v>(lds + r * ROWB + q * 16));
         }
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pipelined MFMA conv (BF16 / FP8)
+
+// BF16 and FP8 activations are channel-blocked: element (z, y, x, c) of a
+// C-channel tensor lives at z*zs*C + (c/16)*zs*16 + (y*rs + x)*16 + c%16
+// (elements; rs, zs in pixels). A 16-channel plane pixel is 32 B (BF16) or
+// 16 B (FP8), so a stage of 16 channels reads whole contiguous rows, and the
+// epilogue writes each (m-block, n-block) as one 512 B / 256 B run.
+//
+// conv_ws is warp-specialised. NCW consumer waves run the implicit GEMM of
+// conv_mfma with both operands in LDS; NPW producer waves fill the LDS. A
+// stage is (tile, channel block): its operand tile (max filter applied) and,
+// for BF16 layers whose packed weights do not fit in LDS next to two operand
+// buffers, its weight slice. BF16 weights that fit are copied to LDS once per
+// workgroup; FP8 consumers read weights through the L1. Stages are double-buffered with one workgroup barrier per stage,
+// and the producers issue the global loads of stage k+1 before that barrier,
+// so the load latency overlaps a whole stage of MFMA work.
+
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int NCW, int NPW>
+struct CfgWS {
+  using T = PT<P>;
+  // channels per stage: 16 (one plane) for BF16; all of CIN for FP8, whose
+  // 128-deep MFMA needs the longer K of a stage to stay filled
+  static constexpr int CB = P == FP8 ? CIN : 16;
+  static_assert(CIN % 16 == 0 && CIN % CB == 0, "channels must be whole planes");
+  static constexpr int NCB = CIN / CB;       // stages per tile
+  static constexpr int NCHB = CB / T::CHB;   // 16-byte chunks per operand pixel
+  static constexpr int NCHK = KS * KS * NCHB;
+  static constexpr int SLOTS = 4 * T::U;
+  static constexpr int NGS = (NCHK + SLOTS - 1) / SLOTS;
+  static constexpr int NB = COUT / 16;
+  static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
+  static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  static constexpr int PSB = (P == FP8 ? pad_words_small(CB * T::BYTES / 4) : pad_words(CB * T::BYTES / 4)) * 4;
+  static constexpr int BUF = LR * LC * PSB;                // one operand buffer
+  static constexpr int WB = NGS * NB * 64 * T::U * 16;     // packed weights of one stage
+  static constexpr int LDS_MAX = 160 * 1024;
+  // BF16 consumers read B fragments from LDS. FP8 fragments are two 16-byte
+  // reads each, and B from LDS on top of A would oversubscribe the LDS
+  // (measured slower), so FP8 consumers read B through the L1.
+  static constexpr bool BL = P != FP8;
+  static constexpr bool WRES = BL && 2 * BUF + NCB * WB <= LDS_MAX;  // all weights resident in LDS
+  static constexpr int WOFF = 2 * BUF;
+  static constexpr int LDS = 2 * BUF + (!BL ? 0 : WRES ? NCB * WB : 2 * WB);
+  static constexpr int MBLK = TY * TX / 16;
+  static_assert(TX % 16 == 0, "TX must be a multiple of 16");
+  static_assert(MBLK % NCW == 0, "m-blocks must split evenly over consumer waves");
+  static constexpr int MW = MBLK / NCW;
+  static_assert(MW % (TX / 16) == 0, "each consumer wave owns whole tile rows");
+  static constexpr int WROWS = MW / (TX / 16);  // tile rows per consumer wave
+  static constexpr int THREADS = (NCW + NPW) * 64;
+  static_assert(THREADS <= 1024, "workgroup size limit");
+  static_assert(LDS <= LDS_MAX, "LDS budget of a gfx950 workgroup");
+};
+
+// Walk of the work items of one workgroup (see item_range), skipping items
+// of gated-off jobs. Every wave of the workgroup walks the same sequence.
+struct TileWalk {
+  int64_t item, end, step;
+  int cur;
+  LayerJob J;
+  __device__ void init(const JobSet& js, const ItemRange& rg) {
+    item = rg.begin - rg.step;
+    end = rg.end;
+    step = rg.step;
+    cur = 0;
+    if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  }
+  __device__ bool next(const JobSet& js) {
+    for (item += step; item < end; item += step) {
+      J = job_at(js, cur, item);
+      if (gated_off(J)) continue;
+      return true;
+    }
+    return false;
+  }
+  // tile origin and slice of the current item
+  template <int TY, int TX>
+  __device__ void coords(int& zz, int& y0, int& x0) const {
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    y0 = (int)(t2 % J.tiles_y) * TY;
+    x0 = bx * TX;
+    zz = (int)(t2 / J.tiles_y);
+  }
+};
+
+// One stage's operand tile held in producer registers between its global
+// loads and its LDS writes. Chunk cg of an operand pixel holds channels
+// c0 + cg*CHB .. +CHB-1, read from plane c / 16 at byte offset
+// ((c % 16) / CHB) * 16 of the plane pixel. With POOL a thread item is a 2x2
+// block of operand pixels of one chunk, loaded as its 3x3 stored
+// neighbourhood (see stage_tile for the clamping); without it, one pixel.
+template <int P, int LR, int LC, int NCHB, int PSB, int NPT, bool POOL>
+struct AStage {
+  using T = PT<P>;
+  static constexpr int PB = 16 * T::BYTES;
+  static constexpr int NST = POOL ? (LR / 2) * (LC / 2) * NCHB : LR * LC * NCHB;
+  static constexpr int NIT = (NST + NPT - 1) / NPT;
+  static constexpr int NL = POOL ? 9 : 1;
+  i4v q[NIT][NL];
+
+  __device__ __forceinline__ void load(const gbyte* slice, int64_t plane_b, int64_t rowb, int c0, int y0,
+                                       int x0, int hp, int wp, int ptid) {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < NST) {
+        const int cg = t % NCHB, it = t / NCHB;
+        const int c = c0 + cg * T::CHB;
+        const gbyte* base = slice + (c >> 4) * plane_b + ((c & 15) / T::CHB) * 16;
+        if constexpr (POOL) {
+          static_assert(LR % 2 == 0 && LC % 2 == 0, "2x2 staging blocks need even tile sides");
+          const int r = 2 * (it / (LC / 2)), cc = 2 * (it % (LC / 2));
+          int ys[3], xs[3];
+          ys[0] = min(y0 + r, hp - 1);
+          ys[1] = ys[0] + 1;
+          ys[2] = min(y0 + r + 1, hp - 1) + 1;
+          xs[0] = min(x0 + cc, wp - 1);
+          xs[1] = xs[0] + 1;
+          xs[2] = min(x0 + cc + 1, wp - 1) + 1;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+              q[k][a * 3 + b] = ld<i4v>(base + (int64_t)ys[a] * rowb + (int64_t)xs[b] * PB);
+        } else {
+          const int r = it / LC, cc = it % LC;
+          const int y = min(y0 + r, hp - 1), x = min(x0 + cc, wp - 1);
+          q[k][0] = ld<i4v>(base + (int64_t)y * rowb + (int64_t)x * PB);
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(unsigned char* lds, int ptid) const {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < NST) {
+        const int cg = t % NCHB, it = t / NCHB;
+        if constexpr (POOL) {
+          const int r = 2 * (it / (LC / 2)), cc = 2 * (it % (LC / 2));
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const i4v v = chunk_max<P>(chunk_max<P>(q[k][d * 3 + e], q[k][d * 3 + e + 1]),
+                                         chunk_max<P>(q[k][(d + 1) * 3 + e], q[k][(d + 1) * 3 + e + 1]));
+              *reinterpret_cast<i4v*>(lds + ((r + d) * LC + cc + e) * PSB + cg * 16) = v;
+            }
+        } else {
+          *reinterpret_cast<i4v*>(lds + it * PSB + cg * 16) = q[k][0];
+        }
+      }
+    }
+  }
+};
+
+// A contiguous block of BYTES bytes (packed weights) held in producer
+// registers between its global loads and its LDS writes.
+template <int BYTES, int NPT>
+struct WStage {
+  static constexpr int N = BYTES / 16;
+  static_assert(N * 16 == BYTES, "whole 16-byte chunks");
+  static constexpr int NIT = (N + NPT - 1) / NPT;
+  i4v v[NIT];
+  __device__ __forceinline__ void load(const gbyte* src, int ptid) {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < N) v[k] = ld<i4v>(src + (int64_t)t * 16);
+    }
+  }
+  __device__ __forceinline__ void store(unsigned char* dst, int ptid) const {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < N) reinterpret_cast<i4v*>(dst)[t] = v[k];
+    }
+  }
+};
+
+// Lane exchange inside groups of 4 lanes (DPP quad permutation).
+template <int CTRL>
+__device__ __forceinline__ int quad_perm(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kQuadXor1 = 0xB1;  // lanes [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // lanes [2, 3, 0, 1]
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const __bf16 a = (__bf16)lo, b = (__bf16)hi;
+  return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+}
+
+__device__ __forceinline__ uint32_t pack_e4m3x2(float lo, float hi) {
+  // non-negative inputs; saturate at the largest finite e4m3fn value
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(lo, 448.0f), fminf(hi, 448.0f), 0, false) & 0xffffu;
+}
+
+// Store one (m-block, n-block) accumulator tile in the channel-blocked layout.
+// Lane (g, n) holds channel n of pixels 4g..4g+3. Two quad exchanges leave
+// lane (g, n) with channels 4(n/4)..4(n/4)+3 of pixel 4g + n%4, so the 64
+// lanes write 16 consecutive plane pixels (one contiguous run).
+template <int P>
+__device__ __forceinline__ void store_block_tile(gbyte* plane_row, int pm_ok, const float (&v)[4], int n16,
+                                                 float inv) {
+  const int b0 = n16 & 1, b1 = (n16 >> 1) & 1, q = n16 >> 2;
+  const float s0 = b0 ? v[0] : v[1], s1 = b0 ? v[2] : v[3];
+  const float r0 = __builtin_bit_cast(float, quad_perm<kQuadXor1>(__builtin_bit_cast(int, s0)));
+  const float r1 = __builtin_bit_cast(float, quad_perm<kQuadXor1>(__builtin_bit_cast(int, s1)));
+  // pixel 4g + b0 and pixel 4g + 2 + b0, channels (n & ~1, n | 1)
+  const float alo = b0 ? r0 : v[0], ahi = b0 ? v[1] : r0;
+  const float blo = b0 ? r1 : v[2], bhi = b0 ? v[3] : r1;
+  if constexpr (P == BF16) {
+    const uint32_t wa = pack_bf16x2(alo, ahi), wb = pack_bf16x2(blo, bhi);
+    const uint32_t rw = (uint32_t)quad_perm<kQuadXor2>((int)(b1 ? wa : wb));
+    const uint32_t lo = b1 ? rw : wa, hi = b1 ? wb : rw;
+    if (pm_ok) st<u2v>(plane_row + q * 8, u2v{lo, hi});
+  } else {
+    const uint32_t wa = pack_e4m3x2(alo * inv, ahi * inv), wb = pack_e4m3x2(blo * inv, bhi * inv);
+    const uint32_t rw = (uint32_t)quad_perm<kQuadXor2>((int)(b1 ? wa : wb));
+    const uint32_t word = b1 ? (rw | (wb << 16)) : (wa | (rw << 16));
+    if (pm_ok) st<uint32_t>(plane_row + q * 4, word);
+  }
+}
+
+template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int NCW, int NPW>
+__global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS)) void conv_ws(JobSet js,
+                                                                                                ConvParams prm) {
+  using C = CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>;
+  using T = PT<P>;
+  static_assert(P != F32, "conv_ws reads and writes the channel-blocked BF16 / FP8 layout");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform role
+  constexpr int MCOLS = TX / 16;
+  constexpr int PB = 16 * T::BYTES;
+  const gbyte* wglob = gin(prm.wpack);
+
+  const ItemRange rg = item_range(js.total_items);
+  TileWalk w;
+  w.init(js, rg);
+  if (!w.next(js)) return;  // no work for this workgroup (uniform)
+
+  if constexpr (C::WRES) {
+    // all packed weights to LDS once (every wave helps)
+    WStage<C::NCB * C::WB, C::THREADS> wl;
+    wl.load(wglob, tid);
+    wl.store(lds + C::WOFF, tid);
+  }
+
+  if (wave >= NCW) {
+    // ---------------- producer waves
+    const int ptid = tid - NCW * 64;
+    AStage<P, C::LR, C::LC, C::NCHB, C::PSB, NPW * 64, POOL> a;
+    WStage<C::WB, NPW * 64> ws;
+    int cb = 0;
+    // global loads of the stage (w.item, cb) into registers
+    auto issue = [&]() __attribute__((always_inline)) {
+      int zz, y0, x0;
+      w.coords<TY, TX>(zz, y0, x0);
+      const int hp = w.J.hin - (POOL ? 1 : 0), wp = w.J.win - (POOL ? 1 : 0);
+      const gbyte* slice = gin(w.J.in) + (int64_t)zz * w.J.in_zs * CIN * T::BYTES;
+      a.load(slice, w.J.in_zs * PB, w.J.in_rs * PB, cb * C::CB, y0, x0, hp, wp, ptid);
+      if constexpr (C::BL && !C::WRES) ws.load(wglob + (size_t)cb * C::WB, ptid);
+    };
+    auto advance = [&]() __attribute__((always_inline)) -> bool {
+      if (++cb < C::NCB) return true;
+      cb = 0;
+      return w.next(js);
+    };
+    auto put = [&](int sel) __attribute__((always_inline)) {
+      a.store(lds + sel * C::BUF, ptid);
+      if constexpr (C::BL && !C::WRES) ws.store(lds + C::WOFF + sel * C::WB, ptid);
+    };
+    issue();
+    put(0);
+    bool more = advance();
+    if (more) issue();
+    __syncthreads();  // stage 0 ready
+    int sel = 1;
+    while (more) {
+      put(sel);  // the consumers finished this buffer's previous stage before the last barrier
+      more = advance();
+      if (more) issue();
+      __syncthreads();  // this stage ready; the consumers finished the previous one
+      sel ^= 1;
+    }
+    __syncthreads();  // the consumers' last stage
+    return;
+  }
+
+  // ---------------- consumer waves: tile rows wave*WROWS .. +WROWS-1. The
+  // m-block offsets inside a wave's rows are compile-time constants, so the
+  // per-m-block LDS and global addresses are immediates on one lane base.
+  const int g = lane >> 4, n16 = lane & 15;
+  const int wrow0 = wave * C::WROWS;
+  __syncthreads();  // the first stage is ready
+  int cb = 0, sel = 0;
+  f4 acc[C::MW][C::NB];
+  for (;;) {
+    if (cb == 0) {
+#pragma unroll
+      for (int u = 0; u < C::MW; ++u)
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) acc[u][nb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    const unsigned char* abase = lds + sel * C::BUF + (wrow0 * C::LC + n16) * C::PSB;
+    // implicit GEMM over the stage's (tap, chunk) slots; B fragments from
+    // LDS (BF16) or global memory (FP8)
+    auto kloop = [&](auto wl) __attribute__((always_inline)) {
+#pragma unroll 2
+      for (int s = 0; s < C::NGS; ++s) {
+        Frag<P> bfr[C::NB];
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const auto p = wl + (s * C::NB + nb) * 64 * (T::U * 16);
+          load_frag<P>(bfr[nb], p, p + 16);
+        }
+        int off[T::U];
+#pragma unroll
+        for (int uu = 0; uu < T::U; ++uu) {
+          int c = (4 * s + g) * T::U + uu;
+          c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
+          const int i = c / (KS * C::NCHB);
+          const int rem = c % (KS * C::NCHB);
+          const int j = rem / C::NCHB, cg = rem % C::NCHB;
+          off[uu] = (i * C::LC + j) * C::PSB + cg * 16;
+        }
+        const unsigned char* a0 = abase + off[0];
+        const unsigned char* a1 = abase + off[T::U - 1];
+#pragma unroll
+        for (int u = 0; u < C::MW; ++u) {
+          const int mo = ((u / MCOLS) * C::LC + (u % MCOLS) * 16) * C::PSB;
+          Frag<P> afr;
+          load_frag<P>(afr, a0 + mo, a1 + mo);
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[u][nb], afr, bfr[nb]);
+        }
+      }
+    };
+    if constexpr (C::BL)
+      kloop(static_cast<const unsigned char*>(lds + C::WOFF + (C::WRES ? cb : sel) * C::WB + lane * (T::U * 16)));
+    else
+      kloop(wglob + (size_t)cb * C::WB + lane * (T::U * 16));
+
+    if (cb == C::NCB - 1) {
+      // ---- epilogue straight from the accumulators
+      int zz, y0, x0;
+      w.coords<TY, TX>(zz, y0, x0);
+      const LayerJob& J = w.J;
+      float bias[C::NB], osc[C::NB], hw[C::NB];
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) {
+        bias[nb] = ldf(prm.bias, nb * 16 + n16);
+        osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
+        hw[nb] = HEAD ? ldf(prm.head_w, nb * 16 + n16) : 0.f;
+      }
+      const int ty0 = y0 + wrow0;
+#pragma unroll
+      for (int u = 0; u < C::MW; ++u) {
+        const int y = ty0 + u / MCOLS;
+        const int xb = x0 + (u % MCOLS) * 16;
+        if constexpr (HEAD) {
+          float part[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            float pv = 0.f;
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) pv = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], pv);
+            pv += __shfl_xor(pv, 1);
+            pv += __shfl_xor(pv, 2);
+            pv += __shfl_xor(pv, 4);
+            pv += __shfl_xor(pv, 8);
+            part[k] = pv;
+          }
+          if (n16 < 4) {
+            const int x = xb + 4 * g + n16;
+            const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
+            if (y < J.hout && x < J.wout)
+              st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
+          }
+        } else {
+          const int pm = 4 * g + (n16 & 3);
+          const int ok = (y < J.hout) && (xb + pm < J.wout);
+          gbyte* orow = gout(J.out) + ((int64_t)zz * J.out_zs * COUT + ((int64_t)y * J.out_rs + xb) * 16) * T::BYTES +
+                        pm * PB;
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) {
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = relu(fmaf(acc[u][nb][k], osc[nb], bias[nb]));
+            store_block_tile<P>(orow + (int64_t)nb * J.out_zs * PB, ok, v, n16, prm.out_inv_scale);
+          }
+        }
+      }
+    }
+
+    __syncthreads();  // done with this buffer; the next stage is ready
+    sel ^= 1;
+    if (++cb == C::NCB) {
+      cb = 0;
+      if (!w.next(js)) break;
     }
   }
 }
@@ -841,6 +1302,27 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
               "conv_mfma_rr<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #MR "," #MC "," #WX "," #WY \
               "," #CBO ">"}
 
+#define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW)                                      \
+  VariantInfo{P, CIN, COUT, KS, POOL, HEAD, TY, TX,                                                   \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::MW,                                          \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS,                                     \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::CB,                                          \
+              PT<P>::CHB,                                                                             \
+              PT<P>::U,                                                                               \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::NGS,                                         \
+              0,                                                                                      \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::LDS,                                         \
+              reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW>), \
+              "conv_ws<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #NCW "," #NPW ">"}
+
+// Pipelined (BF16 / FP8) tile shapes: TY x TX outputs, consumer x producer
+// waves, per layer signature (shapes that fit the LDS and the 168 registers
+// of a 12-wave workgroup without spilling).
+#define EMCNN_WS_NARROW(P, CIN, COUT, KS, POOL, HEAD) \
+  EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 8, 4), EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 8, 48, 8, 4)
+#define EMCNN_WS_SHAPES(P, CIN, COUT, KS, POOL, HEAD) \
+  EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 16, 48, 8, 4), EMCNN_WS_NARROW(P, CIN, COUT, KS, POOL, HEAD)
+
 // Flattened-K tile shapes. The first is each signature's default: 16 x 64
 // outputs with 8 m-blocks per wave (halo overhead 1.33x) measured fastest for
 // the body convs of net B in every precision on MI355X.
@@ -864,24 +1346,21 @@ static const VariantInfo kConv[] = {
     EMCNN_RR_SHAPES(F32, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(F32, 48, 48, 3, true, true),
     EMCNN_RR_SHAPES(F32, 48, 48, 3, true, true, 0),
-    EMCNN_SHAPES(BF16, 48, 48, 5, true, false),
-    EMCNN_RR_SHAPES(BF16, 48, 48, 5, true, false, 0),
-    EMCNN_SHAPES(BF16, 48, 48, 3, true, true),
-    EMCNN_RR_SHAPES(BF16, 48, 48, 3, true, true, 48),
-    EMCNN_SHAPES(FP8, 48, 48, 5, true, false),
-    EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 2, 2, 0),
-    EMCNN_RR(FP8, 48, 48, 5, true, false, 4, 1, 4, 1, 0),
-    EMCNN_SHAPES(FP8, 48, 48, 3, true, true),
+    EMCNN_WS_NARROW(BF16, 48, 48, 5, true, false),
+    EMCNN_WS_SHAPES(BF16, 48, 48, 3, true, true),
+    EMCNN_WS_NARROW(FP8, 48, 48, 5, true, false),
+    EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
+    EMCNN_WS(FP8, 48, 48, 3, true, true, 16, 48, 8, 4),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)
     EMCNN_CONV(F32, 48, 48, 5, false, false, 8, 64, 4),
     EMCNN_CONV(F32, 48, 48, 3, false, true, 8, 64, 4),
     EMCNN_CONV(F32, 48, 48, 5, false, true, 8, 64, 4),
-    EMCNN_CONV(BF16, 48, 48, 5, false, false, 8, 64, 4),
-    EMCNN_CONV(BF16, 48, 48, 3, false, true, 8, 64, 4),
-    EMCNN_CONV(FP8, 48, 48, 5, false, false, 8, 64, 4),
-    EMCNN_CONV(FP8, 48, 48, 3, false, true, 8, 64, 4),
+    EMCNN_WS(BF16, 48, 48, 5, false, false, 8, 64, 8, 4),
+    EMCNN_WS(BF16, 48, 48, 3, false, true, 8, 64, 8, 4),
+    EMCNN_WS(FP8, 48, 48, 5, false, false, 8, 64, 8, 4),
+    EMCNN_WS(FP8, 48, 48, 3, false, true, 8, 64, 8, 4),
     EMCNN_CONV(F32, 16, 16, 5, true, true, 8, 32, 4),
     EMCNN_CONV(F32, 16, 16, 5, false, false, 8, 32, 4),
 };
