@@ -157,7 +157,13 @@ int cnn_profile_read(cnn_net* net, double* ms_per_layer, int32_t* launches_per_l
  * into the last one). cnn_variant_name writes the name of candidate `index`
  * of `layer` (CNN_EINVAL past the last); cnn_set_variant selects a candidate
  * by name for later calls. Candidates of one layer may differ in accumulation
- * order (and so in the last bits of the result). */
+ * order (and so in the last bits of the result).
+ * In BF16 / FP8 nets whose first conv is 1->C 5x5 followed by a max pool and a
+ * C->C 5x5 conv, layer 1 also has candidates (names ending in ",5>") that read
+ * the uint8 input and compute layer 0 themselves, with a bitwise-equal result
+ * and no layer-0 output in HBM; while one is selected, layer 0 is not launched
+ * (no launches in cnn_profile_read). The default keeps the separate layer-0
+ * launch (measured as fast or faster on MI355X). */
 int cnn_variant_name(const cnn_net* net, int32_t layer, int32_t index, char* buf, int32_t buf_len);
 int cnn_set_variant(cnn_net* net, int32_t layer, const char* name);
 

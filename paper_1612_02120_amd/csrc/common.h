@@ -50,6 +50,11 @@ struct ConvParams {
   const float* head_w;   // [cout] head weights (head variants)
   float head_b;
   float out_inv_scale;   // FP8 output codes: e4m3(v * out_inv_scale)
+  // fused variants only: the uint8 first layer computed in the producers
+  const void* w1;        // first-layer B fragments, bf16 [n-block][lane][8 taps], 1/255 folded in
+  const float* b1;       // [cin] first-layer bias
+  float w1_inv_scale;    // FP8: first-layer output codes e4m3(v * w1_inv_scale)
+  float pad_;
 };
 
 struct FirstParams {
@@ -70,6 +75,8 @@ struct VariantInfo {
   int u;                // chunks per lane per MFMA
   int ngs;              // group-steps per channel block (row reuse: per filter row)
   int rr;               // 1: row-reuse kernel (weights packed per filter row)
+  int fused;            // k > 0: the kernel reads the uint8 input and computes the preceding
+                        // 1-channel k x k first layer (and the max filter) itself
   int lds_bytes;
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
   const char* name;

@@ -36,6 +36,7 @@ typedef int i8v __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned char u8x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 // Global-memory access. Pointers read from job tables and parameter structs
 // are generic to the compiler, which then emits FLAT instructions; a FLAT load
@@ -880,7 +881,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 // and the producers issue the global loads of stage k+1 before that barrier,
 // so the load latency overlaps a whole stage of MFMA work.
 
-template <int P, int CIN, int COUT, int KS, int TY, int TX, int NCW, int NPW>
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int NCW, int NPW, int K1 = 0>
 struct CfgWS {
   using T = PT<P>;
   // channels per stage: 16 (one plane) for BF16; all of CIN for FP8, whose
@@ -905,7 +906,19 @@ struct CfgWS {
   static constexpr bool BL = P != FP8;
   static constexpr bool WRES = BL && 2 * BUF + NCB * WB <= LDS_MAX;  // all weights resident in LDS
   static constexpr int WOFF = 2 * BUF;
-  static constexpr int LDS = 2 * BUF + (!BL ? 0 : WRES ? NCB * WB : 2 * WB);
+  static constexpr int WLDS = !BL ? 0 : WRES ? NCB * WB : 2 * WB;
+  // Fused first layer (K1 > 0): producer wave w builds operand rows
+  // [w*RPW, (w+1)*RPW) from RPW + 1 first-layer output rows, computed in
+  // m-blocks of 16 pixels at a column stride of 15 (a block yields 15
+  // max-filtered columns), from its own uint8 rows in LDS.
+  static constexpr int RPW = (LR + NPW - 1) / NPW;
+  static constexpr int NMC = (LC + 14) / 15;
+  static constexpr int U8R = RPW + K1;
+  static constexpr int U8C = (15 * NMC + K1 + 3) / 4 * 4;
+  static constexpr int U8W = K1 ? U8R * U8C : 0;  // uint8 bytes per producer wave
+  static constexpr int U8PL = (U8W + 63) / 64;    // per lane
+  static constexpr int U8OFF = WOFF + WLDS;
+  static constexpr int LDS = U8OFF + NPW * U8W;
   static constexpr int MBLK = TY * TX / 16;
   static_assert(TX % 16 == 0, "TX must be a multiple of 16");
   static_assert(MBLK % NCW == 0, "m-blocks must split evenly over consumer waves");
@@ -915,6 +928,7 @@ struct CfgWS {
   static constexpr int THREADS = (NCW + NPW) * 64;
   static_assert(THREADS <= 1024, "workgroup size limit");
   static_assert(LDS <= LDS_MAX, "LDS budget of a gfx950 workgroup");
+  static_assert(K1 == 0 || K1 * K1 <= 32, "fused first layer: one 16x16x32 MFMA per block");
 };
 
 // Walk of the work items of one workgroup (see item_range), skipping items
@@ -1068,8 +1082,8 @@ __device__ __forceinline__ uint32_t pack_e4m3x2(float lo, float hi) {
 // Lane (g, n) holds channel n of pixels 4g..4g+3. Two quad exchanges leave
 // lane (g, n) with channels 4(n/4)..4(n/4)+3 of pixel 4g + n%4, so the 64
 // lanes write 16 consecutive plane pixels (one contiguous run).
-template <int P>
-__device__ __forceinline__ void store_block_tile(gbyte* plane_row, int pm_ok, const float (&v)[4], int n16,
+template <int P, class B>
+__device__ __forceinline__ void store_block_tile(B* plane_row, int pm_ok, const float (&v)[4], int n16,
                                                  float inv) {
   const int b0 = n16 & 1, b1 = (n16 >> 1) & 1, q = n16 >> 2;
   const float s0 = b0 ? v[0] : v[1], s1 = b0 ? v[2] : v[3];
@@ -1091,10 +1105,11 @@ __device__ __forceinline__ void store_block_tile(gbyte* plane_row, int pm_ok, co
   }
 }
 
-template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int NCW, int NPW>
-__global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS)) void conv_ws(JobSet js,
-                                                                                                ConvParams prm) {
-  using C = CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>;
+template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int NCW, int NPW, int K1>
+__global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THREADS)) void conv_ws(
+    JobSet js, ConvParams prm) {
+  using C = CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>;
+  static_assert(K1 == 0 || POOL, "the fused first layer feeds a max filter");
   using T = PT<P>;
   static_assert(P != F32, "conv_ws reads and writes the channel-blocked BF16 / FP8 layout");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
@@ -1116,7 +1131,155 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS
     wl.store(lds + C::WOFF, tid);
   }
 
-  if (wave >= NCW) {
+  if constexpr (K1 > 0) if (wave >= NCW) {
+    // ---------------- producer waves, fused first layer
+    const int pw = wave - NCW;
+    const int g = lane >> 4, n16 = lane & 15;
+    const int orow0 = pw * C::RPW;  // first operand row of this wave
+    unsigned char* u8r = lds + C::U8OFF + pw * C::U8W;
+    const gbyte* w1 = gin(prm.w1);
+    // per-lane tap offsets in the uint8 rows: lane group g holds taps 8g..8g+7
+    // (taps past K1*K1 read byte 0: their packed weights are zero)
+    int toff[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int t = 8 * g + e;
+      toff[e] = t < K1 * K1 ? (t / K1) * C::U8C + t % K1 : 0;
+    }
+    int ub[C::U8PL];
+    WStage<C::WB, NPW * 64> ws;
+    const int ptid = tid - NCW * 64;
+    int cb = 0;
+    // global loads of the stage's weight slice (BF16 weights that do not stay
+    // resident) and, at a tile's first stage, of the uint8 rows orow0 ..
+    // orow0 + U8R - 1 of the tile of w.item (clamped)
+    auto issue = [&]() __attribute__((always_inline)) {
+      if constexpr (C::BL && !C::WRES) ws.load(wglob + (size_t)cb * C::WB, ptid);
+      if (cb != 0) return;
+      int zz, y0, x0;
+      w.coords<TY, TX>(zz, y0, x0);
+      const gbyte* in = gin(w.J.in) + (int64_t)zz * w.J.in_zs;
+#pragma unroll
+      for (int q = 0; q < C::U8PL; ++q) {
+        const int idx = q * 64 + lane;
+        if (idx < C::U8W) {
+          const int r = idx / C::U8C, c = idx % C::U8C;
+          const int y = min(y0 + orow0 + r, w.J.hin - 1), x = min(x0 + c, w.J.win - 1);
+          ub[q] = in[(int64_t)y * w.J.in_rs + x];
+        }
+      }
+    };
+    auto advance = [&]() __attribute__((always_inline)) -> bool {
+      if (++cb < C::NCB) return true;
+      cb = 0;
+      return w.next(js);
+    };
+    // Operand rows of this wave for stage cb into buffer sel. The first layer
+    // runs as D = W X on a 16x16x32 bf16 MFMA: A = weights (lane (g, c) holds
+    // channel c's taps 8g..8g+7, the packed layout), B = the taps of 16
+    // pixels, so lane (g, n) receives channels 4g..4g+3 of pixel n. The right
+    // neighbour of pixel n is then lane n+1 of the same 16-lane row (one DPP
+    // shift), and a lane's 4 channels are one 8-byte (BF16) / 4-byte (FP8)
+    // operand store. The products are exact (uint8 times bf16), and the
+    // outputs are max-filtered as floats and converted once: bf16 rounding
+    // and e4m3 quantisation are monotone, so this equals filtering the stored
+    // values of the unfused path.
+    auto put = [&](int sel) __attribute__((always_inline)) {
+      if constexpr (C::BL && !C::WRES) ws.store(lds + C::WOFF + sel * C::WB, ptid);
+      if (cb == 0) {
+#pragma unroll
+        for (int q = 0; q < C::U8PL; ++q) {
+          const int idx = q * 64 + lane;
+          if (idx < C::U8W) u8r[idx] = (unsigned char)ub[q];
+        }
+      }
+      unsigned char* obuf = lds + sel * C::BUF;
+      constexpr int NB1 = C::CB / 16;  // first-layer n-blocks per stage
+      bf16x8 wfr[NB1];
+      float b4[NB1][4];
+#pragma unroll
+      for (int nb1 = 0; nb1 < NB1; ++nb1) {
+        const int n1 = cb * NB1 + nb1;  // first-layer output channels 16 n1 .. 16 n1 + 15
+        wfr[nb1] = ld<bf16x8>(w1 + ((int64_t)n1 * 64 + lane) * 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b4[nb1][k] = ldf(prm.b1, n1 * 16 + 4 * g + k);
+      }
+      for (int mc = 0; mc < C::NMC; ++mc) {
+        // taps of pixel 15 mc + n for all RPW + 1 first-layer rows of this wave:
+        // all byte loads are issued before any is used
+        const unsigned char* a0 = u8r + 15 * mc + n16;
+        unsigned int raw[C::RPW + 1][8];
+#pragma unroll
+        for (int rr = 0; rr <= C::RPW; ++rr)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) raw[rr][e] = a0[rr * C::U8C + toff[e]];
+        __builtin_amdgcn_sched_barrier(0);
+        // uint8 -> bf16 is exact: the float of an integer below 256 has a zero low half
+        bf16x8 xb[C::RPW + 1];
+#pragma unroll
+        for (int rr = 0; rr <= C::RPW; ++rr) {
+          u4v pk;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            pk[e] = __builtin_amdgcn_perm(__builtin_bit_cast(unsigned int, (float)raw[rr][2 * e + 1]),
+                                          __builtin_bit_cast(unsigned int, (float)raw[rr][2 * e]), 0x07060302u);
+          xb[rr] = __builtin_bit_cast(bf16x8, pk);
+        }
+        const int col = 15 * mc + n16;
+        const bool colok = (n16 != 15) && (col < C::LC);
+#pragma unroll
+        for (int nb1 = 0; nb1 < NB1; ++nb1) {
+          float hprev[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int rr = 0; rr <= C::RPW; ++rr) {
+            const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[nb1], xb[rr], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            float h[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const float t = relu(acc[k] + b4[nb1][k]);
+              // pixel n + 1 (lane n + 1 of the row; lane 15's value is never stored)
+              const float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, t),
+                                                                                    0x101, 0xF, 0xF, false));
+              h[k] = fmaxf(t, r);
+            }
+            if (rr > 0) {
+              const int orow = orow0 + rr - 1;
+              if (colok && orow < C::LR) {
+                unsigned char* dst = obuf + (orow * C::LC + col) * C::PSB + (nb1 * 16 + 4 * g) * T::BYTES;
+                const float v0 = fmaxf(hprev[0], h[0]), v1 = fmaxf(hprev[1], h[1]);
+                const float v2 = fmaxf(hprev[2], h[2]), v3 = fmaxf(hprev[3], h[3]);
+                if constexpr (P == BF16) {
+                  st<u2v>(dst, u2v{pack_bf16x2(v0, v1), pack_bf16x2(v2, v3)});
+                } else {
+                  const float inv = prm.w1_inv_scale;
+                  st<uint32_t>(dst, pack_e4m3x2(v0 * inv, v1 * inv) | (pack_e4m3x2(v2 * inv, v3 * inv) << 16));
+                }
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) hprev[k] = h[k];
+          }
+        }
+      }
+    };
+    issue();
+    put(0);
+    bool more = advance();
+    if (more) issue();
+    __syncthreads();  // stage 0 ready
+    int sel = 1;
+    while (more) {
+      put(sel);
+      more = advance();
+      if (more) issue();
+      __syncthreads();  // this stage ready; the consumers finished the previous one
+      sel ^= 1;
+    }
+    __syncthreads();  // the consumers' last stage
+    return;
+  }
+
+  if constexpr (K1 == 0) if (wave >= NCW) {
     // ---------------- producer waves
     const int ptid = tid - NCW * 64;
     AStage<P, C::LR, C::LC, C::NCHB, C::PSB, NPW * 64, POOL> a;
@@ -1281,7 +1444,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
               Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::NGS,                                           \
-              0,                                                                                      \
+              0, 0,                                                                                   \
               Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::LDS_TILE,                                      \
               reinterpret_cast<const void*>(&conv_mfma<P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW>), \
               "conv_mfma<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #MW ">"}
@@ -1296,24 +1459,27 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
               CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::NGR,                                \
-              1,                                                                                      \
+              1, 0,                                                                                   \
               CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::LDS,                                \
               reinterpret_cast<const void*>(&conv_mfma_rr<P, CIN, COUT, KS, POOL, HEAD, MR, MC, WX, WY, CBO>), \
               "conv_mfma_rr<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #MR "," #MC "," #WX "," #WY \
               "," #CBO ">"}
 
-#define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW)                                      \
+#define EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, K1)                                \
   VariantInfo{P, CIN, COUT, KS, POOL, HEAD, TY, TX,                                                   \
-              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::MW,                                          \
-              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::THREADS,                                     \
-              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::CB,                                          \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::MW,                                      \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THREADS,                                 \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::CB,                                      \
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
-              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::NGS,                                         \
-              0,                                                                                      \
-              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW>::LDS,                                         \
-              reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW>), \
-              "conv_ws<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #NCW "," #NPW ">"}
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::NGS,                                     \
+              0, K1,                                                                                  \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::LDS,                                     \
+              reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, K1>), \
+              "conv_ws<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #NCW "," #NPW \
+              "," #K1 ">"}
+#define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
+  EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
 
 // Pipelined (BF16 / FP8) tile shapes: TY x TX outputs, consumer x producer
 // waves, per layer signature (shapes that fit the LDS and the 168 registers
@@ -1346,9 +1512,14 @@ static const VariantInfo kConv[] = {
     EMCNN_RR_SHAPES(F32, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(F32, 48, 48, 3, true, true),
     EMCNN_RR_SHAPES(F32, 48, 48, 3, true, true, 0),
+    // conv2: separate first layer (default), then with the first layer computed inside
     EMCNN_WS_NARROW(BF16, 48, 48, 5, true, false),
+    EMCNN_WSK(BF16, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
+    EMCNN_WSK(BF16, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
     EMCNN_WS_SHAPES(BF16, 48, 48, 3, true, true),
     EMCNN_WS_NARROW(FP8, 48, 48, 5, true, false),
+    EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
+    EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
     EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
     EMCNN_WS(FP8, 48, 48, 3, true, true, 16, 48, 8, 4),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)

@@ -30,13 +30,16 @@ Dims layer_dims(const Net* net, int h, int w) {
   return d;
 }
 
-// Bytes per slice of each layer's stored output (0 for the head layer).
+// Bytes per slice of each layer's stored output (0 for the head layer, and
+// for a first layer that the next layer computes itself).
 static std::vector<size_t> layer_bytes(const Net* net, const Dims& d) {
   std::vector<size_t> b;
   const int nl = (int)net->layers.size();
+  const bool fused = first_fused(net);
   for (int l = 0; l < nl; ++l)
-    b.push_back(l == nl - 1 ? 0
-                            : (size_t)d.hout[l] * d.wout[l] * net->layers[l].cout * act_bytes_of(net->prec));
+    b.push_back(l == nl - 1 || (l == 0 && fused)
+                    ? 0
+                    : (size_t)d.hout[l] * d.wout[l] * net->layers[l].cout * act_bytes_of(net->prec));
   return b;
 }
 
@@ -113,12 +116,19 @@ int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipSt
     e = hipLaunchKernel(fn, dim3(grid), dim3(layer_threads(L)), args, 0, st);
   } else {
     ConvParams p;
+    std::memset(&p, 0, sizeof(p));
     p.wpack = L.wpack;
     p.bias = L.bias;
     p.oscale = L.oscale;
     p.head_w = L.head_w;
     p.head_b = L.head_b;
     p.out_inv_scale = L.out_inv_scale;
+    if (conv_variant(L.variant)->fused) {
+      const ExecLayer& L0 = net->layers[0];
+      p.w1 = L0.wpack;
+      p.b1 = L0.bias;
+      p.w1_inv_scale = L0.out_inv_scale;
+    }
     void* args[] = {(void*)&js, (void*)&p};
     e = hipLaunchKernel(fn, dim3(grid), dim3(layer_threads(L)), args, 0, st);
   }
@@ -145,14 +155,17 @@ int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, fl
   unsigned char* buf[2] = {reinterpret_cast<unsigned char*>(net->ws),
                            reinterpret_cast<unsigned char*>(net->ws) + zs * b0};
   const int Ho = d.hout[nl - 1], Wo = d.wout[nl - 1];
+  const bool fused = first_fused(net);
   for (int64_t z0 = 0; z0 < Z; z0 += zs) {
     const int zc = (int)std::min<int64_t>(zs, Z - z0);
-    for (int l = 0; l < nl; ++l) {
+    for (int l = fused ? 1 : 0; l < nl; ++l) {
       const ExecLayer& L = net->layers[l];
-      const void* in = (l == 0) ? (const void*)(vol + z0 * H * W) : (const void*)buf[(l - 1) % 2];
+      // a fused layer 1 reads the uint8 input with layer 0's geometry
+      const int li = (l == 1 && fused) ? 0 : l;
+      const void* in = (li == 0) ? (const void*)(vol + z0 * H * W) : (const void*)buf[(l - 1) % 2];
       void* out = (l == nl - 1) ? (void*)(prob + z0 * (int64_t)Ho * Wo) : (void*)buf[l % 2];
-      LayerJob j = make_job(L, in, out, zc, d.hin[l], d.win[l], d.win[l], (int64_t)d.hin[l] * d.win[l], d.hout[l],
-                            d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
+      LayerJob j = make_job(L, in, out, zc, d.hin[li], d.win[li], d.win[li], (int64_t)d.hin[li] * d.win[li],
+                            d.hout[l], d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
       JobSet js;
       std::memset(&js, 0, sizeof(js));
       js.njobs = 1;
@@ -273,7 +286,8 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
         b += b1[t];
       }
     }
-    for (int l = 0; l < nl; ++l) {
+    const bool fused = first_fused(net);
+    for (int l = fused ? 1 : 0; l < nl; ++l) {
       const ExecLayer& L = net->layers[l];
       const size_t first = pos;
       int64_t item0 = 0;
@@ -288,7 +302,8 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
         };
         const void* in;
         int64_t in_rs, in_zs;
-        if (l == 0) {
+        const int li = (l == 1 && fused) ? 0 : l;  // a fused layer 1 reads the uint8 input
+        if (li == 0) {
           in = R.in;
           in_rs = R.in_rs;
           in_zs = R.in_zs;
@@ -308,8 +323,8 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
           out_rs = d.wout[l];
           out_zs = (int64_t)d.hout[l] * d.wout[l];
         }
-        LayerJob j = make_job(L, in, out, R.z, d.hin[l], d.win[l], in_rs, in_zs, d.hout[l], d.wout[l], out_rs, out_zs,
-                              item0, R.gate);
+        LayerJob j = make_job(L, in, out, R.z, d.hin[li], d.win[li], in_rs, in_zs, d.hout[l], d.wout[l], out_rs,
+                              out_zs, item0, R.gate);
         item0 += job_items(j);
         tab[pos++] = j;
       }
@@ -509,10 +524,12 @@ static int candidate_name_index(const ExecLayer& L, const std::string& name) {
   return -1;
 }
 
-// One launch of layer l over a single H x W slice region.
+// One launch of layer l over a single H x W slice region (a fused layer 1
+// reads the uint8 input, passed as `in`, with layer 0's geometry).
 static int run_one_layer(Net* net, int l, const void* in, void* out, const Dims& d, hipStream_t st) {
   const ExecLayer& L = net->layers[l];
-  LayerJob j = make_job(L, in, out, 1, d.hin[l], d.win[l], d.win[l], (int64_t)d.hin[l] * d.win[l], d.hout[l],
+  const int li = (l == 1 && first_fused(net)) ? 0 : l;
+  LayerJob j = make_job(L, in, out, 1, d.hin[li], d.win[li], d.win[li], (int64_t)d.hin[li] * d.win[li], d.hout[l],
                         d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
   JobSet js;
   std::memset(&js, 0, sizeof(js));
@@ -589,8 +606,11 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   hipMemcpy(bufs[0], host_in.data(), host_in.size(), hipMemcpyHostToDevice);
-  // reference pass with the default variants
-  for (int l = 0; l < nl && !rc; ++l) rc = run_one_layer(net, l, bufs[l], bufs[l + 1], d, st);
+  // reference pass with the default variants (layer 0's output is still made
+  // when layer 1 computes it itself: it is the reference for tuning layer 0)
+  const bool fused = first_fused(net);
+  auto layer_in = [&](int l) { return (l == 1 && fused) ? bufs[0] : bufs[l]; };
+  for (int l = 0; l < nl && !rc; ++l) rc = run_one_layer(net, l, layer_in(l), bufs[l + 1], d, st);
   if (!rc && (e = hipStreamSynchronize(st)) != hipSuccess) rc = hip_fail(e, "cnn_autotune: reference pass");
   if (rc) {
     cleanup();
@@ -602,7 +622,7 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
       select_variant(L, chosen[l]);
       continue;
     }
-    if (L.candidates.size() < 2) continue;
+    if (L.candidates.size() < 2 || (l == 0 && fused)) continue;  // a fused layer 0 is never launched
     std::vector<unsigned char> ref(ob[l]), got(ob[l]);
     hipMemcpy(ref.data(), bufs[l + 1], ob[l], hipMemcpyDeviceToHost);
     const int def = L.variant;
@@ -610,14 +630,15 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
     float best_ms = 1e30f;
     for (int c : L.candidates) {
       // only candidates with the default's accumulation order (K layout and channel block)
-      if (!L.first && (conv_variant(c)->rr != conv_variant(def)->rr || conv_variant(c)->cb != conv_variant(def)->cb))
+      if (!L.first && (conv_variant(c)->rr != conv_variant(def)->rr || conv_variant(c)->cb != conv_variant(def)->cb ||
+                       conv_variant(c)->fused != conv_variant(def)->fused))
         continue;
       select_variant(L, c);
-      rc = run_one_layer(net, l, bufs[l], bufs[nl + 1], d, st);  // warm-up, also the checked output
+      rc = run_one_layer(net, l, layer_in(l), bufs[nl + 1], d, st);  // warm-up, also the checked output
       if (rc) break;
       hipEventRecord(e0, st);
       const int reps = 5;
-      for (int r = 0; r < reps && !rc; ++r) rc = run_one_layer(net, l, bufs[l], bufs[nl + 1], d, st);
+      for (int r = 0; r < reps && !rc; ++r) rc = run_one_layer(net, l, layer_in(l), bufs[nl + 1], d, st);
       hipEventRecord(e1, st);
       if (rc) break;
       if ((e = hipEventSynchronize(e1)) != hipSuccess) {

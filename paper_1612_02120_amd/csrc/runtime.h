@@ -111,5 +111,8 @@ const char* layer_name(const ExecLayer& L);
 int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items);
 // Select candidate `variant` of layer L (binds its packed weights).
 bool select_variant(ExecLayer& L, int variant);
+// True when layer 1 runs a fused variant: it reads the uint8 input and computes
+// layer 0 itself, so layer 0 is not launched and has no output buffer.
+bool first_fused(const Net* net);
 
 }  // namespace emcnn

@@ -279,6 +279,10 @@ bool select_variant(ExecLayer& L, int variant) {
   return false;
 }
 
+bool first_fused(const Net* net) {
+  return net->layers.size() > 1 && !net->layers[1].first && conv_variant(net->layers[1].variant)->fused > 0;
+}
+
 int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items) {
   int per_cu = 0;
   const void* fn = layer_fn(L);
@@ -415,6 +419,16 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
       }
       E.head = fuse_head;
       E.candidates = find_conv_variants(prec, l.cin, l.cout, l.k, E.pool_in, fuse_head);
+      {
+        // variants that compute the first layer themselves apply only right after it
+        const ExecLayer& L0 = net->layers[0];
+        std::vector<int> keep;
+        for (int c : E.candidates) {
+          const int k1 = conv_variant(c)->fused;
+          if (k1 == 0 || (conv_i == 1 && L0.first && L0.ks == k1 && L0.cout == l.cin)) keep.push_back(c);
+        }
+        E.candidates.swap(keep);
+      }
       if (E.candidates.empty()) {
         rc = fail(CNN_EUNSUPPORTED, "cnn_create: no MFMA kernel for conv " + std::to_string(i));
         break;
@@ -493,9 +507,11 @@ extern "C" int cnn_describe(const cnn_net* h, char* buf, int32_t len) {
   if (!h || !buf || len < 1) return fail(CNN_EINVAL, "cnn_describe: bad argument");
   const Net* net = reinterpret_cast<const Net*>(h);
   std::string s;
-  for (auto& E : net->layers) {
+  const bool fused = first_fused(net);
+  for (size_t l = 0; l < net->layers.size(); ++l) {
     if (!s.empty()) s += " | ";
-    s += layer_name(E);
+    s += layer_name(net->layers[l]);
+    if (l == 0 && fused) s += " (computed inside layer 1)";
   }
   std::snprintf(buf, len, "%s", s.c_str());
   return CNN_OK;

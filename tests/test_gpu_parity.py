@@ -155,3 +155,38 @@ def test_every_candidate_variant_matches_reference(emcnn, prec, tol):
             err = np.abs(got - ref).max()
             assert err <= tol, (layer, name, err)
         emcnn.cnn_set_variant(h, layer, defaults[layer])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_fused_first_layer_bitwise_equals_unfused(emcnn, prec):
+    """BF16 / FP8 net B's conv2 has candidates that compute the first layer in
+    their producer waves (no layer-0 launch, no layer-0 output in HBM). Rounding
+    and quantisation are monotone, so filtering before or after them is the
+    same: every fused candidate equals the separate conv_first + conv2 path
+    bitwise, on a ragged multi-slice volume, in direct and batched submission."""
+    vol = em_volume(21, 3, 203, 331)
+    h = emcnn.cnn_create(calibrated_params("B"), NET_B, prec,
+                         act_scales=fp8_act_scales("B") if prec == "fp8" else None)
+    names = emcnn.cnn_variant_names(h, 1)
+    fused_names = [n for n in names if n.endswith(",5>")]
+    assert fused_names and not names[0].endswith(",5>"), names
+    ref = emcnn.cnn_infer(h, _dev(vol))
+    torch.cuda.synchronize()
+    assert "computed inside layer 1" not in emcnn.cnn_describe(h)
+    tin = _dev(vol[:, 20:180, 40:300])
+    tout_ref = torch.empty((3, 160 - 12, 260 - 12), dtype=torch.float32, device="cuda")
+    emcnn.cnn_infer_batch(h, [(tin, 6, tout_ref)])
+    for name in fused_names:
+        emcnn.cnn_set_variant(h, 1, name)
+        emcnn.cnn_profile(h, True)
+        fused = emcnn.cnn_infer(h, _dev(vol))
+        torch.cuda.synchronize()
+        emcnn.cnn_profile(h, False)
+        _, launches = emcnn.cnn_profile_read(h)
+        assert launches[0] == 0 and launches[1] == 1 and launches[2] == 1
+        assert "computed inside layer 1" in emcnn.cnn_describe(h)
+        assert torch.equal(fused, ref), name
+        tout = torch.empty_like(tout_ref)
+        emcnn.cnn_infer_batch(h, [(tin, 6, tout)])
+        torch.cuda.synchronize()
+        assert torch.equal(tout, tout_ref), name
