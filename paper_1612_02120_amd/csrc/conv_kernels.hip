@@ -90,12 +90,6 @@ struct PT<FP8> {
 __host__ __device__ constexpr int pad_words(int w) {
   return (w % 16 == 8) ? w : w + ((24 - (w % 16)) % 16);
 }
-// FP8 tiles keep the smaller stride = 4 (mod 8) dwords (a 2-way conflict on A
-// reads): the conflict-free stride doubles their LDS footprint, and the
-// occupancy lost costs more than the conflicts (measured).
-__host__ __device__ constexpr int pad_words_small(int w) {
-  return (w % 8 == 4) ? w : w + ((12 - (w % 8)) % 8);
-}
 
 template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, bool HEAD = false>
 struct Cfg {
@@ -111,7 +105,7 @@ struct Cfg {
   static constexpr int NB = COUT / 16;
   static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
-  static constexpr int PSB = (P == FP8 ? pad_words_small(CB * T::BYTES / 4) : pad_words(CB * T::BYTES / 4)) * 4;
+  static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
   static constexpr int LDS_IN = LR * LC * PSB;
   // BF16 / FP8 outputs leave through LDS so that each tile row is written as
   // contiguous 16-byte stores (FP32 rows already go out in 64-byte segments)
@@ -506,7 +500,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
 
 // Packed weights: for channel block cb, group-step s, n-block nb, lane l,
 // U chunks of 16 bytes. Lane l (n = l % 16, lane group g = l / 16) holds for
-// chunk slot c = (4 s + g) U + uu the CHB input channels of tap (i, j), chunk
+// chunk slot c = 4 U s + 4 uu + g the CHB input channels of tap (i, j), chunk
 // cg, where c -> (i, j, cg) row-major over (KS, KS, NCHB). The A side decodes
 // the same slot the same way, so the MFMA contracts matching K indices
 // whatever order the instruction uses inside a lane's operand bytes.
@@ -563,7 +557,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
         int off[T::U];
 #pragma unroll
         for (int uu = 0; uu < T::U; ++uu) {
-          int c = (4 * s + g) * T::U + uu;
+          int c = s * (4 * T::U) + 4 * uu + g;
           c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
           const int i = c / (KS * C::NCHB);
           const int rem = c % (KS * C::NCHB);
@@ -896,7 +890,10 @@ struct CfgWS {
   static constexpr int NB = COUT / 16;
   static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
-  static constexpr int PSB = (P == FP8 ? pad_words_small(CB * T::BYTES / 4) : pad_words(CB * T::BYTES / 4)) * 4;
+  // pixel stride = 8 (mod 16) dwords; with the chunk-slot order below the two
+  // lane groups of a half-wave read chunks 16 B apart, which is conflict-free
+  // (FP8: 48 B of data in a 96 B stride)
+  static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
   static constexpr int BUF = LR * LC * PSB;                // one operand buffer
   static constexpr int WB = NGS * NB * 64 * T::U * 16;     // packed weights of one stage
   static constexpr int LDS_MAX = 160 * 1024;
@@ -1350,7 +1347,8 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
         int off[T::U];
 #pragma unroll
         for (int uu = 0; uu < T::U; ++uu) {
-          int c = (4 * s + g) * T::U + uu;
+          // slot order: chunk s*4U + 4uu + g (lane group g, uu-th 16 bytes of its operand)
+          int c = s * (4 * T::U) + 4 * uu + g;
           c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
           const int i = c / (KS * C::NCHB);
           const int rem = c % (KS * C::NCHB);
@@ -1521,7 +1519,6 @@ static const VariantInfo kConv[] = {
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
     EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
-    EMCNN_WS(FP8, 48, 48, 3, true, true, 16, 48, 8, 4),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)

@@ -148,7 +148,7 @@ static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b
               j = c / nchb;
               cg = c % nchb;
             } else {
-              const int c = (4 * s + g) * u + uu;
+              const int c = s * 4 * u + 4 * uu + g;  // the kernels' chunk-slot order
               if (c >= nchk) continue;
               i = c / (ks * nchb);
               const int rem = c % (ks * nchb);
