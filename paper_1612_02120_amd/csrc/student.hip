@@ -21,6 +21,7 @@
 
 #include "../../include/emcnn.h"
 #include "common.h"
+#include "device_util.h"
 #include "runtime.h"
 
 namespace emcnn {
@@ -99,6 +100,120 @@ __global__ __launch_bounds__((TY * TX)) void student_fused(const uint8_t* __rest
   for (int co = 0; co < S_C; ++co) zl = fmaf(ww[OFF_WH + co], s_relu(a2[co]), zl);
   const int y = y0 + ty, x = x0 + tx;
   if (y < Ho && x < Wo) out[(int64_t)z * out_zs + (int64_t)y * out_rs + x] = s_sigmoid(zl);
+}
+
+// BF16 mode on MFMA. Both convs run as D = W X on 16x16x32 bf16 MFMAs: the
+// working weights and h1 are bf16 values and uint8 inputs are exact in bf16,
+// so every product is exact and sums are FP32 (in the MFMA's order). The 8
+// output channels fill half of the MFMA's 16 rows: lane (g, n) receives
+// channels 4g..4g+3 of pixel n, lanes g >= 2 the zero-weight rows. One
+// workgroup of 4 waves computes a TY x TX output tile:
+//   conv1: h1 for (TY+2) x (16 ceil((TX+2)/16)) positions, one MFMA per 16
+//          pixels (K = 25 taps padded to 32), bias, ReLU, bf16 -> LDS
+//          (16 bytes per position: 8 channels);
+//   conv2: K = 9 taps x 8 channels in 3 MFMAs per 16 outputs (taps 4s + g,
+//          padded to 12), one 16-byte LDS read per lane per MFMA;
+//   head:  each lane's 4-channel partial dot, one cross-lane add, sigmoid.
+template <int TY, int TX>
+__global__ __launch_bounds__(256) void student_mfma(const uint8_t* in, int64_t in_rs, int64_t in_zs, float* out,
+                                                    int64_t out_rs, int64_t out_zs, int Ho, int Wo, int crop,
+                                                    const float* ww) {
+  constexpr int HR = TY + 2;            // h1 rows
+  constexpr int HMC = (TX + 2 + 15) / 16;  // h1 m-blocks per row
+  constexpr int HC = HMC * 16;          // h1 row pitch (positions)
+  constexpr int IR = HR + 4, IC = HC + 4;  // uint8 tile (covers the padded h1 columns)
+  static_assert(TX % 16 == 0, "output m-blocks of 16 pixels");
+  __shared__ unsigned char xin[IR * IC];
+  __shared__ __attribute__((aligned(16))) unsigned char h1[HR * HC * 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  const int y0 = blockIdx.y * TY, x0 = blockIdx.x * TX, z = blockIdx.z;
+  const gbyte* src = gin(in) + (int64_t)z * in_zs;
+  const int hin_lim = Ho + 2 * crop + 6, win_lim = Wo + 2 * crop + 6;  // input dims implied by the output
+  for (int t = tid; t < IR * IC; t += 256) {
+    const int r = t / IC, c = t % IC;
+    const int y = min(y0 + crop + r, hin_lim - 1), x = min(x0 + crop + c, win_lim - 1);
+    xin[t] = src[(int64_t)y * in_rs + x];
+  }
+  // weight fragments: lane (g, c) holds output channel c's K elements 8g..8g+7
+  const bool realc = n16 < S_C;
+  bf16x8 w1f, w2f[3];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int t = 8 * g + e;
+    w1f[e] = (__bf16)(realc && t < 25 ? ldf(ww, OFF_W1 + n16 * 25 + t) : 0.f);
+  }
+#pragma unroll
+  for (int s3 = 0; s3 < 3; ++s3) {
+    const int t = 4 * s3 + g;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w2f[s3][e] = (__bf16)(realc && t < 9 ? ldf(ww, OFF_W2 + (n16 * 8 + e) * 9 + t) : 0.f);
+  }
+  const bool realg = g < 2;  // this lane's rows are real channels 4g..4g+3
+  float b1[4], b2[4], wh[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int co = realg ? 4 * g + k : 0;
+    b1[k] = ldf(ww, OFF_B1 + co);
+    b2[k] = ldf(ww, OFF_B2 + co);
+    wh[k] = realg ? ldf(ww, OFF_WH + co) : 0.f;
+  }
+  const float bh = ldf(ww, OFF_BH);
+  // per-lane tap offsets in the uint8 tile (taps past 25 read byte 0: zero weights)
+  int toff[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int t = 8 * g + e;
+    toff[e] = t < 25 ? (t / 5) * IC + t % 5 : 0;
+  }
+  __syncthreads();
+  // ---- conv1
+  for (int mb = wave; mb < HR * HMC; mb += 4) {
+    const int r = mb / HMC, mc = mb % HMC;
+    const unsigned char* a0 = xin + r * IC + mc * 16 + n16;
+    unsigned int raw[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) raw[e] = a0[toff[e]];
+    u4v pk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)  // uint8 -> bf16 exactly: the float's high half
+      pk[e] = __builtin_amdgcn_perm(__builtin_bit_cast(unsigned int, (float)raw[2 * e + 1]),
+                                    __builtin_bit_cast(unsigned int, (float)raw[2 * e]), 0x07060302u);
+    const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, pk), f4{0.f, 0.f, 0.f, 0.f},
+                                                         0, 0, 0);
+    if (realg) {
+      const __bf16 h0 = (__bf16)s_relu(d[0] + b1[0]), h1v = (__bf16)s_relu(d[1] + b1[1]);
+      const __bf16 h2 = (__bf16)s_relu(d[2] + b1[2]), h3 = (__bf16)s_relu(d[3] + b1[3]);
+      const u2v wv = {(unsigned)__builtin_bit_cast(unsigned short, h0) |
+                          ((unsigned)__builtin_bit_cast(unsigned short, h1v) << 16),
+                      (unsigned)__builtin_bit_cast(unsigned short, h2) |
+                          ((unsigned)__builtin_bit_cast(unsigned short, h3) << 16)};
+      st<u2v>(h1 + ((r * HC + mc * 16 + n16) * 16 + g * 8), wv);
+    }
+  }
+  __syncthreads();
+  // ---- conv2 + head
+  int hoff[3];
+#pragma unroll
+  for (int s3 = 0; s3 < 3; ++s3) {
+    const int t = 4 * s3 + g < 9 ? 4 * s3 + g : 0;  // padded taps: zero weights
+    hoff[s3] = ((t / 3) * HC + t % 3) * 16;
+  }
+  for (int mb = wave; mb < TY * (TX / 16); mb += 4) {
+    const int oy = mb / (TX / 16), omc = mb % (TX / 16);
+    const unsigned char* b0 = h1 + (oy * HC + omc * 16 + n16) * 16;
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s3 = 0; s3 < 3; ++s3)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[s3], ld<bf16x8>(b0 + hoff[s3]), acc, 0, 0, 0);
+    float part = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) part = fmaf(wh[k], s_relu(acc[k] + b2[k]), part);
+    part += __shfl(part, (lane + 16) & 63);  // lanes g = 0: channels 0..3 + 4..7
+    const int y = y0 + oy, x = x0 + omc * 16 + n16;
+    if (g == 0 && y < Ho && x < Wo) st<float>(gout(out) + ((int64_t)z * out_zs + (int64_t)y * out_rs + x) * 4,
+                                             s_sigmoid(part + bh));
+  }
 }
 
 // ------------------------------------------------------------------ training kernels
@@ -627,12 +742,20 @@ extern "C" int student_train_step(cnn_student* h, const uint8_t* patches, const 
 
 static int student_launch(Student* s, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, float* out, int64_t out_rs,
                           int64_t out_zs, int Ho, int Wo, int crop, hipStream_t st) {
+  hipError_t e;
+  if (s->prec == CNN_PREC_BF16) {
+    constexpr int TY = 16, TX = 64;
+    dim3 grid((Wo + TX - 1) / TX, (Ho + TY - 1) / TY, (unsigned)Z);
+    hipLaunchKernelGGL((student_mfma<TY, TX>), grid, dim3(256), 0, st, vol, W, H * W, out, out_rs, out_zs, Ho, Wo, crop,
+                       s->ww);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "student_mfma");
+    return CNN_OK;
+  }
   constexpr int TY = 16, TX = 16;
   dim3 grid((Wo + TX - 1) / TX, (Ho + TY - 1) / TY, (unsigned)Z);
   hipLaunchKernelGGL((student_fused<TY, TX>), grid, dim3(TY * TX), 0, st, vol, W, H * W, out, out_rs, out_zs, Ho, Wo,
-                     crop, s->ww, s->prec == CNN_PREC_BF16 ? 1 : 0);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "student_fused");
+                     crop, s->ww, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "student_fused");
   return CNN_OK;
 }
 
