@@ -36,6 +36,7 @@ HBM_GBS = 8000.0
 NET_B_FLOP_PER_VOXEL = 159168
 CONV2_FLOP_PER_POS = 2 * 25 * 48 * 48  # per conv2 output position
 CONV1_FLOP_PER_POS = 2 * 25 * 48  # per conv1 output position
+STUDENT_FLOP_PER_VOXEL = 2 * (200 + 576 + 8)
 
 
 def log(*a):
@@ -142,7 +143,9 @@ def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args):
                        "(64 x 16 x 512^2, batch 16 x 128^2, lr 1e-3) from FP32 net B; eval %d x 2048^2"
                        % (steps, Zs),
            "train_s": t_train, "final_loss": float(losses[-200:].mean().item()),
-           "student_voxels_per_s": nv / t_s}
+           "student_voxels_per_s": nv / t_s,
+           "student_tflops": nv * STUDENT_FLOP_PER_VOXEL / t_s / 1e12,
+           "student_mfma_frac": nv * STUDENT_FLOP_PER_VOXEL / t_s / 1e12 / PEAK_TFLOPS["bf16"]}
     for tau in (0.01, 0.25):
         r, out, st = distill.evaluate(s, teacher, big, tmap, tau=tau, tile=512, n_samples=4, seed=3)
         t_f = timed(lambda: emcnn.student_infer_with_fallback(s, teacher, big, tau=tau, stream=stream), reps=2)
@@ -164,7 +167,9 @@ def main():
     ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
-                    help="time the candidate tile shapes first (the defaults are the measured best)")
+                    help="time the candidate tile shapes first for the FP32 / BF16 / FP8 volumes "
+                         "(the defaults are the measured best); the batched form always autotunes")
+    ap.add_argument("--no-batch-autotune", action="store_true", help="batched form with the default tiles")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (read, then updated)")
     ap.add_argument("--no-headline", action="store_true", help="skip the FP32 headline (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -272,8 +277,11 @@ def main():
         rng = np.random.default_rng(44)
         pool = em_volume(4, 8, 1040, 1040)
         hb = emcnn.cnn_create(p, NET_B, "bf16")
-        if args.autotune:
-            emcnn.cnn_autotune(hb, 512, 512, args.tune_cache, stream)
+        t_tune = 0.0
+        if not args.no_batch_autotune:  # tile shapes picked by the autotuner on a 1024^2 slice
+            t0 = time.perf_counter()
+            emcnn.cnn_autotune(hb, 1024, 1024, args.tune_cache, stream)
+            t_tune = time.perf_counter() - t0
         tiles, nv = [], 0
         for t in tl:
             y = int(rng.integers(0, 1040 - t["h"] + 1))
@@ -305,7 +313,10 @@ def main():
         forms["batch"] = {"workload": "512 tiles, side logU[64,1024], 1-8 slices, halo 8, BF16 net B",
                           "output_voxels": nv, "voxels_per_s_graph": nv / (msb * 1e-3),
                           "ms_graph": msb, "voxels_per_s_per_tile_loop": nv / (msl * 1e-3),
-                          "ms_per_tile_loop": msl}
+                          "ms_per_tile_loop": msl,
+                          "path_mfma_frac": nv * NET_B_FLOP_PER_VOXEL / (msb * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"],
+                          "autotuned": not args.no_batch_autotune, "autotune_s": t_tune,
+                          "tiles": emcnn.cnn_describe(hb)}
         log("batch", json.dumps(forms["batch"]))
         del tiles, hb
     if "student" in want:

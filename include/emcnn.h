@@ -130,7 +130,8 @@ typedef struct cnn_tile {
 int cnn_infer_batch(cnn_net* net, const cnn_tile* tiles, int32_t n, void* stream);
 
 /* Pick, per layer, the fastest compiled tile shape for H x W slices by timing
- * every candidate on the device (synchronous). Each candidate's output must be
+ * every candidate on the device (synchronous; repeated launches totalling about
+ * 5 ms per candidate). Each candidate's output must be
  * bitwise equal to the default's or it is rejected. cache_path (nullable): a
  * text file of earlier choices, read first and updated. */
 int cnn_autotune(cnn_net* net, int64_t H, int64_t W, const char* cache_path, void* stream);

@@ -636,8 +636,19 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
       select_variant(L, c);
       rc = run_one_layer(net, l, layer_in(l), bufs[nl + 1], d, st);  // warm-up, also the checked output
       if (rc) break;
+      // one timed launch sizes the repetitions: about 5 ms of work per candidate
       hipEventRecord(e0, st);
-      const int reps = 5;
+      rc = run_one_layer(net, l, layer_in(l), bufs[nl + 1], d, st);
+      hipEventRecord(e1, st);
+      if (rc) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        rc = hip_fail(e, "cnn_autotune: timing");
+        break;
+      }
+      float ms1 = 0.f;
+      hipEventElapsedTime(&ms1, e0, e1);
+      const int reps = (int)std::min(200.0f, std::max(5.0f, 5.0f / std::max(ms1, 1e-3f)));
+      hipEventRecord(e0, st);
       for (int r = 0; r < reps && !rc; ++r) rc = run_one_layer(net, l, layer_in(l), bufs[nl + 1], d, st);
       hipEventRecord(e1, st);
       if (rc) break;
