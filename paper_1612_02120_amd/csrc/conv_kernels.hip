@@ -73,11 +73,7 @@ struct Cfg {
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
   static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
   static constexpr int LDS_IN = LR * LC * PSB;
-  // BF16 / FP8 outputs leave through LDS so that each tile row is written as
-  // contiguous 16-byte stores (FP32 rows already go out in 64-byte segments)
-  static constexpr bool STAGE_OUT = (P != F32) && !HEAD;
-  static constexpr int LDS_OUT = STAGE_OUT ? TY * TX * COUT * T::BYTES : 0;
-  static constexpr int LDS_TILE = LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT;
+  static constexpr int LDS_TILE = LDS_IN;
   static constexpr int MBLK = TY * TX / 16;
   static_assert(TX % 16 == 0, "TX must be a multiple of 16");
   static_assert(MBLK % MW == 0, "m-blocks must split evenly over waves");
@@ -251,17 +247,15 @@ __device__ __forceinline__ bool gated_off(const LayerJob& J) {
 // outputs that are never stored). With POOL the operand pixel is the 2x2
 // stride-1 max of the stored (pre-filter) input; each thread then covers a 2x2
 // block of operand pixels of one chunk and loads the 3x3 stored neighbourhood
-// once (9 loads for 4 pixels instead of 16). BF16 unrolls the loop so that all
-// of a thread's loads are in flight together (measured faster); FP32 / FP8 keep
-// it rolled (registers and occupancy).
+// once (9 loads for 4 pixels instead of 16). The loop stays rolled (registers
+// and occupancy of the FP32 kernels).
 template <int P, int LR, int LC, int NCHB, int PSB, int THREADS, bool POOL>
 __device__ __forceinline__ void stage_tile(unsigned char* lds, const gbyte* in, int64_t rowb, int elb,
                                            int y0, int x0, int hp, int wp, int tid) {
   if constexpr (!POOL) {
     constexpr int NST = LR * LC * NCHB;
     constexpr int NIT = (NST + THREADS - 1) / THREADS;
-    constexpr int UNR = P == BF16 ? NIT : 1;
-#pragma unroll UNR
+#pragma unroll 1
     for (int k = 0; k < NIT; ++k) {
       const int t = tid + k * THREADS;
       if (t >= NST) break;
@@ -275,8 +269,7 @@ __device__ __forceinline__ void stage_tile(unsigned char* lds, const gbyte* in, 
     constexpr int BR = LR / 2, BC = LC / 2;
     constexpr int NST = BR * BC * NCHB;
     constexpr int NIT = (NST + THREADS - 1) / THREADS;
-    constexpr int UNR = P == BF16 ? NIT : 1;
-#pragma unroll UNR
+#pragma unroll 1
     for (int k = 0; k < NIT; ++k) {
       const int t = tid + k * THREADS;
       if (t >= NST) break;
@@ -474,6 +467,7 @@ template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX
 __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS)) void conv_mfma(JobSet js, ConvParams prm) {
   using C = Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>;
   using T = PT<P>;
+  static_assert(P == F32, "conv_mfma is the FP32 (NHWC) kernel; BF16 / FP8 use conv_ws");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_TILE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
@@ -544,7 +538,6 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
     }
 
     // ---- epilogue: lane holds D[m = 4 g + k][n = n16] of each (m-block, n-block)
-    if constexpr (C::STAGE_OUT) __syncthreads();  // the LDS tile is reused for the output
     float bias[C::NB], osc[C::NB], hw[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) {
@@ -577,16 +570,6 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
           if (y < J.hout && x < J.wout)
             st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
         }
-      } else if constexpr (C::STAGE_OUT) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int pix = mrow * TX + mcol * 16 + 4 * g + k;
-#pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) {
-            const float v = relu(fmaf(acc[u][nb][k], osc[nb], bias[nb]));
-            store_act<P>(lds, (int64_t)pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
-          }
-        }
       } else {
         if (y < J.hout) {
 #pragma unroll
@@ -601,20 +584,6 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
               }
             }
           }
-        }
-      }
-    }
-    if constexpr (C::STAGE_OUT) {
-      __syncthreads();
-      const int vcols = min(TX, J.wout - x0);
-      constexpr int ROWB = TX * COUT * T::BYTES;
-      const int vbytes = vcols * COUT * T::BYTES;  // multiple of 16
-      for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
-        const int r = t / (ROWB / 16), q = t % (ROWB / 16);
-        const int y = y0 + r;
-        if (y < J.hout && q * 16 < vbytes) {
-          gbyte* dst = gout(J.out) + (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
-          st<i4v>(dst, ld<i4v>(lds + r * ROWB + q * 16));
         }
       }
     }
@@ -649,9 +618,7 @@ struct CfgRR {
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
   static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
   static constexpr int LDS_IN = LR * LC * PSB;
-  static constexpr bool STAGE_OUT = (P != F32) && !HEAD;
-  static constexpr int LDS_OUT = STAGE_OUT ? TY * TX * COUT * T::BYTES : 0;
-  static constexpr int LDS = LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT;
+  static constexpr int LDS = LDS_IN;
   static constexpr int THREADS = WX * WY * 64;
   static_assert(LDS <= 160 * 1024, "LDS budget of a gfx950 workgroup");
 };
@@ -661,6 +628,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
     JobSet js, ConvParams prm) {
   using C = CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>;
   using T = PT<P>;
+  static_assert(P == F32, "conv_mfma_rr is the FP32 (NHWC) kernel; BF16 / FP8 use conv_ws");
   constexpr int TY = C::TY, TX = C::TX;
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -747,7 +715,6 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
       }
     }
 
-    if constexpr (C::STAGE_OUT) __syncthreads();  // the LDS tile is reused for the output
     float bias[C::NB], osc[C::NB], hw[C::NB];
 #pragma unroll
     for (int nb = 0; nb < C::NB; ++nb) {
@@ -780,16 +747,6 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
             if (y < J.hout && x < J.wout)
               st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
           }
-        } else if constexpr (C::STAGE_OUT) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int pix = trow * TX + tcol + k;
-#pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb) {
-              const float v = relu(fmaf(acc[r][m][nb][k], osc[nb], bias[nb]));
-              store_act<P>(lds, (int64_t)pix * COUT + nb * 16 + n16, v, prm.out_inv_scale);
-            }
-          }
         } else {
           if (y < J.hout) {
 #pragma unroll
@@ -807,20 +764,6 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
           }
         }
       }
-    if constexpr (C::STAGE_OUT) {
-      __syncthreads();
-      const int vcols = min(TX, J.wout - x0);
-      constexpr int ROWB = TX * COUT * T::BYTES;
-      const int vbytes = vcols * COUT * T::BYTES;
-      for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
-        const int r = t / (ROWB / 16), q = t % (ROWB / 16);
-        const int y = y0 + r;
-        if (y < J.hout && q * 16 < vbytes) {
-          gbyte* dst = gout(J.out) + (((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x0) * COUT) * T::BYTES + q * 16;
-          st<i4v>(dst, ld<i4v>(lds + r * ROWB + q * 16));
-        }
-      }
-    }
   }
 }
 
