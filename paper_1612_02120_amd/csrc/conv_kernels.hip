@@ -779,8 +779,9 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 // conv_mfma with both operands in LDS; NPW producer waves fill the LDS. A
 // stage is (tile, channel block): its operand tile (max filter applied) and,
 // for BF16 layers whose packed weights do not fit in LDS next to two operand
-// buffers, its weight slice. BF16 weights that fit are copied to LDS once per
-// workgroup; FP8 consumers read weights through the L1. Stages are double-buffered with one workgroup barrier per stage,
+// buffers, its weight slice. Weights that fit are copied to LDS once per
+// workgroup; FP8 consumers of layers whose weights do not fit read them
+// through the L1. Stages are double-buffered with one workgroup barrier per stage,
 // and the producers issue the global loads of stage k+1 before that barrier,
 // so the load latency overlaps a whole stage of MFMA work.
 
@@ -806,11 +807,15 @@ struct CfgWS {
   static constexpr int BUF = LR * LC * PSB;                // one operand buffer
   static constexpr int WB = NGS * NB * 64 * T::U * 16;     // packed weights of one stage
   static constexpr int LDS_MAX = 160 * 1024;
-  // BF16 consumers read B fragments from LDS. FP8 fragments are two 16-byte
-  // reads each, and B from LDS on top of A would oversubscribe the LDS
-  // (measured slower), so FP8 consumers read B through the L1.
-  static constexpr bool BL = P != FP8;
-  static constexpr bool WRES = BL && 2 * BUF + NCB * WB <= LDS_MAX;  // all weights resident in LDS
+  // BF16 consumers read B fragments from LDS: resident for the workgroup's
+  // lifetime when all packed weights fit next to the two operand buffers,
+  // else one slice per stage, staged by the producers. FP8 consumers read B
+  // from LDS only when all weights are resident (the 3x3 conv); otherwise
+  // (the 5x5 conv, whose 96-byte-stride operand buffers fill the LDS) they
+  // read B through the L1.
+  static constexpr bool FITS = 2 * BUF + NCB * WB <= LDS_MAX;
+  static constexpr bool BL = P != FP8 || FITS;
+  static constexpr bool WRES = BL && FITS;  // all weights resident in LDS
   static constexpr int WOFF = 2 * BUF;
   static constexpr int WLDS = !BL ? 0 : WRES ? NCB * WB : 2 * WB;
   // Fused first layer (K1 > 0): producer wave w builds operand rows
@@ -973,6 +978,28 @@ __device__ __forceinline__ int quad_perm(int v) {
 }
 constexpr int kQuadXor1 = 0xB1;  // lanes [1, 0, 3, 2]
 constexpr int kQuadXor2 = 0x4E;  // lanes [2, 3, 0, 1]
+constexpr int kRowMirror = 0x140;      // lane i <- lane 15 - i of its 16-lane row
+constexpr int kRowHalfMirror = 0x141;  // lane i <- lane 7 - i of its 8-lane half row
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, quad_perm<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+// Sums of four per-lane values v[0..3] over the 16 lanes of each row, with
+// DPP exchanges only (no LDS): two pairing steps that each keep half of the
+// values (across the row mirror, then the half-row mirror), then a quad
+// reduction. On return every lane n16 of a row holds the row sum of
+// v[n16 >> 2].
+__device__ __forceinline__ float row_sum4_transposed(const float v[4], int n16) {
+  const bool lo = n16 < 8, q0 = ((n16 >> 2) & 1) == 0;
+  const float a = (lo ? v[0] : v[2]) + dpp_f<kRowMirror>(lo ? v[2] : v[0]);
+  const float b = (lo ? v[1] : v[3]) + dpp_f<kRowMirror>(lo ? v[3] : v[1]);
+  float r = (q0 ? a : b) + dpp_f<kRowHalfMirror>(q0 ? b : a);
+  r += dpp_f<kQuadXor1>(r);
+  r += dpp_f<kQuadXor2>(r);
+  return r;
+}
 
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   const __bf16 a = (__bf16)lo, b = (__bf16)hi;
@@ -1234,6 +1261,20 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   __syncthreads();  // the first stage is ready
   int cb = 0, sel = 0;
   f4 acc[C::MW][C::NB];
+  // B fragments through the L1 (FP8): a two-step register ring. The loads of
+  // step s + 1 are issued before the MFMAs of step s, and the last step of a
+  // stage loads the first step of the next stage, so the L1 latency is hidden
+  // behind a whole step (and across the stage barrier).
+  constexpr int U16 = T::U * 16;
+  Frag<P> bq[2][C::NB];
+  auto load_b = [&](Frag<P>* dst, const gbyte* wl, int s) __attribute__((always_inline)) {
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) {
+      const gbyte* p = wl + (s * C::NB + nb) * 64 * U16;
+      load_frag<P>(dst[nb], p, p + 64 * 16);
+    }
+  };
+  if constexpr (!C::BL) load_b(bq[0], wglob + lane * 16, 0);
   for (;;) {
     if (cb == 0) {
 #pragma unroll
@@ -1251,7 +1292,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
           const auto p = wl + (s * C::NB + nb) * 64 * (T::U * 16);
-          load_frag<P>(bfr[nb], p, p + 16);
+          load_frag<P>(bfr[nb], p, p + 64 * 16);
         }
         int off[T::U];
 #pragma unroll
@@ -1276,10 +1317,51 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
         }
       }
     };
-    if constexpr (C::BL)
-      kloop(static_cast<const unsigned char*>(lds + C::WOFF + (C::WRES ? cb : sel) * C::WB + lane * (T::U * 16)));
-    else
-      kloop(wglob + (size_t)cb * C::WB + lane * (T::U * 16));
+    if constexpr (C::BL) {
+      kloop(static_cast<const unsigned char*>(lds + C::WOFF + (C::WRES ? cb : sel) * C::WB + lane * 16));
+    } else {
+      // one step of A fragments and MFMAs with the B fragments in `cur`
+      auto mstep = [&](int s, const Frag<P>* cur) __attribute__((always_inline)) {
+        int off[T::U];
+#pragma unroll
+        for (int uu = 0; uu < T::U; ++uu) {
+          int c = s * (4 * T::U) + 4 * uu + g;
+          c = c < C::NCHK ? c : C::NCHK - 1;
+          const int i = c / (KS * C::NCHB);
+          const int rem = c % (KS * C::NCHB);
+          const int j = rem / C::NCHB, cg = rem % C::NCHB;
+          off[uu] = (i * C::LC + j) * C::PSB + cg * 16;
+        }
+        const unsigned char* a0 = abase + off[0];
+        const unsigned char* a1 = abase + off[T::U - 1];
+#pragma unroll
+        for (int u = 0; u < C::MW; ++u) {
+          const int mo = ((u / MCOLS) * C::LC + (u % MCOLS) * 16) * C::PSB;
+          Frag<P> afr;
+          load_frag<P>(afr, a0 + mo, a1 + mo);
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[u][nb], afr, cur[nb]);
+        }
+      };
+      {
+        static_assert(C::NGS % 2 == 0, "the B ring starts every stage at slot 0");
+        const gbyte* wl = wglob + (size_t)cb * C::WB + lane * 16;
+        const gbyte* wn = wglob + (size_t)(cb + 1 == C::NCB ? 0 : cb + 1) * C::WB + lane * 16;
+        // issue the B loads of the following step into `nxt`, then step s
+        auto step = [&](int s, const Frag<P>* cur, Frag<P>* nxt, const gbyte* np, int ns)
+                        __attribute__((always_inline)) {
+          load_b(nxt, np, ns);
+          __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of this step's MFMAs
+          mstep(s, cur);
+        };
+#pragma unroll 1
+        for (int s = 0; s < C::NGS; s += 2) {
+          step(s, bq[0], bq[1], wl, s + 1);
+          const bool last = s + 2 == C::NGS;
+          step(s + 1, bq[1], bq[0], last ? wn : wl, last ? 0 : s + 2);
+        }
+      }
+    }
 
     if (cb == C::NCB - 1) {
       // ---- epilogue straight from the accumulators
@@ -1294,30 +1376,44 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
         hw[nb] = HEAD ? ldf(prm.head_w, nb * 16 + n16) : 0.f;
       }
       const int ty0 = y0 + wrow0;
+      if constexpr (HEAD) {
+        // 1x1 head + sigmoid. Per m-block, lane (g, n16) holds channel n16 of
+        // pixels 4g..4g+3; the channel sums go through row_sum4_transposed, and
+        // lane n16 of a quad keeps m-block 4 * grp + (n16 & 3), so one
+        // sigmoid and one store per lane cover four m-blocks.
+        const int jq = n16 & 3;
 #pragma unroll
-      for (int u = 0; u < C::MW; ++u) {
-        const int y = ty0 + u / MCOLS;
-        const int xb = x0 + (u % MCOLS) * 16;
-        if constexpr (HEAD) {
-          float part[4];
+        for (int grp = 0; grp < (C::MW + 3) / 4; ++grp) {
+          float mine = 0.f;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            float pv = 0.f;
+          for (int jj = 0; jj < 4; ++jj) {
+            const int u = grp * 4 + jj;
+            if (u < C::MW) {
+              float part[4];
 #pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb) pv = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], pv);
-            pv += __shfl_xor(pv, 1);
-            pv += __shfl_xor(pv, 2);
-            pv += __shfl_xor(pv, 4);
-            pv += __shfl_xor(pv, 8);
-            part[k] = pv;
+              for (int k = 0; k < 4; ++k) {
+                float pv = 0.f;
+#pragma unroll
+                for (int nb = 0; nb < C::NB; ++nb)
+                  pv = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], pv);
+                part[k] = pv;
+              }
+              const float r = row_sum4_transposed(part, n16);
+              mine = jq == jj ? r : mine;
+            }
           }
-          if (n16 < 4) {
-            const int x = xb + 4 * g + n16;
-            const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
-            if (y < J.hout && x < J.wout)
-              st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
-          }
-        } else {
+          const int u = grp * 4 + jq;
+          const int y = ty0 + u / MCOLS;
+          const int x = x0 + (u % MCOLS) * 16 + 4 * g + (n16 >> 2);
+          if (u < C::MW && y < J.hout && x < J.wout)
+            st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4,
+                      sigmoid_f(mine + prm.head_b));
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < C::MW; ++u) {
+          const int y = ty0 + u / MCOLS;
+          const int xb = x0 + (u % MCOLS) * 16;
           const int pm = 4 * g + (n16 & 3);
           const int ok = (y < J.hout) && (xb + pm < J.wout);
           gbyte* orow = gout(J.out) + ((int64_t)zz * J.out_zs * COUT + ((int64_t)y * J.out_rs + xb) * 16) * T::BYTES +
@@ -1393,6 +1489,10 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 // of a 12-wave workgroup without spilling).
 #define EMCNN_WS_NARROW(P, CIN, COUT, KS, POOL, HEAD) \
   EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 8, 4), EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 8, 48, 8, 4)
+// Four consumer waves with two tile rows (8 m-blocks) each: 512 threads, so
+// 256 registers per lane, and B fragments shared by twice the m-blocks.
+#define EMCNN_WS_W4(P, CIN, COUT, KS, POOL, HEAD) \
+  EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 8, 64, 4, 4), EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 8, 48, 4, 4)
 #define EMCNN_WS_SHAPES(P, CIN, COUT, KS, POOL, HEAD) \
   EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, 16, 48, 8, 4), EMCNN_WS_NARROW(P, CIN, COUT, KS, POOL, HEAD)
 
@@ -1423,11 +1523,15 @@ static const VariantInfo kConv[] = {
     EMCNN_WS_NARROW(BF16, 48, 48, 5, true, false),
     EMCNN_WSK(BF16, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
     EMCNN_WSK(BF16, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
+    EMCNN_WS_W4(BF16, 48, 48, 5, true, false),
     EMCNN_WS_SHAPES(BF16, 48, 48, 3, true, true),
+    EMCNN_WS_W4(BF16, 48, 48, 3, true, true),
     EMCNN_WS_NARROW(FP8, 48, 48, 5, true, false),
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
+    EMCNN_WS_W4(FP8, 48, 48, 5, true, false),
     EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
+    EMCNN_WS_W4(FP8, 48, 48, 3, true, true),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)

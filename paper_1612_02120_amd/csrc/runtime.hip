@@ -111,7 +111,9 @@ static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b
   const int cin = v->cin, cout = v->cout, ks = v->ks, cb = v->cb, chb = v->chb, u = v->u, ngs = v->ngs;
   const int ncb = cin / cb, nchb = cb / chb, nchk = ks * ks * nchb, nb = cout / 16;
   const int esz = act_bytes(v->prec);
-  // flattened K: [cb][s][nb][lane][u]; row reuse: [cb][i][rs][nb][lane][u]
+  // flattened K: [cb][s][nb][u][lane]; row reuse: [cb][i][rs][nb][u][lane]. The
+  // 16-byte chunk uu of all 64 lanes is contiguous, so each fragment load of a
+  // wave reads one contiguous 1 KB block.
   const int nsteps = v->rr ? ks * ngs : ngs;
   const size_t bytes = (size_t)ncb * nsteps * nb * 64 * u * 16;
   std::vector<uint8_t> pk(bytes, 0);
@@ -155,7 +157,7 @@ static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b
               j = rem / nchb;
               cg = rem % nchb;
             }
-            uint8_t* dst = pk.data() + ((((size_t)(c0 * nsteps + s) * nb + n_b) * 64 + lane) * u + uu) * 16;
+            uint8_t* dst = pk.data() + ((((size_t)(c0 * nsteps + s) * nb + n_b) * u + uu) * 64 + lane) * 16;
             for (int t = 0; t < chb; ++t) {
               const int ci = c0 * cb + cg * chb + t;
               const double val = wq[(((size_t)co * cin + ci) * ks + i) * ks + j];
