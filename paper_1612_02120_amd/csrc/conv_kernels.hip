@@ -192,6 +192,75 @@ __device__ __forceinline__ void load_frag(Frag<P>& f, const B* p0, const B* p1) 
   }
 }
 
+// Lane exchange inside groups of 4 lanes (DPP quad permutation).
+template <int CTRL>
+__device__ __forceinline__ int quad_perm(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kQuadXor1 = 0xB1;  // lanes [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // lanes [2, 3, 0, 1]
+constexpr int kRowMirror = 0x140;      // lane i <- lane 15 - i of its 16-lane row
+constexpr int kRowHalfMirror = 0x141;  // lane i <- lane 7 - i of its 8-lane half row
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, quad_perm<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+// Sums of four per-lane values v[0..3] over the 16 lanes of each row, with
+// DPP exchanges only (no LDS): two pairing steps that each keep half of the
+// values (across the row mirror, then the half-row mirror), then a quad
+// reduction. On return every lane n16 of a row holds the row sum of
+// v[n16 >> 2].
+__device__ __forceinline__ float row_sum4_transposed(const float v[4], int n16) {
+  const bool lo = n16 < 8, q0 = ((n16 >> 2) & 1) == 0;
+  const float a = (lo ? v[0] : v[2]) + dpp_f<kRowMirror>(lo ? v[2] : v[0]);
+  const float b = (lo ? v[1] : v[3]) + dpp_f<kRowMirror>(lo ? v[3] : v[1]);
+  float r = (q0 ? a : b) + dpp_f<kRowHalfMirror>(q0 ? b : a);
+  r += dpp_f<kQuadXor1>(r);
+  r += dpp_f<kQuadXor2>(r);
+  return r;
+}
+
+
+// 1x1 head + sigmoid straight from MFMA accumulators, for NU m-blocks of 16
+// pixels. val(u, nb, k) is lane (g, n16)'s accumulator for pixel 4g + k of
+// m-block u and channel nb * 16 + n16; pos(u, y, x) gives m-block u's output
+// row and first column. The channel sums go through row_sum4_transposed, after
+// which the four lanes of a quad hold four different m-blocks, so one sigmoid
+// and one store per lane serve four m-blocks.
+template <int NU, int NB, class Val, class Pos>
+__device__ __forceinline__ void head_epilogue(Val val, Pos pos, const float (&bias)[NB], const float (&osc)[NB],
+                                              const float (&hw)[NB], float head_b, int g, int n16, gbyte* out,
+                                              int64_t zoff, int64_t rs, int hout, int wout) {
+  const int jq = n16 & 3;
+#pragma unroll
+  for (int grp = 0; grp < (NU + 3) / 4; ++grp) {
+    float mine = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int u = grp * 4 + jj;
+      if (u < NU) {
+        float part[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float pv = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) pv = fmaf(relu(fmaf(val(u, nb, k), osc[nb], bias[nb])), hw[nb], pv);
+          part[k] = pv;
+        }
+        const float r = row_sum4_transposed(part, n16);
+        mine = jq == jj ? r : mine;
+      }
+    }
+    const int u = grp * 4 + jq;
+    int y, xb;
+    pos(u, y, xb);
+    const int x = xb + 4 * g + (n16 >> 2);
+    if (u < NU && y < hout && x < wout) st<float>(out + (zoff + (int64_t)y * rs + x) * 4, sigmoid_f(mine + head_b));
+  }
+}
+
 // Persistent work distribution: workgroup b serves XCD b % 8 (hardware
 // round-robin) and walks the matching eighth of the item range.
 struct ItemRange {
@@ -545,32 +614,21 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::THREADS))
       osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
       if constexpr (HEAD) hw[nb] = ldf(prm.head_w, nb * 16 + n16);
     }
+    if constexpr (HEAD) {
+      head_epilogue<MW, C::NB>(
+          [&](int u, int nb, int k) __attribute__((always_inline)) { return acc[u][nb][k]; },
+          [&](int u, int& y, int& xb) __attribute__((always_inline)) {
+            const int mb = wave * MW + u;
+            y = y0 + mb / MCOLS;
+            xb = x0 + (mb % MCOLS) * 16;
+          },
+          bias, osc, hw, prm.head_b, g, n16, gout(J.out), (int64_t)zz * J.out_zs, J.out_rs, J.hout, J.wout);
+    } else {
 #pragma unroll
-    for (int u = 0; u < MW; ++u) {
-      const int mb = wave * MW + u;
-      const int mrow = mb / MCOLS, mcol = mb % MCOLS;
-      const int y = y0 + mrow;
-      const int xb = x0 + mcol * 16 + 4 * g;
-      if constexpr (HEAD) {
-        float part[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          float pv = 0.f;
-#pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) pv = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], pv);
-          pv += __shfl_xor(pv, 1);
-          pv += __shfl_xor(pv, 2);
-          pv += __shfl_xor(pv, 4);
-          pv += __shfl_xor(pv, 8);
-          part[k] = pv;
-        }
-        if (n16 < 4) {
-          const int x = xb + n16;
-          const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
-          if (y < J.hout && x < J.wout)
-            st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
-        }
-      } else {
+      for (int u = 0; u < MW; ++u) {
+        const int mb = wave * MW + u;
+        const int y = y0 + mb / MCOLS;
+        const int xb = x0 + (mb % MCOLS) * 16 + 4 * g;
         if (y < J.hout) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
@@ -722,32 +780,20 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
       osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
       if constexpr (HEAD) hw[nb] = ldf(prm.head_w, nb * 16 + n16);
     }
+    if constexpr (HEAD) {
+      head_epilogue<MR * MC, C::NB>(
+          [&](int u, int nb, int k) __attribute__((always_inline)) { return acc[u / MC][u % MC][nb][k]; },
+          [&](int u, int& y, int& xb) __attribute__((always_inline)) {
+            y = y0 + wy * MR + u / MC;
+            xb = x0 + (wx * MC + u % MC) * 16;
+          },
+          bias, osc, hw, prm.head_b, g, n16, gout(J.out), (int64_t)zz * J.out_zs, J.out_rs, J.hout, J.wout);
+    } else {
 #pragma unroll
-    for (int r = 0; r < MR; ++r)
+      for (int r = 0; r < MR; ++r)
 #pragma unroll
-      for (int m = 0; m < MC; ++m) {
-        const int trow = wy * MR + r, tcol = (wx * MC + m) * 16 + 4 * g;
-        const int y = y0 + trow, xb = x0 + tcol;
-        if constexpr (HEAD) {
-          float part[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            float pv = 0.f;
-#pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb) pv = fmaf(relu(fmaf(acc[r][m][nb][k], osc[nb], bias[nb])), hw[nb], pv);
-            pv += __shfl_xor(pv, 1);
-            pv += __shfl_xor(pv, 2);
-            pv += __shfl_xor(pv, 4);
-            pv += __shfl_xor(pv, 8);
-            part[k] = pv;
-          }
-          if (n16 < 4) {
-            const int x = xb + n16;
-            const float zl = (n16 == 0 ? part[0] : n16 == 1 ? part[1] : n16 == 2 ? part[2] : part[3]) + prm.head_b;
-            if (y < J.hout && x < J.wout)
-              st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, sigmoid_f(zl));
-          }
-        } else {
+        for (int m = 0; m < MC; ++m) {
+          const int y = y0 + wy * MR + r, xb = x0 + (wx * MC + m) * 16 + 4 * g;
           if (y < J.hout) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -763,7 +809,7 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
             }
           }
         }
-      }
+    }
   }
 }
 
@@ -970,36 +1016,6 @@ struct WStage {
     }
   }
 };
-
-// Lane exchange inside groups of 4 lanes (DPP quad permutation).
-template <int CTRL>
-__device__ __forceinline__ int quad_perm(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-constexpr int kQuadXor1 = 0xB1;  // lanes [1, 0, 3, 2]
-constexpr int kQuadXor2 = 0x4E;  // lanes [2, 3, 0, 1]
-constexpr int kRowMirror = 0x140;      // lane i <- lane 15 - i of its 16-lane row
-constexpr int kRowHalfMirror = 0x141;  // lane i <- lane 7 - i of its 8-lane half row
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __builtin_bit_cast(float, quad_perm<CTRL>(__builtin_bit_cast(int, v)));
-}
-
-// Sums of four per-lane values v[0..3] over the 16 lanes of each row, with
-// DPP exchanges only (no LDS): two pairing steps that each keep half of the
-// values (across the row mirror, then the half-row mirror), then a quad
-// reduction. On return every lane n16 of a row holds the row sum of
-// v[n16 >> 2].
-__device__ __forceinline__ float row_sum4_transposed(const float v[4], int n16) {
-  const bool lo = n16 < 8, q0 = ((n16 >> 2) & 1) == 0;
-  const float a = (lo ? v[0] : v[2]) + dpp_f<kRowMirror>(lo ? v[2] : v[0]);
-  const float b = (lo ? v[1] : v[3]) + dpp_f<kRowMirror>(lo ? v[3] : v[1]);
-  float r = (q0 ? a : b) + dpp_f<kRowHalfMirror>(q0 ? b : a);
-  r += dpp_f<kQuadXor1>(r);
-  r += dpp_f<kQuadXor2>(r);
-  return r;
-}
 
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   const __bf16 a = (__bf16)lo, b = (__bf16)hi;
@@ -1377,38 +1393,13 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
       }
       const int ty0 = y0 + wrow0;
       if constexpr (HEAD) {
-        // 1x1 head + sigmoid. Per m-block, lane (g, n16) holds channel n16 of
-        // pixels 4g..4g+3; the channel sums go through row_sum4_transposed, and
-        // lane n16 of a quad keeps m-block 4 * grp + (n16 & 3), so one
-        // sigmoid and one store per lane cover four m-blocks.
-        const int jq = n16 & 3;
-#pragma unroll
-        for (int grp = 0; grp < (C::MW + 3) / 4; ++grp) {
-          float mine = 0.f;
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            const int u = grp * 4 + jj;
-            if (u < C::MW) {
-              float part[4];
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                float pv = 0.f;
-#pragma unroll
-                for (int nb = 0; nb < C::NB; ++nb)
-                  pv = fmaf(relu(fmaf(acc[u][nb][k], osc[nb], bias[nb])), hw[nb], pv);
-                part[k] = pv;
-              }
-              const float r = row_sum4_transposed(part, n16);
-              mine = jq == jj ? r : mine;
-            }
-          }
-          const int u = grp * 4 + jq;
-          const int y = ty0 + u / MCOLS;
-          const int x = x0 + (u % MCOLS) * 16 + 4 * g + (n16 >> 2);
-          if (u < C::MW && y < J.hout && x < J.wout)
-            st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4,
-                      sigmoid_f(mine + prm.head_b));
-        }
+        head_epilogue<C::MW, C::NB>(
+            [&](int u, int nb, int k) __attribute__((always_inline)) { return acc[u][nb][k]; },
+            [&](int u, int& y, int& xb) __attribute__((always_inline)) {
+              y = ty0 + u / MCOLS;
+              xb = x0 + (u % MCOLS) * 16;
+            },
+            bias, osc, hw, prm.head_b, g, n16, gout(J.out), (int64_t)zz * J.out_zs, J.out_rs, J.hout, J.wout);
       } else {
 #pragma unroll
         for (int u = 0; u < C::MW; ++u) {
