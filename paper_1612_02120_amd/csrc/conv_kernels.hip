@@ -98,6 +98,16 @@ __device__ __forceinline__ unsigned char to_e4m3(float v) {
   return (unsigned char)(packed & 0xff);
 }
 
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const __bf16 a = (__bf16)lo, b = (__bf16)hi;
+  return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+}
+
+__device__ __forceinline__ uint32_t pack_e4m3x2(float lo, float hi) {
+  // non-negative inputs; saturate at the largest finite e4m3fn value
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(lo, 448.0f), fminf(hi, 448.0f), 0, false) & 0xffffu;
+}
+
 // Store element idx of an activation array (LDS or global) in the layer's format.
 template <int P, class B>
 __device__ __forceinline__ void store_act(B* base, int64_t idx, float v, float inv) {
@@ -397,9 +407,7 @@ struct FirstCfg {
   static constexpr int MW = MBLK / WAVES;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int NSTEP = PO == F32 ? (KS * KS + 3) / 4 : 1;
-  static constexpr int IN_BYTES = (LR * LC + 15) / 16 * 16;
-  static constexpr int OUT_BYTES = TY * TX * COUT * ESZ;
-  static constexpr int LDS = IN_BYTES + OUT_BYTES;
+  static constexpr int LDS = (LR * LC + 15) / 16 * 16;  // the uint8 input tile
   static_assert(KS * KS <= 32, "first layer supports up to 32 taps");
   static_assert(MBLK % WAVES == 0 && TX % 16 == 0, "tile must split into m-blocks per wave");
 };
@@ -407,9 +415,7 @@ struct FirstCfg {
 template <int PO, int COUT, int KS, int TY, int TX>
 __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void conv_first(JobSet js, FirstParams prm) {
   using C = FirstCfg<PO, COUT, KS, TY, TX>;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
-  unsigned char* tile = lds;
-  unsigned char* obuf = lds + C::IN_BYTES;
+  __shared__ __attribute__((aligned(16))) unsigned char tile[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
   constexpr int MCOLS = TX / 16;
@@ -428,9 +434,14 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
         }
       }
   }
-  float bias[C::NB];
+  // D = W X: lane (g, n16) accumulates channels nb * 16 + 4g .. 4g + 3 of
+  // pixel n16 of an m-block, so it stores 4 consecutive channels straight
+  // from registers (the 64 lanes of a channel plane write one contiguous run)
+  float bias[C::NB][4];
 #pragma unroll
-  for (int nb = 0; nb < C::NB; ++nb) bias[nb] = ldf(prm.bias, nb * 16 + n16);
+  for (int nb = 0; nb < C::NB; ++nb)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bias[nb][k] = ldf(prm.bias, nb * 16 + 4 * g + k);
 
   const ItemRange rg = item_range(js.total_items);
   int cur = 0;
@@ -452,6 +463,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
       tile[t] = in[(int64_t)y * J.in_rs + x];
     }
     __syncthreads();
+    gbyte* oslice = gout(J.out) + (int64_t)zz * J.out_zs * COUT * C::ESZ;
 #pragma unroll
     for (int u = 0; u < C::MW; ++u) {
       const int mb = wave * C::MW + u;
@@ -467,7 +479,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
           const float a = k < KS * KS ? (float)a0[(k / KS) * C::LC + k % KS] : 0.f;
 #pragma unroll
           for (int nb = 0; nb < C::NB; ++nb)
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wf[s][nb].v[0], acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wf[s][nb].v[0], a, acc[nb], 0, 0, 0);
         }
       } else {
         bf16x8 a;
@@ -478,46 +490,29 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
         }
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wf[0][nb].v, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][nb].v, a, acc[nb], 0, 0, 0);
       }
-      // D[m = 4 g + k][n = n16] -> tile pixel (mrow, mcol*16 + 4g + k), channel nb*16 + n16
+      const int y = y0 + mrow, x = x0 + mcol * 16 + n16;
+      if (y < J.hout && x < J.wout) {
+        const int64_t pix = (int64_t)y * J.out_rs + x;
 #pragma unroll
-      for (int nb = 0; nb < C::NB; ++nb)
+        for (int nb = 0; nb < C::NB; ++nb) {
+          float v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int pix = mrow * TX + mcol * 16 + 4 * g + k;
-          const float v = relu(acc[nb][k] + bias[nb]);
-          const int64_t idx = C::BLOCKED ? ((int64_t)nb * TY * TX + pix) * 16 + n16 : (int64_t)pix * COUT + nb * 16 + n16;
-          store_act<PO>(obuf, idx, v, prm.out_inv_scale);
-        }
-    }
-    __syncthreads();
-    // coalesced copy-out
-    const int vcols = min(TX, J.wout - x0);
-    gbyte* oslice = gout(J.out) + (int64_t)zz * J.out_zs * COUT * C::ESZ;
-    if constexpr (!C::BLOCKED) {
-      // NHWC: each tile row is one contiguous run
-      constexpr int ROWB = TX * COUT * C::ESZ;
-      const int vbytes = vcols * COUT * C::ESZ;  // multiple of 16
-      for (int t = tid; t < TY * (ROWB / 16); t += C::THREADS) {
-        const int r = t / (ROWB / 16), q = t % (ROWB / 16);
-        const int y = y0 + r;
-        if (y < J.hout && q * 16 < vbytes) {
-          st<i4v>(oslice + ((int64_t)y * J.out_rs + x0) * COUT * C::ESZ + q * 16, ld<i4v>(obuf + r * ROWB + q * 16));
-        }
-      }
-    } else {
-      // channel-blocked: each (plane, tile row) is one contiguous run
-      constexpr int ROWB = TX * 16 * C::ESZ;
-      const int vbytes = vcols * 16 * C::ESZ;  // multiple of 16
-      const int64_t plane_b = J.out_zs * 16 * C::ESZ;
-      for (int t = tid; t < C::NB * TY * (ROWB / 16); t += C::THREADS) {
-        const int q = t % (ROWB / 16), rr = t / (ROWB / 16);
-        const int r = rr % TY, nb = rr / TY;
-        const int y = y0 + r;
-        if (y < J.hout && q * 16 < vbytes) {
-          st<i4v>(oslice + nb * plane_b + ((int64_t)y * J.out_rs + x0) * 16 * C::ESZ + q * 16,
-                  ld<i4v>(obuf + (nb * TY + r) * ROWB + q * 16));
+          for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
+          if constexpr (PO == F32) {
+            // NHWC
+            st<f4>(oslice + (pix * COUT + nb * 16 + 4 * g) * 4, f4{v[0], v[1], v[2], v[3]});
+          } else {
+            // channel-blocked: plane nb, 16 channels per pixel
+            gbyte* dst = oslice + ((int64_t)nb * J.out_zs + pix) * 16 * C::ESZ + 4 * g * C::ESZ;
+            if constexpr (PO == BF16) {
+              st<u2v>(dst, u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])});
+            } else {
+              const float inv = prm.out_inv_scale;
+              st<uint32_t>(dst, pack_e4m3x2(v[0] * inv, v[1] * inv) | (pack_e4m3x2(v[2] * inv, v[3] * inv) << 16));
+            }
+          }
         }
       }
     }
@@ -1017,15 +1012,6 @@ struct WStage {
   }
 };
 
-__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-  const __bf16 a = (__bf16)lo, b = (__bf16)hi;
-  return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
-}
-
-__device__ __forceinline__ uint32_t pack_e4m3x2(float lo, float hi) {
-  // non-negative inputs; saturate at the largest finite e4m3fn value
-  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(lo, 448.0f), fminf(hi, 448.0f), 0, false) & 0xffffu;
-}
 
 // Store one (m-block, n-block) accumulator tile in the channel-blocked layout.
 // Lane (g, n) holds channel n of pixels 4g..4g+3. Two quad exchanges leave
@@ -1544,9 +1530,9 @@ static const VariantInfo kConv[] = {
 
 static const FirstInfo kFirst[] = {
     // defaults (first match per signature) are the measured fastest shapes
-    EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 4, 64), EMCNN_FIRST(FP8, 48, 5, 8, 64),
-    EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64),
-    EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 16, 64),
+    EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64), EMCNN_FIRST(FP8, 48, 5, 16, 64),
+    EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 4, 64),
+    EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 8, 64),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }
