@@ -20,8 +20,8 @@ import numpy as np
 
 from . import build as _build
 
-_KIND = {"conv": 0, "pool": 1}
-_ACT = {"none": 0, "relu": 1, "sigmoid": 2}
+_KIND = {"conv": 0, "pool": 1, "pool2": 2}
+_ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4}
 QMODES = {"exact": 0, "bf16": 1, "fp8": 2}
 
 
@@ -55,6 +55,8 @@ def lib():
         L.orc_sigmoid.argtypes = [ctypes.c_double]
         L.orc_sigmoid.restype = ctypes.c_double
         L.orc_radius.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_patch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -66,7 +68,7 @@ def _layers(net):
         if L["kind"] == "conv":
             arr[i] = _Layer(0, L["k"], L["cin"], L["cout"], _ACT[L["act"]])
         else:
-            arr[i] = _Layer(1, 2, 0, 0, 0)
+            arr[i] = _Layer(_KIND[L["kind"]], 2, 0, 0, 0)
     return arr
 
 
@@ -75,8 +77,28 @@ def _ptr(a):
 
 
 def radius(net) -> int:
-    """R = sum of (k-1) over convs plus 1 per 2x2 stride-1 max filter; FoV = R+1."""
-    return sum(L["k"] - 1 if L["kind"] == "conv" else 1 for L in net)
+    """Receptive radius R (FoV = R + 1): r += (k - 1) j and j *= stride over the
+    layers, a 2x2 pool counting as k = 2 ("pool2" has stride 2, "pool" 1)."""
+    R, j = 0, 1
+    for L in net:
+        R += (L["k"] - 1 if L["kind"] == "conv" else 1) * j
+        if L["kind"] == "pool2":
+            j *= 2
+    return R
+
+
+def patch(img, net, params, y, x):
+    """Patch form at (y, x): the net on the (R+1)^2 window of one slice with
+    plain stride-1 convs and stride-2 pools. Returns (probability, logit)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    out, lg = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().orc_patch(_ptr(img), H, W, _layers(net), len(net), _ptr(params), int(y), int(x),
+                         ctypes.byref(out), ctypes.byref(lg))
+    if rc:
+        raise ValueError("oracle patch failed (%d)" % rc)
+    return out.value, lg.value
 
 
 def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=False):

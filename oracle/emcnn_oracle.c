@@ -20,6 +20,17 @@
  *   sigmoid    1/(1+e^-t) for t >= 0, e^t/(1+e^t) for t < 0; equal to the
  *              two-class softmax whose outputs are interleaved in Section 2.2.
  *
+ * Nets with stride-2 max-pools (FastMemb, Section 2.2: 4x4 convs with 32
+ * features, 2x2/s2 max-pools, max-out, a two-class output):
+ *   dense form (what the GPU computes; "dilation" d starts at 1)
+ *     conv       a'[co][y][x] = b[co] + sum_ci,i,j W[co][ci][i][j] a[ci][y+d i][x+d j]
+ *     pool, s=2  m[c][y][x] = max over i, j in {0,1} of a[c][y+d i][x+d j]; then d *= 2
+ *   max-out      m[c] = max(a[2c], a[2c+1])      (channel pairs, Goodfellow et al.)
+ *   softmax      p = e^{z1} / (e^{z0} + e^{z1}), the class-1 (membrane) output
+ *   patch form (the definition the dense form must reproduce): the same net on
+ *     one field-of-view window with plain stride-1 convs and stride-2 pools,
+ *     which leaves a single output (orc_patch).
+ *
  * Fake-quant modes mirror the number formats declared by the GPU forms (the
  * paper states no precision; these are readings):
  *   BF16: first conv uses weights bf16((float)(w/255)) against the raw uint8
@@ -42,8 +53,8 @@
 #include <omp.h>
 #endif
 
-enum { ORC_CONV = 0, ORC_POOL = 1 };
-enum { ORC_ACT_NONE = 0, ORC_ACT_RELU = 1, ORC_ACT_SIGMOID = 2 };
+enum { ORC_CONV = 0, ORC_POOL = 1, ORC_POOL2 = 2 };
+enum { ORC_ACT_NONE = 0, ORC_ACT_RELU = 1, ORC_ACT_SIGMOID = 2, ORC_ACT_MAXOUT = 3, ORC_ACT_SOFTMAX = 4 };
 enum { ORC_Q_EXACT = 0, ORC_Q_BF16 = 1, ORC_Q_FP8 = 2 };
 
 typedef struct {
@@ -100,9 +111,10 @@ void orc_e4m3_array(const double* in, double* out, int64_t n) {
 
 /* ---------------- layer definitions ---------------- */
 
+/* valid cross-correlation with tap spacing D (D = 1: plain) */
 static void conv_valid(const double* in, int C, int H, int W, const double* w,
-                       const double* b, int K, int Co, double* out) {
-  int Ho = H - K + 1, Wo = W - K + 1;
+                       const double* b, int K, int Co, int D, double* out) {
+  int Ho = H - (K - 1) * D, Wo = W - (K - 1) * D;
 #pragma omp parallel for collapse(2) schedule(static)
   for (int co = 0; co < Co; ++co)
     for (int y = 0; y < Ho; ++y)
@@ -111,23 +123,79 @@ static void conv_valid(const double* in, int C, int H, int W, const double* w,
         for (int ci = 0; ci < C; ++ci)
           for (int i = 0; i < K; ++i)
             for (int j = 0; j < K; ++j)
-              s += w[((co * C + ci) * K + i) * K + j] * in[((int64_t)ci * H + y + i) * W + x + j];
+              s += w[((co * C + ci) * K + i) * K + j] * in[((int64_t)ci * H + y + i * D) * W + x + j * D];
         out[((int64_t)co * Ho + y) * Wo + x] = s;
       }
 }
 
-static void pool2(const double* in, int C, int H, int W, double* out) {
-  int Ho = H - 1, Wo = W - 1;
+/* 2x2 max filter with element spacing D (stride 1) */
+static void pool2(const double* in, int C, int H, int W, int D, double* out) {
+  int Ho = H - D, Wo = W - D;
   for (int c = 0; c < C; ++c)
     for (int y = 0; y < Ho; ++y)
       for (int x = 0; x < Wo; ++x) {
         const double* p = in + ((int64_t)c * H + y) * W + x;
         double m = p[0];
-        if (p[1] > m) m = p[1];
-        if (p[W] > m) m = p[W];
-        if (p[W + 1] > m) m = p[W + 1];
+        if (p[D] > m) m = p[D];
+        if (p[(int64_t)D * W] > m) m = p[(int64_t)D * W];
+        if (p[(int64_t)D * W + D] > m) m = p[(int64_t)D * W + D];
         out[((int64_t)c * Ho + y) * Wo + x] = m;
       }
+}
+
+/* 2x2 max-pool with stride 2 (patch form): out[c][y][x] = max of in[c][2y+i][2x+j] */
+static void pool2_stride2(const double* in, int C, int H, int W, double* out) {
+  int Ho = H / 2, Wo = W / 2;
+  for (int c = 0; c < C; ++c)
+    for (int y = 0; y < Ho; ++y)
+      for (int x = 0; x < Wo; ++x) {
+        double m = in[((int64_t)c * H + 2 * y) * W + 2 * x];
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            double v = in[((int64_t)c * H + 2 * y + i) * W + 2 * x + j];
+            if (v > m) m = v;
+          }
+        out[((int64_t)c * Ho + y) * Wo + x] = m;
+      }
+}
+
+/* Activation of a conv output o (Co x n). Returns the channel count after it
+ * (max-out halves it, softmax leaves the class-1 probability); -1 if invalid.
+ * logit (nullable) receives the pre-activation output of one-channel convs,
+ * and z1 - z0 for the two-class softmax (so that sigmoid(logit) = p). */
+static int activate(double* o, int Co, int64_t n, int act, double* logit) {
+  if (act == ORC_ACT_MAXOUT) {
+    if (Co % 2) return -1;
+    for (int c = 0; c < Co / 2; ++c)
+      for (int64_t i = 0; i < n; ++i) {
+        double a = o[(2 * c) * n + i], b = o[(2 * c + 1) * n + i];
+        o[c * n + i] = a > b ? a : b;
+      }
+    return Co / 2;
+  }
+  if (act == ORC_ACT_SOFTMAX) {
+    if (Co != 2) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+      double z0 = o[i], z1 = o[n + i], m = z0 > z1 ? z0 : z1;
+      double e0 = exp(z0 - m), e1 = exp(z1 - m);
+      if (logit) logit[i] = z1 - z0;
+      o[i] = e1 / (e0 + e1);
+    }
+    return 1;
+  }
+  if (logit && Co == 1) memcpy(logit, o, sizeof(double) * n);
+  for (int64_t i = 0; i < (int64_t)Co * n; ++i) {
+    if (act == ORC_ACT_RELU) o[i] = o[i] > 0.0 ? o[i] : 0.0;
+    else if (act == ORC_ACT_SIGMOID) o[i] = orc_sigmoid(o[i]);
+  }
+  return Co;
+}
+
+/* Nets with stride-2 pools, max-out or softmax are defined in exact FP64 only. */
+static int strided_net(const orc_layer* L, int nl) {
+  for (int l = 0; l < nl; ++l)
+    if (L[l].kind == ORC_POOL2 || L[l].act == ORC_ACT_MAXOUT || L[l].act == ORC_ACT_SOFTMAX) return 1;
+  return 0;
 }
 
 static int param_count(const orc_layer* L, int nl) {
@@ -145,6 +213,8 @@ static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, i
                          double* out_prob, double* out_logit, double** trace,
                          int32_t* trace_dims) {
   int C = 1, h = H, w = W;
+  int dil = 1; /* spacing of the dense form; doubled by every stride-2 pool */
+  if (qmode != ORC_Q_EXACT && strided_net(L, nl)) return -1;
   double* a = (double*)malloc(sizeof(double) * (size_t)H * W);
   if (!a) return -2;
   int first = 1;
@@ -162,7 +232,7 @@ static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, i
       const double* wt = p;
       const double* bs = p + nw;
       p += nw + Co;
-      int Ho = h - K + 1, Wo = w - K + 1;
+      int Ho = h - (K - 1) * dil, Wo = w - (K - 1) * dil;
       if (Ho < 1 || Wo < 1) { free(a); return -1; }
       int is_head = (l == nl - 1) && K == 1 && Co == 1;
       double* wq = (double*)malloc(sizeof(double) * nw);
@@ -204,33 +274,30 @@ static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, i
       o = (double*)malloc(sizeof(double) * (size_t)Co * Ho * Wo);
       if (osc) {
         double* zb = (double*)calloc(Co, sizeof(double));
-        conv_valid(ain, C, h, w, wq, zb, K, Co, o);
+        conv_valid(ain, C, h, w, wq, zb, K, Co, dil, o);
         free(zb);
         for (int co = 0; co < Co; ++co)
           for (int64_t i = 0; i < (int64_t)Ho * Wo; ++i)
             o[(int64_t)co * Ho * Wo + i] = bs[co] + osc[co] * o[(int64_t)co * Ho * Wo + i];
       } else {
-        conv_valid(ain, C, h, w, wq, bs, K, Co, o);
+        conv_valid(ain, C, h, w, wq, bs, K, Co, dil, o);
       }
       free(wq);
       free(aq);
       free(osc);
       first = 0;
       ++conv_idx;
-      C = Co;
       h = Ho;
       w = Wo;
-      if (l == nl - 1 && out_logit) memcpy(out_logit, o, sizeof(double) * (size_t)h * w);
-      for (int64_t i = 0; i < (int64_t)C * h * w; ++i) {
-        if (ly->act == ORC_ACT_RELU) o[i] = o[i] > 0.0 ? o[i] : 0.0;
-        else if (ly->act == ORC_ACT_SIGMOID) o[i] = orc_sigmoid(o[i]);
-      }
-    } else if (ly->kind == ORC_POOL) {
-      if (h < 2 || w < 2) { free(a); return -1; }
-      o = (double*)malloc(sizeof(double) * (size_t)C * (h - 1) * (w - 1));
-      pool2(a, C, h, w, o);
-      h -= 1;
-      w -= 1;
+      C = activate(o, Co, (int64_t)h * w, ly->act, l == nl - 1 ? out_logit : NULL);
+      if (C < 0) { free(o); free(a); return -1; }
+    } else if (ly->kind == ORC_POOL || ly->kind == ORC_POOL2) {
+      if (h <= dil || w <= dil) { free(a); return -1; }
+      o = (double*)malloc(sizeof(double) * (size_t)C * (h - dil) * (w - dil));
+      pool2(a, C, h, w, dil, o);
+      h -= dil;
+      w -= dil;
+      if (ly->kind == ORC_POOL2) dil *= 2;
     } else {
       free(a);
       return -1;
@@ -251,11 +318,68 @@ static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, i
   return 0;
 }
 
-/* Receptive radius R = sum over convs of (k-1) plus 1 per 2x2/s1 pool. */
+/* Receptive radius R (field of view R + 1): the recursion r += (k - 1) j,
+ * j *= s over the layers, with j the input spacing of a layer (a 2x2 pool is
+ * k = 2; stride 2 doubles j). */
 int orc_radius(const orc_layer* L, int nl) {
-  int R = 0;
-  for (int l = 0; l < nl; ++l) R += (L[l].kind == ORC_CONV) ? L[l].k - 1 : 1;
+  int R = 0, j = 1;
+  for (int l = 0; l < nl; ++l) {
+    R += (L[l].kind == ORC_CONV ? L[l].k - 1 : 1) * j;
+    if (L[l].kind == ORC_POOL2) j *= 2;
+  }
   return R;
+}
+
+/* Patch form at one position: the net applied to the (R+1) x (R+1) window of
+ * img (H x W) with top-left corner (y, x), using plain stride-1 convs and
+ * stride-2 pools, as in a sliding-window classifier. out: the single output
+ * (probability); logit (nullable): its logit as orc_forward reports it. */
+int orc_patch(const uint8_t* img, int H, int W, const orc_layer* L, int nl, const double* params,
+              int y, int x, double* out, double* logit) {
+  int F = orc_radius(L, nl) + 1;
+  if (y < 0 || x < 0 || y + F > H || x + F > W) return -1;
+  int C = 1, h = F, w = F;
+  double* a = (double*)malloc(sizeof(double) * (size_t)F * F);
+  if (!a) return -2;
+  for (int r = 0; r < F; ++r)
+    for (int c = 0; c < F; ++c) a[r * F + c] = img[(int64_t)(y + r) * W + x + c] / 255.0;
+  const double* p = params;
+  for (int l = 0; l < nl; ++l) {
+    const orc_layer* ly = &L[l];
+    double* o = NULL;
+    if (ly->kind == ORC_CONV) {
+      int K = ly->k, Co = ly->cout, nw = Co * C * K * K;
+      if (ly->cin != C || h < K || w < K) { free(a); return -1; }
+      o = (double*)malloc(sizeof(double) * (size_t)Co * (h - K + 1) * (w - K + 1));
+      conv_valid(a, C, h, w, p, p + nw, K, Co, 1, o);
+      p += nw + Co;
+      h -= K - 1;
+      w -= K - 1;
+      C = activate(o, Co, (int64_t)h * w, ly->act, l == nl - 1 ? logit : NULL);
+      if (C < 0) { free(o); free(a); return -1; }
+    } else if (ly->kind == ORC_POOL) {
+      if (h < 2 || w < 2) { free(a); return -1; }
+      o = (double*)malloc(sizeof(double) * (size_t)C * (h - 1) * (w - 1));
+      pool2(a, C, h, w, 1, o);
+      h -= 1;
+      w -= 1;
+    } else if (ly->kind == ORC_POOL2) {
+      if (h < 2 || w < 2) { free(a); return -1; }
+      o = (double*)malloc(sizeof(double) * (size_t)C * (h / 2) * (w / 2));
+      pool2_stride2(a, C, h, w, o);
+      h /= 2;
+      w /= 2;
+    } else {
+      free(a);
+      return -1;
+    }
+    free(a);
+    a = o;
+  }
+  int rc = (C == 1 && h == 1 && w == 1) ? 0 : -1;
+  if (!rc && out) *out = a[0];
+  free(a);
+  return rc;
 }
 
 /* vol: Z x H x W uint8; prob (nullable), logit (nullable): Z x (H-R) x (W-R). */
@@ -339,7 +463,7 @@ int orc_student_loss_grad(const uint8_t* patches, int B, int P, const double* te
     for (int l = 0; l < nl; ++l) {
       const double* wt = params + poff[l];
       const double* bs = wt + L[l].cout * L[l].cin * L[l].k * L[l].k;
-      conv_valid(act[l], cs[l], hs[l], hs[l], wt, bs, L[l].k, cs[l + 1], pre[l + 1]);
+      conv_valid(act[l], cs[l], hs[l], hs[l], wt, bs, L[l].k, cs[l + 1], 1, pre[l + 1]);
       int64_t n = (int64_t)cs[l + 1] * hs[l + 1] * hs[l + 1];
       for (int64_t i = 0; i < n; ++i) {
         double v = pre[l + 1][i];

@@ -8,9 +8,16 @@ dense output by replacing pooling with stride-1 max-filtering (Section 2.2,
 * NET_B - teacher: conv5x5 1->48 ReLU, maxpool 2x2/s1, conv5x5 48->48 ReLU,
   maxpool 2x2/s1, conv3x3 48->48 ReLU, conv1x1 48->1 sigmoid.
 * NET_S - student: conv5x5 1->8 ReLU, conv3x3 8->8 ReLU, conv1x1 8->1 sigmoid.
+* NET_FM - FastMemb as the paper describes it (Section 2.2): three pairs of a
+  4x4 conv with 32 features (max-out over channel pairs of a 64-channel conv)
+  and a 2x2 stride-2 max-pool, then a 4x4 conv to two classes and a softmax;
+  no other transfer function. Field of view 53, 67,778 parameters. Computed
+  densely, each stride-2 pool becomes a max filter and doubles the spacing of
+  every later layer.
 
 A layer is a dict: ``{"kind": "conv", "k", "cin", "cout", "act"}`` with act in
-{"none", "relu", "sigmoid"}, or ``{"kind": "pool"}`` (2x2 window, stride 1).
+{"none", "relu", "sigmoid", "maxout", "softmax"}, or ``{"kind": "pool"}``
+(2x2 window, stride 1) or ``{"kind": "pool2"}`` (2x2 window, stride 2).
 
 Parameter vectors are float64, conv layers in order, each as W[cout][cin][k][k]
 (C order) followed by b[cout].
@@ -36,14 +43,17 @@ def _conv(k, cin, cout, act):
 
 
 POOL = {"kind": "pool"}
+POOL2 = {"kind": "pool2"}
 
 NET_A = [_conv(5, 1, 16, "relu"), _conv(5, 16, 16, "relu"), _conv(1, 16, 1, "sigmoid")]
 NET_B = [_conv(5, 1, 48, "relu"), POOL, _conv(5, 48, 48, "relu"), POOL,
          _conv(3, 48, 48, "relu"), _conv(1, 48, 1, "sigmoid")]
 NET_S = [_conv(5, 1, 8, "relu"), _conv(3, 8, 8, "relu"), _conv(1, 8, 1, "sigmoid")]
+NET_FM = [_conv(4, 1, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"), POOL2,
+          _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 2, "softmax")]
 
-NETS = {"A": NET_A, "B": NET_B, "S": NET_S}
-WEIGHT_SEEDS = {"A": 100, "B": 200, "S": 300}
+NETS = {"A": NET_A, "B": NET_B, "S": NET_S, "FM": NET_FM}
+WEIGHT_SEEDS = {"A": 100, "B": 200, "S": 300, "FM": 400}
 CALIBRATION_SEED = 99
 CALIBRATION_SHAPE = (1, 256, 256)
 
