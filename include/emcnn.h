@@ -43,14 +43,27 @@ extern "C" {
 #define CNN_EHIP (-3)         /* a HIP runtime call failed (text in cnn_last_error) */
 #define CNN_EUNSUPPORTED (-4) /* valid request outside what the kernels implement */
 
-enum cnn_layer_kind { CNN_LAYER_CONV = 0, CNN_LAYER_MAXPOOL = 1 };
-enum cnn_act { CNN_ACT_NONE = 0, CNN_ACT_RELU = 1, CNN_ACT_SIGMOID = 2 };
+enum cnn_layer_kind { CNN_LAYER_CONV = 0, CNN_LAYER_MAXPOOL = 1, CNN_LAYER_MAXPOOL_S2 = 2 };
+enum cnn_act {
+  CNN_ACT_NONE = 0,
+  CNN_ACT_RELU = 1,
+  CNN_ACT_SIGMOID = 2,
+  CNN_ACT_MAXOUT = 3,  /* max over channel pairs (2c, 2c+1): cout / 2 channels out */
+  CNN_ACT_SOFTMAX = 4  /* two classes; the output map is the class-1 (membrane) probability */
+};
 enum cnn_precision { CNN_PREC_FP32 = 0, CNN_PREC_BF16 = 1, CNN_PREC_FP8 = 2 };
 
 /* One layer of the network (Section 2.2: alternating convolution and max
  * pooling; pooling is evaluated densely as a 2x2 stride-1 max filter).
- *  kind      CNN_LAYER_CONV (valid k x k cross-correlation, bias, activation) or
- *            CNN_LAYER_MAXPOOL (2x2 window, stride 1; k must be 2, other fields 0).
+ *  kind      CNN_LAYER_CONV (valid k x k cross-correlation, bias, activation),
+ *            CNN_LAYER_MAXPOOL (2x2 window, stride 1; k must be 2, other fields 0) or
+ *            CNN_LAYER_MAXPOOL_S2 (2x2 window, stride 2, as in a sliding-window
+ *            classifier such as FastMemb; k must be 2). The library still
+ *            produces every pixel's label: it evaluates such a pool as a 2x2 max
+ *            filter whose elements are j apart and doubles j for every later
+ *            layer (j = 1 at the input; a conv's taps are then j apart), which
+ *            equals computing the paper's 4 fragments per pool and interleaving
+ *            them.
  *  act_scale FP8 nets only: the per-tensor scale s of this conv's INPUT
  *            activation (codes are e4m3fn(a / s)); ignored for the first conv,
  *            the head and other precisions. */
@@ -72,6 +85,11 @@ typedef struct cnn_layer_spec {
 typedef struct cnn_net cnn_net;
 
 /* Build a network on the current HIP device.
+ * Two families of nets are supported: the ReLU nets described below, and the
+ * FastMemb family (Section 2.2), FP32 only: conv(k=4, 1 -> 64, MAXOUT), then
+ * one or more pairs { MAXPOOL_S2, conv(k=4, 32 -> 64, MAXOUT) }, then
+ * MAXPOOL_S2 and conv(k=4, 32 -> 2, SOFTMAX); no other transfer function.
+ * FastMemb itself has two inner pairs: field of view 53 (R = 52).
  * weights: host float64, for each conv in order W[cout][cin][k][k] (C order)
  *   followed by b[cout]; n_weights must equal that total. Copied, then packed
  *   and quantised once here:

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libemcnn.so")
 
 CNN_OK, CNN_EINVAL, CNN_ENOMEM, CNN_EHIP, CNN_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
-_ACT = {"none": 0, "relu": 1, "sigmoid": 2}
+_ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4}
+_POOL_KIND = {"pool": 1, "pool2": 2}  # 2x2 window, stride 1 / stride 2
 
 
 class CnnError(RuntimeError):
@@ -133,8 +134,14 @@ def _require_cuda(t, dtype, name):
 
 
 def radius_of(net) -> int:
-    """Receptive radius of a layer list: sum of (k-1) over convs, +1 per 2x2/s1 pool."""
-    return sum(L["k"] - 1 if L["kind"] == "conv" else 1 for L in net)
+    """Receptive radius of a layer list: r += (k - 1) j over the layers, where j
+    (the input spacing) doubles after every stride-2 pool; a 2x2 pool has k = 2."""
+    R, j = 0, 1
+    for L in net:
+        R += (L["k"] - 1 if L["kind"] == "conv" else 1) * j
+        if L["kind"] == "pool2":
+            j *= 2
+    return R
 
 
 class Net:
@@ -167,7 +174,7 @@ def cnn_create(weights, net, precision="fp32", act_scales=None) -> Net:
             arr[i] = _Layer(0, L["k"], L["cin"], L["cout"], _ACT[L["act"]], s)
             ci += 1
         else:
-            arr[i] = _Layer(1, 2, 0, 0, 0, 0.0)
+            arr[i] = _Layer(_POOL_KIND[L["kind"]], 2, 0, 0, 0, 0.0)
     spec = _Spec(len(net), arr, PRECISIONS[precision])
     out = ctypes.c_void_p()
     _check(_lib.cnn_create(w.ctypes.data_as(ctypes.c_void_p), w.size, ctypes.byref(spec),

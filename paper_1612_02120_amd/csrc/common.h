@@ -30,7 +30,12 @@ struct LayerJob {
   const int32_t* gate;  // device flag; the job's items are skipped when *gate == 0 (nullptr: always run)
   int32_t z, hin, win, hout, wout;
   int32_t tiles_x, tiles_y;
-  int32_t pad_;
+  // Spaced layers (nets with stride-2 pools, evaluated densely): bits 0-7 the
+  // spacing d of the conv taps, bits 8-15 the spacing of the 2x2 max filter
+  // before it; 0 for the plain kernels. With d > 1 the output splits into d^2
+  // phase sub-lattices (positions py + d r, px + d c) that are tiled
+  // separately: tiles_y counts d^2 x the tile rows of the largest phase.
+  int32_t geom;
 };
 
 // Work description of one layer launch: either a single job passed by value,
@@ -77,6 +82,9 @@ struct VariantInfo {
   int rr;               // 1: row-reuse kernel (weights packed per filter row)
   int fused;            // k > 0: the kernel reads the uint8 input and computes the preceding
                         // 1-channel k x k first layer (and the max filter) itself
+  int epi;              // epilogue: 0 bias + ReLU (or the fused 1x1 sigmoid head),
+                        // 1 bias + max-out over channel pairs (stores cout / 2 channels),
+                        // 2 bias + two-class softmax of channels 0, 1 (stores the class-1 probability)
   int lds_bytes;
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
   const char* name;
@@ -84,6 +92,7 @@ struct VariantInfo {
 
 struct FirstInfo {
   int prec_out, cout, ks;
+  int maxout;  // 1: bias + max-out over channel pairs (stores cout / 2 channels); 0: bias + ReLU
   int ty, tx, threads;
   int lds_bytes;
   const void* fn;

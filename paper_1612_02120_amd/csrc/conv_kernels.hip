@@ -412,9 +412,12 @@ struct FirstCfg {
   static_assert(MBLK % WAVES == 0 && TX % 16 == 0, "tile must split into m-blocks per wave");
 };
 
-template <int PO, int COUT, int KS, int TY, int TX>
+// MAXOUT: bias then max over the channel pairs (2c, 2c + 1), COUT / 2 stored
+// channels (FP32 NHWC only), instead of bias then ReLU.
+template <int PO, int COUT, int KS, int TY, int TX, bool MAXOUT = false>
 __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void conv_first(JobSet js, FirstParams prm) {
   using C = FirstCfg<PO, COUT, KS, TY, TX>;
+  static_assert(!MAXOUT || PO == F32, "max-out first layers are FP32");
   __shared__ __attribute__((aligned(16))) unsigned char tile[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
@@ -463,7 +466,8 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
       tile[t] = in[(int64_t)y * J.in_rs + x];
     }
     __syncthreads();
-    gbyte* oslice = gout(J.out) + (int64_t)zz * J.out_zs * COUT * C::ESZ;
+    constexpr int CST = MAXOUT ? COUT / 2 : COUT;  // stored channels
+    gbyte* oslice = gout(J.out) + (int64_t)zz * J.out_zs * CST * C::ESZ;
 #pragma unroll
     for (int u = 0; u < C::MW; ++u) {
       const int mb = wave * C::MW + u;
@@ -497,6 +501,14 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
         const int64_t pix = (int64_t)y * J.out_rs + x;
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
+          if constexpr (MAXOUT) {
+            // channels nb*16 + 4g + {0,1} and {2,3} pair up inside the lane:
+            // stored channels nb*8 + 2g and nb*8 + 2g + 1
+            const float m0 = fmaxf(acc[nb][0] + bias[nb][0], acc[nb][1] + bias[nb][1]);
+            const float m1 = fmaxf(acc[nb][2] + bias[nb][2], acc[nb][3] + bias[nb][3]);
+            st<f2>(oslice + (pix * CST + nb * 8 + 2 * g) * 4, f2{m0, m1});
+            continue;
+          }
           float v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
@@ -804,6 +816,140 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
             }
           }
         }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- spaced MFMA conv (stride-2 pool nets)
+
+// One conv of a net whose pools have stride 2 (FastMemb, Section 2.2), in its
+// dense form: taps spaced d apart, fed by a 2x2 max filter with spacing pd
+// (the geom field of the job). The paper splits every stride-k operation into
+// k^2 fragments computed independently; here the fragments are the d^2 phase
+// sub-lattices of the output (positions py + d r, px + d c), each tiled like a
+// plain conv: an operand pixel of the LDS tile is the input at spacing d, so
+// the implicit GEMM (K = (tap, 16-byte chunk), 16x16x4 FP32 MFMA) and its
+// packed weights are those of conv_mfma. Staging applies the max filter (4
+// loads per operand chunk: the neighbours pd apart belong to other phases).
+// EPI 1: bias, then max-out over channel pairs, COUT / 2 channels stored
+// (NHWC). EPI 2: bias, then the two-class softmax of channels 0 and 1 (the
+// other output channels are zero padding), storing the class-1 probability.
+template <int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI>
+__global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREADS)) void conv_phase(
+    JobSet js, ConvParams prm) {
+  using C = Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>;
+  static_assert(EPI == 1 || EPI == 2, "max-out or softmax epilogue");
+  static_assert(EPI != 2 || C::NB == 1, "the softmax layer has one 16-channel n-block");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_TILE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  constexpr int MCOLS = TX / 16;
+  constexpr int ELB = CIN * 4;  // bytes per stored input pixel
+  constexpr int NST = C::LR * C::LC * C::NCHB;
+  constexpr int NIT = (NST + C::THREADS - 1) / C::THREADS;
+
+  float bias[C::NB];
+#pragma unroll
+  for (int nb = 0; nb < C::NB; ++nb) bias[nb] = ldf(prm.bias, nb * 16 + n16);
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
+    const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+    const int tpy = J.tiles_y / (d * d);  // tile rows per phase
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int byp = (int)(t2 % J.tiles_y);
+    const int zz = (int)(t2 / J.tiles_y);
+    const int ph = byp / tpy, by = byp % tpy;
+    const int py = ph / d, px = ph % d;
+    const int y0 = by * TY, x0 = bx * TX;  // sub-lattice coordinates of the tile
+    // operand pixel (r, c) is the max filter at input (py + d (y0 + r), px + d (x0 + c));
+    // rows / columns past the last valid one only feed outputs that are not stored
+    const int ylim = J.hin - 1 - pd, xlim = J.win - 1 - pd;
+    const gbyte* in = gin(J.in) + (int64_t)zz * J.in_zs * ELB;
+    const int64_t rowb = J.in_rs * ELB;
+
+    f4 acc[MW][C::NB];
+#pragma unroll
+    for (int u = 0; u < MW; ++u)
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) acc[u][nb] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int cb = 0; cb < C::NCB; ++cb) {
+      __syncthreads();
+      const gbyte* inc = in + cb * C::CB * 4;
+#pragma unroll 2
+      for (int k = 0; k < NIT; ++k) {
+        const int t = tid + k * C::THREADS;
+        if (t < NST) {
+          const int cg = t % C::NCHB, pix = t / C::NCHB;
+          const int r = pix / C::LC, c = pix % C::LC;
+          const int y = min(py + d * (y0 + r), ylim), x = min(px + d * (x0 + c), xlim);
+          const gbyte* q = inc + (int64_t)y * rowb + (int64_t)x * ELB + cg * 16;
+          const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * ELB);
+          const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * ELB);
+          st<i4v>(lds + pix * C::PSB + cg * 16, chunk_max<F32>(chunk_max<F32>(a, b), chunk_max<F32>(e, f)));
+        }
+      }
+      __syncthreads();
+      // ---- implicit GEMM over this block's (tap, chunk) slots (as conv_mfma)
+      const gbyte* wb = gin(prm.wpack) + (size_t)cb * C::NGS * C::NB * 64 * 16;
+#pragma unroll 2
+      for (int s = 0; s < C::NGS; ++s) {
+        Frag<F32> bfr[C::NB];
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          const gbyte* p = wb + ((size_t)(s * C::NB + nb) * 64 + lane) * 16;
+          load_frag<F32>(bfr[nb], p, p);
+        }
+        int c = s * 4 + g;
+        c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
+        const int i = c / (KS * C::NCHB);
+        const int rem = c % (KS * C::NCHB);
+        const int j = rem / C::NCHB, cg = rem % C::NCHB;
+        const int off = (i * C::LC + j) * C::PSB + cg * 16;
+#pragma unroll
+        for (int u = 0; u < MW; ++u) {
+          const int mb = wave * MW + u;
+          const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+          const unsigned char* a0 = lds + (mrow * C::LC + mcol * 16 + n16) * C::PSB;
+          Frag<F32> afr;
+          load_frag<F32>(afr, a0 + off, a0 + off);
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) mma<F32>(acc[u][nb], afr, bfr[nb]);
+        }
+      }
+    }
+
+    // ---- epilogue: lane holds D[m = 4 g + k][n = n16] of each (m-block, n-block)
+#pragma unroll
+    for (int u = 0; u < MW; ++u) {
+      const int mb = wave * MW + u;
+      const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+      const int y = py + d * (y0 + mrow);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = px + d * (x0 + mcol * 16 + 4 * g + k);
+        const bool ok = y < J.hout && x < J.wout;
+        const int64_t pix = (int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x;
+        if constexpr (EPI == 1) {
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) {
+            const float v = acc[u][nb][k] + bias[nb];
+            const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
+            if (ok && (n16 & 1) == 0) st<float>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 4, m);
+          }
+        } else {
+          const float z = acc[u][0][k] + bias[0];
+          const float z0 = dpp_f<kQuadXor1>(z);  // lane 1 receives class 0's logit
+          if (ok && n16 == 1) st<float>(gout(J.out) + pix * 4, sigmoid_f(z - z0));
+        }
+      }
     }
   }
 }
@@ -1424,7 +1570,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
               Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::NGS,                                           \
-              0, 0,                                                                                   \
+              0, 0, 0,                                                                                \
               Cfg<P, CIN, COUT, KS, TY, TX, MW, HEAD>::LDS_TILE,                                      \
               reinterpret_cast<const void*>(&conv_mfma<P, CIN, COUT, KS, POOL, HEAD, TY, TX, MW>), \
               "conv_mfma<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #MW ">"}
@@ -1439,7 +1585,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
               CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::NGR,                                \
-              1, 0,                                                                                   \
+              1, 0, 0,                                                                                \
               CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>::LDS,                                \
               reinterpret_cast<const void*>(&conv_mfma_rr<P, CIN, COUT, KS, POOL, HEAD, MR, MC, WX, WY, CBO>), \
               "conv_mfma_rr<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #MR "," #MC "," #WX "," #WY \
@@ -1453,13 +1599,25 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               PT<P>::CHB,                                                                             \
               PT<P>::U,                                                                               \
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::NGS,                                     \
-              0, K1,                                                                                  \
+              0, K1, 0,                                                                               \
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::LDS,                                     \
               reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, K1>), \
               "conv_ws<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #NCW "," #NPW \
               "," #K1 ">"}
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
   EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
+
+#define EMCNN_PHASE(CIN, COUT, KS, TY, TX, MW, EPI)                                                   \
+  VariantInfo{F32, CIN, COUT, KS, 1, 0, TY, TX, MW,                                                   \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREADS,                                    \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::CB,                                         \
+              PT<F32>::CHB,                                                                           \
+              PT<F32>::U,                                                                             \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::NGS,                                        \
+              0, 0, EPI,                                                                              \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::LDS_TILE,                                   \
+              reinterpret_cast<const void*>(&conv_phase<CIN, COUT, KS, TY, TX, MW, EPI>),             \
+              "conv_phase<" #CIN "," #COUT "," #KS "," #TY "," #TX "," #MW "," #EPI ">"}
 
 // Pipelined (BF16 / FP8) tile shapes: TY x TX outputs, consumer x producer
 // waves, per layer signature (shapes that fit the LDS and the 168 registers
@@ -1521,18 +1679,26 @@ static const VariantInfo kConv[] = {
     EMCNN_WS(FP8, 48, 48, 3, false, true, 8, 64, 8, 4),
     EMCNN_CONV(F32, 16, 16, 5, true, true, 8, 32, 4),
     EMCNN_CONV(F32, 16, 16, 5, false, false, 8, 32, 4),
+    // FastMemb body convs (4x4, 32 -> 64, max-out to 32) and its softmax layer
+    // (4x4, 32 -> 2 classes, computed as 16 MFMA columns), spaced form
+    EMCNN_PHASE(32, 64, 4, 16, 64, 8, 1), EMCNN_PHASE(32, 64, 4, 8, 64, 4, 1),
+    EMCNN_PHASE(32, 16, 4, 16, 64, 8, 2), EMCNN_PHASE(32, 16, 4, 8, 64, 4, 2),
 };
 
-#define EMCNN_FIRST(PO, COUT, KS, TY, TX)                                                            \
-  FirstInfo{PO, COUT, KS, TY, TX, FirstCfg<PO, COUT, KS, TY, TX>::THREADS, FirstCfg<PO, COUT, KS, TY, TX>::LDS, \
-            reinterpret_cast<const void*>(&conv_first<PO, COUT, KS, TY, TX>),                         \
-            "conv_first<" #PO "," #COUT "," #KS "," #TY "," #TX ">"}
+#define EMCNN_FIRSTM(PO, COUT, KS, TY, TX, MX)                                                       \
+  FirstInfo{PO, COUT, KS, MX, TY, TX, FirstCfg<PO, COUT, KS, TY, TX>::THREADS,                        \
+            FirstCfg<PO, COUT, KS, TY, TX>::LDS,                                                      \
+            reinterpret_cast<const void*>(&conv_first<PO, COUT, KS, TY, TX, MX>),                     \
+            "conv_first<" #PO "," #COUT "," #KS "," #TY "," #TX "," #MX ">"}
+#define EMCNN_FIRST(PO, COUT, KS, TY, TX) EMCNN_FIRSTM(PO, COUT, KS, TY, TX, false)
 
 static const FirstInfo kFirst[] = {
     // defaults (first match per signature) are the measured fastest shapes
     EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64), EMCNN_FIRST(FP8, 48, 5, 16, 64),
     EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 4, 64),
     EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 8, 64),
+    // FastMemb first conv: 4x4, 1 -> 64, max-out to 32
+    EMCNN_FIRSTM(F32, 64, 4, 4, 64, true), EMCNN_FIRSTM(F32, 64, 4, 8, 32, true),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }

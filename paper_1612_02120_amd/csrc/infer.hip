@@ -22,8 +22,9 @@ Dims layer_dims(const Net* net, int h, int w) {
   for (const auto& L : net->layers) {
     d.hin.push_back(h);
     d.win.push_back(w);
-    h = h - L.pool_in - L.ks + 1;
-    w = w - L.pool_in - L.ks + 1;
+    const int shrink = (L.pool_in ? L.pd : 0) + (L.ks - 1) * L.dil;
+    h -= shrink;
+    w -= shrink;
     d.hout.push_back(h);
     d.wout.push_back(w);
   }
@@ -39,7 +40,7 @@ static std::vector<size_t> layer_bytes(const Net* net, const Dims& d) {
   for (int l = 0; l < nl; ++l)
     b.push_back(l == nl - 1 || (l == 0 && fused)
                     ? 0
-                    : (size_t)d.hout[l] * d.wout[l] * net->layers[l].cout * act_bytes_of(net->prec));
+                    : (size_t)d.hout[l] * d.wout[l] * stored_channels(net->layers[l]) * act_bytes_of(net->prec));
   return b;
 }
 
@@ -77,8 +78,17 @@ static LayerJob make_job(const ExecLayer& L, const void* in, void* out, int z, i
   j.wout = wout;
   j.out_rs = out_rs;
   j.out_zs = out_zs;
-  j.tiles_x = (wout + layer_tx(L) - 1) / layer_tx(L);
-  j.tiles_y = (hout + layer_ty(L) - 1) / layer_ty(L);
+  if (L.dil > 1) {
+    // d^2 phase sub-lattices, each tiled on its own (the largest phase has
+    // ceil(hout / d) x ceil(wout / d) positions)
+    const int d = L.dil, hs = (hout + d - 1) / d, wsub = (wout + d - 1) / d;
+    j.tiles_x = (wsub + layer_tx(L) - 1) / layer_tx(L);
+    j.tiles_y = d * d * ((hs + layer_ty(L) - 1) / layer_ty(L));
+    j.geom = d | (L.pd << 8);
+  } else {
+    j.tiles_x = (wout + layer_tx(L) - 1) / layer_tx(L);
+    j.tiles_y = (hout + layer_ty(L) - 1) / layer_ty(L);
+  }
   j.item0 = item0;
   j.gate = gate;
   return j;
@@ -585,7 +595,8 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   const int eb = net->prec == F32 ? 4 : net->prec == BF16 ? 2 : 1;
   std::vector<size_t> ob(nl);
   for (int l = 0; l < nl; ++l)
-    ob[l] = (l == nl - 1) ? (size_t)d.hout[l] * d.wout[l] * 4 : (size_t)d.hout[l] * d.wout[l] * net->layers[l].cout * eb;
+    ob[l] = (l == nl - 1) ? (size_t)d.hout[l] * d.wout[l] * 4
+                          : (size_t)d.hout[l] * d.wout[l] * stored_channels(net->layers[l]) * eb;
   std::vector<void*> bufs(nl + 2, nullptr);
   hipError_t e;
   size_t maxb = 0;

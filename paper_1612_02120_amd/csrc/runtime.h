@@ -18,6 +18,11 @@ struct ExecLayer {
   int cin = 0, cout = 0, ks = 0;
   int pool_in = 0, head = 0;
   int in_off = 0;  // receptive radius consumed by earlier layers
+  // nets with stride-2 pools, in their dense form: the conv taps are dil apart
+  // and the 2x2 max filter before the conv (pool_in) takes elements pd apart
+  int dil = 1, pd = 1;
+  int epi = 0;     // epilogue kind (VariantInfo::epi; first layers: 1 = max-out)
+  int cstore = 0;  // channels stored per output pixel: cout, or cout / 2 after max-out
   int variant = -1;
   std::vector<int> candidates;
   std::vector<void*> wpacks;  // packed weights per candidate (layouts differ between variants)
@@ -85,6 +90,7 @@ struct Launch {
 };
 
 Dims layer_dims(const Net* net, int h, int w);
+inline int stored_channels(const ExecLayer& L) { return L.cstore ? L.cstore : L.cout; }
 int ensure_ws(Net* net, size_t need);
 int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, float* prob, hipStream_t st);
 int arena_reserve(Net* net, size_t njobs);

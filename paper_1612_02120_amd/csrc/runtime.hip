@@ -86,20 +86,21 @@ uint8_t e4m3_code(double x) {
 
 static int act_bytes(int prec) { return prec == F32 ? 4 : prec == BF16 ? 2 : 1; }
 
-static int find_first_variant(int prec, int cout, int ks) {
+static std::vector<int> find_first_variants(int prec, int cout, int ks, int maxout) {
+  std::vector<int> v;
   for (int i = 0; i < first_variant_count(); ++i) {
     const FirstInfo* f = first_variant(i);
-    if (f->prec_out == prec && f->cout == cout && f->ks == ks) return i;
+    if (f->prec_out == prec && f->cout == cout && f->ks == ks && f->maxout == maxout) v.push_back(i);
   }
-  return -1;
+  return v;
 }
 
-static std::vector<int> find_conv_variants(int prec, int cin, int cout, int ks, int pool, int head) {
+static std::vector<int> find_conv_variants(int prec, int cin, int cout, int ks, int pool, int head, int epi) {
   std::vector<int> v;
   for (int i = 0; i < conv_variant_count(); ++i) {
     const VariantInfo* c = conv_variant(i);
     if (c->prec == prec && c->cin == cin && c->cout == cout && c->ks == ks && c->pool_in == pool &&
-        c->head == head)
+        c->head == head && c->epi == epi)
       v.push_back(i);
   }
   return v;
@@ -259,6 +260,87 @@ static void free_layer(ExecLayer& L) {
   L.bias = L.oscale = L.head_w = nullptr;
 }
 
+// Nets with stride-2 pools (the FastMemb family, Section 2.2), FP32, in their
+// dense form: conv(4, 1 -> 64, max-out), then one or more of { 2x2/s2 pool,
+// conv(4, 32 -> 64, max-out) }, then a 2x2/s2 pool and conv(4, 32 -> 2,
+// softmax). Every stride-2 pool becomes a 2x2 max filter at the current
+// spacing and doubles the spacing of the later layers.
+static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, int nl) {
+  const auto unsupported = [](const std::string& why) {
+    return fail(CNN_EUNSUPPORTED, "cnn_create: stride-2 pool nets: " + why);
+  };
+  const cnn_layer& l0 = Lr[0];
+  if (l0.kind != CNN_LAYER_CONV || l0.k != 4 || l0.cin != 1 || l0.cout != 64 || l0.act != CNN_ACT_MAXOUT)
+    return unsupported("the first layer must be conv(4, 1 -> 64, max-out)");
+  if (nl < 4 || (nl - 1) % 2) return unsupported("expected conv, then (stride-2 pool, conv) pairs");
+  for (int i = 1; i < nl; i += 2) {
+    const cnn_layer& p = Lr[i];
+    const cnn_layer& c = Lr[i + 1];
+    const bool last = i + 1 == nl - 1;
+    if (p.kind != CNN_LAYER_MAXPOOL_S2) return unsupported("every conv after the first follows a stride-2 pool");
+    if (c.kind != CNN_LAYER_CONV || c.k != 4 || c.cin != 32 ||
+        (last ? (c.cout != 2 || c.act != CNN_ACT_SOFTMAX) : (c.cout != 64 || c.act != CNN_ACT_MAXOUT)))
+      return unsupported("inner convs are conv(4, 32 -> 64, max-out), the last conv(4, 32 -> 2, softmax)");
+  }
+  const double* wp = weights;
+  int sp = 1;  // spacing of the current layer's input
+  for (int i = 0; i < nl; i += (i == 0 ? 1 : 2)) {
+    const cnn_layer& l = Lr[i == 0 ? 0 : i + 1];
+    const int64_t nwl = (int64_t)l.cout * l.cin * l.k * l.k;
+    const double* w = wp;
+    const double* b = wp + nwl;
+    wp += nwl + l.cout;
+    ExecLayer E;
+    E.ks = l.k;
+    E.cin = l.cin;
+    int rc = CNN_OK;
+    if (i == 0) {
+      E.first = 1;
+      E.cout = l.cout;
+      E.cstore = l.cout / 2;
+      E.epi = 1;
+      E.candidates = find_first_variants(CNN_PREC_FP32, l.cout, l.k, 1);
+      if (E.candidates.empty()) return unsupported("no first-layer kernel");
+      for (int c : E.candidates)
+        if (rc == CNN_OK) rc = pack_first(E, c, w, b, 0.0);
+    } else {
+      E.pool_in = 1;
+      E.pd = sp;  // the max filter of the stride-2 pool before this conv
+      sp *= 2;
+      E.dil = sp;
+      const bool soft = l.act == CNN_ACT_SOFTMAX;
+      // the two-class layer runs as 16 MFMA columns: zero weights and bias for classes >= 2
+      E.cout = soft ? 16 : l.cout;
+      E.cstore = soft ? 1 : l.cout / 2;
+      E.epi = soft ? 2 : 1;
+      std::vector<double> wpad, bpad;
+      if (soft) {
+        wpad.assign((size_t)E.cout * l.cin * l.k * l.k, 0.0);
+        bpad.assign(E.cout, 0.0);
+        std::copy(w, w + nwl, wpad.begin());
+        std::copy(b, b + l.cout, bpad.begin());
+        w = wpad.data();
+        b = bpad.data();
+      }
+      E.candidates = find_conv_variants(CNN_PREC_FP32, l.cin, E.cout, l.k, 1, 0, E.epi);
+      if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(i + 1));
+      for (int c : E.candidates)
+        if (rc == CNN_OK) rc = pack_conv(E, c, w, b, nullptr, 0.0, 1.0, 0.0);
+    }
+    E.variant = E.candidates[0];
+    if (rc == CNN_OK) select_variant(E, E.variant);
+    net->layers.push_back(E);
+    if (rc != CNN_OK) return rc;
+  }
+  int off = 0;
+  for (auto& E : net->layers) {
+    E.in_off = off;
+    off += (E.pool_in ? E.pd : 0) + (E.ks - 1) * E.dil;
+  }
+  if (off != net->R) return fail(CNN_EINVAL, "cnn_create: internal radius mismatch");
+  return CNN_OK;
+}
+
 int layer_threads(const ExecLayer& L) {
   return L.first ? first_variant(L.variant)->threads : conv_variant(L.variant)->threads;
 }
@@ -310,21 +392,37 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
   const int prec = spec->precision;
   if (prec != CNN_PREC_FP32 && prec != CNN_PREC_BF16 && prec != CNN_PREC_FP8)
     return fail(CNN_EINVAL, "cnn_create: unknown precision");
-  // structural validation
+  // structural validation; R follows the receptive-field recursion
+  // r += (k - 1) j, j *= stride (a 2x2 pool counts as k = 2)
   int64_t expect = 0;
   int R = 0;
   int C = 1;
+  int sp = 1;  // input spacing j of the current layer
+  bool strided = false;  // stride-2 pools, max-out or softmax: the FastMemb family
   for (int i = 0; i < spec->n_layers; ++i) {
     const cnn_layer& l = spec->layers[i];
     if (l.kind == CNN_LAYER_CONV) {
-      if (l.k < 1 || l.cin != C || l.cout < 1 || (l.act < 0 || l.act > 2))
+      if (l.k < 1 || l.cin != C || l.cout < 1 || (l.act < 0 || l.act > CNN_ACT_SOFTMAX))
         return fail(CNN_EINVAL, "cnn_create: bad conv layer " + std::to_string(i));
       expect += (int64_t)l.cout * l.cin * l.k * l.k + l.cout;
-      R += l.k - 1;
+      R += (l.k - 1) * sp;
       C = l.cout;
-    } else if (l.kind == CNN_LAYER_MAXPOOL) {
+      if (l.act == CNN_ACT_MAXOUT) {
+        if (l.cout % 2) return fail(CNN_EINVAL, "cnn_create: max-out needs an even channel count");
+        C = l.cout / 2;
+        strided = true;
+      } else if (l.act == CNN_ACT_SOFTMAX) {
+        if (l.cout != 2) return fail(CNN_EINVAL, "cnn_create: softmax output needs two classes");
+        C = 1;
+        strided = true;
+      }
+    } else if (l.kind == CNN_LAYER_MAXPOOL || l.kind == CNN_LAYER_MAXPOOL_S2) {
       if (l.k != 2 || i == 0) return fail(CNN_EINVAL, "cnn_create: maxpool must be 2x2 and follow a conv");
-      R += 1;
+      R += sp;
+      if (l.kind == CNN_LAYER_MAXPOOL_S2) {
+        sp *= 2;
+        strided = true;
+      }
     } else {
       return fail(CNN_EINVAL, "cnn_create: bad layer kind at " + std::to_string(i));
     }
@@ -332,16 +430,20 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
   if (expect != n_weights)
     return fail(CNN_EINVAL, "cnn_create: n_weights " + std::to_string(n_weights) + " != " + std::to_string(expect));
   if (C != 1) return fail(CNN_EINVAL, "cnn_create: last layer must have one output channel");
-  // supported shape: first conv(5, 1->C, relu) [pool], body convs (relu) [pool], head conv(1, C->1, sigmoid)
   const cnn_layer* Lr = spec->layers;
   const int nl = spec->n_layers;
-  if (Lr[0].kind != CNN_LAYER_CONV || Lr[0].cin != 1 || Lr[0].act != CNN_ACT_RELU)
-    return fail(CNN_EUNSUPPORTED, "cnn_create: first layer must be a ReLU conv on one channel");
   const cnn_layer& hd = Lr[nl - 1];
-  if (hd.kind != CNN_LAYER_CONV || hd.k != 1 || hd.cout != 1 || hd.act != CNN_ACT_SIGMOID)
-    return fail(CNN_EUNSUPPORTED, "cnn_create: last layer must be a 1x1 conv to one channel with sigmoid");
-  if (Lr[nl - 2].kind != CNN_LAYER_CONV)
-    return fail(CNN_EUNSUPPORTED, "cnn_create: no pooling directly before the head");
+  if (strided) {
+    if (prec != CNN_PREC_FP32) return fail(CNN_EUNSUPPORTED, "cnn_create: stride-2 pool nets are FP32 only");
+  } else {
+    // supported shape: first conv(5, 1->C, relu) [pool], body convs (relu) [pool], head conv(1, C->1, sigmoid)
+    if (Lr[0].kind != CNN_LAYER_CONV || Lr[0].cin != 1 || Lr[0].act != CNN_ACT_RELU)
+      return fail(CNN_EUNSUPPORTED, "cnn_create: first layer must be a ReLU conv on one channel");
+    if (hd.kind != CNN_LAYER_CONV || hd.k != 1 || hd.cout != 1 || hd.act != CNN_ACT_SIGMOID)
+      return fail(CNN_EUNSUPPORTED, "cnn_create: last layer must be a 1x1 conv to one channel with sigmoid");
+    if (Lr[nl - 2].kind != CNN_LAYER_CONV)
+      return fail(CNN_EUNSUPPORTED, "cnn_create: no pooling directly before the head");
+  }
 
   int dev = 0;
   hipGetDevice(&dev);
@@ -361,6 +463,16 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
     return fail(CNN_EUNSUPPORTED, "cnn_create: kernels are built for gfx950, device is " + std::string(prop.gcnArchName));
   }
   if (const char* s = std::getenv("EMCNN_WORKSPACE_MB")) net->ws_budget = (size_t)std::atoll(s) << 20;
+  if (strided) {
+    const int rc = build_strided(net, weights, Lr, nl);
+    if (rc != CNN_OK) {
+      for (auto& E : net->layers) free_layer(E);
+      delete net;
+      return rc;
+    }
+    *out = reinterpret_cast<cnn_net*>(net);
+    return CNN_OK;
+  }
 
   // build executed layers; weights pointer walks convs in order
   const double* wp = weights;
@@ -400,15 +512,12 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
     const double nxt = next_conv_scale(i);
     if (conv_i == 0) {
       E.first = 1;
-      E.variant = find_first_variant(prec, l.cout, l.k);
-      if (E.variant < 0) {
+      E.candidates = find_first_variants(prec, l.cout, l.k, 0);
+      if (E.candidates.empty()) {
         rc = fail(CNN_EUNSUPPORTED, "cnn_create: no first-layer kernel for this shape/precision");
         break;
       }
-      for (int q = 0; q < first_variant_count(); ++q) {
-        const FirstInfo* f = first_variant(q);
-        if (f->prec_out == prec && f->cout == l.cout && f->ks == l.k) E.candidates.push_back(q);
-      }
+      E.variant = E.candidates[0];
       for (int c : E.candidates) {
         if (rc == CNN_OK) rc = pack_first(E, c, w, b, nxt);
       }
@@ -420,7 +529,7 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
         break;
       }
       E.head = fuse_head;
-      E.candidates = find_conv_variants(prec, l.cin, l.cout, l.k, E.pool_in, fuse_head);
+      E.candidates = find_conv_variants(prec, l.cin, l.cout, l.k, E.pool_in, fuse_head, 0);
       {
         // variants that compute the first layer themselves apply only right after it
         const ExecLayer& L0 = net->layers[0];
@@ -466,7 +575,7 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
   int off = 0;
   for (auto& E : net->layers) {
     E.in_off = off;  // radius consumed before this layer
-    off += E.pool_in + E.ks - 1;
+    off += (E.pool_in ? E.pd : 0) + (E.ks - 1) * E.dil;
   }
   *out = reinterpret_cast<cnn_net*>(net);
   return CNN_OK;

@@ -43,7 +43,7 @@ def _spec(m, net, prec="fp32"):
         if L["kind"] == "conv":
             arr[i] = m._Layer(0, L["k"], L["cin"], L["cout"], m._ACT[L["act"]], 0.0)
         else:
-            arr[i] = m._Layer(1, 2, 0, 0, 0, 0.0)
+            arr[i] = m._Layer(m._POOL_KIND[L["kind"]], 2, 0, 0, 0, 0.0)
     return m._Spec(len(net), arr, m.PRECISIONS[prec]), arr
 
 
@@ -77,6 +77,25 @@ def test_create_validates_before_device_use():
     rc, _ = _create_rc(m, w, sig)
     assert rc == m.CNN_EUNSUPPORTED
     assert m._lib.cnn_create(None, 0, None, None) == m.CNN_EINVAL
+
+
+def test_create_validates_fastmemb_specs_before_device_use():
+    import paper_1612_02120_amd as m
+    from synth.nets import NET_FM, he_normal_params
+    w = he_normal_params(NET_FM, 400)
+    assert m.radius_of(NET_FM) == 52  # field of view 53 (Section 2.2)
+    rc, _ = _create_rc(m, w, NET_FM, n=w.size + 1)
+    assert rc == m.CNN_EINVAL and "n_weights" in m.cnn_last_error()
+    rc, _ = _create_rc(m, w, NET_FM, prec="bf16")
+    assert rc == m.CNN_EUNSUPPORTED and "FP32" in m.cnn_last_error()
+    odd = [dict(L) for L in NET_FM]
+    odd[0]["cout"] = 63  # max-out pairs channels
+    rc, _ = _create_rc(m, w, odd)
+    assert rc == m.CNN_EINVAL and "even" in m.cnn_last_error()
+    three = [dict(L) for L in NET_FM]
+    three[-1]["cout"] = 3  # the softmax output has two classes
+    rc, _ = _create_rc(m, np.zeros(w.size + 32 * 16 + 1), three)
+    assert rc == m.CNN_EINVAL and "two classes" in m.cnn_last_error()
 
 
 def test_null_handles_are_rejected():

@@ -1,0 +1,119 @@
+"""GPU parity of FastMemb (Section 2.2) through the C ABI against the FP64 reference.
+
+FastMemb's stride-2 pools are evaluated densely: each becomes a 2x2 max filter
+at the current spacing and doubles the spacing of the later convs, whose d^2
+phase sub-lattices the kernels tile separately. FP32 throughout; tolerance 1e-5
+max abs on the class-1 probability. Shapes span several tiles per phase at the
+largest spacing (8) and ragged tails in every direction.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import em_volume
+from synth.nets import NET_FM, calibrated_params, random_bias_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def emcnn():
+    import paper_1612_02120_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(emcnn, h, vol):
+    out = emcnn.cnn_infer(h, _dev(vol))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _params():
+    # He-normal weights with non-zero biases, so that every bias term is exercised
+    return random_bias_params(NET_FM, 400, 41, sigma=0.2)
+
+
+@pytest.mark.parametrize("shape", [(2, 131, 157), (1, 53, 53), (1, 60, 301), (1, 620, 590)])
+def test_fastmemb_matches_reference(emcnn, shape):
+    vol = em_volume(40 + shape[1], *shape)
+    p = _params()
+    h = emcnn.cnn_create(p, NET_FM, "fp32")
+    assert h.R == 52
+    got = _run(emcnn, h, vol)
+    ref = oracle.forward(vol, NET_FM, p)
+    assert got.shape == ref.shape == (shape[0], shape[1] - 52, shape[2] - 52)
+    err = np.abs(got - ref).max()
+    print("FastMemb fp32", shape, "max err", err)
+    assert err <= TOL
+
+
+def test_every_fastmemb_candidate_matches_reference(emcnn):
+    vol = em_volume(77, 2, 161, 203)
+    p = _params()
+    h = emcnn.cnn_create(p, NET_FM, "fp32")
+    ref = oracle.forward(vol, NET_FM, p)
+    n_layers = 4
+    defaults = [emcnn.cnn_variant_names(h, l)[0] for l in range(n_layers)]
+    assert "conv_phase" in defaults[1] and "conv_phase" in defaults[3]
+    for layer in range(n_layers):
+        for name in emcnn.cnn_variant_names(h, layer):
+            emcnn.cnn_set_variant(h, layer, name)
+            err = np.abs(_run(emcnn, h, vol) - ref).max()
+            assert err <= TOL, (layer, name, err)
+        emcnn.cnn_set_variant(h, layer, defaults[layer])
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_fastmemb_batch_matches_per_tile_and_reference(emcnn, graph):
+    p = _params()
+    h = emcnn.cnn_create(p, NET_FM, "fp32")
+    emcnn.cnn_set_batch_graph(h, graph)
+    rng = np.random.default_rng(9)
+    tiles, vols = [], []
+    for t in range(5):
+        L = int(rng.integers(3, 90))
+        z = int(rng.integers(1, 3))
+        halo = int(rng.choice([26, 29]))  # R / 2 = 26; larger halos are cropped to it
+        v = em_volume(600 + t, z, L + 2 * halo, L + 11 + 2 * halo)
+        vols.append((v, halo))
+        tiles.append((_dev(v), halo, torch.empty((z, L, L + 11), dtype=torch.float32, device="cuda")))
+    for rep in range(3):  # replays of the captured graph
+        for _, _, o in tiles:
+            o.fill_(-1.0)
+        emcnn.cnn_infer_batch(h, tiles)
+        torch.cuda.synchronize()
+        for (v, halo), (_, _, o) in zip(vols, tiles):
+            e = halo - 26
+            single = _run(emcnn, h, v[:, e:v.shape[1] - e, e:v.shape[2] - e])
+            assert np.array_equal(o.cpu().numpy().astype(np.float64), single)
+    v, halo = vols[1]
+    e = halo - 26
+    ref = oracle.forward(v[:, e:v.shape[1] - e, e:v.shape[2] - e], NET_FM, p)
+    assert np.abs(tiles[1][2].cpu().numpy() - ref).max() <= TOL
+
+
+def test_fastmemb_full_size_sampled_windows(emcnn):
+    # the benchmark's workload (32 x 1024 x 1024) in its launch configuration;
+    # sampled outputs against the reference's patch form (one 53 x 53 window each)
+    vol = em_volume(2, 32, 1024, 1024)
+    p = calibrated_params("FM")
+    h = emcnn.cnn_create(p, NET_FM, "fp32")
+    got = emcnn.cnn_infer(h, _dev(vol))
+    torch.cuda.synchronize()
+    assert tuple(got.shape) == (32, 972, 972)
+    assert torch.isfinite(got).all()
+    rng = np.random.default_rng(3)
+    pts = [(int(rng.integers(0, 32)), int(rng.integers(0, 972)), int(rng.integers(0, 972))) for _ in range(40)]
+    pts += [(0, 0, 0), (31, 971, 971), (5, 0, 971), (9, 971, 0)]
+    g = got.cpu().numpy()
+    for z, y, x in pts:
+        want = oracle.patch(vol[z], NET_FM, p, y, x)[0]
+        assert abs(g[z, y, x] - want) <= TOL, (z, y, x, g[z, y, x], want)
