@@ -10,8 +10,8 @@ HBM. Printed as one JSON line; also reported:
 * roofline of the dominant kernel (conv2, 72% of the FLOPs) from HIP events
   recorded on its launch stream over the timed region;
 * the FP64 CPU reference timed on a bounded sample on the host cores;
-* the other forms (BF16 / FP8 precision, batched tiles, student) unless
-  --forms none.
+* the other forms (BF16 / FP8 precision, batched tiles, student, and the
+  paper's own FastMemb net in FP32 on the same volume) unless --forms none.
 
 Only one GPU is used; --gpus N with N > 1 is refused.
 """
@@ -37,6 +37,9 @@ NET_B_FLOP_PER_VOXEL = 159168
 CONV2_FLOP_PER_POS = 2 * 25 * 48 * 48  # per conv2 output position
 CONV1_FLOP_PER_POS = 2 * 25 * 48  # per conv1 output position
 STUDENT_FLOP_PER_VOXEL = 2 * (200 + 576 + 8)
+# FastMemb (4x4 convs 1->64, 32->64, 32->64 with max-out to 32, 32->2) per output voxel
+FASTMEMB_FLOP_PER_VOXEL = 2 * 16 * (64 + 32 * 64 + 32 * 64 + 32 * 2)
+FASTMEMB_BODY_FLOP_PER_POS = 2 * 16 * 32 * 64  # one 32 -> 64 4x4 conv output position
 
 
 def log(*a):
@@ -163,7 +166,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="all", help="all | none | comma list of bf16,fp8,batch,student")
+    ap.add_argument("--forms", default="all",
+                    help="all | none | comma list of bf16,fp8,batch,student,fastmemb")
     ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -240,7 +244,26 @@ def main():
     del out
     forms = {}
     want = set() if args.forms == "none" else (
-        {"bf16", "fp8", "batch", "student"} if args.forms == "all" else set(args.forms.split(",")))
+        {"bf16", "fp8", "batch", "student", "fastmemb"} if args.forms == "all" else set(args.forms.split(",")))
+    if "fastmemb" in want and not args.no_headline:
+        # the paper's own net (Section 2.2) on the headline volume: dense form of
+        # its stride-2 pools (max filters, convs spaced 2, 4, 8 over phase sub-lattices)
+        from synth.nets import NET_FM
+        hf = emcnn.cnn_create(calibrated_params("FM"), NET_FM, "fp32")
+        msf, plf, outf = time_volume(emcnn, torch, hf, vol_dev, max(3, args.steps // 2), 2, stream)
+        nvf = Z * (H - hf.R) * (W - hf.R)
+        body_flop = [Z * (H - 3 - 7) ** 2 * FASTMEMB_BODY_FLOP_PER_POS,
+                     Z * (H - 3 - 7 - 14) ** 2 * FASTMEMB_BODY_FLOP_PER_POS]
+        body_tf = [f / (t * 1e-3) / 1e12 for f, t in zip(body_flop, plf[1:3])]
+        forms["fastmemb"] = {
+            "workload": "FastMemb FP32 (conv4x4 1->64 max-out, 3 x {2x2/s2 pool, conv4x4}, two-class softmax; "
+                        "FoV 53), %d x %d x %d (seed 2) -> %d x %d x %d" % (Z, H, W, Z, H - hf.R, W - hf.R),
+            "voxels_per_s": nvf / (msf * 1e-3), "ms_per_pass": msf,
+            "path_mfma_frac": nvf * FASTMEMB_FLOP_PER_VOXEL / (msf * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+            "body_conv_tflops": body_tf, "body_conv_frac": [t / PEAK_TFLOPS["fp32"] for t in body_tf],
+            "layer_ms": plf[:4], "tiles": emcnn.cnn_describe(hf)}
+        log("fastmemb", json.dumps(forms["fastmemb"]))
+        del outf, hf
     if want & {"bf16", "fp8"}:
         Zp = 128 if args.full else 8
         t0 = time.perf_counter()

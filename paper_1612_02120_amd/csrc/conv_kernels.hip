@@ -57,10 +57,11 @@ __host__ __device__ constexpr int pad_words(int w) {
   return (w % 16 == 8) ? w : w + ((24 - (w % 16)) % 16);
 }
 
-template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, bool HEAD = false>
+// CBO: channels staged per LDS pass (0: the precision's default block)
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, bool HEAD = false, int CBO = 0>
 struct Cfg {
   using T = PT<P>;
-  static constexpr int CB = (T::CB < CIN) ? T::CB : CIN;
+  static constexpr int CB = CBO ? CBO : (T::CB < CIN) ? T::CB : CIN;
   static_assert(CIN % CB == 0, "channel block must divide CIN");
   static constexpr int NCB = CIN / CB;
   static constexpr int NCHB = CB / T::CHB;  // 16-byte chunks per pixel per block
@@ -834,10 +835,36 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 // EPI 1: bias, then max-out over channel pairs, COUT / 2 channels stored
 // (NHWC). EPI 2: bias, then the two-class softmax of channels 0 and 1 (the
 // other output channels are zero padding), storing the class-1 probability.
-template <int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI>
-__global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREADS)) void conv_phase(
+// Stage the LR x LC operand tile of one phase sub-lattice (channel chunks
+// 0 .. NCHB-1 of the block at `in`): operand pixel (r, c) is the 2x2 max
+// filter, elements pd apart, at input (py + d (y0 + r), px + d (x0 + c)). Rows
+// and columns are clamped to ylim / xlim (= last valid filter origin); clamped
+// ones only feed outputs that are not stored.
+template <int LR, int LC, int NCHB, int PSB, int THREADS>
+__device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const gbyte* in, int64_t rowb, int elb, int py,
+                                                 int px, int d, int pd, int y0, int x0, int ylim, int xlim,
+                                                 int tid) {
+  constexpr int NST = LR * LC * NCHB;
+  constexpr int NIT = (NST + THREADS - 1) / THREADS;
+#pragma unroll 2
+  for (int k = 0; k < NIT; ++k) {
+    const int t = tid + k * THREADS;
+    if (t < NST) {
+      const int cg = t % NCHB, pix = t / NCHB;
+      const int r = pix / LC, c = pix % LC;
+      const int y = min(py + d * (y0 + r), ylim), x = min(px + d * (x0 + c), xlim);
+      const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
+      const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
+      const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
+      st<i4v>(lds + pix * PSB + cg * 16, chunk_max<F32>(chunk_max<F32>(a, b), chunk_max<F32>(e, f)));
+    }
+  }
+}
+
+template <int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI, int CB>
+__global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>::THREADS)) void conv_phase(
     JobSet js, ConvParams prm) {
-  using C = Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>;
+  using C = Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>;
   static_assert(EPI == 1 || EPI == 2, "max-out or softmax epilogue");
   static_assert(EPI != 2 || C::NB == 1, "the softmax layer has one 16-channel n-block");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_TILE];
@@ -845,8 +872,6 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREAD
   const int g = lane >> 4, n16 = lane & 15;
   constexpr int MCOLS = TX / 16;
   constexpr int ELB = CIN * 4;  // bytes per stored input pixel
-  constexpr int NST = C::LR * C::LC * C::NCHB;
-  constexpr int NIT = (NST + C::THREADS - 1) / C::THREADS;
 
   float bias[C::NB];
 #pragma unroll
@@ -859,13 +884,18 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREAD
     const LayerJob J = job_at(js, cur, item);
     if (gated_off(J)) continue;
     const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+    // item order: tile column, then phase, then tile row, then slice. The d^2
+    // phases of one tile row are neighbours in the item range, so the
+    // workgroups of an XCD stage them together: their max filters read each
+    // other's pixels, which then meet in that XCD's L2.
     const int tpy = J.tiles_y / (d * d);  // tile rows per phase
     const int64_t local = item - J.item0;
     const int bx = (int)(local % J.tiles_x);
     const int64_t t2 = local / J.tiles_x;
-    const int byp = (int)(t2 % J.tiles_y);
-    const int zz = (int)(t2 / J.tiles_y);
-    const int ph = byp / tpy, by = byp % tpy;
+    const int ph = (int)(t2 % (d * d));
+    const int64_t t3 = t2 / (d * d);
+    const int by = (int)(t3 % tpy);
+    const int zz = (int)(t3 / tpy);
     const int py = ph / d, px = ph % d;
     const int y0 = by * TY, x0 = bx * TX;  // sub-lattice coordinates of the tile
     // operand pixel (r, c) is the max filter at input (py + d (y0 + r), px + d (x0 + c));
@@ -882,20 +912,8 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREAD
 
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
-      const gbyte* inc = in + cb * C::CB * 4;
-#pragma unroll 2
-      for (int k = 0; k < NIT; ++k) {
-        const int t = tid + k * C::THREADS;
-        if (t < NST) {
-          const int cg = t % C::NCHB, pix = t / C::NCHB;
-          const int r = pix / C::LC, c = pix % C::LC;
-          const int y = min(py + d * (y0 + r), ylim), x = min(px + d * (x0 + c), xlim);
-          const gbyte* q = inc + (int64_t)y * rowb + (int64_t)x * ELB + cg * 16;
-          const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * ELB);
-          const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * ELB);
-          st<i4v>(lds + pix * C::PSB + cg * 16, chunk_max<F32>(chunk_max<F32>(a, b), chunk_max<F32>(e, f)));
-        }
-      }
+      stage_phase_tile<C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, in + cb * C::CB * 4, rowb, ELB, py, px, d,
+                                                                   pd, y0, x0, ylim, xlim, tid);
       __syncthreads();
       // ---- implicit GEMM over this block's (tap, chunk) slots (as conv_mfma)
       const gbyte* wb = gin(prm.wpack) + (size_t)cb * C::NGS * C::NB * 64 * 16;
@@ -951,6 +969,79 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREAD
         }
       }
     }
+  }
+}
+
+// The two-class softmax layer of a stride-2 pool net on the VALU. Its two
+// output channels would fill 2 of an MFMA's 16 columns; as FP32 FMAs its
+// 2 x KS^2 x CIN multiply-adds per pixel need no padding. The operand tile is
+// conv_phase's (all CIN channels in one stage); one output pixel per thread,
+// reading operand pixels along a row, which is conflict-free with the
+// 8 (mod 16) dword pixel stride. Weights are laid out
+// [i][cg][j][class][4 channels] and read with wave-uniform (scalar) loads.
+template <int CIN, int KS, int TY, int TX>
+struct CfgHead {
+  static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  static constexpr int NCHB = CIN / 4;  // 16-byte chunks per operand pixel
+  static constexpr int PSB = pad_words(CIN) * 4;
+  static constexpr int LDS = LR * LC * PSB;
+  static constexpr int THREADS = TY * TX;
+  static_assert(THREADS <= 1024 && THREADS % 64 == 0, "one output pixel per thread");
+};
+
+template <int CIN, int KS, int TY, int TX>
+__global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phase(JobSet js, ConvParams prm) {
+  using C = CfgHead<CIN, KS, TY, TX>;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
+  const int tid = threadIdx.x;
+  const int r = tid / TX, c = tid % TX;  // the thread's output pixel inside the tile
+  constexpr int ELB = CIN * 4;
+  // constant address space: the compiler reads uniform addresses with scalar loads
+  const __attribute__((address_space(4))) float* wk = (const __attribute__((address_space(4))) float*)prm.wpack;
+  const float b0 = ldf(prm.bias, 0), b1 = ldf(prm.bias, 1);
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
+    // item order and phase decomposition as conv_phase
+    const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+    const int tpy = J.tiles_y / (d * d);
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int ph = (int)(t2 % (d * d));
+    const int64_t t3 = t2 / (d * d);
+    const int by = (int)(t3 % tpy);
+    const int zz = (int)(t3 / tpy);
+    const int py = ph / d, px = ph % d;
+    const int y0 = by * TY, x0 = bx * TX;
+    __syncthreads();
+    stage_phase_tile<C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(
+        lds, gin(J.in) + (int64_t)zz * J.in_zs * ELB, J.in_rs * ELB, ELB, py, px, d, pd, y0, x0, J.hin - 1 - pd,
+        J.win - 1 - pd, tid);
+    __syncthreads();
+    float z0 = 0.f, z1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int cg = 0; cg < C::NCHB; ++cg)
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          const f4 x = *reinterpret_cast<const f4*>(lds + ((r + i) * C::LC + c + j) * C::PSB + cg * 16);
+          const __attribute__((address_space(4))) float* w = wk + (((i * C::NCHB + cg) * KS + j) * 2) * 4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            z0 = fmaf(x[e], w[e], z0);
+            z1 = fmaf(x[e], w[4 + e], z1);
+          }
+        }
+    const int y = py + d * (y0 + r), x = px + d * (x0 + c);
+    if (y < J.hout && x < J.wout)
+      st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4,
+                sigmoid_f((z1 + b1) - (z0 + b0)));
   }
 }
 
@@ -1607,17 +1698,21 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
   EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
 
-#define EMCNN_PHASE(CIN, COUT, KS, TY, TX, MW, EPI)                                                   \
+#define EMCNN_PHASE(CIN, COUT, KS, TY, TX, MW, EPI, CBL)                                               \
   VariantInfo{F32, CIN, COUT, KS, 1, 0, TY, TX, MW,                                                   \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::THREADS,                                    \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::CB,                                         \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::THREADS,                                \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::CB,                                     \
               PT<F32>::CHB,                                                                           \
               PT<F32>::U,                                                                             \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::NGS,                                        \
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::NGS,                                    \
               0, 0, EPI,                                                                              \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false>::LDS_TILE,                                   \
-              reinterpret_cast<const void*>(&conv_phase<CIN, COUT, KS, TY, TX, MW, EPI>),             \
-              "conv_phase<" #CIN "," #COUT "," #KS "," #TY "," #TX "," #MW "," #EPI ">"}
+              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::LDS_TILE,                               \
+              reinterpret_cast<const void*>(&conv_phase<CIN, COUT, KS, TY, TX, MW, EPI, CBL>),         \
+              "conv_phase<" #CIN "," #COUT "," #KS "," #TY "," #TX "," #MW "," #EPI "," #CBL ">"}
+#define EMCNN_HEAD_PHASE(CIN, KS, TY, TX)                                                              \
+  VariantInfo{F32, CIN, 2, KS, 1, 0, TY, TX, 0, CfgHead<CIN, KS, TY, TX>::THREADS, CIN, PT<F32>::CHB, 1, 0, 0, 0, 3, \
+              CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<CIN, KS, TY, TX>),       \
+              "head_phase<" #CIN "," #KS "," #TY "," #TX ">"}
 
 // Pipelined (BF16 / FP8) tile shapes: TY x TX outputs, consumer x producer
 // waves, per layer signature (shapes that fit the LDS and the 168 registers
@@ -1681,8 +1776,13 @@ static const VariantInfo kConv[] = {
     EMCNN_CONV(F32, 16, 16, 5, false, false, 8, 32, 4),
     // FastMemb body convs (4x4, 32 -> 64, max-out to 32) and its softmax layer
     // (4x4, 32 -> 2 classes, computed as 16 MFMA columns), spaced form
-    EMCNN_PHASE(32, 64, 4, 16, 64, 8, 1), EMCNN_PHASE(32, 64, 4, 8, 64, 4, 1),
-    EMCNN_PHASE(32, 16, 4, 16, 64, 8, 2), EMCNN_PHASE(32, 16, 4, 8, 64, 4, 2),
+    // (all 32 channels per stage use a whole 128-byte pixel line at once)
+    EMCNN_PHASE(32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(32, 64, 4, 8, 64, 8, 1, 32),
+    EMCNN_PHASE(32, 64, 4, 16, 64, 8, 1, 16), EMCNN_PHASE(32, 64, 4, 8, 64, 4, 1, 16),
+    // the softmax layer: on the VALU (default; 2 classes, no padding), or on
+    // MFMA with 14 zero columns
+    EMCNN_HEAD_PHASE(32, 4, 8, 64), EMCNN_HEAD_PHASE(32, 4, 4, 64),
+    EMCNN_PHASE(32, 16, 4, 8, 64, 4, 2, 32), EMCNN_PHASE(32, 16, 4, 16, 64, 8, 2, 16),
 };
 
 #define EMCNN_FIRSTM(PO, COUT, KS, TY, TX, MX)                                                       \

@@ -249,6 +249,35 @@ static int pack_first(ExecLayer& L, int variant, const double* w, const double* 
   return CNN_OK;
 }
 
+// Weights of the VALU two-class layer (head_phase): W[class][ci][i][j] as
+// [i][ci / 4][j][class][ci % 4], FP32; the bias is stored padded to 16 floats
+// (the MFMA candidate of the same layer reads 16).
+static int pack_head_valu(ExecLayer& L, int variant, const double* w, const double* b) {
+  const VariantInfo* v = conv_variant(variant);
+  const int cin = v->cin, ks = v->ks, ncg = cin / 4;
+  std::vector<float> pk((size_t)ks * ncg * ks * 2 * 4);
+  for (int i = 0; i < ks; ++i)
+    for (int cg = 0; cg < ncg; ++cg)
+      for (int j = 0; j < ks; ++j)
+        for (int cls = 0; cls < 2; ++cls)
+          for (int e = 0; e < 4; ++e)
+            pk[((((size_t)i * ncg + cg) * ks + j) * 2 + cls) * 4 + e] =
+                (float)w[(((size_t)cls * cin + 4 * cg + e) * ks + i) * ks + j];
+  hipError_t err;
+  void* wdev = nullptr;
+  if ((err = hipMalloc(&wdev, pk.size() * 4)) != hipSuccess) return hip_fail(err, "hipMalloc(head weights)");
+  L.wpacks.push_back(wdev);
+  if ((err = hipMemcpy(wdev, pk.data(), pk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "hipMemcpy(head weights)");
+  if (L.bias) return CNN_OK;
+  std::vector<float> bf(16, 0.f);
+  bf[0] = (float)b[0];
+  bf[1] = (float)b[1];
+  if ((err = hipMalloc(&L.bias, 16 * sizeof(float))) != hipSuccess) return hip_fail(err, "hipMalloc(head bias)");
+  hipMemcpy(L.bias, bf.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
+  return CNN_OK;
+}
+
 static void free_layer(ExecLayer& L) {
   for (void* p : L.wpacks)
     if (p) hipFree(p);
@@ -308,24 +337,33 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       E.pd = sp;  // the max filter of the stride-2 pool before this conv
       sp *= 2;
       E.dil = sp;
-      const bool soft = l.act == CNN_ACT_SOFTMAX;
-      // the two-class layer runs as 16 MFMA columns: zero weights and bias for classes >= 2
-      E.cout = soft ? 16 : l.cout;
-      E.cstore = soft ? 1 : l.cout / 2;
-      E.epi = soft ? 2 : 1;
-      std::vector<double> wpad, bpad;
-      if (soft) {
-        wpad.assign((size_t)E.cout * l.cin * l.k * l.k, 0.0);
-        bpad.assign(E.cout, 0.0);
+      if (l.act == CNN_ACT_SOFTMAX) {
+        // the two-class layer: VALU kernels (default), then MFMA kernels that
+        // run it as 16 columns with zero weights and bias for classes >= 2
+        E.cout = l.cout;
+        E.cstore = 1;
+        E.epi = 3;
+        E.candidates = find_conv_variants(CNN_PREC_FP32, l.cin, 2, l.k, 1, 0, 3);
+        const std::vector<int> mf = find_conv_variants(CNN_PREC_FP32, l.cin, 16, l.k, 1, 0, 2);
+        E.candidates.insert(E.candidates.end(), mf.begin(), mf.end());
+        if (E.candidates.empty()) return unsupported("no kernel for the softmax layer");
+        std::vector<double> wpad((size_t)16 * l.cin * l.k * l.k, 0.0), bpad(16, 0.0);
         std::copy(w, w + nwl, wpad.begin());
         std::copy(b, b + l.cout, bpad.begin());
-        w = wpad.data();
-        b = bpad.data();
+        for (int c : E.candidates) {
+          if (rc != CNN_OK) break;
+          rc = conv_variant(c)->epi == 3 ? pack_head_valu(E, c, w, b)
+                                        : pack_conv(E, c, wpad.data(), bpad.data(), nullptr, 0.0, 1.0, 0.0);
+        }
+      } else {
+        E.cout = l.cout;
+        E.cstore = l.cout / 2;
+        E.epi = 1;
+        E.candidates = find_conv_variants(CNN_PREC_FP32, l.cin, E.cout, l.k, 1, 0, E.epi);
+        if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(i + 1));
+        for (int c : E.candidates)
+          if (rc == CNN_OK) rc = pack_conv(E, c, w, b, nullptr, 0.0, 1.0, 0.0);
       }
-      E.candidates = find_conv_variants(CNN_PREC_FP32, l.cin, E.cout, l.k, 1, 0, E.epi);
-      if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(i + 1));
-      for (int c : E.candidates)
-        if (rc == CNN_OK) rc = pack_conv(E, c, w, b, nullptr, 0.0, 1.0, 0.0);
     }
     E.variant = E.candidates[0];
     if (rc == CNN_OK) select_variant(E, E.variant);
