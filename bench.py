@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="all",
-                    help="all | none | comma list of bf16,fp8,batch,student,fastmemb")
+                    help="all | none | comma list of bf16,fp8,batch,student,fastmemb,fastmemb_bf16")
     ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -244,25 +244,30 @@ def main():
     del out
     forms = {}
     want = set() if args.forms == "none" else (
-        {"bf16", "fp8", "batch", "student", "fastmemb"} if args.forms == "all" else set(args.forms.split(",")))
-    if "fastmemb" in want and not args.no_headline:
+        {"bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16"} if args.forms == "all"
+        else set(args.forms.split(",")))
+    for fm_prec in ("fp32", "bf16"):
+        key = "fastmemb" if fm_prec == "fp32" else "fastmemb_bf16"
+        if key not in want or args.no_headline:
+            continue
         # the paper's own net (Section 2.2) on the headline volume: dense form of
         # its stride-2 pools (max filters, convs spaced 2, 4, 8 over phase sub-lattices)
         from synth.nets import NET_FM
-        hf = emcnn.cnn_create(calibrated_params("FM"), NET_FM, "fp32")
+        hf = emcnn.cnn_create(calibrated_params("FM"), NET_FM, fm_prec)
         msf, plf, outf = time_volume(emcnn, torch, hf, vol_dev, max(3, args.steps // 2), 2, stream)
         nvf = Z * (H - hf.R) * (W - hf.R)
         body_flop = [Z * (H - 3 - 7) ** 2 * FASTMEMB_BODY_FLOP_PER_POS,
                      Z * (H - 3 - 7 - 14) ** 2 * FASTMEMB_BODY_FLOP_PER_POS]
         body_tf = [f / (t * 1e-3) / 1e12 for f, t in zip(body_flop, plf[1:3])]
-        forms["fastmemb"] = {
-            "workload": "FastMemb FP32 (conv4x4 1->64 max-out, 3 x {2x2/s2 pool, conv4x4}, two-class softmax; "
-                        "FoV 53), %d x %d x %d (seed 2) -> %d x %d x %d" % (Z, H, W, Z, H - hf.R, W - hf.R),
+        forms[key] = {
+            "workload": "FastMemb %s (conv4x4 1->64 max-out, 3 x {2x2/s2 pool, conv4x4}, two-class softmax; "
+                        "FoV 53), %d x %d x %d (seed 2) -> %d x %d x %d"
+                        % (fm_prec.upper(), Z, H, W, Z, H - hf.R, W - hf.R),
             "voxels_per_s": nvf / (msf * 1e-3), "ms_per_pass": msf,
-            "path_mfma_frac": nvf * FASTMEMB_FLOP_PER_VOXEL / (msf * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
-            "body_conv_tflops": body_tf, "body_conv_frac": [t / PEAK_TFLOPS["fp32"] for t in body_tf],
+            "path_mfma_frac": nvf * FASTMEMB_FLOP_PER_VOXEL / (msf * 1e-3) / 1e12 / PEAK_TFLOPS[fm_prec],
+            "body_conv_tflops": body_tf, "body_conv_frac": [t / PEAK_TFLOPS[fm_prec] for t in body_tf],
             "layer_ms": plf[:4], "tiles": emcnn.cnn_describe(hf)}
-        log("fastmemb", json.dumps(forms["fastmemb"]))
+        log(key, json.dumps(forms[key]))
         del outf, hf
     if want & {"bf16", "fp8"}:
         Zp = 128 if args.full else 8

@@ -86,7 +86,9 @@ typedef struct cnn_net cnn_net;
 
 /* Build a network on the current HIP device.
  * Two families of nets are supported: the ReLU nets described below, and the
- * FastMemb family (Section 2.2), FP32 only: conv(k=4, 1 -> 64, MAXOUT), then
+ * FastMemb family (Section 2.2), FP32 or BF16 (bf16 weights and stored
+ * activations with FP32 accumulation, the first conv with bf16(w / 255)
+ * weights; the softmax layer computes in FP32): conv(k=4, 1 -> 64, MAXOUT), then
  * one or more pairs { MAXPOOL_S2, conv(k=4, 32 -> 64, MAXOUT) }, then
  * MAXPOOL_S2 and conv(k=4, 32 -> 2, SOFTMAX); no other transfer function.
  * FastMemb itself has two inner pairs: field of view 53 (R = 52).

@@ -414,11 +414,11 @@ struct FirstCfg {
 };
 
 // MAXOUT: bias then max over the channel pairs (2c, 2c + 1), COUT / 2 stored
-// channels (FP32 NHWC only), instead of bias then ReLU.
+// channels (NHWC, FP32 or BF16), instead of bias then ReLU.
 template <int PO, int COUT, int KS, int TY, int TX, bool MAXOUT = false>
 __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void conv_first(JobSet js, FirstParams prm) {
   using C = FirstCfg<PO, COUT, KS, TY, TX>;
-  static_assert(!MAXOUT || PO == F32, "max-out first layers are FP32");
+  static_assert(!MAXOUT || PO == F32 || PO == BF16, "max-out first layers are FP32 or BF16");
   __shared__ __attribute__((aligned(16))) unsigned char tile[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
@@ -507,7 +507,10 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
             // stored channels nb*8 + 2g and nb*8 + 2g + 1
             const float m0 = fmaxf(acc[nb][0] + bias[nb][0], acc[nb][1] + bias[nb][1]);
             const float m1 = fmaxf(acc[nb][2] + bias[nb][2], acc[nb][3] + bias[nb][3]);
-            st<f2>(oslice + (pix * CST + nb * 8 + 2 * g) * 4, f2{m0, m1});
+            if constexpr (PO == F32)
+              st<f2>(oslice + (pix * CST + nb * 8 + 2 * g) * 4, f2{m0, m1});
+            else
+              st<uint32_t>(oslice + (pix * CST + nb * 8 + 2 * g) * 2, pack_bf16x2(m0, m1));
             continue;
           }
           float v[4];
@@ -835,12 +838,35 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 // EPI 1: bias, then max-out over channel pairs, COUT / 2 channels stored
 // (NHWC). EPI 2: bias, then the two-class softmax of channels 0 and 1 (the
 // other output channels are zero padding), storing the class-1 probability.
+// Elementwise max of two 16-byte chunks of signed activations (nets without
+// ReLU): FP32 compares floats; bf16 values are widened to FP32 (exact) and
+// compared there, and the winner's bits are kept.
+template <int P>
+__device__ __forceinline__ i4v chunk_max_signed(i4v a, i4v b) {
+  if constexpr (P == F32) {
+    return chunk_max<F32>(a, b);
+  } else {
+    static_assert(P == BF16, "signed max: FP32 or BF16 activations");
+    i4v r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t x = (uint32_t)a[e], y = (uint32_t)b[e];
+      const float xl = __builtin_bit_cast(float, x << 16), yl = __builtin_bit_cast(float, y << 16);
+      const float xh = __builtin_bit_cast(float, x & 0xffff0000u), yh = __builtin_bit_cast(float, y & 0xffff0000u);
+      const uint32_t lo = __builtin_bit_cast(uint32_t, fmaxf(xl, yl)) >> 16;
+      const uint32_t hi = __builtin_bit_cast(uint32_t, fmaxf(xh, yh)) & 0xffff0000u;
+      r[e] = (int)(hi | lo);
+    }
+    return r;
+  }
+}
+
 // Stage the LR x LC operand tile of one phase sub-lattice (channel chunks
 // 0 .. NCHB-1 of the block at `in`): operand pixel (r, c) is the 2x2 max
 // filter, elements pd apart, at input (py + d (y0 + r), px + d (x0 + c)). Rows
 // and columns are clamped to ylim / xlim (= last valid filter origin); clamped
-// ones only feed outputs that are not stored.
-template <int LR, int LC, int NCHB, int PSB, int THREADS>
+// ones only feed outputs that are not stored. P: the stored activation type.
+template <int P, int LR, int LC, int NCHB, int PSB, int THREADS>
 __device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const gbyte* in, int64_t rowb, int elb, int py,
                                                  int px, int d, int pd, int y0, int x0, int ylim, int xlim,
                                                  int tid) {
@@ -856,22 +882,24 @@ __device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const gbyte
       const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
       const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
       const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
-      st<i4v>(lds + pix * PSB + cg * 16, chunk_max<F32>(chunk_max<F32>(a, b), chunk_max<F32>(e, f)));
+      st<i4v>(lds + pix * PSB + cg * 16, chunk_max_signed<P>(chunk_max_signed<P>(a, b), chunk_max_signed<P>(e, f)));
     }
   }
 }
 
-template <int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI, int CB>
-__global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>::THREADS)) void conv_phase(
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI, int CB>
+__global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THREADS)) void conv_phase(
     JobSet js, ConvParams prm) {
-  using C = Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>;
+  using C = Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>;
+  using T = PT<P>;
+  static_assert(P == F32 || P == BF16, "FP32 or BF16 activations (NHWC)");
   static_assert(EPI == 1 || EPI == 2, "max-out or softmax epilogue");
-  static_assert(EPI != 2 || C::NB == 1, "the softmax layer has one 16-channel n-block");
+  static_assert(EPI != 2 || C::NB == 1, "the MFMA softmax layer has one 16-channel n-block");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS_TILE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
   constexpr int MCOLS = TX / 16;
-  constexpr int ELB = CIN * 4;  // bytes per stored input pixel
+  constexpr int ELB = CIN * T::BYTES;  // bytes per stored input pixel
 
   float bias[C::NB];
 #pragma unroll
@@ -912,18 +940,18 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>::TH
 
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
-      stage_phase_tile<C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, in + cb * C::CB * 4, rowb, ELB, py, px, d,
-                                                                   pd, y0, x0, ylim, xlim, tid);
+      stage_phase_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, in + cb * C::CB * T::BYTES, rowb, ELB, py,
+                                                                      px, d, pd, y0, x0, ylim, xlim, tid);
       __syncthreads();
       // ---- implicit GEMM over this block's (tap, chunk) slots (as conv_mfma)
       const gbyte* wb = gin(prm.wpack) + (size_t)cb * C::NGS * C::NB * 64 * 16;
 #pragma unroll 2
       for (int s = 0; s < C::NGS; ++s) {
-        Frag<F32> bfr[C::NB];
+        Frag<P> bfr[C::NB];
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
           const gbyte* p = wb + ((size_t)(s * C::NB + nb) * 64 + lane) * 16;
-          load_frag<F32>(bfr[nb], p, p);
+          load_frag<P>(bfr[nb], p, p);
         }
         int c = s * 4 + g;
         c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
@@ -936,10 +964,10 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>::TH
           const int mb = wave * MW + u;
           const int mrow = mb / MCOLS, mcol = mb % MCOLS;
           const unsigned char* a0 = lds + (mrow * C::LC + mcol * 16 + n16) * C::PSB;
-          Frag<F32> afr;
-          load_frag<F32>(afr, a0 + off, a0 + off);
+          Frag<P> afr;
+          load_frag<P>(afr, a0 + off, a0 + off);
 #pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) mma<F32>(acc[u][nb], afr, bfr[nb]);
+          for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[u][nb], afr, bfr[nb]);
         }
       }
     }
@@ -960,7 +988,14 @@ __global__ __launch_bounds__((Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CB>::TH
           for (int nb = 0; nb < C::NB; ++nb) {
             const float v = acc[u][nb][k] + bias[nb];
             const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
-            if (ok && (n16 & 1) == 0) st<float>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 4, m);
+            if constexpr (P == F32) {
+              if (ok && (n16 & 1) == 0) st<float>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 4, m);
+            } else {
+              // lanes n16 = 4q hold stored channel nb*8 + 2q, lanes 4q + 2 channel nb*8 + 2q + 1
+              const float m2 = dpp_f<kQuadXor2>(m);
+              if (ok && (n16 & 3) == 0)
+                st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, pack_bf16x2(m, m2));
+            }
           }
         } else {
           const float z = acc[u][0][k] + bias[0];
@@ -989,13 +1024,48 @@ struct CfgHead {
   static_assert(THREADS <= 1024 && THREADS % 64 == 0, "one output pixel per thread");
 };
 
-template <int CIN, int KS, int TY, int TX>
+// BF16 input (P == BF16): the operand tile is staged widened to FP32, so the
+// layer computes in FP32 in every form.
+template <int LR, int LC, int NCHB_IN, int PSB, int THREADS>
+__device__ __forceinline__ void stage_phase_tile_widen(unsigned char* lds, const gbyte* in, int64_t rowb, int elb,
+                                                       int py, int px, int d, int pd, int y0, int x0, int ylim,
+                                                       int xlim, int tid) {
+  constexpr int NST = LR * LC * NCHB_IN;
+  constexpr int NIT = (NST + THREADS - 1) / THREADS;
+#pragma unroll 2
+  for (int k = 0; k < NIT; ++k) {
+    const int t = tid + k * THREADS;
+    if (t < NST) {
+      const int cg = t % NCHB_IN, pix = t / NCHB_IN;
+      const int r = pix / LC, c = pix % LC;
+      const int y = min(py + d * (y0 + r), ylim), x = min(px + d * (x0 + c), xlim);
+      const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
+      const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
+      const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
+      const i4v m = chunk_max_signed<BF16>(chunk_max_signed<BF16>(a, b), chunk_max_signed<BF16>(e, f));
+      // 8 bf16 channels -> 8 floats (exact)
+      f4 lo, hi;
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        lo[2 * w] = __builtin_bit_cast(float, (uint32_t)m[w] << 16);
+        lo[2 * w + 1] = __builtin_bit_cast(float, (uint32_t)m[w] & 0xffff0000u);
+        hi[2 * w] = __builtin_bit_cast(float, (uint32_t)m[w + 2] << 16);
+        hi[2 * w + 1] = __builtin_bit_cast(float, (uint32_t)m[w + 2] & 0xffff0000u);
+      }
+      st<f4>(lds + pix * PSB + cg * 32, lo);
+      st<f4>(lds + pix * PSB + cg * 32 + 16, hi);
+    }
+  }
+}
+
+template <int P, int CIN, int KS, int TY, int TX>
 __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phase(JobSet js, ConvParams prm) {
   using C = CfgHead<CIN, KS, TY, TX>;
+  static_assert(P == F32 || P == BF16, "FP32 or BF16 input activations (NHWC)");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
   const int tid = threadIdx.x;
   const int r = tid / TX, c = tid % TX;  // the thread's output pixel inside the tile
-  constexpr int ELB = CIN * 4;
+  constexpr int ELB = CIN * PT<P>::BYTES;
   // constant address space: the compiler reads uniform addresses with scalar loads
   const __attribute__((address_space(4))) float* wk = (const __attribute__((address_space(4))) float*)prm.wpack;
   const float b0 = ldf(prm.bias, 0), b1 = ldf(prm.bias, 1);
@@ -1019,9 +1089,14 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
     const int py = ph / d, px = ph % d;
     const int y0 = by * TY, x0 = bx * TX;
     __syncthreads();
-    stage_phase_tile<C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(
-        lds, gin(J.in) + (int64_t)zz * J.in_zs * ELB, J.in_rs * ELB, ELB, py, px, d, pd, y0, x0, J.hin - 1 - pd,
-        J.win - 1 - pd, tid);
+    if constexpr (P == F32)
+      stage_phase_tile<F32, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(
+          lds, gin(J.in) + (int64_t)zz * J.in_zs * ELB, J.in_rs * ELB, ELB, py, px, d, pd, y0, x0, J.hin - 1 - pd,
+          J.win - 1 - pd, tid);
+    else
+      stage_phase_tile_widen<C::LR, C::LC, CIN / 8, C::PSB, C::THREADS>(
+          lds, gin(J.in) + (int64_t)zz * J.in_zs * ELB, J.in_rs * ELB, ELB, py, px, d, pd, y0, x0, J.hin - 1 - pd,
+          J.win - 1 - pd, tid);
     __syncthreads();
     float z0 = 0.f, z1 = 0.f;
 #pragma unroll
@@ -1698,21 +1773,21 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
   EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
 
-#define EMCNN_PHASE(CIN, COUT, KS, TY, TX, MW, EPI, CBL)                                               \
-  VariantInfo{F32, CIN, COUT, KS, 1, 0, TY, TX, MW,                                                   \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::THREADS,                                \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::CB,                                     \
-              PT<F32>::CHB,                                                                           \
-              PT<F32>::U,                                                                             \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::NGS,                                    \
+#define EMCNN_PHASE(P, CIN, COUT, KS, TY, TX, MW, EPI, CBL)                                               \
+  VariantInfo{P, CIN, COUT, KS, 1, 0, TY, TX, MW,                                                   \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CBL>::THREADS,                                \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CBL>::CB,                                     \
+              PT<P>::CHB,                                                                           \
+              PT<P>::U,                                                                             \
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CBL>::NGS,                                    \
               0, 0, EPI,                                                                              \
-              Cfg<F32, CIN, COUT, KS, TY, TX, MW, false, CBL>::LDS_TILE,                               \
-              reinterpret_cast<const void*>(&conv_phase<CIN, COUT, KS, TY, TX, MW, EPI, CBL>),         \
-              "conv_phase<" #CIN "," #COUT "," #KS "," #TY "," #TX "," #MW "," #EPI "," #CBL ">"}
-#define EMCNN_HEAD_PHASE(CIN, KS, TY, TX)                                                              \
-  VariantInfo{F32, CIN, 2, KS, 1, 0, TY, TX, 0, CfgHead<CIN, KS, TY, TX>::THREADS, CIN, PT<F32>::CHB, 1, 0, 0, 0, 3, \
-              CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<CIN, KS, TY, TX>),       \
-              "head_phase<" #CIN "," #KS "," #TY "," #TX ">"}
+              Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CBL>::LDS_TILE,                               \
+              reinterpret_cast<const void*>(&conv_phase<P, CIN, COUT, KS, TY, TX, MW, EPI, CBL>),         \
+              "conv_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #MW "," #EPI "," #CBL ">"}
+#define EMCNN_HEAD_PHASE(P, CIN, KS, TY, TX)                                                              \
+  VariantInfo{P, CIN, 2, KS, 1, 0, TY, TX, 0, CfgHead<CIN, KS, TY, TX>::THREADS, CIN, PT<F32>::CHB, 1, 0, 0, 0, 3, \
+              CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<P, CIN, KS, TY, TX>),       \
+              "head_phase<" #P "," #CIN "," #KS "," #TY "," #TX ">"}
 
 // Pipelined (BF16 / FP8) tile shapes: TY x TX outputs, consumer x producer
 // waves, per layer signature (shapes that fit the LDS and the 168 registers
@@ -1777,12 +1852,16 @@ static const VariantInfo kConv[] = {
     // FastMemb body convs (4x4, 32 -> 64, max-out to 32) and its softmax layer
     // (4x4, 32 -> 2 classes, computed as 16 MFMA columns), spaced form
     // (all 32 channels per stage use a whole 128-byte pixel line at once)
-    EMCNN_PHASE(32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(32, 64, 4, 8, 64, 8, 1, 32),
-    EMCNN_PHASE(32, 64, 4, 16, 64, 8, 1, 16), EMCNN_PHASE(32, 64, 4, 8, 64, 4, 1, 16),
+    EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 8, 1, 32),
+    EMCNN_PHASE(F32, 32, 64, 4, 16, 64, 8, 1, 16), EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 4, 1, 16),
     // the softmax layer: on the VALU (default; 2 classes, no padding), or on
     // MFMA with 14 zero columns
-    EMCNN_HEAD_PHASE(32, 4, 8, 64), EMCNN_HEAD_PHASE(32, 4, 4, 64),
-    EMCNN_PHASE(32, 16, 4, 8, 64, 4, 2, 32), EMCNN_PHASE(32, 16, 4, 16, 64, 8, 2, 16),
+    EMCNN_HEAD_PHASE(F32, 32, 4, 8, 64), EMCNN_HEAD_PHASE(F32, 32, 4, 4, 64),
+    EMCNN_PHASE(F32, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_PHASE(F32, 32, 16, 4, 16, 64, 8, 2, 16),
+    // FastMemb BF16: bf16 activations (NHWC, 64 B per pixel) and weights, FP32
+    // accumulation; the softmax layer reads bf16 and computes in FP32
+    EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(BF16, 32, 64, 4, 16, 64, 8, 1, 32),
+    EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
 };
 
 #define EMCNN_FIRSTM(PO, COUT, KS, TY, TX, MX)                                                       \
@@ -1799,6 +1878,7 @@ static const FirstInfo kFirst[] = {
     EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 8, 64),
     // FastMemb first conv: 4x4, 1 -> 64, max-out to 32
     EMCNN_FIRSTM(F32, 64, 4, 4, 64, true), EMCNN_FIRSTM(F32, 64, 4, 8, 32, true),
+    EMCNN_FIRSTM(BF16, 64, 4, 8, 64, true), EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }

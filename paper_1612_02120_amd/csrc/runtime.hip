@@ -289,12 +289,15 @@ static void free_layer(ExecLayer& L) {
   L.bias = L.oscale = L.head_w = nullptr;
 }
 
-// Nets with stride-2 pools (the FastMemb family, Section 2.2), FP32, in their
-// dense form: conv(4, 1 -> 64, max-out), then one or more of { 2x2/s2 pool,
-// conv(4, 32 -> 64, max-out) }, then a 2x2/s2 pool and conv(4, 32 -> 2,
+// Nets with stride-2 pools (the FastMemb family, Section 2.2), FP32 or BF16,
+// in their dense form: conv(4, 1 -> 64, max-out), then one or more of { 2x2/s2
+// pool, conv(4, 32 -> 64, max-out) }, then a 2x2/s2 pool and conv(4, 32 -> 2,
 // softmax). Every stride-2 pool becomes a 2x2 max filter at the current
-// spacing and doubles the spacing of the later layers.
+// spacing and doubles the spacing of the later layers. BF16: bf16 weights and
+// stored activations with FP32 accumulation (the first conv's weights are
+// bf16(w / 255) against exact uint8 inputs); the softmax layer is FP32.
 static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, int nl) {
+  const int prec = net->prec;
   const auto unsupported = [](const std::string& why) {
     return fail(CNN_EUNSUPPORTED, "cnn_create: stride-2 pool nets: " + why);
   };
@@ -328,7 +331,7 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       E.cout = l.cout;
       E.cstore = l.cout / 2;
       E.epi = 1;
-      E.candidates = find_first_variants(CNN_PREC_FP32, l.cout, l.k, 1);
+      E.candidates = find_first_variants(prec, l.cout, l.k, 1);
       if (E.candidates.empty()) return unsupported("no first-layer kernel");
       for (int c : E.candidates)
         if (rc == CNN_OK) rc = pack_first(E, c, w, b, 0.0);
@@ -338,14 +341,18 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       sp *= 2;
       E.dil = sp;
       if (l.act == CNN_ACT_SOFTMAX) {
-        // the two-class layer: VALU kernels (default), then MFMA kernels that
-        // run it as 16 columns with zero weights and bias for classes >= 2
+        // the two-class layer: FP32 VALU kernels, or MFMA kernels that run it
+        // as 16 columns with zero weights and bias for classes >= 2. FP32
+        // nets default to the VALU form (MFMA would pay 8x padding at the FP32
+        // rate); BF16 nets to the bf16 MFMA form, like their other convs.
         E.cout = l.cout;
         E.cstore = 1;
-        E.epi = 3;
-        E.candidates = find_conv_variants(CNN_PREC_FP32, l.cin, 2, l.k, 1, 0, 3);
-        const std::vector<int> mf = find_conv_variants(CNN_PREC_FP32, l.cin, 16, l.k, 1, 0, 2);
+        std::vector<int> va = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 3);
+        std::vector<int> mf = find_conv_variants(prec, l.cin, 16, l.k, 1, 0, 2);
+        if (prec == CNN_PREC_BF16) va.swap(mf);
+        E.candidates = va;
         E.candidates.insert(E.candidates.end(), mf.begin(), mf.end());
+        if (!E.candidates.empty()) E.epi = conv_variant(E.candidates[0])->epi;
         if (E.candidates.empty()) return unsupported("no kernel for the softmax layer");
         std::vector<double> wpad((size_t)16 * l.cin * l.k * l.k, 0.0), bpad(16, 0.0);
         std::copy(w, w + nwl, wpad.begin());
@@ -359,7 +366,7 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
         E.cout = l.cout;
         E.cstore = l.cout / 2;
         E.epi = 1;
-        E.candidates = find_conv_variants(CNN_PREC_FP32, l.cin, E.cout, l.k, 1, 0, E.epi);
+        E.candidates = find_conv_variants(prec, l.cin, E.cout, l.k, 1, 0, E.epi);
         if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(i + 1));
         for (int c : E.candidates)
           if (rc == CNN_OK) rc = pack_conv(E, c, w, b, nullptr, 0.0, 1.0, 0.0);
@@ -472,7 +479,8 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
   const int nl = spec->n_layers;
   const cnn_layer& hd = Lr[nl - 1];
   if (strided) {
-    if (prec != CNN_PREC_FP32) return fail(CNN_EUNSUPPORTED, "cnn_create: stride-2 pool nets are FP32 only");
+    if (prec != CNN_PREC_FP32 && prec != CNN_PREC_BF16)
+      return fail(CNN_EUNSUPPORTED, "cnn_create: stride-2 pool nets are FP32 or BF16");
   } else {
     // supported shape: first conv(5, 1->C, relu) [pool], body convs (relu) [pool], head conv(1, C->1, sigmoid)
     if (Lr[0].kind != CNN_LAYER_CONV || Lr[0].cin != 1 || Lr[0].act != CNN_ACT_RELU)

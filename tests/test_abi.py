@@ -86,8 +86,8 @@ def test_create_validates_fastmemb_specs_before_device_use():
     assert m.radius_of(NET_FM) == 52  # field of view 53 (Section 2.2)
     rc, _ = _create_rc(m, w, NET_FM, n=w.size + 1)
     assert rc == m.CNN_EINVAL and "n_weights" in m.cnn_last_error()
-    rc, _ = _create_rc(m, w, NET_FM, prec="bf16")
-    assert rc == m.CNN_EUNSUPPORTED and "FP32" in m.cnn_last_error()
+    rc, _ = _create_rc(m, w, NET_FM, prec="fp8")
+    assert rc == m.CNN_EUNSUPPORTED and "FP32 or BF16" in m.cnn_last_error()
     odd = [dict(L) for L in NET_FM]
     odd[0]["cout"] = 63  # max-out pairs channels
     rc, _ = _create_rc(m, w, odd)

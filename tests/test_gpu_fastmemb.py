@@ -2,9 +2,10 @@
 
 FastMemb's stride-2 pools are evaluated densely: each becomes a 2x2 max filter
 at the current spacing and doubles the spacing of the later convs, whose d^2
-phase sub-lattices the kernels tile separately. FP32 throughout; tolerance 1e-5
-max abs on the class-1 probability. Shapes span several tiles per phase at the
-largest spacing (8) and ragged tails in every direction.
+phase sub-lattices the kernels tile separately. Tolerance (max abs on the
+class-1 probability against the exact reference): FP32 1e-5; BF16 (bf16
+weights and stored activations, FP32 accumulation) 2e-2. Shapes span several
+tiles per phase at the largest spacing (8) and ragged tails in every direction.
 """
 import numpy as np
 import pytest
@@ -118,3 +119,44 @@ def test_fastmemb_full_size_sampled_windows(emcnn):
     for z, y, x in pts:
         want = oracle.patch(vol[z], NET_FM, p, y, x)[0]
         assert abs(g[z, y, x] - want) <= TOL, (z, y, x, g[z, y, x], want)
+
+
+@pytest.mark.parametrize("shape", [(2, 131, 157), (1, 620, 590)])
+def test_fastmemb_bf16_matches_reference(emcnn, shape):
+    vol = em_volume(50 + shape[1], *shape)
+    p = _params()
+    h = emcnn.cnn_create(p, NET_FM, "bf16")
+    got = _run(emcnn, h, vol)
+    ref = oracle.forward(vol, NET_FM, p)
+    err = np.abs(got - ref)
+    print("FastMemb bf16", shape, "max err", err.max(), "mean", err.mean())
+    assert err.max() <= 2e-2
+
+
+def test_every_fastmemb_bf16_candidate_matches_reference(emcnn):
+    vol = em_volume(78, 1, 161, 203)
+    p = _params()
+    h = emcnn.cnn_create(p, NET_FM, "bf16")
+    ref = oracle.forward(vol, NET_FM, p)
+    defaults = [emcnn.cnn_variant_names(h, l)[0] for l in range(4)]
+    for layer in range(4):
+        for name in emcnn.cnn_variant_names(h, layer):
+            emcnn.cnn_set_variant(h, layer, name)
+            err = np.abs(_run(emcnn, h, vol) - ref).max()
+            assert err <= 2e-2, (layer, name, err)
+        emcnn.cnn_set_variant(h, layer, defaults[layer])
+
+
+def test_fastmemb_bf16_full_size_sampled_windows(emcnn):
+    vol = em_volume(2, 32, 1024, 1024)
+    p = calibrated_params("FM")
+    h = emcnn.cnn_create(p, NET_FM, "bf16")
+    got = emcnn.cnn_infer(h, _dev(vol))
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    rng = np.random.default_rng(4)
+    pts = [(int(rng.integers(0, 32)), int(rng.integers(0, 972)), int(rng.integers(0, 972))) for _ in range(40)]
+    pts += [(0, 0, 0), (31, 971, 971)]
+    errs = [abs(g[z, y, x] - oracle.patch(vol[z], NET_FM, p, y, x)[0]) for z, y, x in pts]
+    print("FastMemb bf16 full size sampled max err", max(errs))
+    assert max(errs) <= 2e-2
