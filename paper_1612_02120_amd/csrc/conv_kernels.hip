@@ -109,6 +109,20 @@ __device__ __forceinline__ uint32_t pack_e4m3x2(float lo, float hi) {
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(lo, 448.0f), fminf(hi, 448.0f), 0, false) & 0xffffu;
 }
 
+// Signed bf16 activations (nets without ReLU) are stored as order-preserving
+// keys: key = b ^ (b < 0 ? 0xffff : 0x8000) per 16-bit half, so that unsigned
+// order is float order and a max filter is one packed unsigned max per dword
+// (chunk_max<BF16>). bf16_key / bf16_unkey convert two halves at a time.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_key(uint32_t x) {
+  const uint32_t neg = __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, x) >> (short)15);  // 0xffff if < 0
+  return x ^ (neg | 0x80008000u);
+}
+__device__ __forceinline__ uint32_t bf16_unkey(uint32_t k) {
+  const uint32_t pos = __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, k) >> (short)15);  // 0xffff if b >= 0
+  return k ^ (~pos | 0x80008000u);
+}
+
 // Store element idx of an activation array (LDS or global) in the layer's format.
 template <int P, class B>
 __device__ __forceinline__ void store_act(B* base, int64_t idx, float v, float inv) {
@@ -510,7 +524,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
             if constexpr (PO == F32)
               st<f2>(oslice + (pix * CST + nb * 8 + 2 * g) * 4, f2{m0, m1});
             else
-              st<uint32_t>(oslice + (pix * CST + nb * 8 + 2 * g) * 2, pack_bf16x2(m0, m1));
+              st<uint32_t>(oslice + (pix * CST + nb * 8 + 2 * g) * 2, bf16_key(pack_bf16x2(m0, m1)));
             continue;
           }
           float v[4];
@@ -838,27 +852,12 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 // EPI 1: bias, then max-out over channel pairs, COUT / 2 channels stored
 // (NHWC). EPI 2: bias, then the two-class softmax of channels 0 and 1 (the
 // other output channels are zero padding), storing the class-1 probability.
-// Elementwise max of two 16-byte chunks of signed activations (nets without
-// ReLU): FP32 compares floats; bf16 values are widened to FP32 (exact) and
-// compared there, and the winner's bits are kept.
+// Elementwise max of two 16-byte chunks of signed activations: FP32 compares
+// floats; BF16 chunks hold keys (bf16_key) and compare as unsigned halves.
 template <int P>
 __device__ __forceinline__ i4v chunk_max_signed(i4v a, i4v b) {
-  if constexpr (P == F32) {
-    return chunk_max<F32>(a, b);
-  } else {
-    static_assert(P == BF16, "signed max: FP32 or BF16 activations");
-    i4v r;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t x = (uint32_t)a[e], y = (uint32_t)b[e];
-      const float xl = __builtin_bit_cast(float, x << 16), yl = __builtin_bit_cast(float, y << 16);
-      const float xh = __builtin_bit_cast(float, x & 0xffff0000u), yh = __builtin_bit_cast(float, y & 0xffff0000u);
-      const uint32_t lo = __builtin_bit_cast(uint32_t, fmaxf(xl, yl)) >> 16;
-      const uint32_t hi = __builtin_bit_cast(uint32_t, fmaxf(xh, yh)) & 0xffff0000u;
-      r[e] = (int)(hi | lo);
-    }
-    return r;
-  }
+  static_assert(P == F32 || P == BF16, "signed max: FP32 or keyed BF16 activations");
+  return chunk_max<P>(a, b);
 }
 
 // Stage the LR x LC operand tile of one phase sub-lattice (channel chunks
@@ -882,7 +881,12 @@ __device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const gbyte
       const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
       const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
       const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
-      st<i4v>(lds + pix * PSB + cg * 16, chunk_max_signed<P>(chunk_max_signed<P>(a, b), chunk_max_signed<P>(e, f)));
+      i4v m = chunk_max_signed<P>(chunk_max_signed<P>(a, b), chunk_max_signed<P>(e, f));
+      if constexpr (P == BF16) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) m[w] = (int)bf16_unkey((uint32_t)m[w]);  // keys -> bf16 operands
+      }
+      st<i4v>(lds + pix * PSB + cg * 16, m);
     }
   }
 }
@@ -994,7 +998,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
               // lanes n16 = 4q hold stored channel nb*8 + 2q, lanes 4q + 2 channel nb*8 + 2q + 1
               const float m2 = dpp_f<kQuadXor2>(m);
               if (ok && (n16 & 3) == 0)
-                st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, pack_bf16x2(m, m2));
+                st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, bf16_key(pack_bf16x2(m, m2)));
             }
           }
         } else {
@@ -1042,7 +1046,9 @@ __device__ __forceinline__ void stage_phase_tile_widen(unsigned char* lds, const
       const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
       const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
       const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
-      const i4v m = chunk_max_signed<BF16>(chunk_max_signed<BF16>(a, b), chunk_max_signed<BF16>(e, f));
+      i4v m = chunk_max_signed<BF16>(chunk_max_signed<BF16>(a, b), chunk_max_signed<BF16>(e, f));
+#pragma unroll
+      for (int w = 0; w < 4; ++w) m[w] = (int)bf16_unkey((uint32_t)m[w]);
       // 8 bf16 channels -> 8 floats (exact)
       f4 lo, hi;
 #pragma unroll
