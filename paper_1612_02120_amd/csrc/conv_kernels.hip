@@ -18,8 +18,12 @@
 //   conv_ws     - the BF16 / FP8 convs: the same implicit GEMM, warp-specialised
 //                 (producer waves stage the next tile while consumer waves run
 //                 MFMA) over channel-blocked activations.
+//   conv_phase  - the convs of nets with stride-2 pools (FastMemb): taps spaced
+//   head_phase    d apart, tiled per phase sub-lattice (the paper's fragments);
+//                 max-out or two-class softmax epilogues; head_phase is the
+//                 two-class layer on the VALU.
 //
-// Both are persistent: a grid of a multiple of 8 workgroups walks the work
+// All are persistent: a grid of a multiple of 8 workgroups walks the work
 // items (z, tile_y, tile_x) of one or many jobs. Workgroups are dispatched to
 // the 8 XCDs round-robin, so workgroup b works on the b%8-th eighth of the item
 // range: neighbouring tiles, which share halo rows, meet in the same L2.
