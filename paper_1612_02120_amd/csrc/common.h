@@ -35,6 +35,12 @@ struct LayerJob {
   // before it; 0 for the plain kernels. With d > 1 the output splits into d^2
   // phase sub-lattices (positions py + d r, px + d c) that are tiled
   // separately: tiles_y counts d^2 x the tile rows of the largest phase.
+  // Bits 16-19: lg, the output map is stored fragment-major modulo D = 2^lg
+  // (0: row-major). Such a map keeps each of its D^2 fragments (pixels
+  // (fy + D r, fx + D c)) as a separate row-major block: pixel (y, x) of a
+  // slice is at ((y % D) D + x % D) (zs / D^2) + (y / D) rs + x / D, with
+  // rs = ceil(w / D) and zs = D^2 ceil(h / D) ceil(w / D). The input map of a
+  // spaced layer is stored fragment-major modulo its own d.
   int32_t geom;
 };
 

@@ -127,6 +127,51 @@ __device__ __forceinline__ uint32_t bf16_unkey(uint32_t k) {
   return k ^ (~pos | 0x80008000u);
 }
 
+// Pixel index, inside a slice, of map pixel (y, x) when the map is stored
+// fragment-major modulo D = 2^lg (lg = 0: row-major, row stride rs): fragment
+// (y mod D, x mod D) is a row-major block of zs / D^2 pixels holding rows y / D
+// and columns x / D.
+__device__ __forceinline__ int64_t frag_pix(int y, int x, int lg, int64_t rs, int64_t zs) {
+  const int m = (1 << lg) - 1;
+  return (int64_t)(((y & m) << lg) + (x & m)) * (zs >> (2 * lg)) + (int64_t)(y >> lg) * rs + (x >> lg);
+}
+
+// Operand addressing of one phase tile of a spaced conv (taps d apart, 2x2 max
+// filter pd = d / 2 apart before it) whose input map is stored fragment-major
+// modulo d. Operand pixel (r, c) of phase (py, px) is the filter at input
+// (py + d (y0 + r), px + d (x0 + c)): row y0 + r, column x0 + c of fragment
+// (py, px). Its partners at +pd lie at the same row and column of fragments
+// (py + pd) mod d and (px + pd) mod d, one row / column further where that
+// wraps, so each is a fixed offset from the first element for the whole tile.
+// Rows and columns are clamped to the last valid filter origin; clamped ones
+// only feed outputs that are not stored.
+struct FragTile {
+  const gbyte* base;  // fragment (py, px), row 0, column 0
+  int64_t rowb;       // bytes per fragment row
+  int64_t o01, o10, o11;  // byte offsets of the partners at (0, +pd), (+pd, 0), (+pd, +pd)
+  int rmax, cmax;     // last valid filter row / column (fragment coordinates)
+  __device__ __forceinline__ const gbyte* at(int r, int c, int elb) const {
+    return base + (int64_t)min(r, rmax) * rowb + (int64_t)min(c, cmax) * elb;
+  }
+};
+
+__device__ __forceinline__ FragTile frag_tile(const gbyte* slice, int elb, const LayerJob& J, int py, int px) {
+  const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+  const int lg = __builtin_ctz(d);
+  const int64_t plane = (J.in_zs >> (2 * lg)) * elb;  // bytes per fragment
+  FragTile f;
+  f.rowb = J.in_rs * elb;
+  f.base = slice + (int64_t)(py * d + px) * plane;
+  const int fy = (py + pd) & (d - 1), cy = (py + pd) >> lg;
+  const int fx = (px + pd) & (d - 1), cx = (px + pd) >> lg;
+  f.o01 = (int64_t)(fx - px) * plane + (int64_t)cx * elb;
+  f.o10 = (int64_t)(fy - py) * d * plane + (int64_t)cy * f.rowb;
+  f.o11 = f.o01 + f.o10;
+  f.rmax = (J.hin - 1 - pd - py) >> lg;  // y + pd <= hin - 1
+  f.cmax = (J.win - 1 - pd - px) >> lg;
+  return f;
+}
+
 // Store element idx of an activation array (LDS or global) in the layer's format.
 template <int P, class B>
 __device__ __forceinline__ void store_act(B* base, int64_t idx, float v, float inv) {
@@ -517,7 +562,9 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
       }
       const int y = y0 + mrow, x = x0 + mcol * 16 + n16;
       if (y < J.hout && x < J.wout) {
-        const int64_t pix = (int64_t)y * J.out_rs + x;
+        // max-out maps feed a spaced conv and are stored fragment-major
+        const int64_t pix = MAXOUT ? frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs)
+                                   : (int64_t)y * J.out_rs + x;
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
           if constexpr (MAXOUT) {
@@ -865,14 +912,12 @@ __device__ __forceinline__ i4v chunk_max_signed(i4v a, i4v b) {
 }
 
 // Stage the LR x LC operand tile of one phase sub-lattice (channel chunks
-// 0 .. NCHB-1 of the block at `in`): operand pixel (r, c) is the 2x2 max
-// filter, elements pd apart, at input (py + d (y0 + r), px + d (x0 + c)). Rows
-// and columns are clamped to ylim / xlim (= last valid filter origin); clamped
-// ones only feed outputs that are not stored. P: the stored activation type.
+// 0 .. NCHB-1 of the block at byte offset cofs of each pixel): operand pixel
+// (r, c) is the 2x2 max filter addressed by f (frag_tile). P: the stored
+// activation type.
 template <int P, int LR, int LC, int NCHB, int PSB, int THREADS>
-__device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const gbyte* in, int64_t rowb, int elb, int py,
-                                                 int px, int d, int pd, int y0, int x0, int ylim, int xlim,
-                                                 int tid) {
+__device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const FragTile& f, int cofs, int elb, int y0,
+                                                 int x0, int tid) {
   constexpr int NST = LR * LC * NCHB;
   constexpr int NIT = (NST + THREADS - 1) / THREADS;
 #pragma unroll 2
@@ -881,11 +926,10 @@ __device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const gbyte
     if (t < NST) {
       const int cg = t % NCHB, pix = t / NCHB;
       const int r = pix / LC, c = pix % LC;
-      const int y = min(py + d * (y0 + r), ylim), x = min(px + d * (x0 + c), xlim);
-      const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
-      const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
-      const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
-      i4v m = chunk_max_signed<P>(chunk_max_signed<P>(a, b), chunk_max_signed<P>(e, f));
+      const gbyte* q = f.at(y0 + r, x0 + c, elb) + cofs + cg * 16;
+      const i4v a = ld<i4v>(q), b = ld<i4v>(q + f.o01);
+      const i4v e = ld<i4v>(q + f.o10), g = ld<i4v>(q + f.o11);
+      i4v m = chunk_max_signed<P>(chunk_max_signed<P>(a, b), chunk_max_signed<P>(e, g));
       if constexpr (P == BF16) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) m[w] = (int)bf16_unkey((uint32_t)m[w]);  // keys -> bf16 operands
@@ -919,7 +963,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
   for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
     const LayerJob J = job_at(js, cur, item);
     if (gated_off(J)) continue;
-    const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+    const int d = max(J.geom & 0xff, 1);
     // item order: tile column, then phase, then tile row, then slice. The d^2
     // phases of one tile row are neighbours in the item range, so the
     // workgroups of an XCD stage them together: their max filters read each
@@ -934,11 +978,9 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
     const int zz = (int)(t3 / tpy);
     const int py = ph / d, px = ph % d;
     const int y0 = by * TY, x0 = bx * TX;  // sub-lattice coordinates of the tile
-    // operand pixel (r, c) is the max filter at input (py + d (y0 + r), px + d (x0 + c));
-    // rows / columns past the last valid one only feed outputs that are not stored
-    const int ylim = J.hin - 1 - pd, xlim = J.win - 1 - pd;
-    const gbyte* in = gin(J.in) + (int64_t)zz * J.in_zs * ELB;
-    const int64_t rowb = J.in_rs * ELB;
+    // operand pixel (r, c) is the max filter at input (py + d (y0 + r), px + d (x0 + c))
+    const FragTile ft = frag_tile(gin(J.in) + (int64_t)zz * J.in_zs * ELB, ELB, J, py, px);
+    const int lgo = (J.geom >> 16) & 0xf;  // output map: fragment-major modulo 2^lgo
 
     f4 acc[MW][C::NB];
 #pragma unroll
@@ -948,8 +990,8 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
 
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
-      stage_phase_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, in + cb * C::CB * T::BYTES, rowb, ELB, py,
-                                                                      px, d, pd, y0, x0, ylim, xlim, tid);
+      stage_phase_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, ft, cb * C::CB * T::BYTES, ELB, y0, x0,
+                                                                      tid);
       __syncthreads();
       // ---- implicit GEMM over this block's (tap, chunk) slots (as conv_mfma)
       const gbyte* wb = gin(prm.wpack) + (size_t)cb * C::NGS * C::NB * 64 * 16;
@@ -990,7 +1032,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
       for (int k = 0; k < 4; ++k) {
         const int x = px + d * (x0 + mcol * 16 + 4 * g + k);
         const bool ok = y < J.hout && x < J.wout;
-        const int64_t pix = (int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x;
+        const int64_t pix = (int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs);
         if constexpr (EPI == 1) {
 #pragma unroll
           for (int nb = 0; nb < C::NB; ++nb) {
@@ -1035,9 +1077,8 @@ struct CfgHead {
 // BF16 input (P == BF16): the operand tile is staged widened to FP32, so the
 // layer computes in FP32 in every form.
 template <int LR, int LC, int NCHB_IN, int PSB, int THREADS>
-__device__ __forceinline__ void stage_phase_tile_widen(unsigned char* lds, const gbyte* in, int64_t rowb, int elb,
-                                                       int py, int px, int d, int pd, int y0, int x0, int ylim,
-                                                       int xlim, int tid) {
+__device__ __forceinline__ void stage_phase_tile_widen(unsigned char* lds, const FragTile& ft, int elb, int y0, int x0,
+                                                       int tid) {
   constexpr int NST = LR * LC * NCHB_IN;
   constexpr int NIT = (NST + THREADS - 1) / THREADS;
 #pragma unroll 2
@@ -1046,10 +1087,9 @@ __device__ __forceinline__ void stage_phase_tile_widen(unsigned char* lds, const
     if (t < NST) {
       const int cg = t % NCHB_IN, pix = t / NCHB_IN;
       const int r = pix / LC, c = pix % LC;
-      const int y = min(py + d * (y0 + r), ylim), x = min(px + d * (x0 + c), xlim);
-      const gbyte* q = in + (int64_t)y * rowb + (int64_t)x * elb + cg * 16;
-      const i4v a = ld<i4v>(q), b = ld<i4v>(q + pd * elb);
-      const i4v e = ld<i4v>(q + pd * rowb), f = ld<i4v>(q + pd * rowb + pd * elb);
+      const gbyte* q = ft.at(y0 + r, x0 + c, elb) + cg * 16;
+      const i4v a = ld<i4v>(q), b = ld<i4v>(q + ft.o01);
+      const i4v e = ld<i4v>(q + ft.o10), f = ld<i4v>(q + ft.o11);
       i4v m = chunk_max_signed<BF16>(chunk_max_signed<BF16>(a, b), chunk_max_signed<BF16>(e, f));
 #pragma unroll
       for (int w = 0; w < 4; ++w) m[w] = (int)bf16_unkey((uint32_t)m[w]);
@@ -1087,7 +1127,7 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
     const LayerJob J = job_at(js, cur, item);
     if (gated_off(J)) continue;
     // item order and phase decomposition as conv_phase
-    const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+    const int d = max(J.geom & 0xff, 1);
     const int tpy = J.tiles_y / (d * d);
     const int64_t local = item - J.item0;
     const int bx = (int)(local % J.tiles_x);
@@ -1098,15 +1138,12 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
     const int zz = (int)(t3 / tpy);
     const int py = ph / d, px = ph % d;
     const int y0 = by * TY, x0 = bx * TX;
+    const FragTile ft = frag_tile(gin(J.in) + (int64_t)zz * J.in_zs * ELB, ELB, J, py, px);
     __syncthreads();
     if constexpr (P == F32)
-      stage_phase_tile<F32, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(
-          lds, gin(J.in) + (int64_t)zz * J.in_zs * ELB, J.in_rs * ELB, ELB, py, px, d, pd, y0, x0, J.hin - 1 - pd,
-          J.win - 1 - pd, tid);
+      stage_phase_tile<F32, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, ft, 0, ELB, y0, x0, tid);
     else
-      stage_phase_tile_widen<C::LR, C::LC, CIN / 8, C::PSB, C::THREADS>(
-          lds, gin(J.in) + (int64_t)zz * J.in_zs * ELB, J.in_rs * ELB, ELB, py, px, d, pd, y0, x0, J.hin - 1 - pd,
-          J.win - 1 - pd, tid);
+      stage_phase_tile_widen<C::LR, C::LC, CIN / 8, C::PSB, C::THREADS>(lds, ft, ELB, y0, x0, tid);
     __syncthreads();
     float z0 = 0.f, z1 = 0.f;
 #pragma unroll
@@ -1125,7 +1162,7 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
         }
     const int y = py + d * (y0 + r), x = px + d * (x0 + c);
     if (y < J.hout && x < J.wout)
-      st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4,
+      st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs)) * 4,
                 sigmoid_f((z1 + b1) - (z0 + b0)));
   }
 }
@@ -1236,6 +1273,23 @@ struct TileWalk {
     x0 = bx * TX;
     zz = (int)(t2 / J.tiles_y);
   }
+  // phase-tiled items of a spaced conv (the order of conv_phase: tile column,
+  // then phase, then tile row, then slice); (y0, x0) in sub-lattice coordinates
+  template <int TY, int TX>
+  __device__ void phase_coords(int& zz, int& py, int& px, int& y0, int& x0) const {
+    const int d = max(J.geom & 0xff, 1);
+    const int tpy = J.tiles_y / (d * d);
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int ph = (int)(t2 % (d * d));
+    const int64_t t3 = t2 / (d * d);
+    y0 = (int)(t3 % tpy) * TY;
+    x0 = bx * TX;
+    zz = (int)(t3 / tpy);
+    py = ph / d;
+    px = ph % d;
+  }
 };
 
 // One stage's operand tile held in producer registers between its global
@@ -1335,6 +1389,48 @@ struct WStage {
 };
 
 
+// One stage's operand tile of a spaced conv (stride-2 pool nets) held in
+// producer registers: operand pixel (r, c) is the 2x2 max filter addressed by
+// f (frag_tile) over an NHWC map of keyed bf16 activations (elb bytes per
+// pixel; cofs = byte offset of the stage's first channel). The max is taken on
+// keys and the winner is stored to LDS as a bf16 operand.
+template <int LR, int LC, int NCHB, int PSB, int NPT>
+struct PhStage {
+  static constexpr int NST = LR * LC * NCHB;
+  static constexpr int NIT = (NST + NPT - 1) / NPT;
+  i4v q[NIT][4];
+
+  __device__ __forceinline__ void load(const FragTile& f, int cofs, int elb, int y0, int x0, int ptid) {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < NST) {
+        const int cg = t % NCHB, pix = t / NCHB;
+        const int r = pix / LC, c = pix % LC;
+        const gbyte* p = f.at(y0 + r, x0 + c, elb) + cofs + cg * 16;
+        q[k][0] = ld<i4v>(p);
+        q[k][1] = ld<i4v>(p + f.o01);
+        q[k][2] = ld<i4v>(p + f.o10);
+        q[k][3] = ld<i4v>(p + f.o11);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(unsigned char* lds, int ptid) const {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < NST) {
+        const int cg = t % NCHB, pix = t / NCHB;
+        i4v m = chunk_max<BF16>(chunk_max<BF16>(q[k][0], q[k][1]), chunk_max<BF16>(q[k][2], q[k][3]));
+#pragma unroll
+        for (int w = 0; w < 4; ++w) m[w] = (int)bf16_unkey((uint32_t)m[w]);
+        *reinterpret_cast<i4v*>(lds + pix * PSB + cg * 16) = m;
+      }
+    }
+  }
+};
+
 // Store one (m-block, n-block) accumulator tile in the channel-blocked layout.
 // Lane (g, n) holds channel n of pixels 4g..4g+3. Two quad exchanges leave
 // lane (g, n) with channels 4(n/4)..4(n/4)+3 of pixel 4g + n%4, so the 64
@@ -1362,13 +1458,19 @@ __device__ __forceinline__ void store_block_tile(B* plane_row, int pm_ok, const 
   }
 }
 
-template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int NCW, int NPW, int K1>
+// PH = 1: a spaced conv of a stride-2 pool net (the work of conv_phase with
+// max-out, BF16): NHWC keyed input, operand pixels are the spaced 2x2 max
+// filter, items are phase tiles, and the epilogue is bias + max-out over
+// channel pairs, stored as NHWC keys.
+template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int NCW, int NPW, int K1, int PH = 0>
 __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THREADS)) void conv_ws(
     JobSet js, ConvParams prm) {
   using C = CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>;
   static_assert(K1 == 0 || POOL, "the fused first layer feeds a max filter");
   using T = PT<P>;
   static_assert(P != F32, "conv_ws reads and writes the channel-blocked BF16 / FP8 layout");
+  static_assert(!PH || (P == BF16 && POOL && !HEAD && K1 == 0 && C::WRES),
+                "spaced form: BF16 max-out conv with all weights resident in LDS");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform role
@@ -1536,7 +1638,41 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
     return;
   }
 
-  if constexpr (K1 == 0) if (wave >= NCW) {
+  if constexpr (PH) if (wave >= NCW) {
+    // ---------------- producer waves, spaced max filter
+    const int ptid = tid - NCW * 64;
+    constexpr int ELB = CIN * T::BYTES;  // bytes per stored input pixel (NHWC)
+    PhStage<C::LR, C::LC, C::NCHB, C::PSB, NPW * 64> a;
+    int cb = 0;
+    auto issue = [&]() __attribute__((always_inline)) {
+      int zz, py, px, y0, x0;
+      w.phase_coords<TY, TX>(zz, py, px, y0, x0);
+      const FragTile ft = frag_tile(gin(w.J.in) + (int64_t)zz * w.J.in_zs * ELB, ELB, w.J, py, px);
+      a.load(ft, cb * C::CB * T::BYTES, ELB, y0, x0, ptid);
+    };
+    auto advance = [&]() __attribute__((always_inline)) -> bool {
+      if (++cb < C::NCB) return true;
+      cb = 0;
+      return w.next(js);
+    };
+    issue();
+    a.store(lds, ptid);
+    bool more = advance();
+    if (more) issue();
+    __syncthreads();  // stage 0 ready
+    int sel = 1;
+    while (more) {
+      a.store(lds + sel * C::BUF, ptid);  // the consumers finished this buffer's previous stage
+      more = advance();
+      if (more) issue();
+      __syncthreads();  // this stage ready; the consumers finished the previous one
+      sel ^= 1;
+    }
+    __syncthreads();  // the consumers' last stage
+    return;
+  }
+
+  if constexpr (K1 == 0 && !PH) if (wave >= NCW) {
     // ---------------- producer waves
     const int ptid = tid - NCW * 64;
     AStage<P, C::LR, C::LC, C::NCHB, C::PSB, NPW * 64, POOL> a;
@@ -1687,7 +1823,37 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
       }
     }
 
-    if (cb == C::NCB - 1) {
+    if constexpr (PH) {
+      if (cb == C::NCB - 1) {
+        // ---- spaced-form epilogue: lane (g, n16) holds channel n16 of pixels 4g + k
+        int zz, py, px, y0, x0;
+        w.phase_coords<TY, TX>(zz, py, px, y0, x0);
+        const LayerJob& J = w.J;
+        const int d = max(J.geom & 0xff, 1);
+        float bias[C::NB];
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) bias[nb] = ldf(prm.bias, nb * 16 + n16);
+#pragma unroll
+        for (int u = 0; u < C::MW; ++u) {
+          const int y = py + d * (y0 + wrow0 + u / MCOLS);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x = px + d * (x0 + (u % MCOLS) * 16 + 4 * g + k);
+            const bool ok = y < J.hout && x < J.wout;
+            const int64_t pix = (int64_t)zz * J.out_zs + frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs);
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) {
+              const float v = acc[u][nb][k] + bias[nb];
+              const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
+              // lanes n16 = 4q hold stored channel nb*8 + 2q, lanes 4q + 2 channel nb*8 + 2q + 1
+              const float m2 = dpp_f<kQuadXor2>(m);
+              if (ok && (n16 & 3) == 0)
+                st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, bf16_key(pack_bf16x2(m, m2)));
+            }
+          }
+        }
+      }
+    } else if (cb == C::NCB - 1) {
       // ---- epilogue straight from the accumulators
       int zz, y0, x0;
       w.coords<TY, TX>(zz, y0, x0);
@@ -1780,6 +1946,18 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, K1>), \
               "conv_ws<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #NCW "," #NPW \
               "," #K1 ">"}
+#define EMCNN_WS_PHASE(P, CIN, COUT, KS, TY, TX, NCW, NPW)                                           \
+  VariantInfo{P, CIN, COUT, KS, 1, 0, TY, TX,                                                         \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::MW,                                       \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::THREADS,                                  \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::CB,                                       \
+              PT<P>::CHB,                                                                             \
+              PT<P>::U,                                                                               \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::NGS,                                      \
+              0, 0, 1,                                                                                \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::LDS,                                      \
+              reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, true, false, TY, TX, NCW, NPW, 0, 1>), \
+              "conv_ws_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #NCW "," #NPW ">"}
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
   EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
 
@@ -1870,6 +2048,11 @@ static const VariantInfo kConv[] = {
     EMCNN_PHASE(F32, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_PHASE(F32, 32, 16, 4, 16, 64, 8, 2, 16),
     // FastMemb BF16: bf16 activations (NHWC, 64 B per pixel) and weights, FP32
     // accumulation; the softmax layer reads bf16 and computes in FP32
+    // body convs: warp-specialised (16-channel stages, weights resident in
+    // LDS; default), conv_phase with the same 16-channel stages (the same MFMA
+    // sequence), and conv_phase staging all 32 channels at once
+    EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 8, 4), EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 4, 4),
+    EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 16),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(BF16, 32, 64, 4, 16, 64, 8, 1, 32),
     EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
 };

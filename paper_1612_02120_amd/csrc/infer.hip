@@ -37,10 +37,13 @@ static std::vector<size_t> layer_bytes(const Net* net, const Dims& d) {
   std::vector<size_t> b;
   const int nl = (int)net->layers.size();
   const bool fused = first_fused(net);
-  for (int l = 0; l < nl; ++l)
+  for (int l = 0; l < nl; ++l) {
+    int64_t rs, zs;
+    map_strides(net->layers[l], d.hout[l], d.wout[l], rs, zs);
     b.push_back(l == nl - 1 || (l == 0 && fused)
                     ? 0
-                    : (size_t)d.hout[l] * d.wout[l] * stored_channels(net->layers[l]) * act_bytes_of(net->prec));
+                    : (size_t)zs * stored_channels(net->layers[l]) * act_bytes_of(net->prec));
+  }
   return b;
 }
 
@@ -84,8 +87,9 @@ static LayerJob make_job(const ExecLayer& L, const void* in, void* out, int z, i
     const int d = L.dil, hs = (hout + d - 1) / d, wsub = (wout + d - 1) / d;
     j.tiles_x = (wsub + layer_tx(L) - 1) / layer_tx(L);
     j.tiles_y = d * d * ((hs + layer_ty(L) - 1) / layer_ty(L));
-    j.geom = d | (L.pd << 8);
+    j.geom = d | (L.pd << 8) | (L.out_lg << 16);
   } else {
+    j.geom = L.out_lg << 16;
     j.tiles_x = (wout + layer_tx(L) - 1) / layer_tx(L);
     j.tiles_y = (hout + layer_ty(L) - 1) / layer_ty(L);
   }
@@ -174,8 +178,12 @@ int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, fl
       const int li = (l == 1 && fused) ? 0 : l;
       const void* in = (li == 0) ? (const void*)(vol + z0 * H * W) : (const void*)buf[(l - 1) % 2];
       void* out = (l == nl - 1) ? (void*)(prob + z0 * (int64_t)Ho * Wo) : (void*)buf[l % 2];
-      LayerJob j = make_job(L, in, out, zc, d.hin[li], d.win[li], d.win[li], (int64_t)d.hin[li] * d.win[li],
-                            d.hout[l], d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
+      int64_t in_rs = d.win[li], in_zs = (int64_t)d.hin[li] * d.win[li], out_rs = d.wout[l],
+              out_zs = (int64_t)d.hout[l] * d.wout[l];
+      if (li > 0) map_strides(net->layers[li - 1], d.hin[li], d.win[li], in_rs, in_zs);
+      if (l < nl - 1) map_strides(L, d.hout[l], d.wout[l], out_rs, out_zs);
+      LayerJob j = make_job(L, in, out, zc, d.hin[li], d.win[li], in_rs, in_zs, d.hout[l], d.wout[l], out_rs, out_zs,
+                            0, nullptr);
       JobSet js;
       std::memset(&js, 0, sizeof(js));
       js.njobs = 1;
@@ -319,8 +327,7 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
           in_zs = R.in_zs;
         } else {
           in = buf_of(l - 1);
-          in_rs = d.win[l];
-          in_zs = (int64_t)d.hin[l] * d.win[l];
+          map_strides(net->layers[l - 1], d.hin[l], d.win[l], in_rs, in_zs);
         }
         void* out;
         int64_t out_rs, out_zs;
@@ -330,8 +337,7 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
           out_zs = R.out_zs;
         } else {
           out = buf_of(l);
-          out_rs = d.wout[l];
-          out_zs = (int64_t)d.hout[l] * d.wout[l];
+          map_strides(L, d.hout[l], d.wout[l], out_rs, out_zs);
         }
         LayerJob j = make_job(L, in, out, R.z, d.hin[li], d.win[li], in_rs, in_zs, d.hout[l], d.wout[l], out_rs,
                               out_zs, item0, R.gate);
@@ -539,8 +545,13 @@ static int candidate_name_index(const ExecLayer& L, const std::string& name) {
 static int run_one_layer(Net* net, int l, const void* in, void* out, const Dims& d, hipStream_t st) {
   const ExecLayer& L = net->layers[l];
   const int li = (l == 1 && first_fused(net)) ? 0 : l;
-  LayerJob j = make_job(L, in, out, 1, d.hin[li], d.win[li], d.win[li], (int64_t)d.hin[li] * d.win[li], d.hout[l],
-                        d.wout[l], d.wout[l], (int64_t)d.hout[l] * d.wout[l], 0, nullptr);
+  const int nl = (int)net->layers.size();
+  int64_t in_rs = d.win[li], in_zs = (int64_t)d.hin[li] * d.win[li], out_rs = d.wout[l],
+          out_zs = (int64_t)d.hout[l] * d.wout[l];
+  if (li > 0) map_strides(net->layers[li - 1], d.hin[li], d.win[li], in_rs, in_zs);
+  if (l < nl - 1) map_strides(L, d.hout[l], d.wout[l], out_rs, out_zs);
+  LayerJob j = make_job(L, in, out, 1, d.hin[li], d.win[li], in_rs, in_zs, d.hout[l], d.wout[l], out_rs, out_zs, 0,
+                        nullptr);
   JobSet js;
   std::memset(&js, 0, sizeof(js));
   js.njobs = 1;
@@ -594,9 +605,11 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   }
   const int eb = net->prec == F32 ? 4 : net->prec == BF16 ? 2 : 1;
   std::vector<size_t> ob(nl);
-  for (int l = 0; l < nl; ++l)
-    ob[l] = (l == nl - 1) ? (size_t)d.hout[l] * d.wout[l] * 4
-                          : (size_t)d.hout[l] * d.wout[l] * stored_channels(net->layers[l]) * eb;
+  for (int l = 0; l < nl; ++l) {
+    int64_t rs, zs;
+    map_strides(net->layers[l], d.hout[l], d.wout[l], rs, zs);
+    ob[l] = (l == nl - 1) ? (size_t)d.hout[l] * d.wout[l] * 4 : (size_t)zs * stored_channels(net->layers[l]) * eb;
+  }
   std::vector<void*> bufs(nl + 2, nullptr);
   hipError_t e;
   size_t maxb = 0;

@@ -22,6 +22,9 @@ struct ExecLayer {
   // and the 2x2 max filter before the conv (pool_in) takes elements pd apart
   int dil = 1, pd = 1;
   int epi = 0;     // epilogue kind (VariantInfo::epi; first layers: 1 = max-out)
+  // the output map is stored fragment-major modulo 2^out_lg (the spacing of
+  // the conv that reads it; 0: row-major), see LayerJob::geom
+  int out_lg = 0;
   int cstore = 0;  // channels stored per output pixel: cout, or cout / 2 after max-out
   int variant = -1;
   std::vector<int> candidates;
@@ -33,6 +36,15 @@ struct ExecLayer {
   float head_b = 0.f;
   float out_inv_scale = 1.f;
 };
+
+// Stored geometry of a layer's h x w output map in pixels: row stride rs and
+// slice size zs. A fragment-major map (out_lg > 0) holds D^2 fragments of
+// ceil(h / D) x ceil(w / D) pixels each, D = 2^out_lg.
+inline void map_strides(const ExecLayer& L, int64_t h, int64_t w, int64_t& rs, int64_t& zs) {
+  const int64_t D = (int64_t)1 << L.out_lg, hq = (h + D - 1) / D, wq = (w + D - 1) / D;
+  rs = wq;
+  zs = D * D * hq * wq;
+}
 
 struct Net {
   int device = 0;

@@ -383,6 +383,8 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
     off += (E.pool_in ? E.pd : 0) + (E.ks - 1) * E.dil;
   }
   if (off != net->R) return fail(CNN_EINVAL, "cnn_create: internal radius mismatch");
+  // every map but the output feeds a spaced conv: stored fragment-major modulo its spacing
+  for (size_t l = 0; l + 1 < net->layers.size(); ++l) net->layers[l].out_lg = __builtin_ctz(net->layers[l + 1].dil);
   return CNN_OK;
 }
 
