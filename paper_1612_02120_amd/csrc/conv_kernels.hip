@@ -898,11 +898,16 @@ __global__ __launch_bounds__((CfgRR<P, CIN, COUT, KS, MR, MC, WX, WY, HEAD, CBO>
 // sub-lattices of the output (positions py + d r, px + d c), each tiled like a
 // plain conv: an operand pixel of the LDS tile is the input at spacing d, so
 // the implicit GEMM (K = (tap, 16-byte chunk), 16x16x4 FP32 MFMA) and its
-// packed weights are those of conv_mfma. Staging applies the max filter (4
-// loads per operand chunk: the neighbours pd apart belong to other phases).
+// packed weights are those of conv_mfma. The maps between layers are stored
+// as the fragments themselves: a map read by a conv of spacing d holds each of
+// its d^2 phase sub-lattices as a row-major block (fragment-major, see
+// LayerJob::geom), so an operand row is a contiguous run of one fragment.
+// Staging applies the max filter: 4 loads per operand chunk, the partners pd
+// apart being the same run of three other fragments (frag_tile).
 // EPI 1: bias, then max-out over channel pairs, COUT / 2 channels stored
-// (NHWC). EPI 2: bias, then the two-class softmax of channels 0 and 1 (the
-// other output channels are zero padding), storing the class-1 probability.
+// (NHWC pixels, fragment-major modulo the next conv's spacing 2d). EPI 2:
+// bias, then the two-class softmax of channels 0 and 1 (the other output
+// channels are zero padding), storing the class-1 probability (row-major).
 // Elementwise max of two 16-byte chunks of signed activations: FP32 compares
 // floats; BF16 chunks hold keys (bf16_key) and compare as unsigned halves.
 template <int P>

@@ -42,7 +42,10 @@ def _params():
     return random_bias_params(NET_FM, 400, 41, sigma=0.2)
 
 
-@pytest.mark.parametrize("shape", [(2, 131, 157), (1, 53, 53), (1, 60, 301), (1, 620, 590)])
+# (54, 53), (57, 61), (64, 72): every fragment row / column count of the stored
+# maps (ceil(h / D) per fragment) ragged against the phase tiles
+@pytest.mark.parametrize("shape", [(2, 131, 157), (1, 53, 53), (1, 60, 301), (1, 620, 590), (1, 54, 53), (1, 57, 61),
+                                   (3, 64, 72)])
 def test_fastmemb_matches_reference(emcnn, shape):
     vol = em_volume(40 + shape[1], *shape)
     p = _params()
@@ -73,10 +76,11 @@ def test_every_fastmemb_candidate_matches_reference(emcnn):
         emcnn.cnn_set_variant(h, layer, defaults[layer])
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", TOL), ("bf16", 2e-2)])
 @pytest.mark.parametrize("graph", [0, 1])
-def test_fastmemb_batch_matches_per_tile_and_reference(emcnn, graph):
+def test_fastmemb_batch_matches_per_tile_and_reference(emcnn, graph, prec, tol):
     p = _params()
-    h = emcnn.cnn_create(p, NET_FM, "fp32")
+    h = emcnn.cnn_create(p, NET_FM, prec)
     emcnn.cnn_set_batch_graph(h, graph)
     rng = np.random.default_rng(9)
     tiles, vols = [], []
@@ -99,7 +103,7 @@ def test_fastmemb_batch_matches_per_tile_and_reference(emcnn, graph):
     v, halo = vols[1]
     e = halo - 26
     ref = oracle.forward(v[:, e:v.shape[1] - e, e:v.shape[2] - e], NET_FM, p)
-    assert np.abs(tiles[1][2].cpu().numpy() - ref).max() <= TOL
+    assert np.abs(tiles[1][2].cpu().numpy() - ref).max() <= tol
 
 
 def test_fastmemb_full_size_sampled_windows(emcnn):
