@@ -561,23 +561,44 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
           acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][nb].v, a, acc[nb], 0, 0, 0);
       }
       const int y = y0 + mrow, x = x0 + mcol * 16 + n16;
-      if (y < J.hout && x < J.wout) {
-        // max-out maps feed a spaced conv and are stored fragment-major
-        const int64_t pix = MAXOUT ? frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs)
-                                   : (int64_t)y * J.out_rs + x;
+      if constexpr (MAXOUT) {
+        // channels nb*16 + 4g + {0,1} and {2,3} pair up inside the lane: stored
+        // channels nb*8 + 2g and nb*8 + 2g + 1 of pixel n16. The m-block's 16
+        // stored pixels pass through this wave's LDS scratch, so that each lane
+        // stores 16 contiguous bytes. Max-out maps feed a spaced conv and are
+        // stored fragment-major.
+        static_assert(C::NB == 4, "64 channels, 32 stored per pixel");
+        constexpr int PIXB = CST * C::ESZ;  // bytes per stored pixel: 128 (FP32) or 64 (BF16)
+        __shared__ __attribute__((aligned(16))) unsigned char scr_all[C::WAVES * 16 * PIXB];
+        unsigned char* scr = scr_all + wave * 16 * PIXB;
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
-          if constexpr (MAXOUT) {
-            // channels nb*16 + 4g + {0,1} and {2,3} pair up inside the lane:
-            // stored channels nb*8 + 2g and nb*8 + 2g + 1
-            const float m0 = fmaxf(acc[nb][0] + bias[nb][0], acc[nb][1] + bias[nb][1]);
-            const float m1 = fmaxf(acc[nb][2] + bias[nb][2], acc[nb][3] + bias[nb][3]);
-            if constexpr (PO == F32)
-              st<f2>(oslice + (pix * CST + nb * 8 + 2 * g) * 4, f2{m0, m1});
-            else
-              st<uint32_t>(oslice + (pix * CST + nb * 8 + 2 * g) * 2, bf16_key(pack_bf16x2(m0, m1)));
-            continue;
-          }
+          const float m0 = fmaxf(acc[nb][0] + bias[nb][0], acc[nb][1] + bias[nb][1]);
+          const float m1 = fmaxf(acc[nb][2] + bias[nb][2], acc[nb][3] + bias[nb][3]);
+          unsigned char* dst = scr + n16 * PIXB + (nb * 8 + 2 * g) * C::ESZ;
+          if constexpr (PO == F32)
+            *reinterpret_cast<f2*>(dst) = f2{m0, m1};
+          else
+            *reinterpret_cast<uint32_t*>(dst) = bf16_key(pack_bf16x2(m0, m1));
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int lgo = (J.geom >> 16) & 0xf;
+#pragma unroll
+        for (int h = 0; h < PIXB / 64; ++h) {
+          // 16-byte chunk c of the block: pixel c / (PIXB / 16), chunk c % (PIXB / 16)
+          const int c = h * 64 + lane;
+          const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
+          const int pp = c / (PIXB / 16), xx = x0 + mcol * 16 + pp;
+          if (y < J.hout && xx < J.wout)
+            st<i4v>(oslice + frag_pix(y, xx, lgo, J.out_rs, J.out_zs) * PIXB + (c % (PIXB / 16)) * 16, o);
+        }
+        __builtin_amdgcn_wave_barrier();
+        continue;
+      }
+      if (y < J.hout && x < J.wout) {
+        const int64_t pix = (int64_t)y * J.out_rs + x;
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
           float v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
@@ -1830,32 +1851,48 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 
     if constexpr (PH) {
       if (cb == C::NCB - 1) {
-        // ---- spaced-form epilogue: lane (g, n16) holds channel n16 of pixels 4g + k
+        // ---- spaced-form epilogue: lane (g, n16) holds channel n16 of pixels 4g + k.
+        // An m-block's 16 pixels x 32 stored channels (1 KB) pass through this
+        // wave's LDS scratch, so that each lane stores 16 contiguous bytes.
+        static_assert(C::NB == 4, "64 channels, 32 stored: 64 bytes per pixel");
+        __shared__ __attribute__((aligned(16))) unsigned char scr_all[NCW * 1024];
+        unsigned char* scr = scr_all + wave * 1024;
         int zz, py, px, y0, x0;
         w.phase_coords<TY, TX>(zz, py, px, y0, x0);
         const LayerJob& J = w.J;
-        const int d = max(J.geom & 0xff, 1);
+        const int d = max(J.geom & 0xff, 1), lgo = (J.geom >> 16) & 0xf;
         float bias[C::NB];
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) bias[nb] = ldf(prm.bias, nb * 16 + n16);
+        const int j = n16 & 3, q = n16 >> 2;
 #pragma unroll
         for (int u = 0; u < C::MW; ++u) {
-          const int y = py + d * (y0 + wrow0 + u / MCOLS);
+          // the dword of stored channels nb*8 + 2q, +1 of pixel 4g + k reaches all
+          // four lanes of quad q; lane (g, 4q + j) keeps pixel 4g + j's
+          uint32_t keep[C::NB];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int x = px + d * (x0 + (u % MCOLS) * 16 + 4 * g + k);
-            const bool ok = y < J.hout && x < J.wout;
-            const int64_t pix = (int64_t)zz * J.out_zs + frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs);
+          for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int nb = 0; nb < C::NB; ++nb) {
               const float v = acc[u][nb][k] + bias[nb];
               const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
-              // lanes n16 = 4q hold stored channel nb*8 + 2q, lanes 4q + 2 channel nb*8 + 2q + 1
-              const float m2 = dpp_f<kQuadXor2>(m);
-              if (ok && (n16 & 3) == 0)
-                st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, bf16_key(pack_bf16x2(m, m2)));
+              const float m2 = dpp_f<kQuadXor2>(m);          // the quad's other pair
+              const uint32_t dw = bf16_key((n16 & 2) ? pack_bf16x2(m2, m) : pack_bf16x2(m, m2));
+              keep[nb] = (k == 0 || j == k) ? dw : keep[nb];
             }
-          }
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb)
+            *reinterpret_cast<uint32_t*>(scr + (4 * g + j) * 64 + nb * 16 + q * 4) = keep[nb];
+          __builtin_amdgcn_wave_barrier();
+          // lane l: stored channels 8 (l % 4) .. + 7 of pixel l / 4
+          const i4v o = *reinterpret_cast<const i4v*>(scr + lane * 16);
+          __builtin_amdgcn_wave_barrier();
+          const int y = py + d * (y0 + wrow0 + u / MCOLS);
+          const int x = px + d * (x0 + (u % MCOLS) * 16 + (lane >> 2));
+          if (y < J.hout && x < J.wout)
+            st<i4v>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * 64 +
+                        (lane & 3) * 16,
+                    o);
         }
       }
     } else if (cb == C::NCB - 1) {
@@ -1960,7 +1997,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               PT<P>::U,                                                                               \
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::NGS,                                      \
               0, 0, 1,                                                                                \
-              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::LDS,                                      \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::LDS + NCW * 1024,                         \
               reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, true, false, TY, TX, NCW, NPW, 0, 1>), \
               "conv_ws_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #NCW "," #NPW ">"}
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
@@ -2076,7 +2113,7 @@ static const FirstInfo kFirst[] = {
     EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 8, 64),
     // FastMemb first conv: 4x4, 1 -> 64, max-out to 32
     EMCNN_FIRSTM(F32, 64, 4, 4, 64, true), EMCNN_FIRSTM(F32, 64, 4, 8, 32, true),
-    EMCNN_FIRSTM(BF16, 64, 4, 8, 64, true), EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true),
+    EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true), EMCNN_FIRSTM(BF16, 64, 4, 8, 64, true),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }
