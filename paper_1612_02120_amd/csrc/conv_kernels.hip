@@ -17,9 +17,11 @@
 //                 epilogue. conv_mfma_rr is the same layer with a row-reuse K order.
 //   conv_ws     - the BF16 / FP8 convs: the same implicit GEMM, warp-specialised
 //                 (producer waves stage the next tile while consumer waves run
-//                 MFMA) over channel-blocked activations.
+//                 MFMA) over channel-blocked activations; in its spaced mode the
+//                 BF16 body convs of nets with stride-2 pools.
 //   conv_phase  - the convs of nets with stride-2 pools (FastMemb): taps spaced
-//   head_phase    d apart, tiled per phase sub-lattice (the paper's fragments);
+//   head_phase    d apart, tiled per phase sub-lattice (the paper's fragments,
+//                 which the maps between layers store as separate blocks);
 //                 max-out or two-class softmax epilogues; head_phase is the
 //                 two-class layer on the VALU.
 //
