@@ -1228,19 +1228,22 @@ struct CfgWS {
   static constexpr int NB = COUT / 16;
   static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
-  // pixel stride = 8 (mod 16) dwords; with the chunk-slot order below the two
-  // lane groups of a half-wave read chunks 16 B apart, which is conflict-free
-  // (FP8: 48 B of data in a 96 B stride)
-  static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
+  // BF16: pixel stride = 8 (mod 16) dwords; with the chunk-slot order below
+  // the two lane groups of a half-wave read chunks 16 B apart, which is
+  // conflict-free. FP8: the 48 data bytes unpadded (12 dwords), which leaves
+  // room for all packed weights of the 5x5 conv next to the two operand
+  // buffers; with a 96-B stride they did not fit, and B fragments through the
+  // L1 kept the texture addresser ~80 % busy (6 % slower conv2 despite fewer
+  // LDS bank conflicts)
+  static constexpr int PSB = P == FP8 ? CB * T::BYTES : pad_words(CB * T::BYTES / 4) * 4;
   static constexpr int BUF = LR * LC * PSB;                // one operand buffer
   static constexpr int WB = NGS * NB * 64 * T::U * 16;     // packed weights of one stage
   static constexpr int LDS_MAX = 160 * 1024;
   // BF16 consumers read B fragments from LDS: resident for the workgroup's
   // lifetime when all packed weights fit next to the two operand buffers,
   // else one slice per stage, staged by the producers. FP8 consumers read B
-  // from LDS only when all weights are resident (the 3x3 conv); otherwise
-  // (the 5x5 conv, whose 96-byte-stride operand buffers fill the LDS) they
-  // read B through the L1.
+  // from LDS when all weights are resident, else through the L1 (with a
+  // register prefetch ring).
   static constexpr bool FITS = 2 * BUF + NCB * WB <= LDS_MAX;
   static constexpr bool BL = P != FP8 || FITS;
   static constexpr bool WRES = BL && FITS;  // all weights resident in LDS
