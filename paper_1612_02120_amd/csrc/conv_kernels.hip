@@ -597,27 +597,55 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
         __builtin_amdgcn_wave_barrier();
         continue;
       }
-      if (y < J.hout && x < J.wout) {
-        const int64_t pix = (int64_t)y * J.out_rs + x;
+      {
+        // bias + ReLU. The m-block's output (16 pixels x COUT channels, laid out
+        // as stored: NHWC for FP32; for BF16 / FP8 one 16-channel plane after
+        // another, 16 consecutive pixels each) passes through this wave's LDS
+        // scratch, so that each lane stores 16 contiguous bytes.
+        constexpr int BLK = 16 * COUT * C::ESZ;  // bytes of the m-block
+        constexpr int PLB = 16 * 16 * C::ESZ;    // bytes of one plane of it (BF16 / FP8)
+        __shared__ __attribute__((aligned(16))) unsigned char scr_all[C::WAVES * BLK];
+        unsigned char* scr = scr_all + wave * BLK;
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
           float v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
           if constexpr (PO == F32) {
-            // NHWC
-            st<f4>(oslice + (pix * COUT + nb * 16 + 4 * g) * 4, f4{v[0], v[1], v[2], v[3]});
+            *reinterpret_cast<f4*>(scr + (n16 * COUT + nb * 16 + 4 * g) * 4) = f4{v[0], v[1], v[2], v[3]};
           } else {
-            // channel-blocked: plane nb, 16 channels per pixel
-            gbyte* dst = oslice + ((int64_t)nb * J.out_zs + pix) * 16 * C::ESZ + 4 * g * C::ESZ;
+            unsigned char* dst = scr + nb * PLB + (n16 * 16 + 4 * g) * C::ESZ;
             if constexpr (PO == BF16) {
-              st<u2v>(dst, u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])});
+              *reinterpret_cast<u2v*>(dst) = u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])};
             } else {
               const float inv = prm.out_inv_scale;
-              st<uint32_t>(dst, pack_e4m3x2(v[0] * inv, v[1] * inv) | (pack_e4m3x2(v[2] * inv, v[3] * inv) << 16));
+              *reinterpret_cast<uint32_t*>(dst) =
+                  pack_e4m3x2(v[0] * inv, v[1] * inv) | (pack_e4m3x2(v[2] * inv, v[3] * inv) << 16);
             }
           }
         }
+        __builtin_amdgcn_wave_barrier();
+        const int xb = x0 + mcol * 16;  // the m-block's first pixel
+        const int64_t pix0 = (int64_t)y * J.out_rs + xb;
+#pragma unroll
+        for (int h = 0; h < (BLK / 16 + 63) / 64; ++h) {
+          const int c = h * 64 + lane;  // 16-byte chunk of the block
+          if (c < BLK / 16) {
+            const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
+            int pp;
+            gbyte* dst;
+            if constexpr (PO == F32) {
+              pp = c / (COUT / 4);  // COUT / 4 chunks per pixel
+              dst = oslice + (pix0 + pp) * COUT * 4 + (c % (COUT / 4)) * 16;
+            } else {
+              const int pl = c / (PLB / 16), cc = c % (PLB / 16);
+              pp = cc / C::ESZ;  // ESZ chunks per plane pixel
+              dst = oslice + ((int64_t)pl * J.out_zs + pix0) * 16 * C::ESZ + cc * 16;
+            }
+            if (y < J.hout && xb + pp < J.wout) st<i4v>(dst, o);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
   }
