@@ -186,3 +186,29 @@ def test_fastmemb_bf16_full_size_sampled_windows(emcnn):
     errs = [abs(g[z, y, x] - oracle.patch(vol[z], NET_FM, p, y, x)[0]) for z, y, x in pts]
     print("FastMemb bf16 full size sampled max err", max(errs))
     assert max(errs) <= 2e-2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fastmemb_small_workspace_equals_unlimited(emcnn, prec):
+    # a 1 MiB workspace budget: one slice per slab, and batch tiles split into
+    # groups; the fragment-major maps between layers are laid out per group
+    vol = _dev(em_volume(95, 3, 140, 171))
+    p = _params()
+    big = emcnn.cnn_create(p, NET_FM, prec)
+    small = emcnn.cnn_create(p, NET_FM, prec)
+    emcnn.cnn_set_workspace_limit(small, 1 << 20)
+    a = emcnn.cnn_infer(big, vol)
+    b = emcnn.cnn_infer(small, vol)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    tiles_a, tiles_b = [], []
+    for t in range(5):
+        v = _dev(em_volume(700 + t, 1 + t % 3, 60 + 9 * t, 73 + 4 * t))
+        oa = torch.empty((v.shape[0], v.shape[1] - 52, v.shape[2] - 52), device="cuda")
+        tiles_a.append((v, 26, oa))
+        tiles_b.append((v, 26, torch.empty_like(oa)))
+    emcnn.cnn_infer_batch(big, tiles_a)
+    emcnn.cnn_infer_batch(small, tiles_b)
+    torch.cuda.synchronize()
+    for (_, _, x), (_, _, y) in zip(tiles_a, tiles_b):
+        assert torch.equal(x, y)
