@@ -2141,9 +2141,9 @@ static const VariantInfo kConv[] = {
 
 static const FirstInfo kFirst[] = {
     // defaults (first match per signature) are the measured fastest shapes
-    EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64), EMCNN_FIRST(FP8, 48, 5, 16, 64),
+    EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64), EMCNN_FIRST(FP8, 48, 5, 8, 64),
     EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 4, 64),
-    EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 8, 64),
+    EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 16, 64),
     // FastMemb first conv: 4x4, 1 -> 64, max-out to 32
     EMCNN_FIRSTM(F32, 64, 4, 4, 64, true), EMCNN_FIRSTM(F32, 64, 4, 8, 32, true),
     EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true), EMCNN_FIRSTM(BF16, 64, 4, 8, 64, true),
