@@ -91,7 +91,8 @@ struct VariantInfo {
   int epi;              // epilogue: 0 bias + ReLU (or the fused 1x1 sigmoid head),
                         // 1 bias + max-out over channel pairs (stores cout / 2 channels),
                         // 2 bias + two-class softmax of channels 0, 1 (stores the class-1 probability)
-  int lds_bytes;
+  int lds_bytes;        // LDS of the staged operand tiles and weights (descriptive; launches and
+                        // occupancy take the kernel's own static LDS, epilogue scratch included)
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
   const char* name;
 };
@@ -100,7 +101,7 @@ struct FirstInfo {
   int prec_out, cout, ks;
   int maxout;  // 1: bias + max-out over channel pairs (stores cout / 2 channels); 0: bias + ReLU
   int ty, tx, threads;
-  int lds_bytes;
+  int lds_bytes;  // the uint8 input tile (descriptive; the per-wave epilogue scratch comes on top)
   const void* fn;
   const char* name;
 };
