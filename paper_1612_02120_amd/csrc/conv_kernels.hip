@@ -1079,34 +1079,89 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
     }
 
     // ---- epilogue: lane holds D[m = 4 g + k][n = n16] of each (m-block, n-block)
+    if constexpr (EPI == 1 && P == BF16) {
 #pragma unroll
-    for (int u = 0; u < MW; ++u) {
-      const int mb = wave * MW + u;
-      const int mrow = mb / MCOLS, mcol = mb % MCOLS;
-      const int y = py + d * (y0 + mrow);
+      for (int u = 0; u < MW; ++u) {
+        const int mb = wave * MW + u;
+        const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+        const int y = py + d * (y0 + mrow);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = px + d * (x0 + mcol * 16 + 4 * g + k);
-        const bool ok = y < J.hout && x < J.wout;
-        const int64_t pix = (int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs);
-        if constexpr (EPI == 1) {
+        for (int k = 0; k < 4; ++k) {
+          const int x = px + d * (x0 + mcol * 16 + 4 * g + k);
+          const bool ok = y < J.hout && x < J.wout;
+          const int64_t pix = (int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs);
 #pragma unroll
           for (int nb = 0; nb < C::NB; ++nb) {
             const float v = acc[u][nb][k] + bias[nb];
             const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
-            if constexpr (P == F32) {
-              if (ok && (n16 & 1) == 0) st<float>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 4, m);
-            } else {
-              // lanes n16 = 4q hold stored channel nb*8 + 2q, lanes 4q + 2 channel nb*8 + 2q + 1
-              const float m2 = dpp_f<kQuadXor2>(m);
-              if (ok && (n16 & 3) == 0)
-                st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, bf16_key(pack_bf16x2(m, m2)));
-            }
+            // lanes n16 = 4q hold stored channel nb*8 + 2q, lanes 4q + 2 channel nb*8 + 2q + 1
+            const float m2 = dpp_f<kQuadXor2>(m);
+            if (ok && (n16 & 3) == 0)
+              st<uint32_t>(gout(J.out) + (pix * (COUT / 2) + nb * 8 + n16 / 2) * 2, bf16_key(pack_bf16x2(m, m2)));
           }
-        } else {
-          const float z = acc[u][0][k] + bias[0];
-          const float z0 = dpp_f<kQuadXor1>(z);  // lane 1 receives class 0's logit
-          if (ok && n16 == 1) st<float>(gout(J.out) + pix * 4, sigmoid_f(z - z0));
+        }
+      }
+    } else {
+      // The finished operand tile serves as each wave's scratch: FP32 max-out
+      // rows leave as 16 contiguous bytes per lane; the class-1 probabilities
+      // of a wave's m-blocks leave in one store with every lane active.
+      __syncthreads();  // every wave is done reading the operand tile
+      if constexpr (EPI == 1) {
+        constexpr int PIXB = (COUT / 2) * 4;  // one stored FP32 pixel
+        static_assert(C::WAVES * 16 * PIXB <= C::LDS_TILE, "scratch fits in the operand tile");
+        unsigned char* scr = lds + wave * 16 * PIXB;
+        const int e = n16 & 1, pc = n16 >> 1;  // lanes 2pc, 2pc + 1 hold pair pc's max
+#pragma unroll
+        for (int u = 0; u < MW; ++u) {
+          const int mb = wave * MW + u;
+          const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+          const int y = py + d * (y0 + mrow);
+          // lane parity e keeps pixels 4g + e and 4g + 2 + e
+          float keep[2][C::NB];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb) {
+              const float v = acc[u][nb][k] + bias[nb];
+              const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
+              keep[k >> 1][nb] = (k & 1) ? (e ? m : keep[k >> 1][nb]) : m;
+            }
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int nb = 0; nb < C::NB; ++nb)
+              *reinterpret_cast<float*>(scr + (4 * g + 2 * h + e) * PIXB + (nb * 8 + pc) * 4) = keep[h][nb];
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int h = 0; h < PIXB / 64; ++h) {
+            const int c = h * 64 + lane;  // 16-byte chunk: pixel c / (PIXB / 16)
+            const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
+            const int x = px + d * (x0 + mcol * 16 + c / (PIXB / 16));
+            if (y < J.hout && x < J.wout)
+              st<i4v>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * PIXB +
+                          (c % (PIXB / 16)) * 16,
+                      o);
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      } else {
+        float* scr = reinterpret_cast<float*>(lds) + wave * MW * 16;
+        static_assert(C::WAVES * MW * 16 * 4 <= C::LDS_TILE, "scratch fits in the operand tile");
+#pragma unroll
+        for (int u = 0; u < MW; ++u)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float z = acc[u][0][k] + bias[0];
+            const float z0 = dpp_f<kQuadXor1>(z);  // lane 1 receives class 0's logit
+            if (n16 == 1) scr[u * 16 + 4 * g + k] = sigmoid_f(z - z0);
+          }
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < MW * 16; i += 64) {
+          const int mb = wave * MW + i / 16;
+          const int mrow = mb / MCOLS, mcol = mb % MCOLS;
+          const int y = py + d * (y0 + mrow), x = px + d * (x0 + mcol * 16 + i % 16);
+          if (y < J.hout && x < J.wout)
+            st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * 4, scr[i]);
         }
       }
     }
