@@ -511,6 +511,16 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
   for (int nb = 0; nb < C::NB; ++nb)
 #pragma unroll
     for (int k = 0; k < 4; ++k) bias[nb][k] = ldf(prm.bias, nb * 16 + 4 * g + k);
+  // the lane's tap offsets in the uint8 tile (tap 4s + g of step s for FP32,
+  // taps 8g .. 8g + 7 otherwise); taps past KS * KS read the pixel itself:
+  // their packed weights are zero, so every tap read is unconditional
+  constexpr int NT = PO == F32 ? C::NSTEP : 8;
+  int toff[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int k = PO == F32 ? 4 * t + g : 8 * g + t;
+    toff[t] = k < KS * KS ? (k / KS) * C::LC + k % KS : 0;
+  }
 
   const ItemRange rg = item_range(js.total_items);
   int cur = 0;
@@ -545,8 +555,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
       if constexpr (PO == F32) {
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s) {
-          const int k = 4 * s + g;
-          const float a = k < KS * KS ? (float)a0[(k / KS) * C::LC + k % KS] : 0.f;
+          const float a = (float)a0[toff[s]];
 #pragma unroll
           for (int nb = 0; nb < C::NB; ++nb)
             acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wf[s][nb].v[0], a, acc[nb], 0, 0, 0);
@@ -554,10 +563,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
       } else {
         bf16x8 a;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = 8 * g + t;
-          a[t] = (__bf16)(k < KS * KS ? (float)a0[(k / KS) * C::LC + k % KS] : 0.f);
-        }
+        for (int t = 0; t < 8; ++t) a[t] = (__bf16)(float)a0[toff[t]];  // exact: uint8 fits in bf16
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb)
           acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][nb].v, a, acc[nb], 0, 0, 0);
