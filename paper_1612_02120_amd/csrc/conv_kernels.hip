@@ -504,8 +504,8 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
       }
   }
   // D = W X: lane (g, n16) accumulates channels nb * 16 + 4g .. 4g + 3 of
-  // pixel n16 of an m-block, so it stores 4 consecutive channels straight
-  // from registers (the 64 lanes of a channel plane write one contiguous run)
+  // pixel n16 of an m-block: 4 consecutive stored channels, which the
+  // epilogue gathers through the wave's LDS scratch into 16-byte stores
   float bias[C::NB][4];
 #pragma unroll
   for (int nb = 0; nb < C::NB; ++nb)
