@@ -90,24 +90,51 @@ def time_volume(emcnn, torch, h, vol_dev, steps, warmup, stream):
     return (t1 - t0) * 1e3 / steps, per_layer, out
 
 
-def cpu_baseline(vol, net, params, min_seconds=10.0, out_vox_unit="voxels/s"):
-    """The FP64 CPU reference on whole slices of the benchmark volume, one slice
-    after another until at least `min_seconds` of work has run."""
+def _oracle_rate(vol, net, params, min_seconds, threads, native):
+    """Output voxels/s of the FP64 oracle over whole slices (or the given
+    window) of `vol`, one slice after another until min_seconds have run."""
     import oracle
-    threads = oracle.num_threads()
     R = oracle.radius(net)
     nvox, n, t0 = 0, 0, time.perf_counter()
     while n < vol.shape[0]:
-        oracle.forward(np.ascontiguousarray(vol[n:n + 1]), net, params, threads=threads)
+        oracle.forward(np.ascontiguousarray(vol[n:n + 1]), net, params, threads=threads, native=native)
         nvox += (vol.shape[1] - R) * (vol.shape[2] - R)
         n += 1
         if time.perf_counter() - t0 >= min_seconds:
             break
-    dt = time.perf_counter() - t0
-    return {"value": nvox / dt, "unit": out_vox_unit, "cores": threads, "kind": "oracle",
-            "sample": "%d whole slice(s) of the benchmark volume (%d x %d) -> %d output voxels, "
-                      "FP64 direct convolution, %.1f s on %d threads" % (n, vol.shape[1], vol.shape[2], nvox,
-                                                                           dt, threads)}
+    return nvox / (time.perf_counter() - t0), n, nvox, time.perf_counter() - t0
+
+
+def cpu_baseline(vol, net, params, out_vox_unit="voxels/s"):
+    """The FP64 CPU oracle on the host cores, on a bounded sample of the
+    benchmark volume: its -O3 -march=native timing build (compiled for this
+    host; bitwise the same results as the test build) on all threads over whole
+    1024^2 slices, on one thread over a 140-row window of slice 0, and the -O2
+    test build on all threads for comparison."""
+    import oracle
+    from oracle import build as oracle_build
+    threads = oracle.num_threads()
+    native_ok = True
+    try:
+        oracle.native_lib()
+    except Exception as e:  # no compiler on the host: time the test build only
+        log("oracle timing build unavailable (%s); timing the -O2 test build" % e)
+        native_ok = False
+    v_all, n_all, vox_all, dt_all = _oracle_rate(vol, net, params, 8.0, threads, native_ok)
+    win = np.ascontiguousarray(vol[:1, :140, :])
+    v_one, _, vox_one, dt_one = _oracle_rate(win, net, params, 0.0, 1, native_ok)
+    v_o2, n_o2, _, dt_o2 = _oracle_rate(vol, net, params, 4.0, threads, False)
+    build = ("-O3 -march=native -ffp-contract=off (timing build)" if native_ok else
+             "-O2 -ffp-contract=off (test build)")
+    return {"value": v_all, "unit": out_vox_unit, "cores": threads, "kind": "oracle",
+            "cpu_model": oracle_build.cpu_model(), "host_nproc": os.cpu_count(),
+            "build": build,
+            "value_1_thread": v_one,
+            "value_o2_test_build": v_o2,
+            "sample": "%d whole slice(s) of the benchmark volume (%d x %d) -> %d output voxels in %.1f s on %d "
+                      "threads; 1 thread: slice 0 rows 0..139 -> %d output voxels in %.1f s; -O2 test build: "
+                      "%d slice(s) in %.1f s; FP64 direct convolution"
+                      % (n_all, vol.shape[1], vol.shape[2], vox_all, dt_all, threads, vox_one, dt_one, n_o2, dt_o2)}
 
 
 def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args):

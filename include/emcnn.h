@@ -87,8 +87,10 @@ typedef struct cnn_net cnn_net;
 /* Build a network on the current HIP device.
  * Two families of nets are supported: the ReLU nets described below, and the
  * FastMemb family (Section 2.2), FP32 or BF16 (bf16 weights and stored
- * activations with FP32 accumulation, the first conv with bf16(w / 255)
- * weights; the softmax layer computes in FP32): conv(k=4, 1 -> 64, MAXOUT), then
+ * activations with FP32 accumulation in every conv, the first conv with
+ * bf16(w / 255) weights; the softmax layer's default kernel is a bf16 MFMA, its
+ * VALU candidate reads bf16 activations with FP32 weights):
+ * conv(k=4, 1 -> 64, MAXOUT), then
  * one or more pairs { MAXPOOL_S2, conv(k=4, 32 -> 64, MAXOUT) }, then
  * MAXPOOL_S2 and conv(k=4, 32 -> 2, SOFTMAX); no other transfer function.
  * FastMemb itself has two inner pairs: field of view 53 (R = 52).
@@ -128,6 +130,23 @@ int cnn_geometry(const cnn_net* net, int32_t* R, int32_t* fov);
  * it may make). */
 int cnn_infer(cnn_net* net, const uint8_t* volume_u8, const int64_t dims[3], float* prob_out,
               void* stream);
+
+/* cnn_infer for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and result (bit for bit) as cnn_infer, but no
+ * allocation of any kind: the inter-layer maps live in a static device array
+ * of CNN_NOALLOC_SCRATCH_BYTES, which every device the library runs on holds
+ * until the process ends. The volume runs as slabs of whole slices when one
+ * slice fits the array, else as strips of output rows (a multiple of 16) that
+ * overlap by R input rows. Rows too wide for a 16-row strip return CNN_EINVAL
+ * before anything is enqueued (for net B in FP32, widths above about 16,000
+ * columns). All calls on one device share its array and keep no state in it
+ * (every map is written before it is read): calls that overlap on one device
+ * (two streams, two threads) race and must be serialised by the caller.
+ * Per-layer profiling (cnn_profile) does not record these launches. */
+#define CNN_NOALLOC_SCRATCH_BYTES ((int64_t)128 << 20)
+int cnn_infer_noalloc(cnn_net* net, const uint8_t* volume_u8, const int64_t dims[3], float* prob_out,
+                      void* stream);
 
 /* One block of a volume with its halo of input context (Section 2.1, "Block
  * merging": blocks are processed independently).
@@ -226,6 +245,27 @@ int student_set_state(cnn_student* s, const double* w, const double* m, const do
 int student_grad(cnn_student* s, const uint8_t* patches, const float* teacher_prob,
                  int32_t batch, int32_t patch, float* grad_out, double* loss_out, void* stream);
 
+/* One source patch of a training batch: a device volume Z x H x W uint8, its
+ * teacher map Z x (H-R) x (W-R) float32 (R: the teacher's radius) and the
+ * patch origin (z, y, x) in the volume. */
+typedef struct cnn_patch_src {
+  const uint8_t* volume;
+  const float* teacher;
+  int64_t Z, H, W;
+  int32_t z, y, x;
+} cnn_patch_src;
+
+/* Gather a training batch on the device (distillation from the plain net's
+ * maps): patches_out[b] = volume[z, y : y+P, x : x+P] and teacher_out[b] =
+ * teacher[z, y-m : y-m+P-6, x-m : x-m+P-6] with m = (R-6)/2, i.e. the
+ * teacher probabilities centred on the student's (P-6) x (P-6) outputs.
+ * src: host array of `batch` (1..64) sources, read during the call; every
+ * origin must satisfy m <= y <= H-P-m and m <= x <= W-P-m.
+ * patches_out: device batch x P x P uint8; teacher_out: device
+ * batch x (P-6) x (P-6) float32. Only enqueues the copy. */
+int student_gather(const cnn_patch_src* src, int32_t batch, int32_t patch, int32_t teacher_R,
+                   uint8_t* patches_out, float* teacher_out, void* stream);
+
 /* One training step: forward, loss (FP64 sum), backward, FP64 squared gradient
  * norm, Adam update (Kingma & Ba, bias-corrected) of the FP32 master weights.
  * loss_out, gnorm_out: device float64 scalars (nullable); gnorm is ||g||_2. */
@@ -240,19 +280,30 @@ int student_infer(cnn_student* s, const uint8_t* volume_u8, const int64_t dims[3
 /* Student inference aligned to the teacher's output frame, with per-tile
  * fallback to the teacher (a multi-pass scheme: cheap pass everywhere,
  * expensive pass where sampled disagreement is high).
- * prob_out: Z x (H-R) x (W-R) with R the teacher's radius (the student map
- * cropped by (R-6)/2 per side). The output is split into tiles of tile x tile
- * pixels per slice; in each tile n_samples windows of 16 x 16 outputs (seeded
- * by `seed`) are recomputed by the teacher; when the fraction of sampled
- * voxels whose 0.5-threshold decision (p >= 0.5) differs exceeds tau, the
- * whole tile is recomputed by the teacher (tau < 0: every tile; tau >= 1: no
- * tile). All decisions stay on the device; the call returns after the work
- * completes (it synchronises `stream`).
- * stats_out (device int32[2], nullable): {tiles flagged, tiles total}. */
+ * prob_out: device, Z x (H-R) x (W-R) float32 with R the teacher's radius (the
+ * student map cropped by (R-6)/2 per side).
+ * The output of each slice is split into tiles of tile x tile pixels, numbered
+ * t = (z * ty + a) * tx + b for tile row a < ty = ceil((H-R) / tile) and tile
+ * column b < tx = ceil((W-R) / tile); a tile at the lower or right edge keeps
+ * its th x tw in-bounds pixels. In each tile, n_samples windows of
+ * wh x ww = min(16, th) x min(16, tw) outputs are recomputed by the teacher.
+ * Window k of tile t starts at tile offset (r mod (th - wh + 1),
+ * (r >> 32) mod (tw - ww + 1)) with r = m(seed ^ m(64 t + k)), where m is the
+ * splitmix64 output mix (Steele, Lea and Flood 2014) applied to
+ * x + 0x9e3779b97f4a7c15 (64-bit wrap-around). Windows may overlap; every
+ * sampled voxel counts once per window. A voxel flips when its decisions
+ * p >= 0.5 differ between the student and the teacher. A tile whose flip count
+ * exceeds tau times its sampled-voxel count (flips > tau * count, in float32)
+ * is recomputed by the teacher; tau < 0: every tile, tau >= 1: none.
+ * Decisions stay on the device and the call only enqueues work (its pinned
+ * window table is reused once the previous call's upload has run).
+ * stats_out (device int32[2], nullable): {tiles flagged, tiles total}.
+ * flags_out (device int32[Z * ty * tx], nullable): per tile t, 1 if it was
+ * recomputed by the teacher, else 0. */
 int student_infer_with_fallback(cnn_student* s, cnn_net* teacher, const uint8_t* volume_u8,
                                 const int64_t dims[3], float* prob_out, float tau,
                                 int32_t tile, int32_t n_samples, uint64_t seed,
-                                int32_t* stats_out, void* stream);
+                                int32_t* stats_out, int32_t* flags_out, void* stream);
 
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* cnn_last_error(void);

@@ -31,35 +31,51 @@ class _Layer(ctypes.Structure):
 
 
 _lib = None
+_native = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
-        L = ctypes.CDLL(path)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_forward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
-                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
-        L.orc_trace.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
-                                ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-        L.orc_student_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                                            ctypes.c_void_p, dp, ctypes.c_void_p]
-        L.orc_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                               ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                               ctypes.c_double, ctypes.c_double]
-        L.orc_bf16_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
-        L.orc_e4m3_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
-        L.orc_sigmoid.argtypes = [ctypes.c_double]
-        L.orc_sigmoid.restype = ctypes.c_double
-        L.orc_radius.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.orc_patch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
-                                ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
-        L.orc_num_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_build.build(force=False)))
     return _lib
+
+
+def native_lib():
+    """The -O3 -march=native timing build of the same source (bitwise the same
+    results), compiled for this host on first use."""
+    global _native
+    if _native is None:
+        _native = _bind(ctypes.CDLL(_build.build_native()))
+    return _native
+
+
+def _bind(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_forward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    L.orc_trace.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_conv_layer.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_student_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.c_void_p, dp, ctypes.c_void_p]
+    L.orc_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double]
+    L.orc_bf16_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    L.orc_e4m3_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    L.orc_sigmoid.argtypes = [ctypes.c_double]
+    L.orc_sigmoid.restype = ctypes.c_double
+    L.orc_radius.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_patch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
+    L.orc_num_threads.restype = ctypes.c_int
+    return L
 
 
 def _layers(net):
@@ -101,7 +117,7 @@ def patch(img, net, params, y, x):
     return out.value, lg.value
 
 
-def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=False):
+def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=False, native=False):
     """Dense output of ``net`` on every slice of ``vol`` (Z x H x W uint8).
 
     Returns float64 Z x (H-R) x (W-R) probabilities, or pre-sigmoid logits of
@@ -119,7 +135,8 @@ def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=
         [0.0 if s is None else s for s in act_scales], dtype=np.float64)
     out = np.empty((Z, H - R, W - R), dtype=np.float64)
     lay = _layers(net)
-    rc = lib().orc_forward(_ptr(vol), Z, H, W, lay, len(net), _ptr(params), QMODES[qmode],
+    L = native_lib() if native else lib()
+    rc = L.orc_forward(_ptr(vol), Z, H, W, lay, len(net), _ptr(params), QMODES[qmode],
                            _ptr(sc), None if logits else _ptr(out),
                            _ptr(out) if logits else None, int(threads))
     if rc:
@@ -127,23 +144,47 @@ def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=
     return out
 
 
-def trace(img, net, params):
-    """Every layer's output (C x h x w float64) for one slice, exact mode."""
+def trace(img, net, params, qmode="exact", act_scales=None):
+    """Every layer's output (C x h x w float64) for one slice. In a fake-quant
+    mode a conv's output is its FP64 value before the next layer rounds it."""
     img = np.ascontiguousarray(img, dtype=np.uint8)
     H, W = img.shape
     lay = _layers(net)
     dims = np.zeros(3 * len(net), dtype=np.int32)
     params = np.ascontiguousarray(params, dtype=np.float64)
+    n_conv = sum(1 for L in net if L["kind"] == "conv")
+    sc = np.zeros(n_conv) if act_scales is None else np.array(
+        [0.0 if s is None else s for s in act_scales], dtype=np.float64)
     # first pass for dims: run with bufs == NULL
-    rc = lib().orc_trace(_ptr(img), H, W, lay, len(net), _ptr(params), _ptr(dims), None)
+    rc = lib().orc_trace(_ptr(img), H, W, lay, len(net), _ptr(params), QMODES[qmode], _ptr(sc), _ptr(dims), None)
     if rc:
         raise ValueError("oracle trace failed (%d)" % rc)
     bufs = [np.empty(tuple(dims[3 * l:3 * l + 3]), dtype=np.float64) for l in range(len(net))]
     ptrs = (ctypes.c_void_p * len(net))(*[b.ctypes.data for b in bufs])
-    rc = lib().orc_trace(_ptr(img), H, W, lay, len(net), _ptr(params), _ptr(dims), ptrs)
+    rc = lib().orc_trace(_ptr(img), H, W, lay, len(net), _ptr(params), QMODES[qmode], _ptr(sc), _ptr(dims), ptrs)
     if rc:
         raise ValueError("oracle trace failed (%d)" % rc)
     return bufs
+
+
+def conv_layer(a, weights, bias, k, pool=False, qmode="exact", in_scale=0.0):
+    """One inner conv (optionally after the 2x2 stride-1 max filter) on a given
+    C x H x W map in a fake-quant mode's number format; returns (out, absum):
+    the conv output before its activation and the scaled sum of |products|."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    C, H, W = a.shape
+    wt = np.ascontiguousarray(weights, dtype=np.float64)
+    bs = np.ascontiguousarray(bias, dtype=np.float64)
+    Co = bs.size
+    assert wt.size == Co * C * k * k
+    Ho, Wo = H - (1 if pool else 0) - (k - 1), W - (1 if pool else 0) - (k - 1)
+    out = np.empty((Co, Ho, Wo))
+    absum = np.empty((Co, Ho, Wo))
+    rc = lib().orc_conv_layer(_ptr(a), C, H, W, 1 if pool else 0, _ptr(wt), _ptr(bs), int(k), Co, QMODES[qmode],
+                              float(in_scale), _ptr(out), _ptr(absum))
+    if rc:
+        raise ValueError("oracle conv_layer failed (%d)" % rc)
+    return out, absum
 
 
 def student_loss_grad(patches, teacher, net, params):

@@ -406,9 +406,9 @@ int orc_forward(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int
 /* Every layer's output for one slice; bufs[l] must hold dims given by a first
  * call with bufs == NULL (dims only). */
 int orc_trace(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
-              const double* params, int32_t* dims, double** bufs) {
+              const double* params, int qmode, const double* act_scale, int32_t* dims, double** bufs) {
   double** tr = (double**)calloc(nl, sizeof(double*));
-  int rc = forward_slice(img, H, W, L, nl, params, ORC_Q_EXACT, NULL, NULL, NULL, tr, dims);
+  int rc = forward_slice(img, H, W, L, nl, params, qmode, act_scale, NULL, NULL, tr, dims);
   for (int l = 0; l < nl; ++l) {
     if (bufs && tr[l])
       memcpy(bufs[l], tr[l], sizeof(double) * (size_t)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2]);
@@ -520,6 +520,65 @@ int orc_student_loss_grad(const uint8_t* patches, int B, int P, const double* te
 }
 
 /* One Adam step (Kingma & Ba) at step count t >= 1. */
+/* One inner conv layer of a ReLU net on a given input map, in the number
+ * format of a fake-quant mode (the mode's rule for a conv that is neither the
+ * first nor the head): in is C x H x W FP64; with pool the 2x2 stride-1 max
+ * filter is applied first; then exact: plain FP64; BF16: weights and inputs
+ * rounded to bf16; FP8: weights e4m3(w / sw[co]) with sw[co] = max|W[co]| / 448
+ * and inputs e4m3(a / in_scale), rescaled by in_scale * sw[co].
+ * out (Co x Ho x Wo) receives b[co] + the scaled sum, the conv output before
+ * its activation; absum (nullable, same shape) the scaled sum of the absolute
+ * products, which bounds the rounding error of any accumulation order.
+ * Returns 0, or -1 for bad sizes. */
+int orc_conv_layer(const double* in, int C, int H, int W, int pool, const double* wt, const double* bs, int K,
+                   int Co, int qmode, double in_scale, double* out, double* absum) {
+  const int h = H - (pool ? 1 : 0), w = W - (pool ? 1 : 0);
+  const int Ho = h - (K - 1), Wo = w - (K - 1);
+  if (C < 1 || Co < 1 || K < 1 || Ho < 1 || Wo < 1 || (qmode == ORC_Q_FP8 && !(in_scale > 0))) return -1;
+  const int per = C * K * K, nw = Co * per;
+  double* a = (double*)malloc(sizeof(double) * (size_t)C * h * w);
+  double* wq = (double*)malloc(sizeof(double) * nw);
+  double* osc = (double*)malloc(sizeof(double) * Co);
+  double* zb = (double*)calloc(Co, sizeof(double));
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)Co * Ho * Wo);
+  if (pool) pool2(in, C, H, W, 1, a);
+  else memcpy(a, in, sizeof(double) * (size_t)C * h * w);
+  for (int co = 0; co < Co; ++co) {
+    double sw = 1.0;
+    if (qmode == ORC_Q_FP8) {
+      double mx = 0.0;
+      for (int i = 0; i < per; ++i)
+        if (fabs(wt[co * per + i]) > mx) mx = fabs(wt[co * per + i]);
+      sw = mx > 0 ? mx / 448.0 : 1.0;
+    }
+    for (int i = 0; i < per; ++i) {
+      const double v = wt[co * per + i];
+      wq[co * per + i] = qmode == ORC_Q_FP8 ? orc_e4m3(v / sw) : qmode == ORC_Q_BF16 ? orc_bf16(v) : v;
+    }
+    osc[co] = qmode == ORC_Q_FP8 ? in_scale * sw : 1.0;
+  }
+  for (int64_t i = 0; i < (int64_t)C * h * w; ++i)
+    a[i] = qmode == ORC_Q_FP8 ? orc_e4m3(a[i] / in_scale) : qmode == ORC_Q_BF16 ? orc_bf16(a[i]) : a[i];
+  conv_valid(a, C, h, w, wq, zb, K, Co, 1, tmp);
+  for (int co = 0; co < Co; ++co)
+    for (int64_t i = 0; i < (int64_t)Ho * Wo; ++i)
+      out[(int64_t)co * Ho * Wo + i] = bs[co] + osc[co] * tmp[(int64_t)co * Ho * Wo + i];
+  if (absum) {
+    for (int i = 0; i < nw; ++i) wq[i] = fabs(wq[i]);
+    for (int64_t i = 0; i < (int64_t)C * h * w; ++i) a[i] = fabs(a[i]);
+    conv_valid(a, C, h, w, wq, zb, K, Co, 1, tmp);
+    for (int co = 0; co < Co; ++co)
+      for (int64_t i = 0; i < (int64_t)Ho * Wo; ++i)
+        absum[(int64_t)co * Ho * Wo + i] = osc[co] * tmp[(int64_t)co * Ho * Wo + i];
+  }
+  free(a);
+  free(wq);
+  free(osc);
+  free(zb);
+  free(tmp);
+  return 0;
+}
+
 void orc_adam(double* theta, double* m, double* v, const double* g, int64_t n, int t, double lr,
               double b1, double b2, double eps) {
   double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);

@@ -43,6 +43,12 @@ class _Tile(ctypes.Structure):
                 ("w", ctypes.c_int64), ("halo", ctypes.c_int32), ("out", ctypes.c_void_p)]
 
 
+class _PatchSrc(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_void_p), ("teacher", ctypes.c_void_p), ("Z", ctypes.c_int64),
+                ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("z", ctypes.c_int32), ("y", ctypes.c_int32),
+                ("x", ctypes.c_int32)]
+
+
 class _Adam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float)]
@@ -54,6 +60,7 @@ EXPORTS = [
     "student_destroy", "student_get_state", "student_set_state", "student_grad",
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
     "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
+    "cnn_infer_noalloc", "student_gather",
 ]
 
 
@@ -67,6 +74,7 @@ def _load():
         "cnn_destroy": [vp],
         "cnn_geometry": [vp, vp, vp],
         "cnn_infer": [vp, vp, vp, vp, vp],
+        "cnn_infer_noalloc": [vp, vp, vp, vp, vp],
         "cnn_infer_batch": [vp, vp, i32, vp],
         "cnn_autotune": [vp, i64, i64, ctypes.c_char_p, vp],
         "cnn_describe": [vp, ctypes.c_char_p, i32],
@@ -82,8 +90,9 @@ def _load():
         "student_set_state": [vp, vp, vp, vp, i64],
         "student_grad": [vp, vp, vp, i32, i32, vp, vp, vp],
         "student_train_step": [vp, vp, vp, i32, i32, vp, vp, vp, vp],
+        "student_gather": [vp, i32, i32, i32, vp, vp, vp],
         "student_infer": [vp, vp, vp, vp, vp],
-        "student_infer_with_fallback": [vp, vp, vp, vp, vp, f32, i32, i32, ctypes.c_uint64, vp, vp],
+        "student_infer_with_fallback": [vp, vp, vp, vp, vp, f32, i32, i32, ctypes.c_uint64, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -123,14 +132,33 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _require_cuda(t, dtype, name):
+def _check_buf(t, dtype, name, shape=None, min_numel=None):
+    """Host-side checks of a caller buffer before its pointer reaches the
+    library: tensor, dtype, shape (or at least min_numel elements), contiguity."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
     if t.dtype != dtype:
         raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError("%s needs at least %d elements, got %d" % (name, min_numel, t.numel()))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
+
+
+def _on_device(**bufs):
+    """Every buffer passed to the library lives in device memory (checked after
+    the host-side checks of all buffers)."""
+    for name, t in bufs.items():
+        if t is not None and not t.is_cuda:
+            raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+
+
+def _require_cuda(t, dtype, name, shape=None, min_numel=None):
+    _check_buf(t, dtype, name, shape, min_numel)
+    _on_device(**{name: t})
 
 
 def radius_of(net) -> int:
@@ -197,18 +225,29 @@ def cnn_geometry(net: Net):
 def cnn_infer(net: Net, volume, out=None, stream=None):
     """volume: CUDA uint8 Z x H x W; returns (or fills) CUDA float32 Z x (H-R) x (W-R)."""
     import torch
-    _require_cuda(volume, torch.uint8, "volume")
-    if volume.dim() != 3:
-        raise ValueError("volume must be Z x H x W")
-    Z, H, W = volume.shape
+    Z, H, W = _volume_dims(volume)
     if out is None:
         out = torch.empty((Z, max(H - net.R, 0), max(W - net.R, 0)), dtype=torch.float32,
                           device=volume.device)
-    _require_cuda(out, torch.float32, "out")
-    if tuple(out.shape) != (Z, H - net.R, W - net.R):
-        raise ValueError("out must be Z x (H-R) x (W-R)")
+    _check_buf(out, torch.float32, "out", shape=(Z, H - net.R, W - net.R))
+    _on_device(volume=volume, out=out)
     _check(_lib.cnn_infer(net.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
            "cnn_infer")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20  # CNN_NOALLOC_SCRATCH_BYTES of include/emcnn.h
+
+
+def cnn_infer_noalloc(net: Net, volume, out, stream=None):
+    """cnn_infer without any allocation: `out` (CUDA float32 Z x (H-R) x (W-R))
+    is required, and the library works in its static device scratch."""
+    import torch
+    Z, H, W = _volume_dims(volume)
+    _check_buf(out, torch.float32, "out", shape=(Z, H - net.R, W - net.R))
+    _on_device(volume=volume, out=out)
+    _check(_lib.cnn_infer_noalloc(net.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
+           "cnn_infer_noalloc")
     return out
 
 
@@ -322,11 +361,11 @@ def student_set_state(s: Student, w, m, v, step: int):
 
 def _check_patches(patches, teacher):
     import torch
-    _require_cuda(patches, torch.uint8, "patches")
-    _require_cuda(teacher, torch.float32, "teacher_prob")
-    B, P, P2 = patches.shape
-    if P != P2 or tuple(teacher.shape) != (B, P - STUDENT_R, P - STUDENT_R):
-        raise ValueError("patches B x P x P and teacher B x (P-6) x (P-6) expected")
+    if not isinstance(patches, torch.Tensor) or patches.dim() != 3 or patches.shape[1] != patches.shape[2]:
+        raise ValueError("patches must be a B x P x P tensor")
+    B, P, _ = patches.shape
+    _check_buf(patches, torch.uint8, "patches")
+    _check_buf(teacher, torch.float32, "teacher_prob", shape=(B, P - STUDENT_R, P - STUDENT_R))
     return B, P
 
 
@@ -338,9 +377,32 @@ def student_grad(s: Student, patches, teacher, grad_out=None, loss_out=None, str
         grad_out = torch.empty(STUDENT_PARAMS, dtype=torch.float32, device=dev)
     if loss_out is None:
         loss_out = torch.empty(1, dtype=torch.float64, device=dev)
+    _check_buf(grad_out, torch.float32, "grad_out", shape=(STUDENT_PARAMS,))
+    _check_buf(loss_out, torch.float64, "loss_out", min_numel=1)
+    _on_device(patches=patches, teacher_prob=teacher, grad_out=grad_out, loss_out=loss_out)
     _check(_lib.student_grad(s.ptr, _ptr(patches), _ptr(teacher), B, P, _ptr(grad_out),
                              _ptr(loss_out), _stream(stream)), "student_grad")
     return grad_out, loss_out
+
+
+def student_gather(sources, patch, teacher_R, patches_out, teacher_out, stream=None):
+    """Gather a training batch on the device. sources: list of (volume uint8
+    Z x H x W, teacher map float32 Z x (H-R) x (W-R), z, y, x); fills
+    patches_out (B x P x P uint8) and teacher_out (B x (P-6) x (P-6) float32)."""
+    import torch
+    B = len(sources)
+    _check_buf(patches_out, torch.uint8, "patches_out", shape=(B, patch, patch))
+    _check_buf(teacher_out, torch.float32, "teacher_out", shape=(B, patch - STUDENT_R, patch - STUDENT_R))
+    arr = (_PatchSrc * max(B, 1))()
+    for i, (vol, tmap, z, y, x) in enumerate(sources):
+        Z, H, W = _volume_dims(vol)
+        _check_buf(tmap, torch.float32, "teacher map", shape=(Z, H - teacher_R, W - teacher_R))
+        _on_device(volume=vol, teacher_map=tmap)
+        arr[i] = _PatchSrc(vol.data_ptr(), tmap.data_ptr(), Z, H, W, int(z), int(y), int(x))
+    _on_device(patches_out=patches_out, teacher_out=teacher_out)
+    _check(_lib.student_gather(arr, B, int(patch), int(teacher_R), _ptr(patches_out), _ptr(teacher_out),
+                               _stream(stream)), "student_gather")
+    return patches_out, teacher_out
 
 
 def student_train_step(s: Student, patches, teacher, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
@@ -352,6 +414,9 @@ def student_train_step(s: Student, patches, teacher, lr=1e-3, beta1=0.9, beta2=0
         loss_out = torch.empty(1, dtype=torch.float64, device=dev)
     if gnorm_out is None:
         gnorm_out = torch.empty(1, dtype=torch.float64, device=dev)
+    _check_buf(loss_out, torch.float64, "loss_out", min_numel=1)
+    _check_buf(gnorm_out, torch.float64, "gnorm_out", min_numel=1)
+    _on_device(patches=patches, teacher_prob=teacher, loss_out=loss_out, gnorm_out=gnorm_out)
     hp = _Adam(lr, beta1, beta2, eps)
     _check(_lib.student_train_step(s.ptr, _ptr(patches), _ptr(teacher), B, P, ctypes.byref(hp),
                                    _ptr(loss_out), _ptr(gnorm_out), _stream(stream)),
@@ -359,30 +424,54 @@ def student_train_step(s: Student, patches, teacher, lr=1e-3, beta1=0.9, beta2=0
     return loss_out, gnorm_out
 
 
+def _volume_dims(volume):
+    import torch
+    if not isinstance(volume, torch.Tensor) or volume.dim() != 3:
+        raise ValueError("volume must be a Z x H x W tensor")
+    _check_buf(volume, torch.uint8, "volume")
+    return (int(v) for v in volume.shape)
+
+
 def student_infer(s: Student, volume, out=None, stream=None):
     import torch
-    _require_cuda(volume, torch.uint8, "volume")
-    Z, H, W = volume.shape
+    Z, H, W = _volume_dims(volume)
     if out is None:
-        out = torch.empty((Z, H - STUDENT_R, W - STUDENT_R), dtype=torch.float32, device=volume.device)
-    _require_cuda(out, torch.float32, "out")
+        out = torch.empty((Z, max(H - STUDENT_R, 0), max(W - STUDENT_R, 0)), dtype=torch.float32,
+                          device=volume.device)
+    _check_buf(out, torch.float32, "out", shape=(Z, H - STUDENT_R, W - STUDENT_R))
+    _on_device(volume=volume, out=out)
     _check(_lib.student_infer(s.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
            "student_infer")
     return out
 
 
+def fallback_tiles(shape_out, tile):
+    """(ty, tx): fallback tiles per slice along y and x for an output of shape Z x Ho x Wo."""
+    _, Ho, Wo = shape_out
+    return (Ho + tile - 1) // tile, (Wo + tile - 1) // tile
+
+
 def student_infer_with_fallback(s: Student, teacher: Net, volume, tau=0.01, tile=512, n_samples=4,
-                                seed=0, out=None, stats=None, stream=None):
+                                seed=0, out=None, stats=None, flags=None, stream=None):
+    """Returns (out, stats); with flags (an int32 CUDA tensor of Z * ty * tx
+    elements, see fallback_tiles) the per-tile decisions are written there too."""
     import torch
-    _require_cuda(volume, torch.uint8, "volume")
-    Z, H, W = volume.shape
+    Z, H, W = _volume_dims(volume)
     R = teacher.R
     if out is None:
-        out = torch.empty((Z, H - R, W - R), dtype=torch.float32, device=volume.device)
+        out = torch.empty((Z, max(H - R, 0), max(W - R, 0)), dtype=torch.float32, device=volume.device)
     if stats is None:
         stats = torch.zeros(2, dtype=torch.int32, device=volume.device)
+    _check_buf(out, torch.float32, "out", shape=(Z, H - R, W - R))
+    _check_buf(stats, torch.int32, "stats", shape=(2,))
+    if flags is not None:
+        ty, tx = fallback_tiles((Z, H - R, W - R), max(int(tile), 1))
+        _check_buf(flags, torch.int32, "flags", shape=(Z * ty * tx,))
+    _on_device(volume=volume, out=out, stats=stats, flags=flags)
     _check(_lib.student_infer_with_fallback(s.ptr, teacher.ptr, _ptr(volume), _dims(volume),
                                             _ptr(out), float(tau), int(tile), int(n_samples),
-                                            int(seed), _ptr(stats), _stream(stream)),
+                                            int(seed), _ptr(stats),
+                                            None if flags is None else _ptr(flags),
+                                            _stream(stream)),
            "student_infer_with_fallback")
     return out, stats

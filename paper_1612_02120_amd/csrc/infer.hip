@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -111,11 +112,12 @@ static hipEvent_t pool_event(Net* net) {
   return e;
 }
 
-int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st) {
+int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st, bool timed) {
   const void* fn = layer_fn(L);
   hipError_t e;
   Net::Timed tm{(int)(&L - net->layers.data()), nullptr, nullptr};
-  if (net->profiling) {
+  timed = timed && net->profiling;
+  if (timed) {
     tm.a = pool_event(net);
     tm.b = pool_event(net);
     if (tm.a) hipEventRecord(tm.a, st);
@@ -147,86 +149,165 @@ int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipSt
     e = hipLaunchKernel(fn, dim3(grid), dim3(layer_threads(L)), args, 0, st);
   }
   if (e != hipSuccess) return hip_fail(e, layer_name(L));
-  if (net->profiling && tm.a && tm.b) {
+  if (timed && tm.a && tm.b) {
     hipEventRecord(tm.b, st);
     net->timed.push_back(tm);
   }
   return CNN_OK;
 }
 
+// Every layer of one region (zc slices of an h x w input window of the
+// volume, row stride in_rs and slice stride in_zs; output window at prob with
+// strides out_rs / out_zs) as one persistent launch per layer with the job
+// passed by value; inter-layer maps alternate between buf0 and buf1.
+static int run_region(Net* net, const uint8_t* in, int64_t in_rs, int64_t in_zs, int zc, int h, int w, float* prob,
+                      int64_t out_rs, int64_t out_zs, unsigned char* buf0, unsigned char* buf1, hipStream_t st,
+                      bool timed) {
+  const Dims d = layer_dims(net, h, w);
+  const int nl = (int)net->layers.size();
+  const bool fused = first_fused(net);
+  unsigned char* buf[2] = {buf0, buf1};
+  for (int l = fused ? 1 : 0; l < nl; ++l) {
+    const ExecLayer& L = net->layers[l];
+    // a fused layer 1 reads the uint8 input with layer 0's geometry
+    const int li = (l == 1 && fused) ? 0 : l;
+    const void* lin = (li == 0) ? (const void*)in : (const void*)buf[(l - 1) % 2];
+    void* out = (l == nl - 1) ? (void*)prob : (void*)buf[l % 2];
+    int64_t lin_rs = in_rs, lin_zs = in_zs, lout_rs = out_rs, lout_zs = out_zs;
+    if (li > 0) map_strides(net->layers[li - 1], d.hin[li], d.win[li], lin_rs, lin_zs);
+    if (l < nl - 1) map_strides(L, d.hout[l], d.wout[l], lout_rs, lout_zs);
+    LayerJob j = make_job(L, lin, out, zc, d.hin[li], d.win[li], lin_rs, lin_zs, d.hout[l], d.wout[l], lout_rs,
+                          lout_zs, 0, nullptr);
+    JobSet js;
+    std::memset(&js, 0, sizeof(js));
+    js.njobs = 1;
+    js.total_items = job_items(j);
+    js.single = j;
+    const int rc = launch_layer(net, L, js, persistent_grid(net, L, js.total_items), st, timed);
+    if (rc) return rc;
+  }
+  return CNN_OK;
+}
+
+// Inter-layer bytes (both parity halves) of a zc-slice region of h x w input.
+static void region_bytes(const Net* net, int h, int w, size_t& b0, size_t& b1) {
+  const std::vector<size_t> lb = layer_bytes(net, layer_dims(net, h, w));
+  b0 = b1 = 0;
+  for (size_t l = 0; l < lb.size(); ++l) (l % 2 ? b1 : b0) = std::max((l % 2 ? b1 : b0), lb[l]);
+}
+
 // A whole volume: slabs of slices sized so the two inter-layer buffers stay
 // within the workspace budget; one persistent launch per layer per slab.
 int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, float* prob, hipStream_t st) {
-  const Dims d = layer_dims(net, (int)H, (int)W);
-  const std::vector<size_t> lb = layer_bytes(net, d);
-  const int nl = (int)net->layers.size();
   size_t b0 = 0, b1 = 0;
-  for (int l = 0; l < nl; ++l) (l % 2 ? b1 : b0) = std::max((l % 2 ? b1 : b0), lb[l]);
+  region_bytes(net, (int)H, (int)W, b0, b1);
   const size_t per = std::max<size_t>(1, b0 + b1);
   int64_t zs = std::max<int64_t>(1, std::min<int64_t>(Z, (int64_t)(net->ws_budget / per)));
   int rc = ensure_ws(net, zs * (b0 + b1));
   if (rc) return rc;
-  unsigned char* buf[2] = {reinterpret_cast<unsigned char*>(net->ws),
-                           reinterpret_cast<unsigned char*>(net->ws) + zs * b0};
-  const int Ho = d.hout[nl - 1], Wo = d.wout[nl - 1];
-  const bool fused = first_fused(net);
+  unsigned char* buf0 = reinterpret_cast<unsigned char*>(net->ws);
+  unsigned char* buf1 = buf0 + zs * b0;
+  const int64_t Ho = H - net->R, Wo = W - net->R;
   for (int64_t z0 = 0; z0 < Z; z0 += zs) {
     const int zc = (int)std::min<int64_t>(zs, Z - z0);
-    for (int l = fused ? 1 : 0; l < nl; ++l) {
-      const ExecLayer& L = net->layers[l];
-      // a fused layer 1 reads the uint8 input with layer 0's geometry
-      const int li = (l == 1 && fused) ? 0 : l;
-      const void* in = (li == 0) ? (const void*)(vol + z0 * H * W) : (const void*)buf[(l - 1) % 2];
-      void* out = (l == nl - 1) ? (void*)(prob + z0 * (int64_t)Ho * Wo) : (void*)buf[l % 2];
-      int64_t in_rs = d.win[li], in_zs = (int64_t)d.hin[li] * d.win[li], out_rs = d.wout[l],
-              out_zs = (int64_t)d.hout[l] * d.wout[l];
-      if (li > 0) map_strides(net->layers[li - 1], d.hin[li], d.win[li], in_rs, in_zs);
-      if (l < nl - 1) map_strides(L, d.hout[l], d.wout[l], out_rs, out_zs);
-      LayerJob j = make_job(L, in, out, zc, d.hin[li], d.win[li], in_rs, in_zs, d.hout[l], d.wout[l], out_rs, out_zs,
-                            0, nullptr);
-      JobSet js;
-      std::memset(&js, 0, sizeof(js));
-      js.njobs = 1;
-      js.total_items = job_items(j);
-      js.single = j;
-      rc = launch_layer(net, L, js, persistent_grid(net, L, js.total_items), st);
-      if (rc) return rc;
-    }
+    rc = run_region(net, vol + z0 * H * W, W, H * W, zc, (int)H, (int)W, prob + z0 * Ho * Wo, Wo, Ho * Wo, buf0, buf1,
+                    st, true);
+    if (rc) return rc;
   }
+  return CNN_OK;
+}
+
+// ------------------------------------------------------------------ static scratch
+
+// The inter-layer maps of cnn_infer_noalloc live in this file-scope device
+// array; each device holds its own copy, reached through the address that
+// hipGetSymbolAddress returns on that device (never the host-side name).
+static __device__ __align__(256) unsigned char scratch[CNN_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static int scratch_ptr(int device, unsigned char** out) {
+  if (device < 0 || device >= 64) return fail(CNN_EUNSUPPORTED, "cnn_infer_noalloc: device index >= 64");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "cnn_infer_noalloc: hipGetSymbolAddress(scratch)");
+    if (!p) return fail(CNN_EHIP, "cnn_infer_noalloc: null scratch address");
+    g_scratch_ptr[device] = p;
+  }
+  *out = reinterpret_cast<unsigned char*>(g_scratch_ptr[device]);
+  return CNN_OK;
+}
+
+// The volume as regions that fit the static scratch: slabs of whole slices
+// when one slice fits, otherwise strips of output rows (a multiple of 16, so
+// that every phase lattice of a stride-2 pool net starts at the same parity
+// as in the whole slice) with R rows of input overlap. Results are bitwise
+// those of run_volume: each output voxel takes the same arithmetic in the same
+// order whatever region holds it.
+int plan_static(const Net* net, int64_t Z, int64_t H, int64_t W, size_t cap, int64_t& zslab, int64_t& strip) {
+  size_t b0 = 0, b1 = 0;
+  region_bytes(net, (int)H, (int)W, b0, b1);
+  if (b0 + b1 <= cap) {
+    zslab = std::max<int64_t>(1, std::min<int64_t>(Z, (int64_t)(cap / std::max<size_t>(1, b0 + b1))));
+    strip = H - net->R;
+    return CNN_OK;
+  }
+  zslab = 1;
+  const int64_t Ho = H - net->R;
+  int64_t lo = 0;
+  for (int64_t hs = 16; hs < Ho; hs *= 2) {  // largest power-of-two multiple of 16 that fits, then refine
+    region_bytes(net, (int)(hs + net->R), (int)W, b0, b1);
+    if (b0 + b1 > cap) break;
+    lo = hs;
+  }
+  if (lo == 0)
+    return fail(CNN_EINVAL, "cnn_infer_noalloc: a 16-row strip of width " + std::to_string(W) +
+                                " needs more than the static scratch (" + std::to_string(cap) + " bytes)");
+  for (int64_t step = lo / 2; step >= 16; step /= 2) {
+    region_bytes(net, (int)(lo + step + net->R), (int)W, b0, b1);
+    if (lo + step < Ho && b0 + b1 <= cap) lo += step;
+  }
+  strip = lo;
   return CNN_OK;
 }
 
 // ------------------------------------------------------------------ regions
 
-// Wait until earlier submissions no longer read the pinned job-table arena,
-// then make the arena hold `njobs` jobs (host and device copies).
+// Switch to the other job-table arena, wait until the submission that last
+// used it no longer reads its pinned table, then make it hold `njobs` jobs
+// (host and device copies).
 int arena_reserve(Net* net, size_t njobs) {
   hipError_t e;
-  if (net->done_pending) {
-    if ((e = hipEventSynchronize(net->done)) != hipSuccess) return hip_fail(e, "wait previous submission");
-    net->done_pending = false;
+  net->cur ^= 1;
+  Net::Arena& A = net->arena[net->cur];
+  if (A.done_pending) {
+    if ((e = hipEventSynchronize(A.done)) != hipSuccess) return hip_fail(e, "wait for the arena's last submission");
+    A.done_pending = false;
   }
   const size_t bytes = std::max<size_t>(1, njobs) * sizeof(LayerJob);
-  if (net->tab_host_bytes < bytes) {
-    if (net->tab_host) hipHostFree(net->tab_host);
-    net->tab_host = nullptr;
-    net->tab_host_bytes = 0;
-    if ((e = hipHostMalloc(&net->tab_host, bytes)) != hipSuccess) return fail(CNN_ENOMEM, "pinned job table");
-    net->tab_host_bytes = bytes;
+  if (A.tab_host_bytes < bytes) {
+    if (A.tab_host) hipHostFree(A.tab_host);
+    A.tab_host = nullptr;
+    A.tab_host_bytes = 0;
+    if ((e = hipHostMalloc(&A.tab_host, bytes)) != hipSuccess) return fail(CNN_ENOMEM, "pinned job table");
+    A.tab_host_bytes = bytes;
   }
-  if (net->tab_dev_bytes < bytes) {
+  if (A.tab_dev_bytes < bytes) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "job table grow: sync");
-    if (net->tab_dev) hipFree(net->tab_dev);
-    net->tab_dev = nullptr;
-    net->tab_dev_bytes = 0;
-    if ((e = hipMalloc(&net->tab_dev, bytes)) != hipSuccess) return fail(CNN_ENOMEM, "device job table");
-    net->tab_dev_bytes = bytes;
-    if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
-    net->graph_exec = nullptr;
-    net->graph_key.clear();
+    if (A.tab_dev) hipFree(A.tab_dev);
+    A.tab_dev = nullptr;
+    A.tab_dev_bytes = 0;
+    if ((e = hipMalloc(&A.tab_dev, bytes)) != hipSuccess) return fail(CNN_ENOMEM, "device job table");
+    A.tab_dev_bytes = bytes;
+    if (A.graph_exec) hipGraphExecDestroy(A.graph_exec);
+    A.graph_exec = nullptr;
+    A.graph_key.clear();
   }
-  if (!net->done) {
-    if ((e = hipEventCreateWithFlags(&net->done, hipEventDisableTiming)) != hipSuccess)
+  if (!A.done) {
+    if ((e = hipEventCreateWithFlags(&A.done, hipEventDisableTiming)) != hipSuccess)
       return hip_fail(e, "hipEventCreate");
   }
   return CNN_OK;
@@ -284,10 +365,11 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
     ws_need = std::max(ws_need, s0 + s1);
   }
   const size_t need_jobs = job_off + (size_t)n * nl;
-  if (need_jobs * sizeof(LayerJob) > net->tab_host_bytes) return fail(CNN_EINVAL, "internal: job arena too small");
+  Net::Arena& A = net->arena[net->cur];
+  if (need_jobs * sizeof(LayerJob) > A.tab_host_bytes) return fail(CNN_EINVAL, "internal: job arena too small");
   int rc = ensure_ws(net, ws_need);
   if (rc) return rc;
-  LayerJob* tab = reinterpret_cast<LayerJob*>(net->tab_host);
+  LayerJob* tab = reinterpret_cast<LayerJob*>(A.tab_host);
   size_t pos = job_off;
   for (auto& G : groups) {
     size_t half0 = 0;
@@ -347,7 +429,7 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
       Launch la;
       la.layer = l;
       std::memset(&la.js, 0, sizeof(la.js));
-      la.js.table = reinterpret_cast<const LayerJob*>(net->tab_dev) + first;
+      la.js.table = reinterpret_cast<const LayerJob*>(A.tab_dev) + first;
       la.js.njobs = (int)(pos - first);
       la.js.total_items = item0;
       la.grid = persistent_grid(net, L, (int64_t)1 << 40);  // full persistent grid: structure-stable
@@ -378,8 +460,9 @@ size_t count_region_jobs(const Net* net, const std::vector<Region>& regs) {
 int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t njobs, hipStream_t st, bool graph) {
   hipError_t e;
   const size_t tab_bytes = std::max<size_t>(1, njobs) * sizeof(LayerJob);
-  void* dsrc = reinterpret_cast<LayerJob*>(net->tab_dev) + job_off;
-  const void* hsrc = reinterpret_cast<const LayerJob*>(net->tab_host) + job_off;
+  Net::Arena& A = net->arena[net->cur];
+  void* dsrc = reinterpret_cast<LayerJob*>(A.tab_dev) + job_off;
+  const void* hsrc = reinterpret_cast<const LayerJob*>(A.tab_host) + job_off;
   if (!graph) {
     if ((e = hipMemcpyAsync(dsrc, hsrc, tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
       return hip_fail(e, "job table upload");
@@ -404,10 +487,10 @@ int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t
       const int v = net->layers[la.layer].variant;
       put(&v, sizeof(int));
     }
-    if (!net->graph_exec || key != net->graph_key) {
-      if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
-      net->graph_exec = nullptr;
-      net->graph_key.clear();
+    if (!A.graph_exec || key != A.graph_key) {
+      if (A.graph_exec) hipGraphExecDestroy(A.graph_exec);
+      A.graph_exec = nullptr;
+      A.graph_key.clear();
       if (!net->cap_stream) {
         if ((e = hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking)) != hipSuccess)
           return hip_fail(e, "hipStreamCreate");
@@ -428,18 +511,18 @@ int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t
         return crc;
       }
       if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&net->graph_exec, g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&A.graph_exec, g, nullptr, nullptr, 0);
       hipGraphDestroy(g);
       if (e != hipSuccess) {
-        net->graph_exec = nullptr;
+        A.graph_exec = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
       }
-      net->graph_key = key;
+      A.graph_key = key;
     }
-    if ((e = hipGraphLaunch(net->graph_exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if ((e = hipGraphLaunch(A.graph_exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
-  if ((e = hipEventRecord(net->done, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  net->done_pending = true;
+  if ((e = hipEventRecord(A.done, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  A.done_pending = true;
   return CNN_OK;
 }
 
@@ -468,6 +551,40 @@ extern "C" int cnn_infer(cnn_net* h, const uint8_t* vol, const int64_t dims[3], 
   int rc = check_device(net);
   if (rc) return rc;
   return run_volume(net, vol, Z, H, W, prob, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int cnn_infer_noalloc(cnn_net* h, const uint8_t* vol, const int64_t dims[3], float* prob, void* stream) {
+  clear_error();
+  if (!h || !vol || !dims || !prob) return fail(CNN_EINVAL, "cnn_infer_noalloc: null argument");
+  Net* net = reinterpret_cast<Net*>(h);
+  const int64_t Z = dims[0], H = dims[1], W = dims[2];
+  if (Z < 1 || H < net->R + 1 || W < net->R + 1)
+    return fail(CNN_EINVAL, "cnn_infer_noalloc: dims smaller than the field of view (" + std::to_string(net->R + 1) +
+                                ")");
+  if (H >= (1ll << 30) || W >= (1ll << 30) || Z >= (1ll << 30))
+    return fail(CNN_EINVAL, "cnn_infer_noalloc: dims must be < 2^30");
+  int rc = check_device(net);
+  if (rc) return rc;
+  int64_t zslab = 1, strip = 1;
+  rc = plan_static(net, Z, H, W, CNN_NOALLOC_SCRATCH_BYTES, zslab, strip);
+  if (rc) return rc;
+  unsigned char* base = nullptr;
+  rc = scratch_ptr(net->device, &base);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t Ho = H - net->R, Wo = W - net->R;
+  for (int64_t z0 = 0; z0 < Z; z0 += zslab) {
+    const int zc = (int)std::min<int64_t>(zslab, Z - z0);
+    for (int64_t y0 = 0; y0 < Ho; y0 += strip) {
+      const int64_t hs = std::min<int64_t>(strip, Ho - y0);
+      size_t b0 = 0, b1 = 0;
+      region_bytes(net, (int)(hs + net->R), (int)W, b0, b1);
+      rc = run_region(net, vol + z0 * H * W + y0 * W, W, H * W, zc, (int)(hs + net->R), (int)W,
+                      prob + z0 * Ho * Wo + y0 * Wo, Wo, Ho * Wo, base, base + zc * b0, st, false);
+      if (rc) return rc;
+    }
+  }
+  return CNN_OK;
 }
 
 extern "C" int cnn_set_batch_graph(cnn_net* h, int32_t enable) {
@@ -629,7 +746,10 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   }
   hipEventCreate(&e0);
   hipEventCreate(&e1);
-  hipMemcpy(bufs[0], host_in.data(), host_in.size(), hipMemcpyHostToDevice);
+  if ((e = hipMemcpy(bufs[0], host_in.data(), host_in.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "cnn_autotune: input upload");
+  }
   // reference pass with the default variants (layer 0's output is still made
   // when layer 1 computes it itself: it is the reference for tuning layer 0)
   const bool fused = first_fused(net);
@@ -648,7 +768,10 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
     }
     if (L.candidates.size() < 2 || (l == 0 && fused)) continue;  // a fused layer 0 is never launched
     std::vector<unsigned char> ref(ob[l]), got(ob[l]);
-    hipMemcpy(ref.data(), bufs[l + 1], ob[l], hipMemcpyDeviceToHost);
+    if ((e = hipMemcpy(ref.data(), bufs[l + 1], ob[l], hipMemcpyDeviceToHost)) != hipSuccess) {
+      rc = hip_fail(e, "cnn_autotune: reference copy");
+      break;
+    }
     const int def = L.variant;
     int best = def;
     float best_ms = 1e30f;
@@ -683,7 +806,10 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
       float ms = 0.f;
       hipEventElapsedTime(&ms, e0, e1);
       ms /= reps;
-      hipMemcpy(got.data(), bufs[nl + 1], ob[l], hipMemcpyDeviceToHost);
+      if ((e = hipMemcpy(got.data(), bufs[nl + 1], ob[l], hipMemcpyDeviceToHost)) != hipSuccess) {
+        rc = hip_fail(e, "cnn_autotune: candidate copy");
+        break;
+      }
       const bool same = std::memcmp(got.data(), ref.data(), ob[l]) == 0;
       if (same && ms < best_ms) {
         best_ms = ms;

@@ -57,16 +57,22 @@ struct Net {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_budget = (size_t)24 << 30;
-  // batched submissions
-  void* tab_dev = nullptr;
-  size_t tab_dev_bytes = 0;
-  void* tab_host = nullptr;  // pinned
-  size_t tab_host_bytes = 0;
+  // batched submissions: two job-table arenas used in turn, so a submission
+  // waits on the host only for the one two calls back (still reading its
+  // pinned table) and never for the previous one
+  struct Arena {
+    void* tab_dev = nullptr;
+    size_t tab_dev_bytes = 0;
+    void* tab_host = nullptr;  // pinned
+    size_t tab_host_bytes = 0;
+    hipGraphExec_t graph_exec = nullptr;  // captured submission reading this arena
+    std::vector<unsigned char> graph_key;
+    hipEvent_t done = nullptr;  // recorded behind the arena's last submission
+    bool done_pending = false;
+  };
+  Arena arena[2];
+  int cur = 0;  // arena of the submission being planned
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  std::vector<unsigned char> graph_key;
-  hipEvent_t done = nullptr;
-  bool done_pending = false;
   int use_graph = 1;
   // optional per-layer timing: events recorded on the launch stream around
   // every layer kernel while enabled
@@ -110,7 +116,7 @@ size_t count_region_jobs(const Net* net, const std::vector<Region>& regs);
 int plan_regions(Net* net, const std::vector<Region>& regs, size_t job_off, std::vector<Launch>& launches,
                  size_t& njobs_used, size_t& ws_need);
 int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t njobs, hipStream_t st, bool graph);
-int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st);
+int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st, bool timed = true);
 int check_device(const Net* net);
 
 int fail(int code, const std::string& msg);

@@ -186,15 +186,18 @@ static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b
     return hip_fail(e, "hipMemcpy(weights)");
   if (L.bias) return CNN_OK;  // per-channel data shared by all candidates is already set
   if ((e = hipMalloc(&L.bias, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(bias)");
-  hipMemcpy(L.bias, bias.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+  if ((e = hipMemcpy(L.bias, bias.data(), cout * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(bias)");
   if (v->prec == FP8) {
     if ((e = hipMalloc(&L.oscale, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(scale)");
-    hipMemcpy(L.oscale, osc.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+    if ((e = hipMemcpy(L.oscale, osc.data(), cout * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy(scale)");
   }
   if (v->head) {
     std::vector<float> h(hw, hw + cout);
     if ((e = hipMalloc(&L.head_w, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(head)");
-    hipMemcpy(L.head_w, h.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+    if ((e = hipMemcpy(L.head_w, h.data(), cout * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy(head)");
     L.head_b = (float)hb;
   }
   L.out_inv_scale = next_scale > 0 ? (float)(1.0 / next_scale) : 1.0f;
@@ -241,10 +244,12 @@ static int pack_first(ExecLayer& L, int variant, const double* w, const double* 
   void* wdev = nullptr;
   if ((e = hipMalloc(&wdev, pk.size())) != hipSuccess) return hip_fail(e, "hipMalloc(w1)");
   L.wpacks.push_back(wdev);
-  hipMemcpy(wdev, pk.data(), pk.size(), hipMemcpyHostToDevice);
+  if ((e = hipMemcpy(wdev, pk.data(), pk.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(w1)");
   if (L.bias) return CNN_OK;
   if ((e = hipMalloc(&L.bias, cout * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(b1)");
-  hipMemcpy(L.bias, bf.data(), cout * sizeof(float), hipMemcpyHostToDevice);
+  if ((e = hipMemcpy(L.bias, bf.data(), cout * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(b1)");
   L.out_inv_scale = next_scale > 0 ? (float)(1.0 / next_scale) : 1.0f;
   return CNN_OK;
 }
@@ -274,7 +279,8 @@ static int pack_head_valu(ExecLayer& L, int variant, const double* w, const doub
   bf[0] = (float)b[0];
   bf[1] = (float)b[1];
   if ((err = hipMalloc(&L.bias, 16 * sizeof(float))) != hipSuccess) return hip_fail(err, "hipMalloc(head bias)");
-  hipMemcpy(L.bias, bf.data(), 16 * sizeof(float), hipMemcpyHostToDevice);
+  if ((err = hipMemcpy(L.bias, bf.data(), 16 * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "hipMemcpy(head bias)");
   return CNN_OK;
 }
 
@@ -636,11 +642,13 @@ extern "C" int cnn_destroy(cnn_net* h) {
   hipDeviceSynchronize();
   for (auto& E : net->layers) free_layer(E);
   if (net->ws) hipFree(net->ws);
-  if (net->tab_dev) hipFree(net->tab_dev);
-  if (net->tab_host) hipHostFree(net->tab_host);
-  if (net->graph_exec) hipGraphExecDestroy(net->graph_exec);
+  for (Net::Arena& A : net->arena) {
+    if (A.tab_dev) hipFree(A.tab_dev);
+    if (A.tab_host) hipHostFree(A.tab_host);
+    if (A.graph_exec) hipGraphExecDestroy(A.graph_exec);
+    if (A.done) hipEventDestroy(A.done);
+  }
   if (net->cap_stream) hipStreamDestroy(net->cap_stream);
-  if (net->done) hipEventDestroy(net->done);
   for (auto& t : net->timed) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);

@@ -521,6 +521,41 @@ __global__ __launch_bounds__(256) void st_count_flags(const int32_t* __restrict_
   }
 }
 
+// ------------------------------------------------------------------ training batches
+
+// One training batch gathered from device volumes and their teacher maps:
+// block (., b) copies patch b (P x P bytes) and its centred targets
+// ((P-6) x (P-6) floats). Sources are passed by value (at most 64).
+struct GatherSrc {
+  const uint8_t* vol;  // first byte of the patch
+  const float* map;    // first target value
+  int64_t vol_rs;      // bytes per volume row
+  int64_t map_rs;      // floats per map row
+};
+struct GatherArgs {
+  GatherSrc src[64];
+  int batch, P;
+};
+
+__global__ __launch_bounds__(256) void st_gather(GatherArgs a, uint8_t* __restrict__ patches,
+                                                  float* __restrict__ targets) {
+  const int b = blockIdx.y;
+  const GatherSrc g = a.src[b];
+  const int P = a.P, Pt = a.P - 6;
+  const gbyte* vs = gin(g.vol);
+  const gbyte* ms = gin(g.map);
+  gbyte* po = gout(patches) + (int64_t)b * P * P;
+  gbyte* to = gout(targets) + (int64_t)b * Pt * Pt * 4;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < P * P; i += gridDim.x * 256) {
+    const int r = i / P, c = i % P;
+    st<uint8_t>(po + i, ld<uint8_t>(vs + (int64_t)r * g.vol_rs + c));
+  }
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < Pt * Pt; i += gridDim.x * 256) {
+    const int r = i / Pt, c = i % Pt;
+    st<float>(to + (int64_t)i * 4, ld<float>(ms + ((int64_t)r * g.map_rs + c) * 4));
+  }
+}
+
 // ------------------------------------------------------------------ host object
 
 struct Student {
@@ -537,7 +572,12 @@ struct Student {
   // fallback workspace
   void* fb = nullptr;
   size_t fb_bytes = 0;
-  std::vector<int32_t> win_host;
+  // sample-window table: pinned host memory, uploaded asynchronously; rewritten
+  // only after the event recorded behind the previous upload has completed
+  int32_t* win_host = nullptr;
+  size_t win_host_n = 0;
+  hipEvent_t win_done = nullptr;
+  bool win_pending = false;
 };
 
 static int student_ws(Student* s, size_t need) {
@@ -651,10 +691,14 @@ extern "C" int student_create(const double* w_init, int64_t n, int32_t precision
   s->m = s->master + S_NP;
   s->v = s->m + S_NP;
   s->ww = s->v + S_NP;
-  hipMemcpy(s->master, w.data(), S_NP * sizeof(float), hipMemcpyHostToDevice);
-  hipMemset(s->m, 0, 2 * S_NP * sizeof(float));
-  hipLaunchKernelGGL(st_refresh, dim3(4), dim3(256), 0, 0, s->ww, s->master, s->prec == CNN_PREC_BF16 ? 1 : 0);
-  if ((e = hipDeviceSynchronize()) != hipSuccess) {
+  e = hipMemcpy(s->master, w.data(), S_NP * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(s->m, 0, 2 * S_NP * sizeof(float));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(st_refresh, dim3(4), dim3(256), 0, 0, s->ww, s->master, s->prec == CNN_PREC_BF16 ? 1 : 0);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
     hipFree(s->master);
     delete s;
     return hip_fail(e, "student_create");
@@ -671,6 +715,8 @@ extern "C" int student_destroy(cnn_student* h) {
   if (s->master) hipFree(s->master);
   if (s->ws) hipFree(s->ws);
   if (s->fb) hipFree(s->fb);
+  if (s->win_host) hipHostFree(s->win_host);
+  if (s->win_done) hipEventDestroy(s->win_done);
   delete s;
   return CNN_OK;
 }
@@ -682,7 +728,8 @@ extern "C" int student_get_state(cnn_student* h, double* w_out, double* m_out, d
   std::vector<float> buf(3 * S_NP);
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "student_get_state");
-  hipMemcpy(buf.data(), s->master, 3 * S_NP * sizeof(float), hipMemcpyDeviceToHost);
+  if ((e = hipMemcpy(buf.data(), s->master, 3 * S_NP * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "student_get_state: copy");
   for (int i = 0; i < S_NP; ++i) {
     if (w_out) w_out[i] = buf[i];
     if (m_out) m_out[i] = buf[S_NP + i];
@@ -702,11 +749,14 @@ extern "C" int student_set_state(cnn_student* h, const double* w, const double* 
     buf[S_NP + i] = (float)m[i];
     buf[2 * S_NP + i] = (float)v[i];
   }
-  hipDeviceSynchronize();
-  hipMemcpy(s->master, buf.data(), 3 * S_NP * sizeof(float), hipMemcpyHostToDevice);
-  hipLaunchKernelGGL(st_refresh, dim3(4), dim3(256), 0, 0, s->ww, s->master, s->prec == CNN_PREC_BF16 ? 1 : 0);
-  s->step = step;
   hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(s->master, buf.data(), 3 * S_NP * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(st_refresh, dim3(4), dim3(256), 0, 0, s->ww, s->master, s->prec == CNN_PREC_BF16 ? 1 : 0);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) s->step = step;
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "student_set_state");
   return CNN_OK;
 }
@@ -780,7 +830,7 @@ static uint64_t mix64(uint64_t x) {
 
 extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const uint8_t* vol, const int64_t dims[3],
                                            float* prob, float tau, int32_t tile, int32_t n_samples, uint64_t seed,
-                                           int32_t* stats, void* stream) {
+                                           int32_t* stats, int32_t* flags_out, void* stream) {
   clear_error();
   if (!h || !th || !vol || !dims || !prob) return fail(CNN_EINVAL, "student_infer_with_fallback: null argument");
   Student* s = reinterpret_cast<Student*>(h);
@@ -797,30 +847,42 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int Ho = (int)(H - R), Wo = (int)(W - R);
   const int crop = (R - 6) / 2;
-  // 1) student everywhere, in the teacher's output frame
-  rc = student_launch(s, vol, Z, H, W, prob, Wo, (int64_t)Ho * Wo, Ho, Wo, crop, st);
-  if (rc) return rc;
-  // 2) seeded sample windows per tile (positions do not depend on the data)
   const int ty = (Ho + tile - 1) / tile, tx = (Wo + tile - 1) / tile;
   const int64_t ntile = Z * ty * tx;
   if (ntile > (1 << 24)) return fail(CNN_EINVAL, "fallback: too many tiles");
-  s->win_host.assign((size_t)ntile * n_samples * 5, 0);
-  std::vector<Region> sample_regs, rerun_regs;
+  // workspace: teacher samples, window table, flags (grown before anything is enqueued)
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t sz_samp = al((size_t)ntile * n_samples * 256 * 4), sz_win = al(s->win_host.size() * 4),
-               sz_flag = al((size_t)ntile * 4);
+  const size_t nwin = (size_t)ntile * n_samples * 5;
+  const size_t sz_samp = al((size_t)ntile * n_samples * 256 * 4), sz_win = al(nwin * 4), sz_flag = al((size_t)ntile * 4);
   const size_t need = sz_samp + sz_win + sz_flag;
+  hipError_t e;
   if (need > s->fb_bytes) {
-    hipDeviceSynchronize();
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "fallback: workspace grow");
     if (s->fb) hipFree(s->fb);
     s->fb = nullptr;
     s->fb_bytes = 0;
     if (hipMalloc(&s->fb, need) != hipSuccess) return fail(CNN_ENOMEM, "fallback workspace");
     s->fb_bytes = need;
   }
+  // the pinned window table is rewritten only after the previous call's upload has run
+  if (s->win_pending) {
+    if ((e = hipEventSynchronize(s->win_done)) != hipSuccess) return hip_fail(e, "fallback: previous window upload");
+    s->win_pending = false;
+  }
+  if (s->win_host_n < nwin) {
+    if (s->win_host) hipHostFree(s->win_host);
+    s->win_host = nullptr;
+    s->win_host_n = 0;
+    if (hipHostMalloc((void**)&s->win_host, nwin * 4) != hipSuccess) return fail(CNN_ENOMEM, "fallback: pinned window table");
+    s->win_host_n = nwin;
+  }
+  if (!s->win_done && (e = hipEventCreateWithFlags(&s->win_done, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "fallback: hipEventCreate");
   float* samples = reinterpret_cast<float*>(s->fb);
   int32_t* win_dev = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(s->fb) + sz_samp);
   int32_t* flags = reinterpret_cast<int32_t*>(reinterpret_cast<unsigned char*>(s->fb) + sz_samp + sz_win);
+  // 1) seeded sample windows per tile (positions do not depend on the data)
+  std::vector<Region> sample_regs, rerun_regs;
   for (int64_t z = 0; z < Z; ++z)
     for (int a = 0; a < ty; ++a)
       for (int b = 0; b < tx; ++b) {
@@ -832,7 +894,7 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
           const uint64_t r = mix64(seed ^ mix64((uint64_t)t * 64 + k));
           const int oy = (int)(r % (uint64_t)(th_ - wh + 1));
           const int ox = (int)((r >> 32) % (uint64_t)(tw_ - wwid + 1));
-          int32_t* w = &s->win_host[((size_t)t * n_samples + k) * 5];
+          int32_t* w = s->win_host + ((size_t)t * n_samples + k) * 5;
           w[0] = (int32_t)z;
           w[1] = y0 + oy;
           w[2] = x0 + ox;
@@ -864,10 +926,6 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
         q.gate = flags + t;
         rerun_regs.push_back(q);
       }
-  hipError_t e;
-  if ((e = hipMemcpyAsync(win_dev, s->win_host.data(), s->win_host.size() * 4, hipMemcpyHostToDevice, st)) !=
-      hipSuccess)
-    return hip_fail(e, "fallback: window upload");
   const size_t nj1 = count_region_jobs(net, sample_regs), nj2 = count_region_jobs(net, rerun_regs);
   rc = arena_reserve(net, nj1 + nj2);
   if (rc) return rc;
@@ -875,19 +933,63 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
   size_t used1 = 0, used2 = 0, ws1 = 0, ws2 = 0;
   rc = plan_regions(net, sample_regs, 0, l1, used1, ws1);
   if (rc) return rc;
-  rc = submit(net, l1, 0, used1, st, false);
+  rc = plan_regions(net, rerun_regs, used1, l2, used2, ws2);
   if (rc) return rc;
-  // 3) per-tile decisions on the device
+  // 2) student everywhere, in the teacher's output frame
+  rc = student_launch(s, vol, Z, H, W, prob, Wo, (int64_t)Ho * Wo, Ho, Wo, crop, st);
+  if (rc) return rc;
+  if ((e = hipMemcpyAsync(win_dev, s->win_host, nwin * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "fallback: window upload");
+  if ((e = hipEventRecord(s->win_done, st)) != hipSuccess) return hip_fail(e, "fallback: hipEventRecord");
+  s->win_pending = true;
+  // 3) teacher on the sample windows, then the per-tile decisions on the device
+  rc = submit(net, l1, 0, used1 + used2, st, false);
+  if (rc) return rc;
   hipLaunchKernelGGL(st_flag_tiles, dim3((unsigned)ntile), dim3(256), 0, st, prob, (int64_t)Wo, (int64_t)Ho * Wo,
                      samples, win_dev, n_samples, tau, flags);
   if (stats) hipLaunchKernelGGL(st_count_flags, dim3(1), dim3(256), 0, st, flags, (int)ntile, stats);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "fallback: flag kernels");
-  // 4) teacher re-run of flagged tiles (unflagged tiles are skipped by the gate)
-  rc = plan_regions(net, rerun_regs, used1, l2, used2, ws2);
-  if (rc) return rc;
-  rc = submit(net, l2, used1, used2, st, false);
-  if (rc) return rc;
-  // the host window buffer must outlive the async upload
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "fallback: sync");
+  if (flags_out && (e = hipMemcpyAsync(flags_out, flags, (size_t)ntile * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(e, "fallback: flag copy");
+  // 4) teacher re-run of flagged tiles (unflagged tiles are skipped by the gate);
+  // the job table of both passes went up with the first submission
+  for (const Launch& la : l2) {
+    rc = launch_layer(net, net->layers[la.layer], la.js, la.grid, st);
+    if (rc) return rc;
+  }
+  if ((e = hipEventRecord(net->arena[net->cur].done, st)) != hipSuccess) return hip_fail(e, "fallback: hipEventRecord");
+  return CNN_OK;
+}
+
+extern "C" int student_gather(const cnn_patch_src* src, int32_t batch, int32_t patch, int32_t teacher_R,
+                              uint8_t* patches_out, float* teacher_out, void* stream) {
+  clear_error();
+  if (!src || !patches_out || !teacher_out) return fail(CNN_EINVAL, "student_gather: null argument");
+  if (batch < 1 || batch > 64 || patch < 7 || patch > 4096)
+    return fail(CNN_EINVAL, "student_gather: 1 <= batch <= 64 and 7 <= patch <= 4096 required");
+  if (teacher_R < 6 || (teacher_R - 6) % 2) return fail(CNN_EINVAL, "student_gather: teacher radius even and >= 6");
+  const int m = (teacher_R - 6) / 2;  // centring offset between the two output frames
+  GatherArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.batch = batch;
+  a.P = patch;
+  for (int b = 0; b < batch; ++b) {
+    const cnn_patch_src& q = src[b];
+    if (!q.volume || !q.teacher) return fail(CNN_EINVAL, "student_gather: source " + std::to_string(b) + " is null");
+    if (q.H < teacher_R + 1 || q.W < teacher_R + 1 || q.Z < 1 || q.z < 0 || q.z >= q.Z || q.y < m || q.x < m ||
+        (int64_t)q.y + patch + m > q.H || (int64_t)q.x + patch + m > q.W)
+      return fail(CNN_EINVAL, "student_gather: source " + std::to_string(b) +
+                                  " is outside its volume (origin must lie in [m, side - patch - m], m = (R-6)/2)");
+    const int64_t Hm = q.H - teacher_R, Wm = q.W - teacher_R;
+    a.src[b].vol = q.volume + ((int64_t)q.z * q.H + q.y) * q.W + q.x;
+    a.src[b].map = q.teacher + ((int64_t)q.z * Hm + (q.y - m)) * Wm + (q.x - m);
+    a.src[b].vol_rs = q.W;
+    a.src[b].map_rs = Wm;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int gx = std::max(1, std::min(64, (patch * patch + 4095) / 4096));
+  hipLaunchKernelGGL(st_gather, dim3(gx, batch), dim3(256), 0, st, a, patches_out, teacher_out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "student_gather");
   return CNN_OK;
 }

@@ -11,8 +11,9 @@ Recipe: BCE on soft teacher probabilities, Adam (lr 1e-3, betas 0.9 / 0.999,
 eps 1e-8), batches of 16 patches of 128 x 128 drawn uniformly over (volume,
 slice, origin) with origins in [3, side - 131], targets = the teacher map
 cropped to the student's centred 122 x 122 output (the teacher's receptive
-radius is 12, the student's 6). Only argument marshalling and patch gathering
-happen here; every arithmetic step runs in the library's kernels.
+radius is 12, the student's 6). Only argument marshalling and the seeded draw
+of patch origins happen here; the gather and every arithmetic step run in the
+library's kernels.
 """
 from __future__ import annotations
 
@@ -20,7 +21,7 @@ import time
 
 import numpy as np
 
-from . import (STUDENT_R, Net, Student, cnn_infer, student_create, student_infer,
+from . import (STUDENT_R, Net, Student, cnn_infer, student_create, student_gather, student_infer,
                student_infer_with_fallback, student_train_step)
 
 
@@ -30,8 +31,9 @@ def teacher_maps(teacher: Net, volumes, stream=None):
 
 
 def sample_batch(rng: np.random.Generator, volumes, maps, teacher_R: int, batch: int = 16,
-                 patch: int = 128):
-    """Seeded patch draw: (patches uint8 B x P x P, targets float32 B x (P-6) x (P-6))."""
+                 patch: int = 128, out=None, stream=None):
+    """Seeded patch draw: (patches uint8 B x P x P, targets float32 B x (P-6) x (P-6)),
+    gathered on the device by the library (student_gather) into `out` if given."""
     import torch
     m = (teacher_R - STUDENT_R) // 2  # centring offset between the two output frames
     Z, H, W = volumes[0].shape
@@ -39,10 +41,12 @@ def sample_batch(rng: np.random.Generator, volumes, maps, teacher_R: int, batch:
     z = rng.integers(0, Z, size=batch)
     y = rng.integers(m, H - patch - m + 1, size=batch)
     x = rng.integers(m, W - patch - m + 1, size=batch)
-    po = patch - STUDENT_R
-    pt = torch.stack([volumes[a][b, c:c + patch, d:d + patch] for a, b, c, d in zip(v, z, y, x)])
-    tt = torch.stack([maps[a][b, c - m:c - m + po, d - m:d - m + po] for a, b, c, d in zip(v, z, y, x)])
-    return pt.contiguous(), tt.contiguous()
+    if out is None:
+        dev = volumes[0].device
+        out = (torch.empty((batch, patch, patch), dtype=torch.uint8, device=dev),
+               torch.empty((batch, patch - STUDENT_R, patch - STUDENT_R), dtype=torch.float32, device=dev))
+    srcs = [(volumes[a], maps[a], b, c, d) for a, b, c, d in zip(v, z, y, x)]
+    return student_gather(srcs, patch, teacher_R, out[0], out[1], stream=stream)
 
 
 def train(student: Student, volumes, maps, teacher_R: int, steps: int, *, batch: int = 16,
@@ -55,8 +59,14 @@ def train(student: Student, volumes, maps, teacher_R: int, steps: int, *, batch:
     losses = torch.empty(steps, dtype=torch.float64, device=dev)
     gnorms = torch.empty(steps, dtype=torch.float64, device=dev)
     t0 = time.perf_counter()
+    bufs = None
     for it in range(steps):
-        pt, tt = sample_batch(rng, volumes, maps, teacher_R, batch, patch)
+        # two batch buffers in turn: the gather of step it+1 may run while step it reads its own
+        if bufs is None:
+            bufs = [(torch.empty((batch, patch, patch), dtype=torch.uint8, device=dev),
+                     torch.empty((batch, patch - STUDENT_R, patch - STUDENT_R), dtype=torch.float32, device=dev))
+                    for _ in range(2)]
+        pt, tt = sample_batch(rng, volumes, maps, teacher_R, batch, patch, out=bufs[it % 2], stream=stream)
         student_train_step(student, pt, tt, lr=lr, loss_out=losses[it:it + 1],
                            gnorm_out=gnorms[it:it + 1], stream=stream)
         if log and log_every and (it + 1) % log_every == 0:

@@ -105,3 +105,54 @@ def test_null_handles_are_rejected():
     assert m._lib.cnn_destroy(None) == m.CNN_OK
     assert m._lib.student_train_step(None, None, None, 1, 128, None, None, None, None) == m.CNN_EINVAL
     assert m._lib.cnn_geometry(None, None, None) == m.CNN_EINVAL
+
+
+def test_binding_checks_caller_buffers_before_the_library():
+    """Caller buffers with a wrong dtype, shape or size are rejected by the
+    binding before their pointers reach the library (an undersized or
+    mistyped buffer would otherwise receive out-of-bounds device writes).
+    CPU tensors stand in here: the device check comes last, so a buffer that
+    passes the host-side checks fails only on being a CPU tensor."""
+    torch = pytest.importorskip("torch")
+    import paper_1612_02120_amd as m
+    s = m.Student(None)
+    net = m.Net(None, 12)
+    vol = torch.zeros((2, 40, 50), dtype=torch.uint8)
+    pt = torch.zeros((3, 20, 20), dtype=torch.uint8)
+    tt = torch.zeros((3, 14, 14), dtype=torch.float32)
+
+    def raises(exc, fn, *a, **k):
+        with pytest.raises(exc) as e:
+            fn(*a, **k)
+        return str(e.value)
+
+    # inference outputs: shape and dtype
+    assert "shape" in raises(ValueError, m.cnn_infer, net, vol, out=torch.zeros((2, 28, 37)))
+    assert "float32" in raises(TypeError, m.cnn_infer, net, vol, out=torch.zeros((2, 28, 38), dtype=torch.float64))
+    assert "shape" in raises(ValueError, m.student_infer, s, vol, out=torch.zeros((2, 34, 43)))
+    assert "CUDA" in raises(TypeError, m.student_infer, s, vol, out=torch.zeros((2, 34, 44)))
+    # fallback: out in the teacher frame, stats int32[2], flags int32[tiles]
+    good_out = torch.zeros((2, 28, 38))
+    assert "shape" in raises(ValueError, m.student_infer_with_fallback, s, net, vol, out=torch.zeros((2, 34, 44)))
+    assert "shape" in raises(ValueError, m.student_infer_with_fallback, s, net, vol, out=good_out,
+                             stats=torch.zeros(1, dtype=torch.int32))
+    assert "int32" in raises(TypeError, m.student_infer_with_fallback, s, net, vol, out=good_out,
+                             stats=torch.zeros(2, dtype=torch.int64))
+    assert "shape" in raises(ValueError, m.student_infer_with_fallback, s, net, vol, out=good_out,
+                             stats=torch.zeros(2, dtype=torch.int32), tile=16,
+                             flags=torch.zeros(2 * 2 * 3 - 1, dtype=torch.int32))
+    assert "CUDA" in raises(TypeError, m.student_infer_with_fallback, s, net, vol, out=good_out,
+                            stats=torch.zeros(2, dtype=torch.int32), tile=16,
+                            flags=torch.zeros(2 * 2 * 3, dtype=torch.int32))
+    # training: targets, gradient, FP64 scalars
+    assert "shape" in raises(ValueError, m.student_grad, s, pt, torch.zeros((3, 14, 13)))
+    assert "shape" in raises(ValueError, m.student_grad, s, pt, tt, grad_out=torch.zeros(800))
+    assert "float32" in raises(TypeError, m.student_grad, s, pt, tt, grad_out=torch.zeros(801, dtype=torch.float64))
+    assert "float64" in raises(TypeError, m.student_grad, s, pt, tt, grad_out=torch.zeros(801),
+                               loss_out=torch.zeros(1, dtype=torch.float32))
+    assert "float64" in raises(TypeError, m.student_train_step, s, pt, tt,
+                               loss_out=torch.zeros(1, dtype=torch.float64), gnorm_out=torch.zeros(1))
+    assert "at least" in raises(ValueError, m.student_train_step, s, pt, tt,
+                                loss_out=torch.zeros(0, dtype=torch.float64), gnorm_out=torch.zeros(1, dtype=torch.float64))
+    assert "CUDA" in raises(TypeError, m.student_train_step, s, pt, tt,
+                            loss_out=torch.zeros(1, dtype=torch.float64), gnorm_out=torch.zeros(1, dtype=torch.float64))

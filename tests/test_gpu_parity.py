@@ -128,15 +128,45 @@ def test_batch_matches_per_tile_and_oracle(emcnn, graph):
 
 
 def test_invalid_arguments_leave_stream_untouched(emcnn):
+    """Arguments are validated before anything is enqueued: with per-layer
+    profiling on (every layer launch brackets itself with events), rejected
+    calls record no launch, leave their sentinel outputs untouched, and the
+    stream they were given is idle right after them."""
+    import ctypes
     h = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")
-    small = _dev(np.zeros((1, 12, 40), np.uint8))
-    with pytest.raises(emcnn.CnnError) as ei:
-        emcnn.cnn_infer(h, small, out=torch.empty((1, 0, 28), device="cuda"))
-    assert ei.value.code == emcnn.CNN_EINVAL
+    emcnn.cnn_set_batch_graph(h, False)  # direct launches, which the profiler records
+    emcnn.cnn_profile_read(h)
+    emcnn.cnn_profile(h, True)
+    st = torch.cuda.Stream()
+    sp = st.cuda_stream
+    small = _dev(np.zeros((1, 12, 40), np.uint8))  # H < field of view 13
+    out = torch.full((1, 4, 28), 7.0, device="cuda")
+    dims = (ctypes.c_int64 * 3)(1, 12, 40)
+    lib = emcnn._lib
+    codes = [
+        lib.cnn_infer(h.ptr, emcnn._ptr(small), dims, emcnn._ptr(out), sp),
+        lib.cnn_infer_noalloc(h.ptr, emcnn._ptr(small), dims, emcnn._ptr(out), sp),
+    ]
     t = _dev(np.zeros((1, 30, 30), np.uint8))
+    tout = torch.full((1, 20, 20), 7.0, device="cuda")
     with pytest.raises(emcnn.CnnError) as ei:
-        emcnn.cnn_infer_batch(h, [(t, 5, torch.empty((1, 20, 20), device="cuda"))])  # halo < R/2
-    assert ei.value.code == emcnn.CNN_EINVAL
+        emcnn.cnn_infer_batch(h, [(t, 5, tout)], stream=st)  # halo < R/2
+    codes.append(ei.value.code)
+    s = emcnn.student_create(np.zeros(801), "bf16")
+    big = _dev(np.zeros((1, 60, 60), np.uint8))
+    fout = torch.full((1, 48, 48), 7.0, device="cuda")
+    stats = torch.full((2,), -5, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    with pytest.raises(emcnn.CnnError) as ei:  # tile < 16
+        emcnn.student_infer_with_fallback(s, h, big, tau=0.1, tile=8, out=fout, stats=stats, stream=st)
+    codes.append(ei.value.code)
+    assert st.query()  # nothing pending on the caller's stream
+    assert codes == [emcnn.CNN_EINVAL] * 4
+    ms, n = emcnn.cnn_profile_read(h)
+    assert sum(n) == 0, n
+    torch.cuda.synchronize()
+    assert (out == 7.0).all() and (tout == 7.0).all() and (fout == 7.0).all()
+    assert stats.tolist() == [-5, -5]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2), ("fp8", 6e-2)])

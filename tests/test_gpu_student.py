@@ -165,7 +165,79 @@ def test_fallback_endpoints(emcnn):
     out, st = emcnn.student_infer_with_fallback(z, teacher, vd, tau=0.01, tile=128, n_samples=4, seed=3)
     assert st.tolist()[0] == st.tolist()[1]
     assert torch.equal(out, tmap)
-    # sampled windows agree with the teacher map where they were taken
-    out, st = emcnn.student_infer_with_fallback(s, teacher, vd, tau=0.05, tile=128, n_samples=4, seed=3)
-    flagged = st.tolist()[0]
-    assert 0 <= flagged <= 18
+
+
+@pytest.mark.parametrize("tile,n_samples,seed", [(128, 4, 3), (96, 7, 11)])
+def test_fallback_decisions_match_host_reference(emcnn, tile, n_samples, seed):
+    """Per-tile flags against a host reference: windows placed by the documented
+    splitmix64 rule, flips counted with numpy from the student map (checked
+    against the FP64 reference by test_student_forward_vs_reference) and the FP32
+    teacher map (checked against it by the parity tests), flips > tau * count in
+    float32. Edge tiles are ragged (288 x 268 outputs). One tau equals a full
+    tile's flip fraction exactly: that tile must stay unflagged (the rule is >)."""
+    from tests import fallback_ref as ref
+    vol = em_volume(95, 2, 300, 280)
+    vd = _dev(vol)
+    teacher = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")
+    tmap = emcnn.cnn_infer(teacher, vd)
+    s = emcnn.student_create(random_bias_params(NET_S, 304, 97, sigma=0.1), "bf16")
+    smap = emcnn.student_infer(s, vd)
+    torch.cuda.synchronize()
+    T = tmap.cpu().numpy()
+    S = smap[:, 3:-3, 3:-3].cpu().numpy()
+    Z, Ho, Wo = T.shape
+    wins = ref.tile_windows(Z, Ho, Wo, tile, n_samples, seed)
+    flips, counts = ref.flips_and_counts(S, T, wins)
+    frac = flips / counts
+    ty, tx = emcnn.fallback_tiles(T.shape, tile)
+    assert len(wins) == Z * ty * tx
+    print("flip fractions per tile:", np.round(frac, 3).tolist())
+    assert frac.min() < frac.max()  # the decisions below are not all alike
+    full = np.flatnonzero((counts == n_samples * 256) & (flips > 0))
+    t_eq = int(full[np.argsort(frac[full])[len(full) // 2]])
+    tau_eq = float(np.float32(flips[t_eq]) / np.float32(counts[t_eq]))
+    assert np.float32(tau_eq) * np.float32(counts[t_eq]) == np.float32(flips[t_eq])
+    taus = [0.01, 0.05, 0.25, float(np.median(frac)), tau_eq]
+    mixed = 0
+    for tau in taus:
+        want = ref.decide(flips, counts, tau)
+        got_flags = torch.full((Z * ty * tx,), -1, dtype=torch.int32, device="cuda")
+        out, st = emcnn.student_infer_with_fallback(s, teacher, vd, tau=tau, tile=tile, n_samples=n_samples,
+                                                    seed=seed, flags=got_flags)
+        torch.cuda.synchronize()
+        got = got_flags.cpu().numpy()
+        assert np.array_equal(got, want), (tau, np.flatnonzero(got != want))
+        assert st.tolist() == [int(want.sum()), Z * ty * tx]
+        mixed += 0 < want.sum() < want.size
+        # flagged tiles hold the teacher's map, the others the student's, exactly
+        O = out.cpu().numpy()
+        for t in range(Z * ty * tx):
+            z, a, b = t // (ty * tx), (t // tx) % ty, t % tx
+            sl = (z, slice(a * tile, (a + 1) * tile), slice(b * tile, (b + 1) * tile))
+            assert np.array_equal(O[sl], T[sl] if want[t] else S[sl]), (tau, t)
+    assert ref.decide(flips, counts, tau_eq)[t_eq] == 0
+    assert mixed >= 2
+
+
+def test_student_gather_equals_slicing(emcnn):
+    """The device gather of a training batch equals plain slicing of the
+    volume and of the teacher map centred on the student's outputs."""
+    vols = [_dev(em_volume(5100 + i, 3, 150, 170)) for i in range(2)]
+    maps = [_dev(np.random.default_rng(i).uniform(0, 1, (3, 138, 158)).astype(np.float32)) for i in range(2)]
+    R, P, m = 12, 40, 3
+    rng = np.random.default_rng(4)
+    srcs = []
+    for b in range(9):
+        a = int(rng.integers(0, 2))
+        srcs.append((vols[a], maps[a], int(rng.integers(0, 3)), int(rng.integers(m, 150 - P - m + 1)),
+                     int(rng.integers(m, 170 - P - m + 1))))
+    srcs.append((vols[1], maps[1], 2, 150 - P - m, 170 - P - m))  # last valid origin
+    pt = torch.zeros((len(srcs), P, P), dtype=torch.uint8, device="cuda")
+    tt = torch.zeros((len(srcs), P - 6, P - 6), dtype=torch.float32, device="cuda")
+    emcnn.student_gather(srcs, P, R, pt, tt)
+    torch.cuda.synchronize()
+    for b, (v, mp, z, y, x) in enumerate(srcs):
+        assert torch.equal(pt[b], v[z, y:y + P, x:x + P])
+        assert torch.equal(tt[b], mp[z, y - m:y - m + P - 6, x - m:x - m + P - 6])
+    with pytest.raises(emcnn.CnnError):  # origin past the last valid one
+        emcnn.student_gather([(vols[0], maps[0], 0, 150 - P - m + 1, m)], P, R, pt[:1], tt[:1])

@@ -54,9 +54,11 @@ def test_bruteforce_bitwise_net_a_window():
 def _torch_forward(vol, net, params):
     x = torch.from_numpy(vol.astype(np.float64) / 255.0)[:, None]
     off = 0
+    outs = []
     for L in net:
         if L["kind"] == "pool":
             x = torch.nn.functional.max_pool2d(x, 2, stride=1)
+            outs.append(x.numpy())
             continue
         k, ci, co = L["k"], L["cin"], L["cout"]
         nw = co * ci * k * k
@@ -205,15 +207,18 @@ def test_e4m3_encoder_against_torch():
     assert np.array_equal(oracle.e4m3_round(big), np.array([448.0, 448.0, 448.0, -448.0]))
 
 
-def _fake_quant_reference(vol, net, p, mode, scales):
+def _fake_quant_reference(vol, net, p, mode, scales, layers=False):
     """The declared fake-quant forms composed from library primitives (torch
-    float64 conv2d) and the separately pinned encoders."""
+    float64 conv2d) and the separately pinned encoders. layers: also return
+    every layer's output (Z x C x h x w)."""
     x = torch.from_numpy(vol.astype(np.float64))[:, None]  # raw uint8 values
     off, first, ci_idx = 0, True, 0
     nconv = sum(1 for L in net if L["kind"] == "conv")
+    outs = []
     for L in net:
         if L["kind"] == "pool":
             x = torch.nn.functional.max_pool2d(x, 2, stride=1)
+            outs.append(x.numpy())
             continue
         k, ci, co = L["k"], L["cin"], L["cout"]
         nw = co * ci * k * k
@@ -243,6 +248,9 @@ def _fake_quant_reference(vol, net, p, mode, scales):
         elif L["act"] == "sigmoid":
             y = torch.sigmoid(y)
         x = y
+        outs.append(x.numpy())
+    if layers:
+        return x[:, 0].numpy(), outs
     return x[:, 0].numpy()
 
 
@@ -264,3 +272,73 @@ def test_fp8_weight_scale_maps_max_to_448():
     sw = np.abs(w).max(axis=1) / 448.0
     q = oracle.e4m3_round(w / sw[:, None])
     assert q[0, 1] == -448.0 and q[1, 0] == 448.0
+
+
+@pytest.mark.parametrize("mode", ["exact", "bf16", "fp8"])
+def test_fake_quant_trace_and_single_layer(mode):
+    """The per-layer trace in each number format equals the torch composition
+    layer by layer; the single-layer reference (conv_layer) applied to a traced
+    map reproduces the next traced conv; its |product| sums are checked by
+    brute force at sampled outputs."""
+    vol = em_volume(12, 1, 36, 33)
+    p = random_bias_params(NET_B, 200, 13)
+    scales = [None, 0.0049, 0.0053, None]
+    tr = oracle.trace(vol[0], NET_B, p, qmode=mode, act_scales=None if mode == "exact" else scales)
+    if mode == "exact":
+        ref = [a[0] for a in _torch_layers(vol, NET_B, p)]
+    else:
+        ref = [a[0] for a in _fake_quant_reference(vol, NET_B, p, mode, scales, layers=True)[1]]
+    assert len(tr) == len(ref) == len(NET_B)
+    for l, (a, b) in enumerate(zip(tr, ref)):
+        assert a.shape == b.shape, l
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(b).max()), l
+    offs, o = [], 0
+    for L in NET_B:
+        if L["kind"] == "conv":
+            offs.append(o)
+            o += L["cout"] * L["cin"] * L["k"] ** 2 + L["cout"]
+    for ci, (lin, lout) in ((1, (0, 2)), (2, (2, 4))):
+        L = NET_B[lout]
+        nw = L["cout"] * L["cin"] * L["k"] ** 2
+        w, b = p[offs[ci]:offs[ci] + nw], p[offs[ci] + nw:offs[ci] + nw + L["cout"]]
+        out, absum = oracle.conv_layer(tr[lin], w, b, L["k"], pool=True, qmode=mode,
+                                       in_scale=0.0 if mode == "exact" else scales[ci])
+        assert np.abs(np.maximum(out, 0) - tr[lout]).max() <= 1e-12 * max(1.0, np.abs(tr[lout]).max())
+        assert (absum + 1e-12 >= np.abs(out - b[:, None, None])).all()
+        # brute force of the scaled |product| sum at a few outputs
+        a = torch.nn.functional.max_pool2d(torch.from_numpy(tr[lin])[None], 2, stride=1)[0].numpy()
+        W = w.reshape(L["cout"], L["cin"], L["k"], L["k"])
+        if mode == "fp8":
+            sw = np.abs(W).reshape(L["cout"], -1).max(axis=1) / 448.0
+            Wq, aq, osc = oracle.e4m3_round(W / sw[:, None, None, None]), oracle.e4m3_round(a / scales[ci]), scales[ci] * sw
+        elif mode == "bf16":
+            Wq, aq, osc = oracle.bf16_round(W), oracle.bf16_round(a), np.ones(L["cout"])
+        else:
+            Wq, aq, osc = W, a, np.ones(L["cout"])
+        rng = np.random.default_rng(5)
+        for _ in range(6):
+            co = int(rng.integers(0, L["cout"]))
+            y = int(rng.integers(0, out.shape[1]))
+            x = int(rng.integers(0, out.shape[2]))
+            win = aq[:, y:y + L["k"], x:x + L["k"]]
+            assert absum[co, y, x] == pytest.approx(osc[co] * np.abs(Wq[co] * win).sum(), rel=1e-12)
+            assert out[co, y, x] == pytest.approx(b[co] + osc[co] * (Wq[co] * win).sum(), rel=1e-12, abs=1e-12)
+
+
+def _torch_layers(vol, net, params):
+    """Every layer's output of the exact net, composed from torch float64 ops."""
+    x = torch.from_numpy(vol.astype(np.float64) / 255.0)[:, None]
+    off, outs = 0, []
+    for L in net:
+        if L["kind"] == "pool":
+            x = torch.nn.functional.max_pool2d(x, 2, stride=1)
+        else:
+            k, ci, co = L["k"], L["cin"], L["cout"]
+            nw = co * ci * k * k
+            w = torch.from_numpy(params[off:off + nw].reshape(co, ci, k, k))
+            b = torch.from_numpy(params[off + nw:off + nw + co])
+            off += nw + co
+            x = torch.nn.functional.conv2d(x, w, b)
+            x = torch.relu(x) if L["act"] == "relu" else torch.sigmoid(x)
+        outs.append(x.numpy())
+    return outs
