@@ -36,6 +36,7 @@ HBM_GBS = 8000.0
 NET_B_FLOP_PER_VOXEL = 159168
 CONV2_FLOP_PER_POS = 2 * 25 * 48 * 48  # per conv2 output position
 CONV1_FLOP_PER_POS = 2 * 25 * 48  # per conv1 output position
+CONV3_FLOP_PER_POS = 2 * 9 * 48 * 48 + 2 * 48  # per conv3 output position, head included
 STUDENT_FLOP_PER_VOXEL = 2 * (200 + 576 + 8)
 # FastMemb (4x4 convs 1->64, 32->64, 32->64 with max-out to 32, 32->2) per output voxel
 FASTMEMB_FLOP_PER_VOXEL = 2 * 16 * (64 + 32 * 64 + 32 * 64 + 32 * 2)
@@ -137,13 +138,16 @@ def cpu_baseline(vol, net, params, out_vox_unit="voxels/s"):
                       % (n_all, vol.shape[1], vol.shape[2], vox_all, dt_all, threads, vox_one, dt_one, n_o2, dt_o2)}
 
 
-def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args):
+def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args, big):
     """Distil the student (64 volumes of 16 x 512 x 512, Adam lr 1e-3, batch 16 x
-    128^2) from the FP32 net's maps, then time student, student + fallback and
-    the plain net on a 2048^2 slab and report agreement and fallback rate."""
+    128^2; 20k steps, 4k with --quick) from the FP32 net's maps, then on the
+    evaluation volume `big` (the precision volume, 128 x 2048^2 by default) time
+    the student, the plain net in FP32 and BF16, and student + fallback over a
+    grid of fallback tile sizes and thresholds tau, with agreement and fallback
+    rate at each point."""
     from paper_1612_02120_amd import distill
     from synth.nets import NET_S, he_normal_params
-    steps = 20000 if args.full else 4000
+    steps = 4000 if args.quick else 20000
     t0 = time.perf_counter()
     vols = [torch.from_numpy(em_volume(5000 + i, 16, 512, 512)).to(dev) for i in range(64)]
     teacher = emcnn.cnn_create(p, NET_B, "fp32")
@@ -153,11 +157,10 @@ def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del vols, maps
-    Zs = 128 if args.full else 8
-    big = torch.from_numpy(em_volume(3, Zs, 2048, 2048)).to(dev)
+    Zs = big.shape[0]
     tmap = emcnn.cnn_infer(teacher, big)
     b16 = emcnn.cnn_create(p, NET_B, "bf16")
-    nv = Zs * (2048 - teacher.R) ** 2
+    nv = Zs * (big.shape[1] - teacher.R) * (big.shape[2] - teacher.R)
 
     def timed(fn, reps=3):
         fn()
@@ -169,23 +172,62 @@ def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args):
         return (time.perf_counter() - a) / reps
 
     t_s = timed(lambda: emcnn.student_infer(s, big, stream=stream))
+    t32 = timed(lambda: emcnn.cnn_infer(teacher, big, stream=stream))
+    t16 = timed(lambda: emcnn.cnn_infer(b16, big, stream=stream))
+    v32, v16 = nv / t32, nv / t16
+    raw, _, _ = distill.evaluate(s, teacher, big, tmap, tau=1.0, tile=512, n_samples=1, seed=3)
     res = {"workload": "student conv5x5 1->8, conv3x3 8->8, 1x1 sigmoid, BF16; distilled %d steps "
-                       "(64 x 16 x 512^2, batch 16 x 128^2, lr 1e-3) from FP32 net B; eval %d x 2048^2"
-                       % (steps, Zs),
+                       "(64 x 16 x 512^2, batch 16 x 128^2, lr 1e-3) from FP32 net B; eval %d x %d x %d (seed 3)"
+                       % (steps, Zs, big.shape[1], big.shape[2]),
            "train_s": t_train, "final_loss": float(losses[-200:].mean().item()),
            "student_voxels_per_s": nv / t_s,
            "student_tflops": nv * STUDENT_FLOP_PER_VOXEL / t_s / 1e12,
-           "student_mfma_frac": nv * STUDENT_FLOP_PER_VOXEL / t_s / 1e12 / PEAK_TFLOPS["bf16"]}
-    for tau in (0.01, 0.25):
-        r, out, st = distill.evaluate(s, teacher, big, tmap, tau=tau, tile=512, n_samples=4, seed=3)
-        t_f = timed(lambda: emcnn.student_infer_with_fallback(s, teacher, big, tau=tau, stream=stream), reps=2)
-        res["tau_%g" % tau] = dict(r, voxels_per_s=nv / t_f)
-    t32 = timed(lambda: emcnn.cnn_infer(teacher, big, stream=stream))
-    t16 = timed(lambda: emcnn.cnn_infer(b16, big, stream=stream))
-    res["net_b_fp32_voxels_per_s"] = nv / t32
-    res["net_b_bf16_voxels_per_s"] = nv / t16
-    res["bf16_teacher_agreement_with_fp32"] = distill.agreement(emcnn.cnn_infer(b16, big), tmap)
+           "student_mfma_frac": nv * STUDENT_FLOP_PER_VOXEL / t_s / 1e12 / PEAK_TFLOPS["bf16"],
+           "raw_agreement": raw["raw_agreement"],
+           "net_b_fp32_voxels_per_s": v32, "net_b_bf16_voxels_per_s": v16,
+           "bf16_teacher_agreement_with_fp32": distill.agreement(emcnn.cnn_infer(b16, big), tmap)}
+    grid = []
+    for tile in (64, 128, 256, 512):
+        ns = max(1, tile // 64)  # sampled windows grow with the tile
+        for tau in (0.0, 0.01, 0.05, 0.1, 0.25):
+            r, out, st = distill.evaluate(s, teacher, big, tmap, tau=tau, tile=tile, n_samples=ns, seed=3)
+            del out
+            t_f = timed(lambda: emcnn.student_infer_with_fallback(s, teacher, big, tau=tau, tile=tile,
+                                                                  n_samples=ns, seed=3, stream=stream), reps=1)
+            pt = {"tile": tile, "n_samples": ns, "tau": tau, "fallback_rate": r["fallback_rate"],
+                  "agreement": r["agreement"], "voxels_per_s": nv / t_f}
+            grid.append(pt)
+            log("student fallback", json.dumps(pt))
+    res["fallback_grid"] = grid
+    ok = [g for g in grid if g["agreement"] >= 0.99]
+    best = max(ok, key=lambda g: g["voxels_per_s"]) if ok else None
+    res["target_0.99"] = {
+        "met_by": best, "beats_fp32_net_b": bool(best and best["voxels_per_s"] > v32),
+        "beats_bf16_net_b": bool(best and best["voxels_per_s"] > v16),
+        "best_point_any_agreement": max(grid, key=lambda g: g["agreement"] - 1e-12 * g["voxels_per_s"])}
     return res
+
+
+def mfma_ceiling(emcnn, torch, dev):
+    """Measured MFMA throughput of each precision's instruction on random
+    operands (register operands, 8 accumulators per wave, 16 waves per CU),
+    with the shader clock the waves ran at."""
+    rng = np.random.default_rng(7)
+    out = {}
+    for prec in ("fp32", "bf16", "fp8"):
+        ops = rng.integers(0, 256, size=(256 * 2 * 64 * 32,)).astype(np.uint8)
+        if prec == "fp8":
+            ops[ops == 0x7F] = 0x7E  # no NaN codes
+            ops[ops == 0xFF] = 0xFE
+        elif prec == "bf16":
+            ops[1::2] &= 0xBF  # finite bf16 values (exponent below the top half)
+        else:
+            ops[3::4] &= 0xBF
+        tf, mhz = emcnn.cnn_mfma_bench(prec, torch.from_numpy(ops).to(dev), blocks=4096, iters=2048)
+        out[prec] = {"tflops": tf, "frac_of_vendor_peak": tf / PEAK_TFLOPS[prec], "shader_mhz": mhz,
+                     "vendor_peak_tflops": PEAK_TFLOPS[prec]}
+        log("mfma ceiling", prec, json.dumps(out[prec]))
+    return out
 
 
 def main():
@@ -194,8 +236,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="all",
-                    help="all | none | comma list of bf16,fp8,batch,student,fastmemb,fastmemb_bf16")
-    ap.add_argument("--full", action="store_true", help="precision forms on the full 128 x 2048^2 volume")
+                    help="all | none | comma list of mfma,bf16,fp8,batch,student,fastmemb,fastmemb_bf16")
+    ap.add_argument("--quick", action="store_true",
+                    help="smaller secondary forms: precision / student volume 8 x 2048^2, 4k training steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate tile shapes first for the FP32 / BF16 / FP8 volumes "
@@ -271,8 +314,10 @@ def main():
     del out
     forms = {}
     want = set() if args.forms == "none" else (
-        {"bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16"} if args.forms == "all"
+        {"mfma", "bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16"} if args.forms == "all"
         else set(args.forms.split(",")))
+    if "mfma" in want:
+        forms["mfma_ceiling"] = mfma_ceiling(emcnn, torch, dev)
     for fm_prec in ("fp32", "bf16"):
         key = "fastmemb" if fm_prec == "fp32" else "fastmemb_bf16"
         if key not in want or args.no_headline:
@@ -296,13 +341,16 @@ def main():
             "layer_ms": plf[:4], "tiles": emcnn.cnn_describe(hf)}
         log(key, json.dumps(forms[key]))
         del outf, hf
-    if want & {"bf16", "fp8"}:
-        Zp = 128 if args.full else 8
+    volp_dev = None
+    if want & {"bf16", "fp8", "student"}:
+        Zp = 8 if args.quick else 128
         t0 = time.perf_counter()
         volp = em_volume(3, Zp, 2048, 2048)
         log("generated precision volume %s in %.1fs" % ((Zp, 2048, 2048), time.perf_counter() - t0))
         volp_dev = torch.from_numpy(volp).to(dev)
+        del volp
         nv = Zp * (2048 - R) ** 2
+    if want & {"bf16", "fp8"}:
         for prec in ("bf16", "fp8"):
             if prec not in want:
                 continue
@@ -317,15 +365,19 @@ def main():
             if fused:
                 flop2 += Zp * (2048 - 4) ** 2 * CONV1_FLOP_PER_POS
             ach = flop2 / (pl[1] * 1e-3) / 1e12
+            ach3 = Zp * (2048 - 12) ** 2 * CONV3_FLOP_PER_POS / (pl[2] * 1e-3) / 1e12
+            ceil = forms.get("mfma_ceiling", {}).get(prec, {}).get("tflops")
             forms[prec] = {"workload": "net B %s, %d x 2048 x 2048 (seed 3)" % (prec, Zp),
                            "voxels_per_s": nv / (msp * 1e-3), "ms_per_pass": msp,
                            "path_mfma_frac": nv * NET_B_FLOP_PER_VOXEL / (msp * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
                            "conv2_tflops": ach, "conv2_frac": ach / PEAK_TFLOPS[prec],
+                           "conv3_tflops": ach3, "conv3_frac": ach3 / PEAK_TFLOPS[prec],
+                           "conv2_frac_of_measured_ceiling": ach / ceil if ceil else None,
+                           "conv3_frac_of_measured_ceiling": ach3 / ceil if ceil else None,
                            "conv2_kernel_includes_conv1": fused, "layer_ms": pl[:3],
                            "tiles": emcnn.cnn_describe(hp)}
             log(prec, json.dumps(forms[prec]))
             del outp, hp
-        del volp_dev
     if "batch" in want:
         from synth import batch_tiles
         tl = batch_tiles()
@@ -356,26 +408,32 @@ def main():
                 emcnn.cnn_infer_batch(hb, tiles, stream=stream)
             torch.cuda.synchronize()
             msb = (time.perf_counter() - t0) * 1e3 / reps
-            emcnn.cnn_set_batch_graph(hb, False)
-            for (inp, halo, out) in tiles[:4]:
-                emcnn.cnn_infer_batch(hb, [(inp, halo, out)], stream=stream)
+            # per-tile loop: cnn_infer on each tile's input cropped to a halo of R/2
+            # (copied contiguous before timing), one direct launch per layer
+            e = 8 - R // 2
+            cropped = [(inp[:, e:inp.shape[1] - e, e:inp.shape[2] - e].contiguous(), out) for (inp, _, out) in tiles]
+            for (cin_, out) in cropped[:4]:
+                emcnn.cnn_infer(hb, cin_, out=out, stream=stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for (inp, halo, out) in tiles:
-                emcnn.cnn_infer_batch(hb, [(inp, halo, out)], stream=stream)
+            for (cin_, out) in cropped:
+                emcnn.cnn_infer(hb, cin_, out=out, stream=stream)
             torch.cuda.synchronize()
             msl = (time.perf_counter() - t0) * 1e3
+            del cropped
         forms["batch"] = {"workload": "512 tiles, side logU[64,1024], 1-8 slices, halo 8, BF16 net B",
                           "output_voxels": nv, "voxels_per_s_graph": nv / (msb * 1e-3),
                           "ms_graph": msb, "voxels_per_s_per_tile_loop": nv / (msl * 1e-3),
                           "ms_per_tile_loop": msl,
+                          "per_tile_loop": "cnn_infer per tile (input cropped to a halo of R/2), 3 direct "
+                                           "launches per tile, no host waits",
                           "path_mfma_frac": nv * NET_B_FLOP_PER_VOXEL / (msb * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"],
                           "autotuned": not args.no_batch_autotune, "autotune_s": t_tune,
                           "tiles": emcnn.cnn_describe(hb)}
         log("batch", json.dumps(forms["batch"]))
         del tiles, hb
     if "student" in want:
-        forms["student"] = student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args)
+        forms["student"] = student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args, volp_dev)
         log("student", json.dumps(forms["student"]))
     if forms:
         res["forms"] = forms

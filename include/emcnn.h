@@ -207,6 +207,20 @@ int cnn_profile_read(cnn_net* net, double* ms_per_layer, int32_t* launches_per_l
 int cnn_variant_name(const cnn_net* net, int32_t layer, int32_t index, char* buf, int32_t buf_len);
 int cnn_set_variant(cnn_net* net, int32_t layer, const char* name);
 
+/* Diagnostics (layer-by-layer tests): copy the stored output map of executed
+ * layer `layer` (0 = first conv, up to the last body conv before the one that
+ * carries the head) of the most recent cnn_infer on this handle into dst
+ * (device, dst_bytes), in its stored layout: FP32 maps NHWC [z][y][x][c]
+ * float32; BF16 / FP8 maps channel-blocked [z][c/16][y][x][16] bf16 values /
+ * e4m3fn codes (x fastest), before the max filter that the next layer applies.
+ * shape_out (host int64[4]) receives {Z, C, h, w}, also when dst_bytes is too
+ * small (CNN_EINVAL, nothing copied). The last cnn_infer must have
+ * run as one slab (the volume fit the workspace) and the map must be row-major
+ * (not a stride-2 pool net, not a first layer computed inside layer 1);
+ * CNN_EINVAL / CNN_EUNSUPPORTED otherwise. Only enqueues the copy. */
+int cnn_read_activation(cnn_net* net, int32_t layer, void* dst, int64_t dst_bytes, int64_t shape_out[4],
+                        void* stream);
+
 /* Describe the current tile choice (for logs); writes a NUL-terminated string. */
 int cnn_describe(const cnn_net* net, char* buf, int32_t buf_len);
 
@@ -304,6 +318,35 @@ int student_infer_with_fallback(cnn_student* s, cnn_net* teacher, const uint8_t*
                                 const int64_t dims[3], float* prob_out, float tau,
                                 int32_t tile, int32_t n_samples, uint64_t seed,
                                 int32_t* stats_out, int32_t* flags_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics: the matrix-core instructions the conv kernels use, for tests
+ * of their arithmetic and for a measured throughput ceiling.
+ * ---------------------------------------------------------------------- */
+
+/* D = sum over c < chain of A_c B_c for ntiles independent 16 x 16 output
+ * tiles, with the instruction a conv of `precision` uses per operand chunk
+ * (FP32: four 16x16x4 f32 MFMAs; BF16: one 16x16x32 bf16; FP8: one
+ * 16x16x128 f8f6f4 with e4m3fn operands and unit block scales), each step
+ * accumulating onto the previous result from zero, as over a conv's K steps.
+ * a, b: device, ntiles x chain x 64 lanes x 16 bytes (FP8: 32); lane
+ * (g, n) = (lane / 16, lane % 16) holds its k-slot g bytes of row n of A and
+ * column n of B; byte t of a lane's A bytes meets byte t of the matching B
+ * lane, so A_c B_c [m][n] = sum over g, t of A(16 g + m)[t] B(16 g + n)[t].
+ * d: device, ntiles x 64 lanes x 4 float32; lane (g, n) receives D[4g + k][n]
+ * in element k. 1 <= chain <= 64. Only enqueues. */
+int cnn_mfma_probe(int32_t precision, const void* a, const void* b, float* d, int32_t ntiles,
+                   int32_t chain, void* stream);
+
+/* MFMA throughput of `precision`'s instruction: `blocks` workgroups of 4 waves,
+ * each wave running iters x 8 MFMAs on register operands read from ops (device,
+ * at least 256 x 2 x 64 x 32 bytes of the caller's data, e.g. random codes),
+ * after a shorter warm-up launch. Writes the algorithmic TFLOP/s over the
+ * timed launch (HIP events) and the mean shader clock in MHz that the waves
+ * ran at (s_memtime cycles over s_memrealtime's 100 MHz ticks). Synchronous;
+ * allocates its own small result buffers. */
+int cnn_mfma_bench(int32_t precision, int32_t blocks, int32_t iters, const void* ops, double* tflops,
+                   double* mhz, void* stream);
 
 /* Thread-local text of the last error on this thread ("" if none). */
 const char* cnn_last_error(void);

@@ -20,7 +20,7 @@ import numpy as np
 
 from . import build as _build
 
-_KIND = {"conv": 0, "pool": 1, "pool2": 2}
+_KIND = {"conv": 0, "pool": 1, "pool2": 2, "sub2": 3}
 _ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4}
 QMODES = {"exact": 0, "bf16": 1, "fp8": 2}
 
@@ -75,6 +75,10 @@ def _bind(L):
     L.orc_patch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_out_dims.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.orc_forward_full.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     return L
 
 
@@ -94,13 +98,24 @@ def _ptr(a):
 
 def radius(net) -> int:
     """Receptive radius R (FoV = R + 1): r += (k - 1) j and j *= stride over the
-    layers, a 2x2 pool counting as k = 2 ("pool2" has stride 2, "pool" 1)."""
+    layers, a 2x2 pool counting as k = 2 ("pool2" has stride 2, "pool" 1) and a
+    subsample ("sub2") as k = 1 with stride 2."""
     R, j = 0, 1
     for L in net:
-        R += (L["k"] - 1 if L["kind"] == "conv" else 1) * j
-        if L["kind"] == "pool2":
+        R += (L["k"] - 1 if L["kind"] == "conv" else 0 if L["kind"] == "sub2" else 1) * j
+        if L["kind"] in ("pool2", "sub2"):
             j *= 2
     return R
+
+
+def out_dims(net, H, W, full=False):
+    """Dense output dims (Ho, Wo) of an H x W slice: H - R without subsampling;
+    with a subsample, the pruned form's half-resolution map (full: every position)."""
+    Ho, Wo = ctypes.c_int(0), ctypes.c_int(0)
+    if lib().orc_out_dims(_layers(net), len(net), int(H), int(W), 1 if full else 0, ctypes.byref(Ho),
+                          ctypes.byref(Wo)):
+        raise ValueError("net does not fit %d x %d" % (H, W))
+    return Ho.value, Wo.value
 
 
 def patch(img, net, params, y, x):
@@ -128,12 +143,12 @@ def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=
     if vol.ndim == 2:
         vol = vol[None]
     Z, H, W = vol.shape
-    R = radius(net)
+    Ho, Wo = out_dims(net, H, W)
     params = np.ascontiguousarray(params, dtype=np.float64)
     n_conv = sum(1 for L in net if L["kind"] == "conv")
     sc = np.zeros(n_conv) if act_scales is None else np.array(
         [0.0 if s is None else s for s in act_scales], dtype=np.float64)
-    out = np.empty((Z, H - R, W - R), dtype=np.float64)
+    out = np.empty((Z, Ho, Wo), dtype=np.float64)
     lay = _layers(net)
     L = native_lib() if native else lib()
     rc = L.orc_forward(_ptr(vol), Z, H, W, lay, len(net), _ptr(params), QMODES[qmode],
@@ -141,6 +156,23 @@ def forward(vol, net, params, qmode="exact", act_scales=None, threads=0, logits=
                            _ptr(out) if logits else None, int(threads))
     if rc:
         raise ValueError("oracle forward failed (%d)" % rc)
+    return out
+
+
+def forward_full(vol, net, params, threads=0):
+    """The full dense form (exact FP64): a subsampling layer keeps every position
+    and doubles the spacing of the later layers, so output (z, Y, X) is the net
+    on the window at input (Y, X); Z x (H - R) x (W - R)."""
+    vol = np.ascontiguousarray(vol, dtype=np.uint8)
+    if vol.ndim == 2:
+        vol = vol[None]
+    Z, H, W = vol.shape
+    Ho, Wo = out_dims(net, H, W, full=True)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    out = np.empty((Z, Ho, Wo), dtype=np.float64)
+    rc = lib().orc_forward_full(_ptr(vol), Z, H, W, _layers(net), len(net), _ptr(params), _ptr(out), int(threads))
+    if rc:
+        raise ValueError("oracle forward_full failed (%d)" % rc)
     return out
 
 

@@ -31,6 +31,20 @@
  *     one field-of-view window with plain stride-1 convs and stride-2 pools,
  *     which leaves a single output (orc_patch).
  *
+ * Subsampling (Section 2.2, "A subsampling CNN for 3 nm data": a pool layer
+ * of the net is replaced by a subsampling layer, so that the output map has
+ * half the input resolution):
+ *   patch form   s[c][y][x] = a[c][2y][2x]  (stride 2, window 1)
+ *   dense form, pruned (what the GPU computes; the layer must come before any
+ *                stride-2 pool): the map itself is subsampled, a := a[::2, ::2],
+ *                and the later layers run densely on it; output (y, x) is the
+ *                net on the field-of-view window at input (2y, 2x)
+ *   dense form, full (orc_forward_full; the reference the pruned form is pinned
+ *                to): the subsample keeps every position and doubles the spacing
+ *                d like a stride-2 pool without the max, so that output (Y, X)
+ *                is the net on the window at input (Y, X) for every Y, X; the
+ *                pruned output is its every second sample in each direction.
+ *
  * Fake-quant modes mirror the number formats declared by the GPU forms (the
  * paper states no precision; these are readings):
  *   BF16: first conv uses weights bf16((float)(w/255)) against the raw uint8
@@ -53,7 +67,7 @@
 #include <omp.h>
 #endif
 
-enum { ORC_CONV = 0, ORC_POOL = 1, ORC_POOL2 = 2 };
+enum { ORC_CONV = 0, ORC_POOL = 1, ORC_POOL2 = 2, ORC_SUB2 = 3 };
 enum { ORC_ACT_NONE = 0, ORC_ACT_RELU = 1, ORC_ACT_SIGMOID = 2, ORC_ACT_MAXOUT = 3, ORC_ACT_SOFTMAX = 4 };
 enum { ORC_Q_EXACT = 0, ORC_Q_BF16 = 1, ORC_Q_FP8 = 2 };
 
@@ -194,7 +208,8 @@ static int activate(double* o, int Co, int64_t n, int act, double* logit) {
 /* Nets with stride-2 pools, max-out or softmax are defined in exact FP64 only. */
 static int strided_net(const orc_layer* L, int nl) {
   for (int l = 0; l < nl; ++l)
-    if (L[l].kind == ORC_POOL2 || L[l].act == ORC_ACT_MAXOUT || L[l].act == ORC_ACT_SOFTMAX) return 1;
+    if (L[l].kind == ORC_POOL2 || L[l].kind == ORC_SUB2 || L[l].act == ORC_ACT_MAXOUT || L[l].act == ORC_ACT_SOFTMAX)
+      return 1;
   return 0;
 }
 
@@ -211,7 +226,7 @@ static int param_count(const orc_layer* L, int nl) {
 static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
                          const double* params, int qmode, const double* act_scale,
                          double* out_prob, double* out_logit, double** trace,
-                         int32_t* trace_dims) {
+                         int32_t* trace_dims, int full) {
   int C = 1, h = H, w = W;
   int dil = 1; /* spacing of the dense form; doubled by every stride-2 pool */
   if (qmode != ORC_Q_EXACT && strided_net(L, nl)) return -1;
@@ -298,6 +313,20 @@ static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, i
       h -= dil;
       w -= dil;
       if (ly->kind == ORC_POOL2) dil *= 2;
+    } else if (ly->kind == ORC_SUB2 && full) {
+      o = (double*)malloc(sizeof(double) * (size_t)C * h * w);
+      memcpy(o, a, sizeof(double) * (size_t)C * h * w);
+      dil *= 2;
+    } else if (ly->kind == ORC_SUB2) {
+      if (dil != 1) { free(a); return -1; }
+      const int hs = (h + 1) / 2, ws = (w + 1) / 2;
+      o = (double*)malloc(sizeof(double) * (size_t)C * hs * ws);
+      for (int c = 0; c < C; ++c)
+        for (int y = 0; y < hs; ++y)
+          for (int x = 0; x < ws; ++x)
+            o[((int64_t)c * hs + y) * ws + x] = a[((int64_t)c * h + 2 * y) * w + 2 * x];
+      h = hs;
+      w = ws;
     } else {
       free(a);
       return -1;
@@ -324,8 +353,8 @@ static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, i
 int orc_radius(const orc_layer* L, int nl) {
   int R = 0, j = 1;
   for (int l = 0; l < nl; ++l) {
-    R += (L[l].kind == ORC_CONV ? L[l].k - 1 : 1) * j;
-    if (L[l].kind == ORC_POOL2) j *= 2;
+    R += (L[l].kind == ORC_CONV ? L[l].k - 1 : L[l].kind == ORC_SUB2 ? 0 : 1) * j;
+    if (L[l].kind == ORC_POOL2 || L[l].kind == ORC_SUB2) j *= 2;
   }
   return R;
 }
@@ -369,6 +398,14 @@ int orc_patch(const uint8_t* img, int H, int W, const orc_layer* L, int nl, cons
       pool2_stride2(a, C, h, w, o);
       h /= 2;
       w /= 2;
+    } else if (ly->kind == ORC_SUB2) {
+      const int hs = (h + 1) / 2, ws = (w + 1) / 2;
+      o = (double*)malloc(sizeof(double) * (size_t)C * hs * ws);
+      for (int c = 0; c < C; ++c)
+        for (int r = 0; r < hs; ++r)
+          for (int q = 0; q < ws; ++q) o[((int64_t)c * hs + r) * ws + q] = a[((int64_t)c * h + 2 * r) * w + 2 * q];
+      h = hs;
+      w = ws;
     } else {
       free(a);
       return -1;
@@ -383,24 +420,66 @@ int orc_patch(const uint8_t* img, int H, int W, const orc_layer* L, int nl, cons
 }
 
 /* vol: Z x H x W uint8; prob (nullable), logit (nullable): Z x (H-R) x (W-R). */
-int orc_forward(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int nl,
-                const double* params, int qmode, const double* act_scale, double* prob,
-                double* logit, int nthreads) {
+/* Output dims of the dense form for an H x W slice (full: subsampling layers
+ * keep every position). Returns 0, or -1 if the net does not fit. */
+int orc_out_dims(const orc_layer* L, int nl, int H, int W, int full, int* Ho, int* Wo) {
+  int h = H, w = W, dil = 1;
+  for (int l = 0; l < nl; ++l) {
+    if (L[l].kind == ORC_CONV) {
+      h -= (L[l].k - 1) * dil;
+      w -= (L[l].k - 1) * dil;
+    } else if (L[l].kind == ORC_POOL || L[l].kind == ORC_POOL2) {
+      h -= dil;
+      w -= dil;
+      if (L[l].kind == ORC_POOL2) dil *= 2;
+    } else if (L[l].kind == ORC_SUB2) {
+      if (full) {
+        dil *= 2;
+      } else {
+        if (dil != 1) return -1;
+        h = (h + 1) / 2;
+        w = (w + 1) / 2;
+      }
+    } else {
+      return -1;
+    }
+    if (h < 1 || w < 1) return -1;
+  }
+  *Ho = h;
+  *Wo = w;
+  return 0;
+}
+
+static int forward_all(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int nl, const double* params,
+                       int qmode, const double* act_scale, double* prob, double* logit, int nthreads, int full) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
   (void)nthreads;
 #endif
-  int R = orc_radius(L, nl);
-  int Ho = H - R, Wo = W - R;
-  if (Ho < 1 || Wo < 1) return -1;
+  int Ho = 0, Wo = 0;
+  if (orc_out_dims(L, nl, H, W, full, &Ho, &Wo)) return -1;
   for (int z = 0; z < Z; ++z) {
     int rc = forward_slice(vol + (int64_t)z * H * W, H, W, L, nl, params, qmode, act_scale,
                            prob ? prob + (int64_t)z * Ho * Wo : NULL,
-                           logit ? logit + (int64_t)z * Ho * Wo : NULL, NULL, NULL);
+                           logit ? logit + (int64_t)z * Ho * Wo : NULL, NULL, NULL, full);
     if (rc) return rc;
   }
   return 0;
+}
+
+/* Dense output of every slice (Z x Ho x Wo, orc_out_dims; H - R for nets
+ * without subsampling). */
+int orc_forward(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int nl,
+                const double* params, int qmode, const double* act_scale, double* prob,
+                double* logit, int nthreads) {
+  return forward_all(vol, Z, H, W, L, nl, params, qmode, act_scale, prob, logit, nthreads, 0);
+}
+
+/* The full dense form (subsampling layers keep every position), exact FP64. */
+int orc_forward_full(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int nl, const double* params,
+                     double* prob, int nthreads) {
+  return forward_all(vol, Z, H, W, L, nl, params, ORC_Q_EXACT, NULL, prob, NULL, nthreads, 1);
 }
 
 /* Every layer's output for one slice; bufs[l] must hold dims given by a first
@@ -408,7 +487,7 @@ int orc_forward(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int
 int orc_trace(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
               const double* params, int qmode, const double* act_scale, int32_t* dims, double** bufs) {
   double** tr = (double**)calloc(nl, sizeof(double*));
-  int rc = forward_slice(img, H, W, L, nl, params, qmode, act_scale, NULL, NULL, tr, dims);
+  int rc = forward_slice(img, H, W, L, nl, params, qmode, act_scale, NULL, NULL, tr, dims, 0);
   for (int l = 0; l < nl; ++l) {
     if (bufs && tr[l])
       memcpy(bufs[l], tr[l], sizeof(double) * (size_t)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2]);

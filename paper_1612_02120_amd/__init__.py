@@ -60,7 +60,7 @@ EXPORTS = [
     "student_destroy", "student_get_state", "student_set_state", "student_grad",
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
     "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
-    "cnn_infer_noalloc", "student_gather",
+    "cnn_infer_noalloc", "student_gather", "cnn_read_activation", "cnn_mfma_probe", "cnn_mfma_bench",
 ]
 
 
@@ -75,6 +75,9 @@ def _load():
         "cnn_geometry": [vp, vp, vp],
         "cnn_infer": [vp, vp, vp, vp, vp],
         "cnn_infer_noalloc": [vp, vp, vp, vp, vp],
+        "cnn_read_activation": [vp, i32, vp, i64, vp, vp],
+        "cnn_mfma_probe": [i32, vp, vp, vp, i32, i32, vp],
+        "cnn_mfma_bench": [i32, i32, i32, vp, vp, vp, vp],
         "cnn_infer_batch": [vp, vp, i32, vp],
         "cnn_autotune": [vp, i64, i64, ctypes.c_char_p, vp],
         "cnn_describe": [vp, ctypes.c_char_p, i32],
@@ -175,9 +178,10 @@ def radius_of(net) -> int:
 class Net:
     """Owning handle of a cnn_net."""
 
-    def __init__(self, ptr, R):
+    def __init__(self, ptr, R, precision=0):
         self.ptr = ptr
         self.R = R
+        self.precision = precision
 
     def __del__(self):
         if getattr(self, "ptr", None) and _lib is not None:
@@ -209,7 +213,7 @@ def cnn_create(weights, net, precision="fp32", act_scales=None) -> Net:
                            ctypes.byref(out)), "cnn_create")
     R = ctypes.c_int32()
     _check(_lib.cnn_geometry(out, ctypes.byref(R), None), "cnn_geometry")
-    return Net(out, R.value)
+    return Net(out, R.value, PRECISIONS[precision])
 
 
 def cnn_destroy(net: Net):
@@ -284,6 +288,57 @@ def cnn_set_batch_graph(net: Net, enable: bool):
 
 def cnn_set_workspace_limit(net: Net, nbytes: int):
     _check(_lib.cnn_set_workspace_limit(net.ptr, int(nbytes)), "cnn_set_workspace_limit")
+
+
+def cnn_read_activation(net: Net, layer: int, stream=None):
+    """Stored output map of executed layer `layer` from the last cnn_infer, as a
+    CUDA tensor in the stored layout (FP32: Z x h x w x C float32; BF16 / FP8:
+    Z x C/16 x h x w x 16 bfloat16 / uint8 e4m3fn codes) and its (Z, C, h, w)."""
+    import torch
+    dt = {0: torch.float32, 1: torch.bfloat16, 2: torch.uint8}
+    shape = (ctypes.c_int64 * 4)()
+    # first call with a one-byte buffer only reports the shape (and fails on size)
+    probe = torch.empty(1, dtype=torch.uint8, device="cuda")
+    _lib.cnn_read_activation(net.ptr, int(layer), _ptr(probe), 0, shape, _stream(stream))
+    Z, C, h, w = (int(v) for v in shape)
+    if Z == 0:
+        _check(_lib.cnn_read_activation(net.ptr, int(layer), _ptr(probe), 0, shape, _stream(stream)),
+               "cnn_read_activation")
+    prec = net.precision
+    out = torch.empty((Z, h, w, C) if prec == 0 else (Z, C // 16, h, w, 16), dtype=dt[prec], device="cuda")
+    _check(_lib.cnn_read_activation(net.ptr, int(layer), _ptr(out), out.numel() * out.element_size(), shape,
+                                    _stream(stream)), "cnn_read_activation")
+    return out, (Z, C, h, w)
+
+
+def cnn_mfma_probe(precision, a, b, chain=1, stream=None):
+    """D of ntiles 16 x 16 MFMA tiles, each accumulated over `chain` operand
+    tiles (include/emcnn.h, cnn_mfma_probe): a, b are uint8 CUDA tensors
+    (ntiles * chain) x 64 x 16 (FP8: x 32) holding each lane's operand bytes;
+    returns float32 ntiles x 64 x 4 (lane (g, n): D[4g + k][n])."""
+    import torch
+    ch = 32 if precision == "fp8" else 16
+    n = a.shape[0]
+    if n % chain:
+        raise ValueError("the operand tiles must be a multiple of chain")
+    _check_buf(a, torch.uint8, "a", shape=(n, 64, ch))
+    _check_buf(b, torch.uint8, "b", shape=(n, 64, ch))
+    d = torch.empty((n // chain, 64, 4), dtype=torch.float32, device=a.device)
+    _on_device(a=a, b=b)
+    _check(_lib.cnn_mfma_probe(PRECISIONS[precision], _ptr(a), _ptr(b), _ptr(d), n // chain, int(chain),
+                               _stream(stream)), "cnn_mfma_probe")
+    return d
+
+
+def cnn_mfma_bench(precision, ops, blocks=2048, iters=4096, stream=None):
+    """(TFLOP/s, shader MHz) of the precision's MFMA on register operands from ops."""
+    import torch
+    _check_buf(ops, torch.uint8, "ops", min_numel=256 * 2 * 64 * 32)
+    _on_device(ops=ops)
+    tf, mhz = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.cnn_mfma_bench(PRECISIONS[precision], int(blocks), int(iters), _ptr(ops), ctypes.byref(tf),
+                               ctypes.byref(mhz), _stream(stream)), "cnn_mfma_bench")
+    return tf.value, mhz.value
 
 
 def cnn_variant_names(net: Net, layer: int):

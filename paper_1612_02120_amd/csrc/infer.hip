@@ -208,6 +208,11 @@ int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, fl
   unsigned char* buf0 = reinterpret_cast<unsigned char*>(net->ws);
   unsigned char* buf1 = buf0 + zs * b0;
   const int64_t Ho = H - net->R, Wo = W - net->R;
+  net->last_Z = Z;
+  net->last_H = H;
+  net->last_W = W;
+  net->last_zslab = zs;
+  net->last_half = zs * b0;
   for (int64_t z0 = 0; z0 < Z; z0 += zs) {
     const int zc = (int)std::min<int64_t>(zs, Z - z0);
     rc = run_region(net, vol + z0 * H * W, W, H * W, zc, (int)H, (int)W, prob + z0 * Ho * Wo, Wo, Ho * Wo, buf0, buf1,
@@ -584,6 +589,32 @@ extern "C" int cnn_infer_noalloc(cnn_net* h, const uint8_t* vol, const int64_t d
       if (rc) return rc;
     }
   }
+  return CNN_OK;
+}
+
+extern "C" int cnn_read_activation(cnn_net* h, int32_t layer, void* dst, int64_t dst_bytes, int64_t* shape,
+                                   void* stream) {
+  clear_error();
+  if (!h || !dst || !shape) return fail(CNN_EINVAL, "cnn_read_activation: null argument");
+  Net* net = reinterpret_cast<Net*>(h);
+  const int nl = (int)net->layers.size();
+  if (layer < 0 || layer >= nl - 1) return fail(CNN_EINVAL, "cnn_read_activation: layer must be a stored map");
+  if (net->last_Z < 1 || net->last_zslab < net->last_Z)
+    return fail(CNN_EINVAL, "cnn_read_activation: the last cnn_infer did not run as a single slab");
+  const ExecLayer& L = net->layers[layer];
+  if (L.out_lg != 0 || (layer == 0 && first_fused(net)))
+    return fail(CNN_EUNSUPPORTED, "cnn_read_activation: the map is not stored row-major");
+  const Dims d = layer_dims(net, (int)net->last_H, (int)net->last_W);
+  const int64_t C = stored_channels(L), hh = d.hout[layer], ww = d.wout[layer];
+  const int64_t bytes = net->last_Z * C * hh * ww * act_bytes_of(net->prec);
+  shape[0] = net->last_Z;
+  shape[1] = C;
+  shape[2] = hh;
+  shape[3] = ww;
+  if (dst_bytes < bytes) return fail(CNN_EINVAL, "cnn_read_activation: dst holds fewer than " + std::to_string(bytes) + " bytes");
+  const unsigned char* src = reinterpret_cast<const unsigned char*>(net->ws) + (layer % 2 ? net->last_half : 0);
+  const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "cnn_read_activation");
   return CNN_OK;
 }
 

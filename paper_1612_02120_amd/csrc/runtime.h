@@ -73,6 +73,10 @@ struct Net {
   Arena arena[2];
   int cur = 0;  // arena of the submission being planned
   hipStream_t cap_stream = nullptr;
+  // geometry of the last run_volume (for cnn_read_activation): dims, slices per
+  // slab and the byte offset of the odd-layer half of the workspace
+  int64_t last_Z = 0, last_H = 0, last_W = 0, last_zslab = 0;
+  size_t last_half = 0;
   int use_graph = 1;
   // optional per-layer timing: events recorded on the launch stream around
   // every layer kernel while enabled

@@ -17,7 +17,8 @@ dense output by replacing pooling with stride-1 max-filtering (Section 2.2,
 
 A layer is a dict: ``{"kind": "conv", "k", "cin", "cout", "act"}`` with act in
 {"none", "relu", "sigmoid", "maxout", "softmax"}, or ``{"kind": "pool"}``
-(2x2 window, stride 1) or ``{"kind": "pool2"}`` (2x2 window, stride 2).
+(2x2 window, stride 1), ``{"kind": "pool2"}`` (2x2 window, stride 2) or
+``{"kind": "sub2"}`` (keep every second pixel in each direction).
 
 Parameter vectors are float64, conv layers in order, each as W[cout][cin][k][k]
 (C order) followed by b[cout].
@@ -52,8 +53,19 @@ NET_S = [_conv(5, 1, 8, "relu"), _conv(3, 8, 8, "relu"), _conv(1, 8, 1, "sigmoid
 NET_FM = [_conv(4, 1, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"), POOL2,
           _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 2, "softmax")]
 
-NETS = {"A": NET_A, "B": NET_B, "S": NET_S, "FM": NET_FM}
-WEIGHT_SEEDS = {"A": 100, "B": 200, "S": 300, "FM": 400}
+# FastMemb_ss (Section 2.2, "A subsampling CNN for 3 nm data"), under the
+# reading stated in the design notes: FastMemb_3nm is FastMemb with one more
+# {stride-2 pool, conv(4, 32 -> 64, max-out)} pair, and FastMemb_ss replaces its
+# first (highest-resolution) stride-2 pool by a 2x subsample, so that 3 nm input
+# gives a 6 nm map. Field of view 108 at 3 nm.
+SUB2 = {"kind": "sub2"}
+NET_FM3 = [_conv(4, 1, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"),
+           POOL2, _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 2, "softmax")]
+NET_FMSS = [_conv(4, 1, 64, "maxout"), SUB2, _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"),
+            POOL2, _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 2, "softmax")]
+
+NETS = {"A": NET_A, "B": NET_B, "S": NET_S, "FM": NET_FM, "FMSS": NET_FMSS, "FM3": NET_FM3}
+WEIGHT_SEEDS = {"A": 100, "B": 200, "S": 300, "FM": 400, "FMSS": 410, "FM3": 420}
 CALIBRATION_SEED = 99
 CALIBRATION_SHAPE = (1, 256, 256)
 
