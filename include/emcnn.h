@@ -21,10 +21,16 @@
  *    surface at the caller's next synchronisation of that stream.
  *  - A handle owns device workspace: do not use one handle on two streams
  *    concurrently.
- *  - Dense geometry: a net with receptive radius R (sum of k-1 over convs plus
- *    1 per 2x2/s1 max filter; field of view R+1) maps a Z x H x W volume to a
- *    Z x (H-R) x (W-R) float32 map, C order; output (z, y, x) is centred on
- *    input (z, y + R/2, x + R/2). Slices are independent (2-D nets).
+ *  - Dense geometry: a net with receptive radius R (r += (k-1) j over the
+ *    layers, a 2x2 pool counting as k = 2, a subsample as k = 1, with j the
+ *    input spacing, doubled after every stride-2 layer; field of view R+1)
+ *    maps a Z x H x W volume to a Z x (H-R) x (W-R) float32 map, C order;
+ *    output (z, y, x) is the net on the field-of-view window at input (z, y, x),
+ *    centred on (z, y + R/2, x + R/2). A net with a 2x subsample
+ *    (CNN_LAYER_SUBSAMPLE2) outputs every second of those rows and columns:
+ *    Z x Ho x Wo with Ho = (H - R - 1) / 2 + 1, output (z, y, x) being the
+ *    window at input (z, 2y, 2x) (cnn_output_dims). Slices are independent
+ *    (2-D nets).
  *  - Input scaling: the network sees V/255; the library folds 1/255 into the
  *    first convolution.
  */
@@ -43,7 +49,12 @@ extern "C" {
 #define CNN_EHIP (-3)         /* a HIP runtime call failed (text in cnn_last_error) */
 #define CNN_EUNSUPPORTED (-4) /* valid request outside what the kernels implement */
 
-enum cnn_layer_kind { CNN_LAYER_CONV = 0, CNN_LAYER_MAXPOOL = 1, CNN_LAYER_MAXPOOL_S2 = 2 };
+enum cnn_layer_kind {
+  CNN_LAYER_CONV = 0,
+  CNN_LAYER_MAXPOOL = 1,
+  CNN_LAYER_MAXPOOL_S2 = 2,
+  CNN_LAYER_SUBSAMPLE2 = 3 /* keep every second row and column (window 1, stride 2) */
+};
 enum cnn_act {
   CNN_ACT_NONE = 0,
   CNN_ACT_RELU = 1,
@@ -93,7 +104,12 @@ typedef struct cnn_net cnn_net;
  * conv(k=4, 1 -> 64, MAXOUT), then
  * one or more pairs { MAXPOOL_S2, conv(k=4, 32 -> 64, MAXOUT) }, then
  * MAXPOOL_S2 and conv(k=4, 32 -> 2, SOFTMAX); no other transfer function.
- * FastMemb itself has two inner pairs: field of view 53 (R = 52).
+ * FastMemb itself has two inner pairs: field of view 53 (R = 52). The first
+ * conv may be followed by SUBSAMPLE2 and a conv(k=4, 32 -> 64, MAXOUT) without
+ * a pool before the pairs (FastMemb_ss, Section 2.2, "A subsampling CNN for
+ * 3 nm data": a 3 nm stack gives a 6 nm map); only the kept fragment is
+ * computed: the first conv at every second row and column, the rest densely
+ * on that half-resolution map.
  * weights: host float64, for each conv in order W[cout][cin][k][k] (C order)
  *   followed by b[cout]; n_weights must equal that total. Copied, then packed
  *   and quantised once here:
@@ -121,11 +137,17 @@ int cnn_destroy(cnn_net* net);
 /* Receptive radius R and field of view R+1 (either pointer may be NULL). */
 int cnn_geometry(const cnn_net* net, int32_t* R, int32_t* fov);
 
+/* Output dims of an H x W slice: H - R and W - R, or for a net with a 2x
+ * subsample (H - R - 1) / 2 + 1 and (W - R - 1) / 2 + 1. CNN_EINVAL if H or W
+ * is below the field of view. */
+int cnn_output_dims(const cnn_net* net, int64_t H, int64_t W, int64_t* Ho, int64_t* Wo);
+
 /* Dense inference of a whole volume (Section 2.2: every pixel label in one
  * pass, no per-patch recomputation).
  * volume_u8: device, Z x H x W uint8, C order (x fastest).
  * dims: host {Z, H, W}; H and W must be >= R+1, Z >= 1, each < 2^30.
- * prob_out: device, Z x (H-R) x (W-R) float32, fully overwritten.
+ * prob_out: device, Z x Ho x Wo float32 (cnn_output_dims; Z x (H-R) x (W-R)
+ * for nets without a subsample), fully overwritten.
  * Grows the handle's workspace with hipMalloc when needed (the only allocation
  * it may make). */
 int cnn_infer(cnn_net* net, const uint8_t* volume_u8, const int64_t dims[3], float* prob_out,

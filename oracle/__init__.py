@@ -75,6 +75,8 @@ def _bind(L):
     L.orc_patch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_watershed.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                ctypes.c_void_p]
     L.orc_out_dims.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.orc_forward_full.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -261,3 +263,17 @@ def sigmoid(t: float) -> float:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def watershed(prob, t_seed):
+    """3-D watershed by steepest descent with seeded minima (see emcnn_oracle.c):
+    int32 labels of a Z x H x W float32 probability map."""
+    p = np.ascontiguousarray(prob, dtype=np.float32)
+    if p.ndim == 2:
+        p = p[None]
+    Z, H, W = p.shape
+    lab = np.empty((Z, H, W), dtype=np.int32)
+    rc = lib().orc_watershed(_ptr(p), Z, H, W, float(np.float32(t_seed)), _ptr(lab))
+    if rc:
+        raise ValueError("oracle watershed failed (%d)" % rc)
+    return lab

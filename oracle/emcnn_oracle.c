@@ -682,3 +682,86 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ---------------- 3-D watershed (Section 2.1, over-segmentation) ----------------
+ *
+ * The stage after the membrane map: a 3-D watershed over the probability map
+ * (membranes high, cell interiors low) yields an over-segmentation. The paper
+ * names the algorithm only; the reading implemented here is the watershed by
+ * steepest descent ("drop of water") with seeded minima, which has one result:
+ *   order   u < v iff p[u] < p[v], or p[u] == p[v] and index(u) < index(v),
+ *           index = (z H + y) W + x (a total order: ties broken by index)
+ *   seeds   S = { v : p[v] < t }; its 6-connected components, each labelled
+ *           1 + the least index in it
+ *   descent next(v) = v for v in S, else the least (in the order) of v and
+ *           its 6-neighbours inside the volume; following next from v ends at
+ *           a fixed point r(v) (the order strictly decreases along the way)
+ *   label   the label of r(v)'s seed component if r(v) is in S, else
+ *           1 + index(r(v)) (a local minimum that is not a seed)
+ * p: Z x H x W float32 (finite values), labels: int32 of the same size;
+ * Z H W < 2^31 - 1. Returns 0, -1 for bad sizes, -2 if out of memory. */
+int orc_watershed(const float* p, int Z, int H, int W, float t, int32_t* label) {
+  if (Z < 1 || H < 1 || W < 1 || (int64_t)Z * H * W >= 2147483647LL) return -1;
+  const int64_t N = (int64_t)Z * H * W, HW = (int64_t)H * W;
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * N);
+  int32_t* next = (int32_t*)malloc(sizeof(int32_t) * N);
+  if (!queue || !next) {
+    free(queue);
+    free(next);
+    return -2;
+  }
+  for (int64_t v = 0; v < N; ++v) label[v] = 0;
+  /* seed components, breadth first from each unlabelled seed in index order:
+     the start is the least index of its component */
+  for (int64_t v0 = 0; v0 < N; ++v0) {
+    if (!(p[v0] < t) || label[v0]) continue;
+    int64_t head = 0, tail = 0;
+    queue[tail++] = (int32_t)v0;
+    label[v0] = (int32_t)(v0 + 1);
+    while (head < tail) {
+      const int64_t v = queue[head++];
+      const int z = (int)(v / HW), y = (int)((v / W) % H), x = (int)(v % W);
+      const int64_t nb[6] = {z > 0 ? v - HW : -1, z < Z - 1 ? v + HW : -1, y > 0 ? v - W : -1,
+                             y < H - 1 ? v + W : -1, x > 0 ? v - 1 : -1, x < W - 1 ? v + 1 : -1};
+      for (int k = 0; k < 6; ++k) {
+        const int64_t u = nb[k];
+        if (u >= 0 && p[u] < t && !label[u]) {
+          label[u] = (int32_t)(v0 + 1);
+          queue[tail++] = (int32_t)u;
+        }
+      }
+    }
+  }
+  /* descent pointers */
+  for (int64_t v = 0; v < N; ++v) {
+    if (p[v] < t) {
+      next[v] = (int32_t)v;
+      continue;
+    }
+    const int z = (int)(v / HW), y = (int)((v / W) % H), x = (int)(v % W);
+    const int64_t nb[6] = {z > 0 ? v - HW : -1, z < Z - 1 ? v + HW : -1, y > 0 ? v - W : -1,
+                           y < H - 1 ? v + W : -1, x > 0 ? v - 1 : -1, x < W - 1 ? v + 1 : -1};
+    int64_t best = v;
+    for (int k = 0; k < 6; ++k) {
+      const int64_t u = nb[k];
+      if (u >= 0 && (p[u] < p[best] || (p[u] == p[best] && u < best))) best = u;
+    }
+    next[v] = (int32_t)best;
+  }
+  /* roots: follow next to its fixed point; label[] of a resolved voxel is
+     final (seeds already hold theirs), so a walk stops at the first one */
+  for (int64_t v0 = 0; v0 < N; ++v0) {
+    if (label[v0]) continue;
+    int64_t n = 0, v = v0;
+    while (!label[v] && next[v] != v) {
+      queue[n++] = (int32_t)v;
+      v = next[v];
+    }
+    const int32_t lab = label[v] ? label[v] : (int32_t)(v + 1);
+    label[v] = lab;
+    for (int64_t i = 0; i < n; ++i) label[queue[i]] = lab;
+  }
+  free(queue);
+  free(next);
+  return 0;
+}

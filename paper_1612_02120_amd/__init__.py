@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libemcnn.so")
 CNN_OK, CNN_EINVAL, CNN_ENOMEM, CNN_EHIP, CNN_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 _ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4}
-_POOL_KIND = {"pool": 1, "pool2": 2}  # 2x2 window, stride 1 / stride 2
+_POOL_KIND = {"pool": 1, "pool2": 2, "sub2": 3}  # 2x2 window, stride 1 / stride 2; 2x subsample
 
 
 class CnnError(RuntimeError):
@@ -61,6 +61,7 @@ EXPORTS = [
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
     "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
     "cnn_infer_noalloc", "student_gather", "cnn_read_activation", "cnn_mfma_probe", "cnn_mfma_bench",
+    "cnn_output_dims",
 ]
 
 
@@ -73,6 +74,7 @@ def _load():
         "cnn_create": [vp, i64, vp, vp],
         "cnn_destroy": [vp],
         "cnn_geometry": [vp, vp, vp],
+        "cnn_output_dims": [vp, i64, i64, vp, vp],
         "cnn_infer": [vp, vp, vp, vp, vp],
         "cnn_infer_noalloc": [vp, vp, vp, vp, vp],
         "cnn_read_activation": [vp, i32, vp, i64, vp, vp],
@@ -166,11 +168,12 @@ def _require_cuda(t, dtype, name, shape=None, min_numel=None):
 
 def radius_of(net) -> int:
     """Receptive radius of a layer list: r += (k - 1) j over the layers, where j
-    (the input spacing) doubles after every stride-2 pool; a 2x2 pool has k = 2."""
+    (the input spacing) doubles after every stride-2 layer; a 2x2 pool has
+    k = 2, a subsample k = 1."""
     R, j = 0, 1
     for L in net:
-        R += (L["k"] - 1 if L["kind"] == "conv" else 1) * j
-        if L["kind"] == "pool2":
+        R += (L["k"] - 1 if L["kind"] == "conv" else 0 if L["kind"] == "sub2" else 1) * j
+        if L["kind"] in ("pool2", "sub2"):
             j *= 2
     return R
 
@@ -191,6 +194,15 @@ class Net:
     def close(self):
         self.__del__()
 
+    def out_dims(self, H, W):
+        """(Ho, Wo) of an H x W slice (cnn_output_dims); (0, 0) below the field of view."""
+        if H < self.R + 1 or W < self.R + 1:
+            return 0, 0
+        Ho, Wo = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.cnn_output_dims(self.ptr, int(H), int(W), ctypes.byref(Ho), ctypes.byref(Wo)),
+               "cnn_output_dims")
+        return Ho.value, Wo.value
+
 
 def cnn_create(weights, net, precision="fp32", act_scales=None) -> Net:
     """weights: float64 vector (per conv W[cout][cin][k][k] then b[cout]);
@@ -206,7 +218,7 @@ def cnn_create(weights, net, precision="fp32", act_scales=None) -> Net:
             arr[i] = _Layer(0, L["k"], L["cin"], L["cout"], _ACT[L["act"]], s)
             ci += 1
         else:
-            arr[i] = _Layer(_POOL_KIND[L["kind"]], 2, 0, 0, 0, 0.0)
+            arr[i] = _Layer(_POOL_KIND[L["kind"]], 1 if L["kind"] == "sub2" else 2, 0, 0, 0, 0.0)
     spec = _Spec(len(net), arr, PRECISIONS[precision])
     out = ctypes.c_void_p()
     _check(_lib.cnn_create(w.ctypes.data_as(ctypes.c_void_p), w.size, ctypes.byref(spec),
@@ -230,10 +242,10 @@ def cnn_infer(net: Net, volume, out=None, stream=None):
     """volume: CUDA uint8 Z x H x W; returns (or fills) CUDA float32 Z x (H-R) x (W-R)."""
     import torch
     Z, H, W = _volume_dims(volume)
+    Ho, Wo = net.out_dims(H, W) if net.ptr else (H - net.R, W - net.R)
     if out is None:
-        out = torch.empty((Z, max(H - net.R, 0), max(W - net.R, 0)), dtype=torch.float32,
-                          device=volume.device)
-    _check_buf(out, torch.float32, "out", shape=(Z, H - net.R, W - net.R))
+        out = torch.empty((Z, max(Ho, 0), max(Wo, 0)), dtype=torch.float32, device=volume.device)
+    _check_buf(out, torch.float32, "out", shape=(Z, Ho, Wo))
     _on_device(volume=volume, out=out)
     _check(_lib.cnn_infer(net.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
            "cnn_infer")
@@ -248,7 +260,8 @@ def cnn_infer_noalloc(net: Net, volume, out, stream=None):
     is required, and the library works in its static device scratch."""
     import torch
     Z, H, W = _volume_dims(volume)
-    _check_buf(out, torch.float32, "out", shape=(Z, H - net.R, W - net.R))
+    Ho, Wo = net.out_dims(H, W) if net.ptr else (H - net.R, W - net.R)
+    _check_buf(out, torch.float32, "out", shape=(Z, Ho, Wo))
     _on_device(volume=volume, out=out)
     _check(_lib.cnn_infer_noalloc(net.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
            "cnn_infer_noalloc")

@@ -32,7 +32,7 @@ struct LayerJob {
   int32_t tiles_x, tiles_y;
   // Spaced layers (nets with stride-2 pools, evaluated densely): bits 0-7 the
   // spacing d of the conv taps, bits 8-15 the spacing of the 2x2 max filter
-  // before it; 0 for the plain kernels. With d > 1 the output splits into d^2
+  // before it (0: no max filter); 0 for the plain kernels. With d > 1 the output splits into d^2
   // phase sub-lattices (positions py + d r, px + d c) that are tiled
   // separately: tiles_y counts d^2 x the tile rows of the largest phase.
   // Bits 16-19: lg, the output map is stored fragment-major modulo D = 2^lg
@@ -100,6 +100,7 @@ struct VariantInfo {
 struct FirstInfo {
   int prec_out, cout, ks;
   int maxout;  // 1: bias + max-out over channel pairs (stores cout / 2 channels); 0: bias + ReLU
+  int stride;  // output stride: 2 evaluates the conv at every second input row and column only
   int ty, tx, threads;
   int lds_bytes;  // the uint8 input tile (descriptive; the per-wave epilogue scratch comes on top)
   const void* fn;

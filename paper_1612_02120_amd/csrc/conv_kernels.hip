@@ -158,7 +158,8 @@ struct FragTile {
 };
 
 __device__ __forceinline__ FragTile frag_tile(const gbyte* slice, int elb, const LayerJob& J, int py, int px) {
-  const int d = max(J.geom & 0xff, 1), pd = max((J.geom >> 8) & 0xff, 1);
+  // pd = 0: no max filter before this conv (its partners are the pixel itself)
+  const int d = max(J.geom & 0xff, 1), pd = (J.geom >> 8) & 0xff;
   const int lg = __builtin_ctz(d);
   const int64_t plane = (J.in_zs >> (2 * lg)) * elb;  // bytes per fragment
   FragTile f;
@@ -462,9 +463,11 @@ __device__ __forceinline__ void stage_tile(unsigned char* lds, const gbyte* in, 
 // stages the whole output tile in LDS and writes each tile row as one
 // contiguous run of 16-byte stores: FP32 output is NHWC (a tile row is one
 // run), BF16 / FP8 output is channel-blocked (one run per 16-channel plane).
-template <int PO, int COUT, int KS, int TY, int TX>
+template <int PO, int COUT, int KS, int TY, int TX, int ST = 1>
 struct FirstCfg {
-  static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
+  // ST: output stride (2: the conv is evaluated only at every second input
+  // row and column, as a 2x subsample right after it keeps them)
+  static constexpr int LR = ST * (TY - 1) + KS, LC = ST * (TX - 1) + KS;
   static constexpr int ESZ = PO == F32 ? 4 : PO == BF16 ? 2 : 1;
   static constexpr bool BLOCKED = PO != F32;  // BF16 / FP8 activations are channel-blocked
   static constexpr int NB = COUT / 16;
@@ -480,9 +483,10 @@ struct FirstCfg {
 
 // MAXOUT: bias then max over the channel pairs (2c, 2c + 1), COUT / 2 stored
 // channels (NHWC, FP32 or BF16), instead of bias then ReLU.
-template <int PO, int COUT, int KS, int TY, int TX, bool MAXOUT = false>
-__global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void conv_first(JobSet js, FirstParams prm) {
-  using C = FirstCfg<PO, COUT, KS, TY, TX>;
+template <int PO, int COUT, int KS, int TY, int TX, bool MAXOUT = false, int ST = 1>
+__global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void conv_first(JobSet js,
+                                                                                           FirstParams prm) {
+  using C = FirstCfg<PO, COUT, KS, TY, TX, ST>;
   static_assert(!MAXOUT || PO == F32 || PO == BF16, "max-out first layers are FP32 or BF16");
   __shared__ __attribute__((aligned(16))) unsigned char tile[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -538,7 +542,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
     __syncthreads();
     for (int t = tid; t < C::LR * C::LC; t += C::THREADS) {
       const int r = t / C::LC, c = t % C::LC;
-      const int y = min(y0 + r, J.hin - 1), x = min(x0 + c, J.win - 1);
+      const int y = min(ST * y0 + r, J.hin - 1), x = min(ST * x0 + c, J.win - 1);
       tile[t] = in[(int64_t)y * J.in_rs + x];
     }
     __syncthreads();
@@ -548,7 +552,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX>::THREADS)) void con
     for (int u = 0; u < C::MW; ++u) {
       const int mb = wave * C::MW + u;
       const int mrow = mb / MCOLS, mcol = mb % MCOLS;
-      const unsigned char* a0 = tile + mrow * C::LC + mcol * 16 + n16;
+      const unsigned char* a0 = tile + ST * (mrow * C::LC + mcol * 16 + n16);
       f4 acc[C::NB];
 #pragma unroll
       for (int nb = 0; nb < C::NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
@@ -2193,11 +2197,12 @@ static const VariantInfo kConv[] = {
     EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
 };
 
-#define EMCNN_FIRSTM(PO, COUT, KS, TY, TX, MX)                                                       \
-  FirstInfo{PO, COUT, KS, MX, TY, TX, FirstCfg<PO, COUT, KS, TY, TX>::THREADS,                        \
-            FirstCfg<PO, COUT, KS, TY, TX>::LDS,                                                      \
-            reinterpret_cast<const void*>(&conv_first<PO, COUT, KS, TY, TX, MX>),                     \
-            "conv_first<" #PO "," #COUT "," #KS "," #TY "," #TX "," #MX ">"}
+#define EMCNN_FIRSTS(PO, COUT, KS, TY, TX, MX, ST)                                                   \
+  FirstInfo{PO, COUT, KS, MX, ST, TY, TX, FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS,                \
+            FirstCfg<PO, COUT, KS, TY, TX, ST>::LDS,                                                  \
+            reinterpret_cast<const void*>(&conv_first<PO, COUT, KS, TY, TX, MX, ST>),                 \
+            "conv_first<" #PO "," #COUT "," #KS "," #TY "," #TX "," #MX "," #ST ">"}
+#define EMCNN_FIRSTM(PO, COUT, KS, TY, TX, MX) EMCNN_FIRSTS(PO, COUT, KS, TY, TX, MX, 1)
 #define EMCNN_FIRST(PO, COUT, KS, TY, TX) EMCNN_FIRSTM(PO, COUT, KS, TY, TX, false)
 
 static const FirstInfo kFirst[] = {
@@ -2208,6 +2213,9 @@ static const FirstInfo kFirst[] = {
     // FastMemb first conv: 4x4, 1 -> 64, max-out to 32
     EMCNN_FIRSTM(F32, 64, 4, 4, 64, true), EMCNN_FIRSTM(F32, 64, 4, 8, 32, true),
     EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true), EMCNN_FIRSTM(BF16, 64, 4, 8, 64, true),
+    // FastMemb_ss first conv: evaluated only where the 2x subsample after it keeps a pixel
+    EMCNN_FIRSTS(F32, 64, 4, 4, 64, true, 2), EMCNN_FIRSTS(F32, 64, 4, 8, 32, true, 2),
+    EMCNN_FIRSTS(BF16, 64, 4, 4, 64, true, 2), EMCNN_FIRSTS(BF16, 64, 4, 8, 64, true, 2),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }

@@ -24,8 +24,9 @@ Dims layer_dims(const Net* net, int h, int w) {
     d.hin.push_back(h);
     d.win.push_back(w);
     const int shrink = (L.pool_in ? L.pd : 0) + (L.ks - 1) * L.dil;
-    h -= shrink;
-    w -= shrink;
+    // a strided first layer is evaluated at every stride-th position only
+    h = (h - shrink - 1) / L.stride + 1;
+    w = (w - shrink - 1) / L.stride + 1;
     d.hout.push_back(h);
     d.wout.push_back(w);
   }
@@ -82,7 +83,7 @@ static LayerJob make_job(const ExecLayer& L, const void* in, void* out, int z, i
   j.wout = wout;
   j.out_rs = out_rs;
   j.out_zs = out_zs;
-  if (L.dil > 1) {
+  if (L.spaced && !L.first) {
     // d^2 phase sub-lattices, each tiled on its own (the largest phase has
     // ceil(hout / d) x ceil(wout / d) positions)
     const int d = L.dil, hs = (hout + d - 1) / d, wsub = (wout + d - 1) / d;
@@ -207,7 +208,8 @@ int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, fl
   if (rc) return rc;
   unsigned char* buf0 = reinterpret_cast<unsigned char*>(net->ws);
   unsigned char* buf1 = buf0 + zs * b0;
-  const int64_t Ho = H - net->R, Wo = W - net->R;
+  const Dims d = layer_dims(net, (int)H, (int)W);
+  const int64_t Ho = d.hout.back(), Wo = d.wout.back();
   net->last_Z = Z;
   net->last_H = H;
   net->last_W = W;
@@ -246,6 +248,10 @@ static int scratch_ptr(int device, unsigned char** out) {
   return CNN_OK;
 }
 
+// Input rows that produce hs output rows (field of view R + 1; a net with a
+// 2x subsample advances two input rows per output row).
+static int64_t strip_rows(const Net* net, int64_t hs) { return net->out_stride * (hs - 1) + net->R + 1; }
+
 // The volume as regions that fit the static scratch: slabs of whole slices
 // when one slice fits, otherwise strips of output rows (a multiple of 16, so
 // that every phase lattice of a stride-2 pool net starts at the same parity
@@ -257,14 +263,14 @@ int plan_static(const Net* net, int64_t Z, int64_t H, int64_t W, size_t cap, int
   region_bytes(net, (int)H, (int)W, b0, b1);
   if (b0 + b1 <= cap) {
     zslab = std::max<int64_t>(1, std::min<int64_t>(Z, (int64_t)(cap / std::max<size_t>(1, b0 + b1))));
-    strip = H - net->R;
+    strip = layer_dims(net, (int)H, (int)W).hout.back();
     return CNN_OK;
   }
   zslab = 1;
-  const int64_t Ho = H - net->R;
+  const int64_t Ho = layer_dims(net, (int)H, (int)W).hout.back();
   int64_t lo = 0;
   for (int64_t hs = 16; hs < Ho; hs *= 2) {  // largest power-of-two multiple of 16 that fits, then refine
-    region_bytes(net, (int)(hs + net->R), (int)W, b0, b1);
+    region_bytes(net, (int)strip_rows(net, hs), (int)W, b0, b1);
     if (b0 + b1 > cap) break;
     lo = hs;
   }
@@ -272,7 +278,7 @@ int plan_static(const Net* net, int64_t Z, int64_t H, int64_t W, size_t cap, int
     return fail(CNN_EINVAL, "cnn_infer_noalloc: a 16-row strip of width " + std::to_string(W) +
                                 " needs more than the static scratch (" + std::to_string(cap) + " bytes)");
   for (int64_t step = lo / 2; step >= 16; step /= 2) {
-    region_bytes(net, (int)(lo + step + net->R), (int)W, b0, b1);
+    region_bytes(net, (int)strip_rows(net, lo + step), (int)W, b0, b1);
     if (lo + step < Ho && b0 + b1 <= cap) lo += step;
   }
   strip = lo;
@@ -577,14 +583,16 @@ extern "C" int cnn_infer_noalloc(cnn_net* h, const uint8_t* vol, const int64_t d
   rc = scratch_ptr(net->device, &base);
   if (rc) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int64_t Ho = H - net->R, Wo = W - net->R;
+  const Dims dv = layer_dims(net, (int)H, (int)W);
+  const int64_t Ho = dv.hout.back(), Wo = dv.wout.back();
   for (int64_t z0 = 0; z0 < Z; z0 += zslab) {
     const int zc = (int)std::min<int64_t>(zslab, Z - z0);
     for (int64_t y0 = 0; y0 < Ho; y0 += strip) {
       const int64_t hs = std::min<int64_t>(strip, Ho - y0);
+      const int64_t rows = hs == Ho ? H : strip_rows(net, hs);
       size_t b0 = 0, b1 = 0;
-      region_bytes(net, (int)(hs + net->R), (int)W, b0, b1);
-      rc = run_region(net, vol + z0 * H * W + y0 * W, W, H * W, zc, (int)(hs + net->R), (int)W,
+      region_bytes(net, (int)rows, (int)W, b0, b1);
+      rc = run_region(net, vol + z0 * H * W + net->out_stride * y0 * W, W, H * W, zc, (int)rows, (int)W,
                       prob + z0 * Ho * Wo + y0 * Wo, Wo, Ho * Wo, base, base + zc * b0, st, false);
       if (rc) return rc;
     }
@@ -618,6 +626,18 @@ extern "C" int cnn_read_activation(cnn_net* h, int32_t layer, void* dst, int64_t
   return CNN_OK;
 }
 
+extern "C" int cnn_output_dims(const cnn_net* h, int64_t H, int64_t W, int64_t* Ho, int64_t* Wo) {
+  clear_error();
+  if (!h || !Ho || !Wo) return fail(CNN_EINVAL, "cnn_output_dims: null argument");
+  const Net* net = reinterpret_cast<const Net*>(h);
+  if (H < net->R + 1 || W < net->R + 1 || H >= (1ll << 30) || W >= (1ll << 30))
+    return fail(CNN_EINVAL, "cnn_output_dims: dims must be >= the field of view and < 2^30");
+  const Dims d = layer_dims(net, (int)H, (int)W);
+  *Ho = d.hout.back();
+  *Wo = d.wout.back();
+  return CNN_OK;
+}
+
 extern "C" int cnn_set_batch_graph(cnn_net* h, int32_t enable) {
   clear_error();
   if (!h) return fail(CNN_EINVAL, "cnn_set_batch_graph: null net");
@@ -638,7 +658,8 @@ extern "C" int cnn_infer_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, voi
   Net* net = reinterpret_cast<Net*>(h);
   int rc = check_device(net);
   if (rc) return rc;
-  if (net->R % 2) return fail(CNN_EUNSUPPORTED, "cnn_infer_batch: odd receptive radius");
+  if (net->R % 2 || net->out_stride != 1)
+    return fail(CNN_EUNSUPPORTED, "cnn_infer_batch: blocks need an odd field of view and a full-resolution output");
   const int R2 = net->R / 2;
   std::vector<Region> regs(n);
   for (int t = 0; t < n; ++t) {

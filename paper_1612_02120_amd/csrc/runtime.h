@@ -26,6 +26,8 @@ struct ExecLayer {
   // the conv that reads it; 0: row-major), see LayerJob::geom
   int out_lg = 0;
   int cstore = 0;  // channels stored per output pixel: cout, or cout / 2 after max-out
+  int stride = 1;  // output stride of a first layer (2: only where a 2x subsample keeps pixels)
+  int spaced = 0;  // conv of a stride-2 pool net: tiled per phase, max-filter spacing from the job
   int variant = -1;
   std::vector<int> candidates;
   std::vector<void*> wpacks;  // packed weights per candidate (layouts differ between variants)
@@ -50,6 +52,7 @@ struct Net {
   int device = 0;
   int prec = 0;
   int R = 0;
+  int out_stride = 1;  // 2 for nets with a 2x subsample: output (y, x) is the window at input (2y, 2x)
   int num_cus = 256;
   std::string arch;
   std::vector<ExecLayer> layers;

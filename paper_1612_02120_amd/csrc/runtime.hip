@@ -86,11 +86,12 @@ uint8_t e4m3_code(double x) {
 
 static int act_bytes(int prec) { return prec == F32 ? 4 : prec == BF16 ? 2 : 1; }
 
-static std::vector<int> find_first_variants(int prec, int cout, int ks, int maxout) {
+static std::vector<int> find_first_variants(int prec, int cout, int ks, int maxout, int stride = 1) {
   std::vector<int> v;
   for (int i = 0; i < first_variant_count(); ++i) {
     const FirstInfo* f = first_variant(i);
-    if (f->prec_out == prec && f->cout == cout && f->ks == ks && f->maxout == maxout) v.push_back(i);
+    if (f->prec_out == prec && f->cout == cout && f->ks == ks && f->maxout == maxout && f->stride == stride)
+      v.push_back(i);
   }
   return v;
 }
@@ -299,9 +300,13 @@ static void free_layer(ExecLayer& L) {
 // in their dense form: conv(4, 1 -> 64, max-out), then one or more of { 2x2/s2
 // pool, conv(4, 32 -> 64, max-out) }, then a 2x2/s2 pool and conv(4, 32 -> 2,
 // softmax). Every stride-2 pool becomes a 2x2 max filter at the current
-// spacing and doubles the spacing of the later layers. BF16: bf16 weights and
-// stored activations with FP32 accumulation (the first conv's weights are
-// bf16(w / 255) against exact uint8 inputs); the softmax layer is FP32.
+// spacing and doubles the spacing of the later layers. A 2x subsample right
+// after the first conv (FastMemb_ss, "A subsampling CNN for 3 nm data") keeps
+// one fragment only: the first conv is evaluated at every second row and
+// column, and the conv after it runs densely on that half-resolution map with
+// no max filter before it. BF16: bf16 weights and stored activations with FP32
+// accumulation (the first conv's weights are bf16(w / 255) against exact uint8
+// inputs).
 static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, int nl) {
   const int prec = net->prec;
   const auto unsupported = [](const std::string& why) {
@@ -310,20 +315,35 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
   const cnn_layer& l0 = Lr[0];
   if (l0.kind != CNN_LAYER_CONV || l0.k != 4 || l0.cin != 1 || l0.cout != 64 || l0.act != CNN_ACT_MAXOUT)
     return unsupported("the first layer must be conv(4, 1 -> 64, max-out)");
-  if (nl < 4 || (nl - 1) % 2) return unsupported("expected conv, then (stride-2 pool, conv) pairs");
-  for (int i = 1; i < nl; i += 2) {
-    const cnn_layer& p = Lr[i];
-    const cnn_layer& c = Lr[i + 1];
-    const bool last = i + 1 == nl - 1;
-    if (p.kind != CNN_LAYER_MAXPOOL_S2) return unsupported("every conv after the first follows a stride-2 pool");
-    if (c.kind != CNN_LAYER_CONV || c.k != 4 || c.cin != 32 ||
-        (last ? (c.cout != 2 || c.act != CNN_ACT_SOFTMAX) : (c.cout != 64 || c.act != CNN_ACT_MAXOUT)))
+  const bool sub = nl > 1 && Lr[1].kind == CNN_LAYER_SUBSAMPLE2;
+  // layer indices of the convs, and of the pool before each (-1: none)
+  std::vector<int> conv_at{0}, pool_at{-1};
+  int i = 1;
+  if (sub) {
+    if (nl < 3 || Lr[2].kind != CNN_LAYER_CONV) return unsupported("a subsample must be followed by a conv");
+    conv_at.push_back(2);
+    pool_at.push_back(-1);
+    i = 3;
+  }
+  for (; i < nl; i += 2) {
+    if (i + 1 >= nl || Lr[i].kind != CNN_LAYER_MAXPOOL_S2)
+      return unsupported("after the first conv (and a subsample), expected (stride-2 pool, conv) pairs");
+    conv_at.push_back(i + 1);
+    pool_at.push_back(i);
+  }
+  if (conv_at.size() < 3) return unsupported("expected at least one inner conv before the softmax conv");
+  for (size_t c = 1; c < conv_at.size(); ++c) {
+    const cnn_layer& l = Lr[conv_at[c]];
+    const bool last = c + 1 == conv_at.size();
+    if (l.kind != CNN_LAYER_CONV || l.k != 4 || l.cin != 32 ||
+        (last ? (l.cout != 2 || l.act != CNN_ACT_SOFTMAX) : (l.cout != 64 || l.act != CNN_ACT_MAXOUT)))
       return unsupported("inner convs are conv(4, 32 -> 64, max-out), the last conv(4, 32 -> 2, softmax)");
+    if (last && pool_at[c] < 0) return unsupported("the softmax conv must follow a stride-2 pool");
   }
   const double* wp = weights;
   int sp = 1;  // spacing of the current layer's input
-  for (int i = 0; i < nl; i += (i == 0 ? 1 : 2)) {
-    const cnn_layer& l = Lr[i == 0 ? 0 : i + 1];
+  for (size_t c = 0; c < conv_at.size(); ++c) {
+    const cnn_layer& l = Lr[conv_at[c]];
     const int64_t nwl = (int64_t)l.cout * l.cin * l.k * l.k;
     const double* w = wp;
     const double* b = wp + nwl;
@@ -331,20 +351,27 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
     ExecLayer E;
     E.ks = l.k;
     E.cin = l.cin;
+    E.spaced = 1;
     int rc = CNN_OK;
-    if (i == 0) {
+    if (c == 0) {
       E.first = 1;
       E.cout = l.cout;
       E.cstore = l.cout / 2;
       E.epi = 1;
-      E.candidates = find_first_variants(prec, l.cout, l.k, 1);
+      E.stride = sub ? 2 : 1;
+      E.candidates = find_first_variants(prec, l.cout, l.k, 1, E.stride);
       if (E.candidates.empty()) return unsupported("no first-layer kernel");
-      for (int c : E.candidates)
-        if (rc == CNN_OK) rc = pack_first(E, c, w, b, 0.0);
+      for (int v : E.candidates)
+        if (rc == CNN_OK) rc = pack_first(E, v, w, b, 0.0);
     } else {
-      E.pool_in = 1;
-      E.pd = sp;  // the max filter of the stride-2 pool before this conv
-      sp *= 2;
+      if (pool_at[c] >= 0) {
+        E.pool_in = 1;
+        E.pd = sp;  // the max filter of the stride-2 pool before this conv
+        sp *= 2;
+      } else {
+        E.pool_in = 0;  // after the subsample: no max filter, dense at spacing 1
+        E.pd = 0;
+      }
       E.dil = sp;
       if (l.act == CNN_ACT_SOFTMAX) {
         // the two-class layer: FP32 VALU kernels, or MFMA kernels that run it
@@ -363,19 +390,21 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
         std::vector<double> wpad((size_t)16 * l.cin * l.k * l.k, 0.0), bpad(16, 0.0);
         std::copy(w, w + nwl, wpad.begin());
         std::copy(b, b + l.cout, bpad.begin());
-        for (int c : E.candidates) {
+        for (int v : E.candidates) {
           if (rc != CNN_OK) break;
-          rc = conv_variant(c)->epi == 3 ? pack_head_valu(E, c, w, b)
-                                        : pack_conv(E, c, wpad.data(), bpad.data(), nullptr, 0.0, 1.0, 0.0);
+          rc = conv_variant(v)->epi == 3 ? pack_head_valu(E, v, w, b)
+                                        : pack_conv(E, v, wpad.data(), bpad.data(), nullptr, 0.0, 1.0, 0.0);
         }
       } else {
         E.cout = l.cout;
         E.cstore = l.cout / 2;
         E.epi = 1;
+        // the spaced kernels take the max filter's spacing from the job: the
+        // same kernels serve a conv without a max filter (spacing 0)
         E.candidates = find_conv_variants(prec, l.cin, E.cout, l.k, 1, 0, E.epi);
-        if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(i + 1));
-        for (int c : E.candidates)
-          if (rc == CNN_OK) rc = pack_conv(E, c, w, b, nullptr, 0.0, 1.0, 0.0);
+        if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(c));
+        for (int v : E.candidates)
+          if (rc == CNN_OK) rc = pack_conv(E, v, w, b, nullptr, 0.0, 1.0, 0.0);
       }
     }
     E.variant = E.candidates[0];
@@ -388,7 +417,8 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
     E.in_off = off;
     off += (E.pool_in ? E.pd : 0) + (E.ks - 1) * E.dil;
   }
-  if (off != net->R) return fail(CNN_EINVAL, "cnn_create: internal radius mismatch");
+  if (!sub && off != net->R) return fail(CNN_EINVAL, "cnn_create: internal radius mismatch");
+  net->out_stride = sub ? 2 : 1;
   // every map but the output feeds a spaced conv: stored fragment-major modulo its spacing
   for (size_t l = 0; l + 1 < net->layers.size(); ++l) net->layers[l].out_lg = __builtin_ctz(net->layers[l + 1].dil);
   return CNN_OK;
@@ -476,6 +506,11 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
         sp *= 2;
         strided = true;
       }
+    } else if (l.kind == CNN_LAYER_SUBSAMPLE2) {
+      if (i == 0 || spec->layers[i - 1].kind != CNN_LAYER_CONV)
+        return fail(CNN_EINVAL, "cnn_create: a subsample must follow a conv");
+      sp *= 2;  // window 1: no growth of the field of view
+      strided = true;
     } else {
       return fail(CNN_EINVAL, "cnn_create: bad layer kind at " + std::to_string(i));
     }

@@ -1,0 +1,89 @@
+"""GPU parity of FastMemb_ss (Section 2.2, "A subsampling CNN for 3 nm data")
+through the C ABI against the FP64 reference's pruned dense form (itself pinned
+to every second sample of the full dense map, the patch form and the paper's
+fragments in tests/test_oracle_fastmemb_ss.py).
+
+The first conv runs only where the 2x subsample keeps pixels (stride-2 first
+layer), the conv after it densely on the half-resolution map with no max filter
+(the spaced kernels with max-filter spacing 0), then FastMemb's pool / conv
+pairs at spacings 2, 4, 8. Tolerances against the exact reference: FP32 1e-5,
+BF16 2e-2. Shapes give ragged tails at 3 nm (odd sizes) and at 6 nm.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import em_volume
+from synth.nets import NET_FMSS, he_normal_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def emcnn():
+    import paper_1612_02120_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _params(seed=410, sigma=0.1):
+    from synth.nets import random_bias_params
+    return random_bias_params(NET_FMSS, seed, seed + 7, sigma=sigma)
+
+
+@pytest.mark.parametrize("shape", [(1, 108, 108), (2, 140, 131), (1, 300, 257), (1, 109, 400), (2, 640, 610)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_fastmemb_ss_matches_reference(emcnn, shape, prec, tol):
+    print("FastMemb_ss case", prec, shape, flush=True)
+    vol = em_volume(60 + shape[1], *shape)
+    p = _params()
+    h = emcnn.cnn_create(p, NET_FMSS, prec)
+    assert h.R == 107
+    Ho, Wo = h.out_dims(shape[1], shape[2])
+    assert (Ho, Wo) == oracle.out_dims(NET_FMSS, shape[1], shape[2])
+    out = emcnn.cnn_infer(h, torch.from_numpy(vol).cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.forward(vol, NET_FMSS, p)
+    assert got.shape == ref.shape == (shape[0], Ho, Wo)
+    err = np.abs(got - ref)
+    print("FastMemb_ss %s %s max err %.3g mean %.3g" % (prec, shape, err.max(), err.mean()))
+    assert err.max() <= tol
+
+
+def test_fastmemb_ss_every_candidate_and_noalloc(emcnn):
+    vol = em_volume(71, 2, 260, 233)
+    p = _params(412)
+    ref = oracle.forward(vol, NET_FMSS, p)
+    h = emcnn.cnn_create(p, NET_FMSS, "fp32")
+    v = torch.from_numpy(vol).cuda()
+    base = emcnn.cnn_infer(h, v)
+    names = [emcnn.cnn_variant_names(h, l) for l in range(5)]
+    for layer in range(5):
+        for name in names[layer]:
+            emcnn.cnn_set_variant(h, layer, name)
+            got = emcnn.cnn_infer(h, v)
+            torch.cuda.synchronize()
+            err = np.abs(got.cpu().numpy() - ref).max()
+            assert err <= 1e-5, (layer, name, err)
+        emcnn.cnn_set_variant(h, layer, names[layer][0])
+    out = torch.full_like(base, float("nan"))
+    emcnn.cnn_infer_noalloc(h, v, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, base)
+
+
+def test_fastmemb_ss_workspace_slabs_and_batch_rejected(emcnn):
+    vol = em_volume(72, 3, 190, 170)
+    p = _params(413)
+    h = emcnn.cnn_create(p, NET_FMSS, "fp32")
+    v = torch.from_numpy(vol).cuda()
+    full = emcnn.cnn_infer(h, v)
+    emcnn.cnn_set_workspace_limit(h, 1 << 20)  # one slice per slab
+    slab = emcnn.cnn_infer(h, v)
+    torch.cuda.synchronize()
+    assert torch.equal(full, slab)
+    with pytest.raises(emcnn.CnnError) as e:
+        emcnn.cnn_infer_batch(h, [(v[:1], 60, torch.empty((1, 70, 50), device="cuda"))])
+    assert e.value.code == emcnn.CNN_EUNSUPPORTED
