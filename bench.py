@@ -41,6 +41,8 @@ STUDENT_FLOP_PER_VOXEL = 2 * (200 + 576 + 8)
 # FastMemb (4x4 convs 1->64, 32->64, 32->64 with max-out to 32, 32->2) per output voxel
 FASTMEMB_FLOP_PER_VOXEL = 2 * 16 * (64 + 32 * 64 + 32 * 64 + 32 * 2)
 FASTMEMB_BODY_FLOP_PER_POS = 2 * 16 * 32 * 64  # one 32 -> 64 4x4 conv output position
+# FastMemb_ss per 6 nm output voxel: the 1 -> 64 conv only where the subsample keeps pixels, three 32 -> 64 convs
+FASTMEMB_SS_FLOP_PER_VOXEL = 2 * 16 * (64 + 3 * 32 * 64 + 32 * 2)
 
 
 def log(*a):
@@ -72,8 +74,8 @@ def traffic_from_profiles(name):
 
 
 def time_volume(emcnn, torch, h, vol_dev, steps, warmup, stream):
-    out = torch.empty((vol_dev.shape[0], vol_dev.shape[1] - h.R, vol_dev.shape[2] - h.R),
-                      dtype=torch.float32, device=vol_dev.device)
+    Ho, Wo = h.out_dims(vol_dev.shape[1], vol_dev.shape[2])
+    out = torch.empty((vol_dev.shape[0], Ho, Wo), dtype=torch.float32, device=vol_dev.device)
     with torch.cuda.stream(stream):
         for _ in range(warmup):
             emcnn.cnn_infer(h, vol_dev, out=out, stream=stream)
@@ -208,6 +210,65 @@ def student_form(emcnn, torch, em_volume, p, NET_B, dev, stream, args, big):
     return res
 
 
+def fastmemb_ss_form(emcnn, torch, em_volume, calibrated_params, dev, stream, args, forms):
+    """FastMemb_ss (Section 2.2, "A subsampling CNN for 3 nm data"; the reading:
+    FastMemb plus one more {pool, conv} pair with its first stride-2 pool
+    replaced by a 2x subsample) on a 32 x 2048 x 2048 stack taken as 3 nm
+    sections, giving a 32 x 971 x 971 map at 6 nm: the same output size as
+    FastMemb on 32 x 1024^2 (6 nm sections). Reports the closed-form cost
+    ratio to FastMemb_6nm beside the paper's figure, and the measured one."""
+    from synth.nets import NET_FMSS, he_normal_params
+    Z = 32
+    vol = torch.from_numpy(em_volume(5, Z, 2048, 2048)).to(dev)
+    p = he_normal_params(NET_FMSS, 410)
+    out = {}
+    for prec in ("fp32", "bf16"):
+        h = emcnn.cnn_create(p, NET_FMSS, prec)
+        ms, pl, o = time_volume(emcnn, torch, h, vol, max(3, args.steps // 2), 2, stream)
+        nv = o.numel()
+        out[prec] = {"voxels_per_s": nv / (ms * 1e-3), "ms_per_pass": ms, "output": list(o.shape),
+                     "path_tflops": nv * FASTMEMB_SS_FLOP_PER_VOXEL / (ms * 1e-3) / 1e12,
+                     "path_mfma_frac": nv * FASTMEMB_SS_FLOP_PER_VOXEL / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                     "layer_ms": pl[:5], "tiles": emcnn.cnn_describe(h)}
+        fm = forms.get("fastmemb" if prec == "fp32" else "fastmemb_bf16")
+        if fm:
+            out[prec]["time_ratio_vs_fastmemb_6nm"] = ms / fm["ms_per_pass"] * (32 * 972 ** 2) / nv
+        del o, h
+    res = {"workload": "FastMemb_ss (conv4x4 1->64 max-out, 2x subsample, conv4x4 32->64 max-out, 3 x {2x2/s2 "
+                       "pool, conv4x4}, two-class softmax; FoV 108 at 3 nm) on %d x 2048 x 2048 (seed 5) -> "
+                       "%d x 971 x 971 at 6 nm" % (Z, Z),
+           "flop_ratio_vs_fastmemb_6nm": FASTMEMB_SS_FLOP_PER_VOXEL / FASTMEMB_FLOP_PER_VOXEL,
+           "paper_flop_ratio": 1.17, **out}
+    log("fastmemb_ss", json.dumps(res))
+    return res
+
+
+def watershed_form(emcnn, torch, pmap, stream, reps=5):
+    """The 3-D watershed (Section 2.1, over-segmentation) on the headline
+    membrane map (32 x 1012 x 1012 FP32), seeds below its 25 % quantile.
+    Algorithmic traffic: 4 B read + 4 B written per voxel."""
+    t = float(torch.quantile(pmap[0].flatten()[::97].float(), 0.25).item())
+    lab = torch.empty(pmap.shape, dtype=torch.int32, device=pmap.device)
+    work = torch.empty(pmap.numel() + 1, dtype=torch.int32, device=pmap.device)
+    with torch.cuda.stream(stream):
+        emcnn.watershed_3d(pmap, t, labels=lab, work=work, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            emcnn.watershed_3d(pmap, t, labels=lab, work=work, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    n = pmap.numel()
+    nb = int(torch.unique(lab).numel())
+    res = {"workload": "3-D watershed (steepest descent, seeded minima, 6-neighbours) of the net B FP32 map "
+                       "%s, seeds p < %.4f" % (tuple(pmap.shape), t),
+           "voxels_per_s": n / dt, "ms_per_pass": dt * 1e3, "basins": nb,
+           "roofline": {"bound": "hbm", "achieved": n * 8 / dt / 1e9, "peak": HBM_GBS, "unit": "GB/s",
+                        "frac": n * 8 / dt / 1e9 / HBM_GBS, "algorithmic_bytes_per_voxel": 8}}
+    log("watershed", json.dumps(res))
+    return res
+
+
 def mfma_ceiling(emcnn, torch, dev):
     """Measured MFMA throughput of each precision's instruction on random
     operands (register operands, 8 accumulators per wave, 16 waves per CU),
@@ -236,7 +297,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="all",
-                    help="all | none | comma list of mfma,bf16,fp8,batch,student,fastmemb,fastmemb_bf16")
+                    help="all | none | comma list of mfma,watershed,bf16,fp8,batch,student,fastmemb,"
+                         "fastmemb_bf16,fastmemb_ss")
     ap.add_argument("--quick", action="store_true",
                     help="smaller secondary forms: precision / student volume 8 x 2048^2, 4k training steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -311,10 +373,13 @@ def main():
                      "flop_per_launch": conv2_flop, "avg_launch_ms": conv2_ms,
                      "traffic": traffic_from_profiles("conv2_fp32_plain_traffic.json")},
     }
-    del out
     forms = {}
+    if args.forms == "all" or "watershed" in args.forms.split(","):
+        forms["watershed"] = watershed_form(emcnn, torch, out, stream)
+    del out
     want = set() if args.forms == "none" else (
-        {"mfma", "bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16"} if args.forms == "all"
+        {"mfma", "bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16", "fastmemb_ss"}
+        if args.forms == "all"
         else set(args.forms.split(",")))
     if "mfma" in want:
         forms["mfma_ceiling"] = mfma_ceiling(emcnn, torch, dev)
@@ -341,6 +406,9 @@ def main():
             "layer_ms": plf[:4], "tiles": emcnn.cnn_describe(hf)}
         log(key, json.dumps(forms[key]))
         del outf, hf
+    if "fastmemb_ss" in want and not args.no_headline:
+        forms["fastmemb_ss"] = fastmemb_ss_form(emcnn, torch, em_volume, calibrated_params, dev, stream, args,
+                                                forms)
     volp_dev = None
     if want & {"bf16", "fp8", "student"}:
         Zp = 8 if args.quick else 128

@@ -342,6 +342,27 @@ int student_infer_with_fallback(cnn_student* s, cnn_net* teacher, const uint8_t*
                                 int32_t* stats_out, int32_t* flags_out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * 3-D watershed (Section 2.1: the membrane map is turned into an
+ * over-segmentation by a 3-D watershed before agglomeration).
+ * ---------------------------------------------------------------------- */
+
+/* Watershed by steepest descent with seeded minima, in 3-D with 6-neighbours:
+ * voxels are ordered by (p, index), index = (z H + y) W + x; seeds are the
+ * voxels with p < seed_threshold, grouped into 6-connected components labelled
+ * 1 + the least index in each; every other voxel descends to the least of
+ * itself and its neighbours until it reaches a seed (and takes its
+ * component's label) or a local minimum of the order m (label 1 + index(m)).
+ * The labelling is unique; it is an over-segmentation whose seeded basins are
+ * the cells when the map separates them.
+ * prob: device Z x H x W float32, finite; labels_out: device int32, same
+ * shape; work: device int32[Z H W + 1] scratch (caller-owned, overwritten);
+ * Z H W < 2^31 - 1. The call synchronises `stream` once per round of the seed
+ * components (typically a few rounds) and returns with the labelling
+ * enqueued. */
+int watershed_3d(const float* prob, const int64_t dims[3], float seed_threshold, int32_t* labels_out,
+                 int32_t* work, void* stream);
+
+/* ------------------------------------------------------------------------
  * Diagnostics: the matrix-core instructions the conv kernels use, for tests
  * of their arithmetic and for a measured throughput ceiling.
  * ---------------------------------------------------------------------- */

@@ -61,7 +61,7 @@ EXPORTS = [
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
     "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
     "cnn_infer_noalloc", "student_gather", "cnn_read_activation", "cnn_mfma_probe", "cnn_mfma_bench",
-    "cnn_output_dims",
+    "cnn_output_dims", "watershed_3d",
 ]
 
 
@@ -75,6 +75,7 @@ def _load():
         "cnn_destroy": [vp],
         "cnn_geometry": [vp, vp, vp],
         "cnn_output_dims": [vp, i64, i64, vp, vp],
+        "watershed_3d": [vp, vp, f32, vp, vp, vp],
         "cnn_infer": [vp, vp, vp, vp, vp],
         "cnn_infer_noalloc": [vp, vp, vp, vp, vp],
         "cnn_read_activation": [vp, i32, vp, i64, vp, vp],
@@ -543,3 +544,25 @@ def student_infer_with_fallback(s: Student, teacher: Net, volume, tau=0.01, tile
                                             _stream(stream)),
            "student_infer_with_fallback")
     return out, stats
+
+
+# ---------------------------------------------------------------- watershed
+
+
+def watershed_3d(prob, seed_threshold, labels=None, work=None, stream=None):
+    """3-D watershed of a float32 CUDA map Z x H x W (include/emcnn.h); returns
+    int32 labels of the same shape."""
+    import torch
+    if not isinstance(prob, torch.Tensor) or prob.dim() != 3:
+        raise ValueError("prob must be a Z x H x W tensor")
+    _check_buf(prob, torch.float32, "prob")
+    if labels is None:
+        labels = torch.empty(prob.shape, dtype=torch.int32, device=prob.device)
+    if work is None:
+        work = torch.empty(prob.numel() + 1, dtype=torch.int32, device=prob.device)
+    _check_buf(labels, torch.int32, "labels", shape=tuple(prob.shape))
+    _check_buf(work, torch.int32, "work", min_numel=prob.numel() + 1)
+    _on_device(prob=prob, labels=labels, work=work)
+    _check(_lib.watershed_3d(_ptr(prob), _dims(prob), float(seed_threshold), _ptr(labels), _ptr(work),
+                             _stream(stream)), "watershed_3d")
+    return labels
