@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 _KIND = {"conv": 0, "pool": 1, "pool2": 2, "sub2": 3}
-_ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4}
+_ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4, "softmax0": 5}
 QMODES = {"exact": 0, "bf16": 1, "fp8": 2}
 
 
@@ -75,6 +75,11 @@ def _bind(L):
     L.orc_patch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp]
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_forward_maps.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    L.orc_patch_maps.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double)]
     L.orc_watershed.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                                 ctypes.c_void_p]
     L.orc_out_dims.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -277,3 +282,29 @@ def watershed(prob, t_seed):
     if rc:
         raise ValueError("oracle watershed failed (%d)" % rc)
     return lab
+
+
+def forward_maps(maps, net, params, threads=0):
+    """Dense output of a multi-channel net on real-valued maps (Z x C x H x W,
+    planar), exact FP64: Z x Ho x Wo."""
+    m = np.ascontiguousarray(maps, dtype=np.float64)
+    Z, C, H, W = m.shape
+    Ho, Wo = out_dims(net, H, W)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    out = np.empty((Z, Ho, Wo), dtype=np.float64)
+    rc = lib().orc_forward_maps(_ptr(m), Z, C, H, W, _layers(net), len(net), _ptr(params), _ptr(out), int(threads))
+    if rc:
+        raise ValueError("oracle forward_maps failed (%d)" % rc)
+    return out
+
+
+def patch_maps(maps, net, params, y, x):
+    """Patch form of a multi-channel net on one window of C x H x W maps."""
+    m = np.ascontiguousarray(maps, dtype=np.float64)
+    C, H, W = m.shape
+    out = ctypes.c_double(0.0)
+    rc = lib().orc_patch_maps(_ptr(m), C, H, W, _layers(net), len(net),
+                              _ptr(np.ascontiguousarray(params, dtype=np.float64)), int(y), int(x), ctypes.byref(out))
+    if rc:
+        raise ValueError("oracle patch_maps failed (%d)" % rc)
+    return out.value

@@ -45,6 +45,12 @@
  *                is the net on the window at input (Y, X) for every Y, X; the
  *                pruned output is its every second sample in each direction.
  *
+ * Multi-channel nets (MaskExtend, Section 3, "MaskExtend: sparse segmentation
+ * via CNN": twelve input maps, 4x4 max-out convs with 2x2 stride-2 pools, three
+ * output classes) take real-valued input maps as they are (orc_forward_maps,
+ * orc_patch_maps), and may end in a softmax over several classes keeping
+ * class 0 ("softmax0"): p0 = e^{z0} / sum_c e^{zc}.
+ *
  * Fake-quant modes mirror the number formats declared by the GPU forms (the
  * paper states no precision; these are readings):
  *   BF16: first conv uses weights bf16((float)(w/255)) against the raw uint8
@@ -68,7 +74,8 @@
 #endif
 
 enum { ORC_CONV = 0, ORC_POOL = 1, ORC_POOL2 = 2, ORC_SUB2 = 3 };
-enum { ORC_ACT_NONE = 0, ORC_ACT_RELU = 1, ORC_ACT_SIGMOID = 2, ORC_ACT_MAXOUT = 3, ORC_ACT_SOFTMAX = 4 };
+enum { ORC_ACT_NONE = 0, ORC_ACT_RELU = 1, ORC_ACT_SIGMOID = 2, ORC_ACT_MAXOUT = 3, ORC_ACT_SOFTMAX = 4,
+       ORC_ACT_SOFTMAX0 = 5 };
 enum { ORC_Q_EXACT = 0, ORC_Q_BF16 = 1, ORC_Q_FP8 = 2 };
 
 typedef struct {
@@ -187,6 +194,20 @@ static int activate(double* o, int Co, int64_t n, int act, double* logit) {
       }
     return Co / 2;
   }
+  if (act == ORC_ACT_SOFTMAX0) {
+    /* softmax over the Co classes; the map keeps class 0's probability */
+    if (Co < 2) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+      double m = o[i];
+      for (int c = 1; c < Co; ++c)
+        if (o[c * n + i] > m) m = o[c * n + i];
+      double den = 0.0;
+      for (int c = 0; c < Co; ++c) den += exp(o[c * n + i] - m);
+      if (logit) logit[i] = o[i];
+      o[i] = exp(o[i] - m) / den;
+    }
+    return 1;
+  }
   if (act == ORC_ACT_SOFTMAX) {
     if (Co != 2) return -1;
     for (int64_t i = 0; i < n; ++i) {
@@ -208,7 +229,8 @@ static int activate(double* o, int Co, int64_t n, int act, double* logit) {
 /* Nets with stride-2 pools, max-out or softmax are defined in exact FP64 only. */
 static int strided_net(const orc_layer* L, int nl) {
   for (int l = 0; l < nl; ++l)
-    if (L[l].kind == ORC_POOL2 || L[l].kind == ORC_SUB2 || L[l].act == ORC_ACT_MAXOUT || L[l].act == ORC_ACT_SOFTMAX)
+    if (L[l].kind == ORC_POOL2 || L[l].kind == ORC_SUB2 || L[l].act == ORC_ACT_MAXOUT || L[l].act == ORC_ACT_SOFTMAX ||
+        L[l].act == ORC_ACT_SOFTMAX0)
       return 1;
   return 0;
 }
@@ -223,18 +245,24 @@ static int param_count(const orc_layer* L, int nl) {
 /* Forward pass of one slice.  trace (nullable) receives, for every layer, a
  * pointer to a malloc'd buffer with that layer's output (caller frees); dims
  * of layer l's output are trace_dims[3l..3l+2] = C, H, W. */
-static int forward_slice(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
+/* img: one uint8 slice (input V / 255), or maps (nullable otherwise): C0 x H x
+ * W real-valued input maps taken as they are (multi-channel nets). */
+static int forward_slice(const uint8_t* img, const double* maps, int C0, int H, int W, const orc_layer* L, int nl,
                          const double* params, int qmode, const double* act_scale,
                          double* out_prob, double* out_logit, double** trace,
                          int32_t* trace_dims, int full) {
-  int C = 1, h = H, w = W;
+  int C = maps ? C0 : 1, h = H, w = W;
   int dil = 1; /* spacing of the dense form; doubled by every stride-2 pool */
-  if (qmode != ORC_Q_EXACT && strided_net(L, nl)) return -1;
-  double* a = (double*)malloc(sizeof(double) * (size_t)H * W);
+  if (qmode != ORC_Q_EXACT && (strided_net(L, nl) || maps)) return -1;
+  double* a = (double*)malloc(sizeof(double) * (size_t)C * H * W);
   if (!a) return -2;
   int first = 1;
-  for (int64_t i = 0; i < (int64_t)H * W; ++i)
-    a[i] = (qmode == ORC_Q_EXACT) ? img[i] / 255.0 : (double)img[i];
+  if (maps) {
+    memcpy(a, maps, sizeof(double) * (size_t)C * H * W);
+  } else {
+    for (int64_t i = 0; i < (int64_t)H * W; ++i)
+      a[i] = (qmode == ORC_Q_EXACT) ? img[i] / 255.0 : (double)img[i];
+  }
   const double* p = params;
   int conv_idx = 0;
   for (int l = 0; l < nl; ++l) {
@@ -363,15 +391,20 @@ int orc_radius(const orc_layer* L, int nl) {
  * img (H x W) with top-left corner (y, x), using plain stride-1 convs and
  * stride-2 pools, as in a sliding-window classifier. out: the single output
  * (probability); logit (nullable): its logit as orc_forward reports it. */
-int orc_patch(const uint8_t* img, int H, int W, const orc_layer* L, int nl, const double* params,
-              int y, int x, double* out, double* logit) {
+/* Patch form on one field-of-view window at (y, x): of a uint8 slice (img),
+ * or of C0 x H x W real-valued maps (maps, when img is NULL). */
+static int patch_any(const uint8_t* img, const double* maps, int C0, int H, int W, const orc_layer* L, int nl,
+                     const double* params, int y, int x, double* out, double* logit) {
   int F = orc_radius(L, nl) + 1;
   if (y < 0 || x < 0 || y + F > H || x + F > W) return -1;
-  int C = 1, h = F, w = F;
-  double* a = (double*)malloc(sizeof(double) * (size_t)F * F);
+  int C = img ? 1 : C0, h = F, w = F;
+  double* a = (double*)malloc(sizeof(double) * (size_t)C * F * F);
   if (!a) return -2;
-  for (int r = 0; r < F; ++r)
-    for (int c = 0; c < F; ++c) a[r * F + c] = img[(int64_t)(y + r) * W + x + c] / 255.0;
+  for (int ch = 0; ch < C; ++ch)
+    for (int r = 0; r < F; ++r)
+      for (int c = 0; c < F; ++c)
+        a[((int64_t)ch * F + r) * F + c] = img ? img[(int64_t)(y + r) * W + x + c] / 255.0
+                                              : maps[((int64_t)ch * H + y + r) * W + x + c];
   const double* p = params;
   for (int l = 0; l < nl; ++l) {
     const orc_layer* ly = &L[l];
@@ -419,6 +452,16 @@ int orc_patch(const uint8_t* img, int H, int W, const orc_layer* L, int nl, cons
   return rc;
 }
 
+int orc_patch(const uint8_t* img, int H, int W, const orc_layer* L, int nl, const double* params,
+              int y, int x, double* out, double* logit) {
+  return patch_any(img, NULL, 1, H, W, L, nl, params, y, x, out, logit);
+}
+
+int orc_patch_maps(const double* maps, int C, int H, int W, const orc_layer* L, int nl, const double* params,
+                   int y, int x, double* out) {
+  return patch_any(NULL, maps, C, H, W, L, nl, params, y, x, out, NULL);
+}
+
 /* vol: Z x H x W uint8; prob (nullable), logit (nullable): Z x (H-R) x (W-R). */
 /* Output dims of the dense form for an H x W slice (full: subsampling layers
  * keep every position). Returns 0, or -1 if the net does not fit. */
@@ -460,7 +503,7 @@ static int forward_all(const uint8_t* vol, int Z, int H, int W, const orc_layer*
   int Ho = 0, Wo = 0;
   if (orc_out_dims(L, nl, H, W, full, &Ho, &Wo)) return -1;
   for (int z = 0; z < Z; ++z) {
-    int rc = forward_slice(vol + (int64_t)z * H * W, H, W, L, nl, params, qmode, act_scale,
+    int rc = forward_slice(vol + (int64_t)z * H * W, NULL, 1, H, W, L, nl, params, qmode, act_scale,
                            prob ? prob + (int64_t)z * Ho * Wo : NULL,
                            logit ? logit + (int64_t)z * Ho * Wo : NULL, NULL, NULL, full);
     if (rc) return rc;
@@ -476,6 +519,25 @@ int orc_forward(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int
   return forward_all(vol, Z, H, W, L, nl, params, qmode, act_scale, prob, logit, nthreads, 0);
 }
 
+/* Dense output of a multi-channel net on real-valued input maps: maps is
+ * Z x C x H x W (each slice's C maps, planar), exact FP64; prob Z x Ho x Wo. */
+int orc_forward_maps(const double* maps, int Z, int C, int H, int W, const orc_layer* L, int nl, const double* params,
+                     double* prob, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  int Ho = 0, Wo = 0;
+  if (C < 1 || orc_out_dims(L, nl, H, W, 0, &Ho, &Wo)) return -1;
+  for (int z = 0; z < Z; ++z) {
+    int rc = forward_slice(NULL, maps + (int64_t)z * C * H * W, C, H, W, L, nl, params, ORC_Q_EXACT, NULL,
+                           prob + (int64_t)z * Ho * Wo, NULL, NULL, NULL, 0);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
 /* The full dense form (subsampling layers keep every position), exact FP64. */
 int orc_forward_full(const uint8_t* vol, int Z, int H, int W, const orc_layer* L, int nl, const double* params,
                      double* prob, int nthreads) {
@@ -487,7 +549,7 @@ int orc_forward_full(const uint8_t* vol, int Z, int H, int W, const orc_layer* L
 int orc_trace(const uint8_t* img, int H, int W, const orc_layer* L, int nl,
               const double* params, int qmode, const double* act_scale, int32_t* dims, double** bufs) {
   double** tr = (double**)calloc(nl, sizeof(double*));
-  int rc = forward_slice(img, H, W, L, nl, params, qmode, act_scale, NULL, NULL, tr, dims, 0);
+  int rc = forward_slice(img, NULL, 1, H, W, L, nl, params, qmode, act_scale, NULL, NULL, tr, dims, 0);
   for (int l = 0; l < nl; ++l) {
     if (bufs && tr[l])
       memcpy(bufs[l], tr[l], sizeof(double) * (size_t)dims[3 * l] * dims[3 * l + 1] * dims[3 * l + 2]);

@@ -20,6 +20,12 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Wno-unused-result"]
 
 
+# Per-file extra flags. The MFMA throughput loop keeps its accumulators in the
+# VGPR form of the instructions: without it the register allocator rotates the
+# loop-carried accumulator tuples through AGPR copies every iteration.
+FILE_FLAGS = {"probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
@@ -30,7 +36,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(OUT_DIR, "obj", os.path.basename(src) + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         msg = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
         if r.returncode != 0:

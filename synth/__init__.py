@@ -12,5 +12,5 @@ from .nets import (  # noqa: F401
     calibrated_params, param_count, load_calibration,
 )
 from .workloads import (  # noqa: F401
-    CONFIGS, batch_tiles, student_patch_origins, mixed_difficulty_volume,
+    CONFIGS, batch_tiles, student_patch_origins, mixed_difficulty_volume, maskextend_maps,
 )

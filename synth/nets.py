@@ -16,7 +16,7 @@ dense output by replacing pooling with stride-1 max-filtering (Section 2.2,
   every later layer.
 
 A layer is a dict: ``{"kind": "conv", "k", "cin", "cout", "act"}`` with act in
-{"none", "relu", "sigmoid", "maxout", "softmax"}, or ``{"kind": "pool"}``
+{"none", "relu", "sigmoid", "maxout", "softmax", "softmax0"}, or ``{"kind": "pool"}``
 (2x2 window, stride 1), ``{"kind": "pool2"}`` (2x2 window, stride 2) or
 ``{"kind": "sub2"}`` (keep every second pixel in each direction).
 
@@ -64,8 +64,17 @@ NET_FM3 = [_conv(4, 1, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"), POOL2, 
 NET_FMSS = [_conv(4, 1, 64, "maxout"), SUB2, _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 64, "maxout"),
             POOL2, _conv(4, 32, 64, "maxout"), POOL2, _conv(4, 32, 2, "softmax")]
 
-NETS = {"A": NET_A, "B": NET_B, "S": NET_S, "FM": NET_FM, "FMSS": NET_FMSS, "FM3": NET_FM3}
-WEIGHT_SEEDS = {"A": 100, "B": 200, "S": 300, "FM": 400, "FMSS": 410, "FM3": 420}
+# MaskExtend (Section 3, "MaskExtend: sparse segmentation via CNN"), under the
+# reading stated in the design notes: twelve input maps; four pairs of a 4x4
+# conv with max-out to 32, 40, 48, 56 features and a 2x2 stride-2 pool, a fifth
+# 4x4 conv with max-out to 64 features, and a 1x1 conv to the three classes
+# (object, other neurons, membrane) with a softmax; the map is the object
+# class's probability. Field of view 109.
+NET_ME = [_conv(4, 12, 64, "maxout"), POOL2, _conv(4, 32, 80, "maxout"), POOL2, _conv(4, 40, 96, "maxout"),
+          POOL2, _conv(4, 48, 112, "maxout"), POOL2, _conv(4, 56, 128, "maxout"), _conv(1, 64, 3, "softmax0")]
+
+NETS = {"A": NET_A, "B": NET_B, "S": NET_S, "FM": NET_FM, "FMSS": NET_FMSS, "FM3": NET_FM3, "ME": NET_ME}
+WEIGHT_SEEDS = {"A": 100, "B": 200, "S": 300, "FM": 400, "FMSS": 410, "FM3": 420, "ME": 500}
 CALIBRATION_SEED = 99
 CALIBRATION_SHAPE = (1, 256, 256)
 

@@ -79,3 +79,30 @@ def mixed_difficulty_volume(seed: int, Z: int, H: int, W: int, tile: int = 512,
         else:
             vol[z] = easy
     return vol, hard
+
+
+def maskextend_maps(seed: int, Z: int, H: int, W: int) -> np.ndarray:
+    """Synthetic input of MaskExtend (Section 3): for each of Z output sections
+    the twelve maps the paper stacks, as float32 Z x H x W x 12 (channel
+    fastest). The paper's EM, object masks and membrane maps are not available;
+    the stand-ins come from an EM-like stack E of Z + 6 sections (em_slice with
+    this seed), section s = z + 4 for output z:
+
+    * channels 0-2: E[s-1], E[s], E[s+1] / 255 (the three EM sections);
+    * channels 3-6: object masks of sections s-4 .. s-1, 1 where the section
+      blurred with sigma 2 exceeds 150 (bright cell interiors), else 0;
+    * channels 7-11: membrane probabilities of sections s-2 .. s+2, a logistic
+      of the section blurred with sigma 1: 1 / (1 + exp((b - 120) / 15)).
+    """
+    from scipy.ndimage import gaussian_filter
+    E = np.stack([em_slice(seed, k, H, W) for k in range(Z + 6)]).astype(np.float64)
+    mask = np.stack([(gaussian_filter(e, 2.0) > 150.0) for e in E]).astype(np.float64)
+    prob = np.stack([1.0 / (1.0 + np.exp((gaussian_filter(e, 1.0) - 120.0) / 15.0)) for e in E])
+    out = np.empty((Z, H, W, 12), dtype=np.float32)
+    for z in range(Z):
+        s = z + 4
+        chans = [E[s - 1] / 255.0, E[s] / 255.0, E[s + 1] / 255.0]
+        chans += [mask[k] for k in range(s - 4, s)]
+        chans += [prob[k] for k in range(s - 2, s + 3)]
+        out[z] = np.stack(chans, axis=-1)
+    return out

@@ -66,7 +66,10 @@ def test_mfma_probe_accumulation(emcnn, prec, bound, chain):
         got = d.cpu().numpy().astype(np.float64).reshape(nt, 4, 16, 4).transpose(0, 1, 3, 2).reshape(nt, 16, 16)
         err = np.abs(got - exact)
         ratio = (err / np.where(mag > 0, mag, 1.0)).max()
-        print("%s %s chain %d: max |D - exact| / sum|ab| = %.3g (bound %.3g)" % (prec, kind, chain, ratio, bound))
+        big = np.einsum("tcgme,tcgne->tcgmne", np.abs(A), np.abs(B)).max(axis=(1, 2, 5)) if E <= 32 else None
+        rmax = (err / np.where(big > 0, big, 1.0)).max() if big is not None else float("nan")
+        print("%s %s chain %d: max |D - exact| / sum|ab| = %.3g (bound %.3g); / max|ab| = %.3g"
+              % (prec, kind, chain, ratio, bound, rmax))
         if kind == "small":
             assert np.array_equal(got, exact)
         else:
