@@ -43,6 +43,8 @@ FASTMEMB_FLOP_PER_VOXEL = 2 * 16 * (64 + 32 * 64 + 32 * 64 + 32 * 2)
 FASTMEMB_BODY_FLOP_PER_POS = 2 * 16 * 32 * 64  # one 32 -> 64 4x4 conv output position
 # FastMemb_ss per 6 nm output voxel: the 1 -> 64 conv only where the subsample keeps pixels, three 32 -> 64 convs
 FASTMEMB_SS_FLOP_PER_VOXEL = 2 * 16 * (64 + 3 * 32 * 64 + 32 * 2)
+# MaskExtend per output voxel: five 4x4 convs (12->64, 32->80, 40->96, 48->112, 56->128), 1x1 64->3
+MASKEXTEND_FLOP_PER_VOXEL = 2 * 16 * (12 * 64 + 32 * 80 + 40 * 96 + 48 * 112 + 56 * 128) + 2 * 64 * 3
 
 
 def log(*a):
@@ -243,6 +245,45 @@ def fastmemb_ss_form(emcnn, torch, em_volume, calibrated_params, dev, stream, ar
     return res
 
 
+def maskextend_form(emcnn, torch, dev, stream, args):
+    """MaskExtend (Section 3; the reading in the design notes) in FP32 on
+    8 x 1024 x 1024 sections of twelve synthetic input maps (EM, object masks,
+    membrane maps; synth.maskextend_maps) -> 8 x 916 x 916 object probabilities."""
+    from synth import maskextend_maps
+    from synth.nets import NET_ME, he_normal_params
+    Z = 4 if args.quick else 8
+    t0 = time.perf_counter()
+    maps = torch.from_numpy(maskextend_maps(6, Z, 1024, 1024)).to(dev)
+    log("generated MaskExtend maps %s in %.1fs" % (tuple(maps.shape), time.perf_counter() - t0))
+    h = emcnn.cnn_create(he_normal_params(NET_ME, 500), NET_ME, "fp32")
+    out = emcnn.cnn_infer_maps(h, maps)
+    torch.cuda.synchronize()
+    reps = max(3, args.steps // 2)
+    with torch.cuda.stream(stream):
+        emcnn.cnn_infer_maps(h, maps, out=out, stream=stream)
+        torch.cuda.synchronize()
+        emcnn.cnn_profile_read(h)
+        emcnn.cnn_profile(h, True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            emcnn.cnn_infer_maps(h, maps, out=out, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        emcnn.cnn_profile(h, False)
+    ms, n = emcnn.cnn_profile_read(h)
+    nv = out.numel()
+    res = {"workload": "MaskExtend FP32 (12 input maps; 4x4 max-out convs to 32/40/48/56/64 features with 2x2/s2 "
+                       "pools; 1x1 three-class softmax; FoV 109) on %d x 1024 x 1024 x 12 -> %d x 916 x 916"
+                       % (Z, Z),
+           "voxels_per_s": nv / dt, "ms_per_pass": dt * 1e3,
+           "path_tflops": nv * MASKEXTEND_FLOP_PER_VOXEL / dt / 1e12,
+           "path_mfma_frac": nv * MASKEXTEND_FLOP_PER_VOXEL / dt / 1e12 / PEAK_TFLOPS["fp32"],
+           "layer_ms": [m / c if c else 0.0 for m, c in zip(ms[:6], n[:6])], "tiles": emcnn.cnn_describe(h)}
+    log("maskextend", json.dumps(res))
+    del maps, out, h
+    return res
+
+
 def watershed_form(emcnn, torch, pmap, stream, reps=5):
     """The 3-D watershed (Section 2.1, over-segmentation) on the headline
     membrane map (32 x 1012 x 1012 FP32), seeds below its 25 % quantile.
@@ -298,7 +339,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="all",
                     help="all | none | comma list of mfma,watershed,bf16,fp8,batch,student,fastmemb,"
-                         "fastmemb_bf16,fastmemb_ss")
+                         "fastmemb_bf16,fastmemb_ss,maskextend")
     ap.add_argument("--quick", action="store_true",
                     help="smaller secondary forms: precision / student volume 8 x 2048^2, 4k training steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -378,7 +419,7 @@ def main():
         forms["watershed"] = watershed_form(emcnn, torch, out, stream)
     del out
     want = set() if args.forms == "none" else (
-        {"mfma", "bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16", "fastmemb_ss"}
+        {"mfma", "bf16", "fp8", "batch", "student", "fastmemb", "fastmemb_bf16", "fastmemb_ss", "maskextend"}
         if args.forms == "all"
         else set(args.forms.split(",")))
     if "mfma" in want:
@@ -406,6 +447,8 @@ def main():
             "layer_ms": plf[:4], "tiles": emcnn.cnn_describe(hf)}
         log(key, json.dumps(forms[key]))
         del outf, hf
+    if "maskextend" in want:
+        forms["maskextend"] = maskextend_form(emcnn, torch, dev, stream, args)
     if "fastmemb_ss" in want and not args.no_headline:
         forms["fastmemb_ss"] = fastmemb_ss_form(emcnn, torch, em_volume, calibrated_params, dev, stream, args,
                                                 forms)

@@ -60,7 +60,8 @@ enum cnn_act {
   CNN_ACT_RELU = 1,
   CNN_ACT_SIGMOID = 2,
   CNN_ACT_MAXOUT = 3,  /* max over channel pairs (2c, 2c+1): cout / 2 channels out */
-  CNN_ACT_SOFTMAX = 4  /* two classes; the output map is the class-1 (membrane) probability */
+  CNN_ACT_SOFTMAX = 4, /* two classes; the output map is the class-1 (membrane) probability */
+  CNN_ACT_SOFTMAX0 = 5 /* softmax over cout classes; the output map is class 0's probability */
 };
 enum cnn_precision { CNN_PREC_FP32 = 0, CNN_PREC_BF16 = 1, CNN_PREC_FP8 = 2 };
 
@@ -109,7 +110,11 @@ typedef struct cnn_net cnn_net;
  * a pool before the pairs (FastMemb_ss, Section 2.2, "A subsampling CNN for
  * 3 nm data": a 3 nm stack gives a 6 nm map); only the kept fragment is
  * computed: the first conv at every second row and column, the rest densely
- * on that half-resolution map.
+ * on that half-resolution map. FP32 nets may instead start with
+ * conv(k=4, C -> 2F, MAXOUT) on C > 1 real-valued maps (cnn_infer_maps), use
+ * any widths conv(k=4, F -> 2F', MAXOUT) that the library has kernels for, and
+ * end with a conv(1x1, F -> n, SOFTMAX0) right after the last conv: MaskExtend
+ * (Section 3) has C = 12 and widths 32, 40, 48, 56, 64 with three classes.
  * weights: host float64, for each conv in order W[cout][cin][k][k] (C order)
  *   followed by b[cout]; n_weights must equal that total. Copied, then packed
  *   and quantised once here:
@@ -152,6 +157,14 @@ int cnn_output_dims(const cnn_net* net, int64_t H, int64_t W, int64_t* Ho, int64
  * it may make). */
 int cnn_infer(cnn_net* net, const uint8_t* volume_u8, const int64_t dims[3], float* prob_out,
               void* stream);
+
+/* Dense inference of a net whose first conv reads C > 1 real-valued input
+ * maps (MaskExtend, Section 3: EM sections, object masks and membrane maps
+ * stacked as the input of one section), FP32.
+ * maps: device, Z x H x W x C float32 (C fastest), taken as they are (no
+ * scaling); dims: host {Z, H, W, C} with C the first conv's cin.
+ * prob_out: device, Z x (H-R) x (W-R) float32. Otherwise as cnn_infer. */
+int cnn_infer_maps(cnn_net* net, const float* maps, const int64_t dims[4], float* prob_out, void* stream);
 
 /* cnn_infer for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.

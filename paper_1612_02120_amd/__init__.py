@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libemcnn.so")
 
 CNN_OK, CNN_EINVAL, CNN_ENOMEM, CNN_EHIP, CNN_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
-_ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4}
+_ACT = {"none": 0, "relu": 1, "sigmoid": 2, "maxout": 3, "softmax": 4, "softmax0": 5}
 _POOL_KIND = {"pool": 1, "pool2": 2, "sub2": 3}  # 2x2 window, stride 1 / stride 2; 2x subsample
 
 
@@ -61,7 +61,7 @@ EXPORTS = [
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
     "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
     "cnn_infer_noalloc", "student_gather", "cnn_read_activation", "cnn_mfma_probe", "cnn_mfma_bench",
-    "cnn_output_dims", "watershed_3d",
+    "cnn_output_dims", "watershed_3d", "cnn_infer_maps",
 ]
 
 
@@ -78,6 +78,7 @@ def _load():
         "watershed_3d": [vp, vp, f32, vp, vp, vp],
         "cnn_infer": [vp, vp, vp, vp, vp],
         "cnn_infer_noalloc": [vp, vp, vp, vp, vp],
+        "cnn_infer_maps": [vp, vp, vp, vp, vp],
         "cnn_read_activation": [vp, i32, vp, i64, vp, vp],
         "cnn_mfma_probe": [i32, vp, vp, vp, i32, i32, vp],
         "cnn_mfma_bench": [i32, i32, i32, vp, vp, vp, vp],
@@ -250,6 +251,24 @@ def cnn_infer(net: Net, volume, out=None, stream=None):
     _on_device(volume=volume, out=out)
     _check(_lib.cnn_infer(net.ptr, _ptr(volume), _dims(volume), _ptr(out), _stream(stream)),
            "cnn_infer")
+    return out
+
+
+def cnn_infer_maps(net: Net, maps, out=None, stream=None):
+    """maps: CUDA float32 Z x H x W x C (the net's first-conv input maps);
+    returns (or fills) CUDA float32 Z x (H-R) x (W-R)."""
+    import torch
+    if not isinstance(maps, torch.Tensor) or maps.dim() != 4:
+        raise ValueError("maps must be a Z x H x W x C tensor")
+    _check_buf(maps, torch.float32, "maps")
+    Z, H, W, C = (int(v) for v in maps.shape)
+    Ho, Wo = net.out_dims(H, W) if net.ptr else (H - net.R, W - net.R)
+    if out is None:
+        out = torch.empty((Z, max(Ho, 0), max(Wo, 0)), dtype=torch.float32, device=maps.device)
+    _check_buf(out, torch.float32, "out", shape=(Z, Ho, Wo))
+    _on_device(maps=maps, out=out)
+    dims = (ctypes.c_int64 * 4)(Z, H, W, C)
+    _check(_lib.cnn_infer_maps(net.ptr, _ptr(maps), dims, _ptr(out), _stream(stream)), "cnn_infer_maps")
     return out
 
 

@@ -90,7 +90,9 @@ struct VariantInfo {
                         // 1-channel k x k first layer (and the max filter) itself
   int epi;              // epilogue: 0 bias + ReLU (or the fused 1x1 sigmoid head),
                         // 1 bias + max-out over channel pairs (stores cout / 2 channels),
-                        // 2 bias + two-class softmax of channels 0, 1 (stores the class-1 probability)
+                        // 2 bias + two-class softmax of channels 0, 1 (stores the class-1 probability),
+                        // 3 the two-class softmax layer on the VALU (head_phase),
+                        // 4 a 1x1 conv to cout classes with a softmax, storing class 0 (head_1x1)
   int lds_bytes;        // LDS of the staged operand tiles and weights (descriptive; launches and
                         // occupancy take the kernel's own static LDS, epilogue scratch included)
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)

@@ -1142,9 +1142,12 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
             for (int nb = 0; nb < C::NB; ++nb)
               *reinterpret_cast<float*>(scr + (4 * g + 2 * h + e) * PIXB + (nb * 8 + pc) * 4) = keep[h][nb];
           __builtin_amdgcn_wave_barrier();
+          // 16 pixels x PIXB / 16 chunks = PIXB chunks of 16 bytes (40 or 56
+          // stored channels leave a partly filled last round)
 #pragma unroll
-          for (int h = 0; h < PIXB / 64; ++h) {
+          for (int h = 0; h < (PIXB + 63) / 64; ++h) {
             const int c = h * 64 + lane;  // 16-byte chunk: pixel c / (PIXB / 16)
+            if (PIXB % 64 != 0 && c >= PIXB) break;
             const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
             const int x = px + d * (x0 + mcol * 16 + c / (PIXB / 16));
             if (y < J.hout && x < J.wout)
@@ -1285,6 +1288,51 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
     if (y < J.hout && x < J.wout)
       st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs)) * 4,
                 sigmoid_f((z1 + b1) - (z0 + b0)));
+  }
+}
+
+// A 1x1 conv to NCLS classes with a softmax, keeping class 0's probability:
+// the output layer of a multi-class net (MaskExtend), on the VALU, one output
+// pixel per thread. Input: row-major NHWC FP32 maps of CIN channels, read as
+// 16-byte chunks; weights [class][CIN] and biases read with scalar loads.
+// The softmax subtracts the largest logit before exponentiating.
+template <int CIN, int NCLS, int TX>
+__global__ __launch_bounds__(TX) void head_1x1(JobSet js, ConvParams prm) {
+  static_assert(CIN % 4 == 0 && NCLS >= 2 && NCLS <= 4, "4-channel chunks, 2 to 4 classes");
+  const __attribute__((address_space(4))) float* wk = (const __attribute__((address_space(4))) float*)prm.wpack;
+  const __attribute__((address_space(4))) float* bk = (const __attribute__((address_space(4))) float*)prm.bias;
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int y = (int)(t2 % J.tiles_y);
+    const int zz = (int)(t2 / J.tiles_y);
+    const int x = bx * TX + (int)threadIdx.x;
+    if (x >= J.wout) continue;
+    const gbyte* px = gin(J.in) + ((int64_t)zz * J.in_zs + (int64_t)y * J.in_rs + x) * (CIN * 4);
+    float z[NCLS];
+#pragma unroll
+    for (int k = 0; k < NCLS; ++k) z[k] = bk[k];
+#pragma unroll
+    for (int c = 0; c < CIN / 4; ++c) {
+      const f4 v = ld<f4>(px + c * 16);
+#pragma unroll
+      for (int k = 0; k < NCLS; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) z[k] = fmaf(v[e], wk[k * CIN + 4 * c + e], z[k]);
+    }
+    float m = z[0];
+#pragma unroll
+    for (int k = 1; k < NCLS; ++k) m = fmaxf(m, z[k]);
+    float den = 0.f;
+#pragma unroll
+    for (int k = 0; k < NCLS; ++k) den += expf(z[k] - m);
+    st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + (int64_t)y * J.out_rs + x) * 4, expf(z[0] - m) / den);
   }
 }
 
@@ -2117,6 +2165,10 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<P, CIN, KS, TY, TX>),       \
               "head_phase<" #P "," #CIN "," #KS "," #TY "," #TX ">"}
 
+#define EMCNN_HEAD1(P, CIN, NCLS, TX)                                                                    \
+  VariantInfo{P, CIN, NCLS, 1, 0, 0, 1, TX, 0, TX, CIN, PT<F32>::CHB, 1, 0, 0, 0, 4, 0,                     \
+              reinterpret_cast<const void*>(&head_1x1<CIN, NCLS, TX>), "head_1x1<" #CIN "," #NCLS "," #TX ">"}
+
 // Pipelined (BF16 / FP8) tile shapes: TY x TX outputs, consumer x producer
 // waves, per layer signature (shapes that fit the LDS and the 168 registers
 // of a 12-wave workgroup without spilling).
@@ -2195,6 +2247,12 @@ static const VariantInfo kConv[] = {
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 16),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(BF16, 32, 64, 4, 16, 64, 8, 1, 32),
     EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
+    // MaskExtend (FP32): twelve input maps, max-out convs to 32, 40, 48, 56, 64
+    // features (channels staged per LDS pass chosen to fit 160 KB with the
+    // 8 (mod 16) dword pixel stride), the 1x1 three-class softmax on the VALU
+    EMCNN_PHASE(F32, 12, 64, 4, 8, 64, 4, 1, 12), EMCNN_PHASE(F32, 32, 80, 4, 8, 64, 4, 1, 32),
+    EMCNN_PHASE(F32, 40, 96, 4, 8, 64, 4, 1, 40), EMCNN_PHASE(F32, 48, 112, 4, 8, 64, 4, 1, 24),
+    EMCNN_PHASE(F32, 56, 128, 4, 8, 64, 4, 1, 28), EMCNN_HEAD1(F32, 64, 3, 256),
 };
 
 #define EMCNN_FIRSTS(PO, COUT, KS, TY, TX, MX, ST)                                                   \

@@ -217,8 +217,8 @@ int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, fl
   net->last_half = zs * b0;
   for (int64_t z0 = 0; z0 < Z; z0 += zs) {
     const int zc = (int)std::min<int64_t>(zs, Z - z0);
-    rc = run_region(net, vol + z0 * H * W, W, H * W, zc, (int)H, (int)W, prob + z0 * Ho * Wo, Wo, Ho * Wo, buf0, buf1,
-                    st, true);
+    rc = run_region(net, vol + z0 * H * W * net->in_elb, W, H * W, zc, (int)H, (int)W, prob + z0 * Ho * Wo, Wo,
+                    Ho * Wo, buf0, buf1, st, true);
     if (rc) return rc;
   }
   return CNN_OK;
@@ -554,6 +554,7 @@ extern "C" int cnn_infer(cnn_net* h, const uint8_t* vol, const int64_t dims[3], 
   clear_error();
   if (!h || !vol || !dims || !prob) return fail(CNN_EINVAL, "cnn_infer: null argument");
   Net* net = reinterpret_cast<Net*>(h);
+  if (net->in_channels != 1) return fail(CNN_EINVAL, "cnn_infer: this net reads real-valued maps (cnn_infer_maps)");
   const int64_t Z = dims[0], H = dims[1], W = dims[2];
   if (Z < 1 || H < net->R + 1 || W < net->R + 1)
     return fail(CNN_EINVAL, "cnn_infer: dims smaller than the field of view (" + std::to_string(net->R + 1) + ")");
@@ -564,10 +565,28 @@ extern "C" int cnn_infer(cnn_net* h, const uint8_t* vol, const int64_t dims[3], 
   return run_volume(net, vol, Z, H, W, prob, reinterpret_cast<hipStream_t>(stream));
 }
 
+extern "C" int cnn_infer_maps(cnn_net* h, const float* maps, const int64_t dims[4], float* prob, void* stream) {
+  clear_error();
+  if (!h || !maps || !dims || !prob) return fail(CNN_EINVAL, "cnn_infer_maps: null argument");
+  Net* net = reinterpret_cast<Net*>(h);
+  const int64_t Z = dims[0], H = dims[1], W = dims[2], C = dims[3];
+  if (net->in_channels == 1 || C != net->in_channels)
+    return fail(CNN_EINVAL, "cnn_infer_maps: the net's first conv takes " + std::to_string(net->in_channels) +
+                                " input maps (nets on one uint8 channel use cnn_infer)");
+  if (Z < 1 || H < net->R + 1 || W < net->R + 1)
+    return fail(CNN_EINVAL, "cnn_infer_maps: dims smaller than the field of view (" + std::to_string(net->R + 1) + ")");
+  if (H >= (1ll << 30) || W >= (1ll << 30) || Z >= (1ll << 30))
+    return fail(CNN_EINVAL, "cnn_infer_maps: dims must be < 2^30");
+  int rc = check_device(net);
+  if (rc) return rc;
+  return run_volume(net, reinterpret_cast<const uint8_t*>(maps), Z, H, W, prob, reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" int cnn_infer_noalloc(cnn_net* h, const uint8_t* vol, const int64_t dims[3], float* prob, void* stream) {
   clear_error();
   if (!h || !vol || !dims || !prob) return fail(CNN_EINVAL, "cnn_infer_noalloc: null argument");
   Net* net = reinterpret_cast<Net*>(h);
+  if (net->in_channels != 1) return fail(CNN_EUNSUPPORTED, "cnn_infer_noalloc: nets on one uint8 channel only");
   const int64_t Z = dims[0], H = dims[1], W = dims[2];
   if (Z < 1 || H < net->R + 1 || W < net->R + 1)
     return fail(CNN_EINVAL, "cnn_infer_noalloc: dims smaller than the field of view (" + std::to_string(net->R + 1) +
@@ -658,8 +677,9 @@ extern "C" int cnn_infer_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, voi
   Net* net = reinterpret_cast<Net*>(h);
   int rc = check_device(net);
   if (rc) return rc;
-  if (net->R % 2 || net->out_stride != 1)
-    return fail(CNN_EUNSUPPORTED, "cnn_infer_batch: blocks need an odd field of view and a full-resolution output");
+  if (net->R % 2 || net->out_stride != 1 || net->in_channels != 1)
+    return fail(CNN_EUNSUPPORTED,
+                "cnn_infer_batch: blocks need an odd field of view, a full-resolution output and uint8 input");
   const int R2 = net->R / 2;
   std::vector<Region> regs(n);
   for (int t = 0; t < n; ++t) {
@@ -737,6 +757,7 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   Net* net = reinterpret_cast<Net*>(h);
   if (H < net->R + 1 || W < net->R + 1 || H > 16384 || W > 16384)
     return fail(CNN_EINVAL, "cnn_autotune: need R+1 <= H, W <= 16384");
+  if (net->in_channels != 1) return fail(CNN_EUNSUPPORTED, "cnn_autotune: nets on one uint8 channel only");
   int rc = check_device(net);
   if (rc) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

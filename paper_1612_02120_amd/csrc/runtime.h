@@ -53,6 +53,8 @@ struct Net {
   int prec = 0;
   int R = 0;
   int out_stride = 1;  // 2 for nets with a 2x subsample: output (y, x) is the window at input (2y, 2x)
+  int in_channels = 1;  // > 1: the input is real-valued maps, NHWC float32 (cnn_infer_maps)
+  int in_elb = 1;       // bytes per input pixel: 1 (uint8) or 4 in_channels
   int num_cus = 256;
   std::string arch;
   std::vector<ExecLayer> layers;

@@ -285,6 +285,26 @@ static int pack_head_valu(ExecLayer& L, int variant, const double* w, const doub
   return CNN_OK;
 }
 
+// Weights of a 1x1 multi-class output conv (head_1x1): W[class][cin] and the
+// biases, FP32 as given.
+static int pack_head1(ExecLayer& L, int variant, const double* w, const double* b) {
+  const VariantInfo* v = conv_variant(variant);
+  std::vector<float> pk((size_t)v->cout * v->cin), bf(v->cout);
+  for (size_t i = 0; i < pk.size(); ++i) pk[i] = (float)w[i];
+  for (int k = 0; k < v->cout; ++k) bf[k] = (float)b[k];
+  hipError_t err;
+  void* wdev = nullptr;
+  if ((err = hipMalloc(&wdev, pk.size() * 4)) != hipSuccess) return hip_fail(err, "hipMalloc(head weights)");
+  L.wpacks.push_back(wdev);
+  if ((err = hipMemcpy(wdev, pk.data(), pk.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "hipMemcpy(head weights)");
+  if (L.bias) return CNN_OK;
+  if ((err = hipMalloc(&L.bias, bf.size() * 4)) != hipSuccess) return hip_fail(err, "hipMalloc(head bias)");
+  if ((err = hipMemcpy(L.bias, bf.data(), bf.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "hipMemcpy(head bias)");
+  return CNN_OK;
+}
+
 static void free_layer(ExecLayer& L) {
   for (void* p : L.wpacks)
     if (p) hipFree(p);
@@ -313,9 +333,12 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
     return fail(CNN_EUNSUPPORTED, "cnn_create: stride-2 pool nets: " + why);
   };
   const cnn_layer& l0 = Lr[0];
-  if (l0.kind != CNN_LAYER_CONV || l0.k != 4 || l0.cin != 1 || l0.cout != 64 || l0.act != CNN_ACT_MAXOUT)
-    return unsupported("the first layer must be conv(4, 1 -> 64, max-out)");
+  const bool maps = l0.cin > 1;  // real-valued input maps (MaskExtend) instead of one uint8 channel
+  if (l0.kind != CNN_LAYER_CONV || l0.k != 4 || l0.act != CNN_ACT_MAXOUT || (!maps && l0.cout != 64))
+    return unsupported("the first layer must be conv(4, C -> 2F, max-out) (C = 1: F = 32)");
+  if (maps && prec != CNN_PREC_FP32) return unsupported("nets on real-valued input maps are FP32");
   const bool sub = nl > 1 && Lr[1].kind == CNN_LAYER_SUBSAMPLE2;
+  if (sub && maps) return unsupported("a subsample after a multi-channel first layer");
   // layer indices of the convs, and of the pool before each (-1: none)
   std::vector<int> conv_at{0}, pool_at{-1};
   int i = 1;
@@ -325,19 +348,28 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
     pool_at.push_back(-1);
     i = 3;
   }
-  for (; i < nl; i += 2) {
-    if (i + 1 >= nl || Lr[i].kind != CNN_LAYER_MAXPOOL_S2)
+  while (i < nl) {
+    if (Lr[i].kind == CNN_LAYER_MAXPOOL_S2 && i + 1 < nl && Lr[i + 1].kind == CNN_LAYER_CONV) {
+      conv_at.push_back(i + 1);
+      pool_at.push_back(i);
+      i += 2;
+    } else if (i == nl - 1 && Lr[i].kind == CNN_LAYER_CONV && Lr[i].k == 1 && Lr[i].act == CNN_ACT_SOFTMAX0) {
+      conv_at.push_back(i);  // a 1x1 multi-class output right after the last conv
+      pool_at.push_back(-1);
+      i += 1;
+    } else {
       return unsupported("after the first conv (and a subsample), expected (stride-2 pool, conv) pairs");
-    conv_at.push_back(i + 1);
-    pool_at.push_back(i);
+    }
   }
-  if (conv_at.size() < 3) return unsupported("expected at least one inner conv before the softmax conv");
+  if (conv_at.size() < 3) return unsupported("expected at least one inner conv before the output conv");
   for (size_t c = 1; c < conv_at.size(); ++c) {
     const cnn_layer& l = Lr[conv_at[c]];
     const bool last = c + 1 == conv_at.size();
-    if (l.kind != CNN_LAYER_CONV || l.k != 4 || l.cin != 32 ||
-        (last ? (l.cout != 2 || l.act != CNN_ACT_SOFTMAX) : (l.cout != 64 || l.act != CNN_ACT_MAXOUT)))
-      return unsupported("inner convs are conv(4, 32 -> 64, max-out), the last conv(4, 32 -> 2, softmax)");
+    if (last && l.act == CNN_ACT_SOFTMAX0) continue;  // 1x1 output: checked by kernel availability
+    if (l.kind != CNN_LAYER_CONV || l.k != 4 ||
+        (last ? (l.cin != 32 || l.cout != 2 || l.act != CNN_ACT_SOFTMAX) : l.act != CNN_ACT_MAXOUT))
+      return unsupported("inner convs are conv(4, F -> 2F', max-out), the last conv(4, 32 -> 2, softmax) or a "
+                         "1x1 softmax over classes");
     if (last && pool_at[c] < 0) return unsupported("the softmax conv must follow a stride-2 pool");
   }
   const double* wp = weights;
@@ -353,7 +385,20 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
     E.cin = l.cin;
     E.spaced = 1;
     int rc = CNN_OK;
-    if (c == 0) {
+    if (c == 0 && maps) {
+      // a spaced conv straight on the caller's NHWC float maps: no max filter, spacing 1
+      E.cout = l.cout;
+      E.cstore = l.cout / 2;
+      E.epi = 1;
+      E.pool_in = 0;
+      E.pd = 0;
+      E.dil = 1;
+      E.candidates = find_conv_variants(prec, l.cin, l.cout, l.k, 1, 0, 1);
+      if (E.candidates.empty()) return unsupported("no kernel for a first conv " + std::to_string(l.cin) + " -> " +
+                                                   std::to_string(l.cout));
+      for (int v : E.candidates)
+        if (rc == CNN_OK) rc = pack_conv(E, v, w, b, nullptr, 0.0, 1.0, 0.0);
+    } else if (c == 0) {
       E.first = 1;
       E.cout = l.cout;
       E.cstore = l.cout / 2;
@@ -363,6 +408,18 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       if (E.candidates.empty()) return unsupported("no first-layer kernel");
       for (int v : E.candidates)
         if (rc == CNN_OK) rc = pack_first(E, v, w, b, 0.0);
+    } else if (l.act == CNN_ACT_SOFTMAX0) {
+      // 1x1 output conv over the classes (row-major input, no spacing)
+      E.spaced = 0;
+      E.cout = l.cout;
+      E.cstore = 1;
+      E.epi = 4;
+      E.dil = 1;
+      E.candidates = find_conv_variants(prec, l.cin, l.cout, 1, 0, 0, 4);
+      if (E.candidates.empty()) return unsupported("no kernel for a 1x1 softmax over " + std::to_string(l.cout) +
+                                                   " classes from " + std::to_string(l.cin) + " channels");
+      for (int v : E.candidates)
+        if (rc == CNN_OK) rc = pack_head1(E, v, w, b);
     } else {
       if (pool_at[c] >= 0) {
         E.pool_in = 1;
@@ -402,7 +459,9 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
         // the spaced kernels take the max filter's spacing from the job: the
         // same kernels serve a conv without a max filter (spacing 0)
         E.candidates = find_conv_variants(prec, l.cin, E.cout, l.k, 1, 0, E.epi);
-        if (E.candidates.empty()) return unsupported("no MFMA kernel for conv " + std::to_string(c));
+        if (E.candidates.empty())
+          return unsupported("no MFMA kernel for conv " + std::to_string(c) + " (" + std::to_string(l.cin) + " -> " +
+                             std::to_string(l.cout) + ")");
         for (int v : E.candidates)
           if (rc == CNN_OK) rc = pack_conv(E, v, w, b, nullptr, 0.0, 1.0, 0.0);
       }
@@ -419,6 +478,8 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
   }
   if (!sub && off != net->R) return fail(CNN_EINVAL, "cnn_create: internal radius mismatch");
   net->out_stride = sub ? 2 : 1;
+  net->in_channels = maps ? l0.cin : 1;
+  net->in_elb = maps ? 4 * l0.cin : 1;
   // every map but the output feeds a spaced conv: stored fragment-major modulo its spacing
   for (size_t l = 0; l + 1 < net->layers.size(); ++l) net->layers[l].out_lg = __builtin_ctz(net->layers[l + 1].dil);
   return CNN_OK;
@@ -479,13 +540,14 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
   // r += (k - 1) j, j *= stride (a 2x2 pool counts as k = 2)
   int64_t expect = 0;
   int R = 0;
-  int C = 1;
+  // input channels: one uint8 channel, or real-valued maps (the first conv's cin)
+  int C = spec->layers[0].kind == CNN_LAYER_CONV && spec->layers[0].cin > 1 ? spec->layers[0].cin : 1;
   int sp = 1;  // input spacing j of the current layer
   bool strided = false;  // stride-2 pools, max-out or softmax: the FastMemb family
   for (int i = 0; i < spec->n_layers; ++i) {
     const cnn_layer& l = spec->layers[i];
     if (l.kind == CNN_LAYER_CONV) {
-      if (l.k < 1 || l.cin != C || l.cout < 1 || (l.act < 0 || l.act > CNN_ACT_SOFTMAX))
+      if (l.k < 1 || l.cin != C || l.cout < 1 || (l.act < 0 || l.act > CNN_ACT_SOFTMAX0))
         return fail(CNN_EINVAL, "cnn_create: bad conv layer " + std::to_string(i));
       expect += (int64_t)l.cout * l.cin * l.k * l.k + l.cout;
       R += (l.k - 1) * sp;
@@ -496,6 +558,10 @@ extern "C" int cnn_create(const double* weights, int64_t n_weights, const cnn_la
         strided = true;
       } else if (l.act == CNN_ACT_SOFTMAX) {
         if (l.cout != 2) return fail(CNN_EINVAL, "cnn_create: softmax output needs two classes");
+        C = 1;
+        strided = true;
+      } else if (l.act == CNN_ACT_SOFTMAX0) {
+        if (l.cout < 2) return fail(CNN_EINVAL, "cnn_create: a softmax over classes needs two or more");
         C = 1;
         strided = true;
       }

@@ -837,7 +837,7 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
   Net* net = reinterpret_cast<Net*>(th);
   const int64_t Z = dims[0], H = dims[1], W = dims[2];
   const int R = net->R;
-  if (R < 6 || (R - 6) % 2 || net->out_stride != 1)
+  if (R < 6 || (R - 6) % 2 || net->out_stride != 1 || net->in_channels != 1)
     return fail(CNN_EUNSUPPORTED, "fallback: teacher radius must be even and >= 6, output at full resolution");
   if (Z < 1 || Z > 65535 || H < R + 1 || W < R + 1 || H >= (1 << 30) || W >= (1 << 30))
     return fail(CNN_EINVAL, "fallback: bad dims");
