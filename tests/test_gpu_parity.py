@@ -4,10 +4,12 @@ Tolerances (max abs probability error): FP32 1e-5; BF16 2e-2 and FP8 6e-2
 against the exact reference. Against the reference's fake-quant form of the same
 number formats (exact accumulation of the rounded operands): BF16 2e-3 (rare
 one-ulp flips of an intermediate rounding); FP8 1e-2, because the gfx950
-16x16x128 f8f6f4 MFMA sums its 128 products with about 2^-13.6 relative
-precision (measured: error up to 8e-5 of sum|a b|, where FP32 accumulation
-gives 6e-8), which moves e4m3 codes of the next layer across rounding
-boundaries.
+16x16x128 f8f6f4 MFMA sums its 128 products with less precision than FP32
+(tests/bounds.py, measured by tests/test_gpu_mfma.py), which moves a few
+hundredths of a percent of the next layer's e4m3 codes across rounding
+boundaries; each such code then moves the probability by up to a few 1e-3.
+The element-wise, layer-by-layer pin of the FP8 and BF16 kernels is
+tests/test_gpu_layers.py.
 """
 import numpy as np
 import pytest
