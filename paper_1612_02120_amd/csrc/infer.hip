@@ -329,7 +329,7 @@ int arena_reserve(Net* net, size_t njobs) {
 // (group, layer, region) into the arena from `job_off` on and appends the
 // launches. Returns the workspace bytes needed in ws_need.
 int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off, std::vector<Launch>& launches,
-                 size_t& njobs_used, size_t& ws_need) {
+                 size_t& njobs_used, size_t& ws_need, bool dry) {
   const int nl = (int)net->layers.size();
   // per-region geometry; regions with too many slices are split by z
   std::vector<Region> regs;
@@ -375,9 +375,14 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
     groups.push_back({g0, n});
     ws_need = std::max(ws_need, s0 + s1);
   }
+  if (dry) return CNN_OK;  // only the workspace size was asked for
   const size_t need_jobs = job_off + (size_t)n * nl;
   Net::Arena& A = net->arena[net->cur];
   if (need_jobs * sizeof(LayerJob) > A.tab_host_bytes) return fail(CNN_EINVAL, "internal: job arena too small");
+  // growing the workspace frees the old one: jobs planned earlier into it (by
+  // a caller that plans several region lists before submitting) would be
+  // left pointing at freed memory, so such callers size the workspace first
+  // with dry runs (see the fallback in student.hip)
   int rc = ensure_ws(net, ws_need);
   if (rc) return rc;
   LayerJob* tab = reinterpret_cast<LayerJob*>(A.tab_host);

@@ -122,8 +122,11 @@ int ensure_ws(Net* net, size_t need);
 int run_volume(Net* net, const uint8_t* vol, int64_t Z, int64_t H, int64_t W, float* prob, hipStream_t st);
 int arena_reserve(Net* net, size_t njobs);
 size_t count_region_jobs(const Net* net, const std::vector<Region>& regs);
+// Plan the regions' launches into the job arena from job_off on; ws_need
+// receives the workspace bytes they need, which this call allocates (growing
+// frees the previous workspace). dry: compute ws_need only, write nothing.
 int plan_regions(Net* net, const std::vector<Region>& regs, size_t job_off, std::vector<Launch>& launches,
-                 size_t& njobs_used, size_t& ws_need);
+                 size_t& njobs_used, size_t& ws_need, bool dry = false);
 int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t njobs, hipStream_t st, bool graph);
 int launch_layer(Net* net, const ExecLayer& L, const JobSet& js, int grid, hipStream_t st, bool timed = true);
 int check_device(const Net* net);

@@ -932,10 +932,21 @@ extern "C" int student_infer_with_fallback(cnn_student* h, cnn_net* th, const ui
   if (rc) return rc;
   std::vector<Launch> l1, l2;
   size_t used1 = 0, used2 = 0, ws1 = 0, ws2 = 0;
+  // both passes are planned before either is submitted: size the shared
+  // workspace for the larger one first, so that planning the second cannot
+  // reallocate the workspace the first one's jobs point into
+  rc = plan_regions(net, sample_regs, 0, l1, used1, ws1, true);
+  if (rc) return rc;
+  rc = plan_regions(net, rerun_regs, 0, l2, used2, ws2, true);
+  if (rc) return rc;
+  rc = ensure_ws(net, std::max(ws1, ws2));
+  if (rc) return rc;
+  const void* ws_before = net->ws;
   rc = plan_regions(net, sample_regs, 0, l1, used1, ws1);
   if (rc) return rc;
   rc = plan_regions(net, rerun_regs, used1, l2, used2, ws2);
   if (rc) return rc;
+  if (net->ws != ws_before) return fail(CNN_EHIP, "fallback: internal: workspace moved during planning");
   // 2) student everywhere, in the teacher's output frame
   rc = student_launch(s, vol, Z, H, W, prob, Wo, (int64_t)Ho * Wo, Ho, Wo, crop, st);
   if (rc) return rc;

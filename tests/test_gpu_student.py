@@ -241,3 +241,22 @@ def test_student_gather_equals_slicing(emcnn):
         assert torch.equal(tt[b], mp[z, y - m:y - m + P - 6, x - m:x - m + P - 6])
     with pytest.raises(emcnn.CnnError):  # origin past the last valid one
         emcnn.student_gather([(vols[0], maps[0], 0, 150 - P - m + 1, m)], P, R, pt[:1], tt[:1])
+
+
+def test_fallback_on_fresh_teacher_handle(emcnn):
+    """The first fallback call on a new teacher handle plans the sample pass and
+    the re-run pass before submitting either; the re-run needs more workspace
+    than the samples, so the workspace is sized for both before any job is
+    written (growing it later would free memory the sample jobs point into)."""
+    vol = em_volume(96, 2, 420, 400)
+    vd = _dev(vol)
+    ref_teacher = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")
+    tmap = emcnn.cnn_infer(ref_teacher, vd)
+    s = emcnn.student_create(he_normal_params(NET_S, 300), "bf16")
+    smap = emcnn.student_infer(s, vd)
+    for tau, want in ((-1.0, "teacher"), (1.0, "student")):
+        teacher = emcnn.cnn_create(calibrated_params("B"), NET_B, "fp32")  # empty workspace
+        out, st = emcnn.student_infer_with_fallback(s, teacher, vd, tau=tau, tile=192, n_samples=2, seed=5)
+        torch.cuda.synchronize()
+        assert torch.equal(out, tmap if want == "teacher" else smap[:, 3:-3, 3:-3])
+        teacher.close()
