@@ -91,7 +91,10 @@ def time_volume(emcnn, torch, h, vol_dev, steps, warmup, stream):
         t1 = time.perf_counter()
         emcnn.cnn_profile(h, False)
     ms, n = emcnn.cnn_profile_read(h)
-    per_layer = [m / c if c else 0.0 for m, c in zip(ms, n)]
+    # per pass: a volume larger than the handle's slab budget runs each layer
+    # once per slab, and a pass is all of them
+    per_layer = [m / steps for m in ms]
+    time_volume.launches_per_pass = [c / steps for c in n]
     return (t1 - t0) * 1e3 / steps, per_layer, out
 
 
@@ -278,7 +281,7 @@ def maskextend_form(emcnn, torch, dev, stream, args):
            "voxels_per_s": nv / dt, "ms_per_pass": dt * 1e3,
            "path_tflops": nv * MASKEXTEND_FLOP_PER_VOXEL / dt / 1e12,
            "path_mfma_frac": nv * MASKEXTEND_FLOP_PER_VOXEL / dt / 1e12 / PEAK_TFLOPS["fp32"],
-           "layer_ms": [m / c if c else 0.0 for m, c in zip(ms[:6], n[:6])], "tiles": emcnn.cnn_describe(h)}
+           "layer_ms": [m / reps for m in ms[:6]], "tiles": emcnn.cnn_describe(h)}
     log("maskextend", json.dumps(res))
     del maps, out, h
     return res
@@ -389,6 +392,8 @@ def main():
     ms, per_layer, out = time_volume(emcnn, torch, h, vol_dev, 1 if args.no_headline else args.steps,
                                      0 if args.no_headline else args.warmup, stream)
     value = nvox / (ms * 1e-3)
+    if time_volume.launches_per_pass[1] != 1:
+        raise SystemExit("headline volume must run as one slab (one conv2 launch per pass)")
     conv2_ms = per_layer[1]
     conv2_units = Z * (H - 9) * (W - 9)
     conv2_flop = conv2_units * CONV2_FLOP_PER_POS
@@ -486,6 +491,7 @@ def main():
                            "conv2_frac_of_measured_ceiling": ach / ceil if ceil else None,
                            "conv3_frac_of_measured_ceiling": ach3 / ceil if ceil else None,
                            "conv2_kernel_includes_conv1": fused, "layer_ms": pl[:3],
+                           "slabs_per_pass": time_volume.launches_per_pass[2],
                            "tiles": emcnn.cnn_describe(hp)}
             log(prec, json.dumps(forms[prec]))
             del outp, hp

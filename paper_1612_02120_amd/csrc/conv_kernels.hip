@@ -31,6 +31,8 @@
 // range: neighbouring tiles, which share halo rows, meet in the same L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "device_util.h"
 
@@ -459,10 +461,15 @@ __device__ __forceinline__ void stage_tile(unsigned char* lds, const gbyte* in, 
 // lane group g holding taps 8g..8g+7 (taps >= KS*KS are zero); the uint8 input
 // is exact in bf16. FP32 nets: 16x16x4 f32 MFMAs, lane group g holding tap
 // 4s+g of step s. Weights are pre-packed per lane (wpack, see the host).
-// The epilogue applies bias and ReLU, casts to the stored activation format,
-// stages the whole output tile in LDS and writes each tile row as one
-// contiguous run of 16-byte stores: FP32 output is NHWC (a tile row is one
-// run), BF16 / FP8 output is channel-blocked (one run per 16-channel plane).
+// The uint8 input tile is read in 16-byte row chunks where the rows are
+// 16-byte aligned, and converted once, as it is staged, to the MFMA operand
+// type (float or bf16) in LDS.
+// The epilogue applies bias and ReLU and casts to the stored activation
+// format. BF16 / FP8 output is channel-blocked: a lane's four channels of one
+// plane are 8 / 4 contiguous bytes, and the 64 lanes of an n-block together
+// write the plane's 16 pixels, one contiguous run, straight from registers.
+// FP32 output (NHWC) and max-out output pass the m-block through a per-wave
+// LDS scratch so that each lane stores 16 contiguous bytes.
 template <int PO, int COUT, int KS, int TY, int TX, int ST = 1>
 struct FirstCfg {
   // ST: output stride (2: the conv is evaluated only at every second input
@@ -476,9 +483,14 @@ struct FirstCfg {
   static constexpr int MW = MBLK / WAVES;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int NSTEP = PO == F32 ? (KS * KS + 3) / 4 : 1;
-  static constexpr int LDS = (LR * LC + 15) / 16 * 16;  // the uint8 input tile
+  // the input tile in LDS: float (FP32 nets) or bf16 elements, rows LCP apart
+  static constexpr int AEL = PO == F32 ? 4 : 2;
+  static constexpr int NCK = (LC + 15) / 16;  // 16-byte uint8 chunks per tile row
+  static constexpr int LCP = NCK * 16;
+  static constexpr int LDS = LR * LCP * AEL;
   static_assert(KS * KS <= 32, "first layer supports up to 32 taps");
   static_assert(MBLK % WAVES == 0 && TX % 16 == 0, "tile must split into m-blocks per wave");
+  static_assert(MW % (TX / 16) == 0, "each wave owns whole tile rows");
 };
 
 // MAXOUT: bias then max over the channel pairs (2c, 2c + 1), COUT / 2 stored
@@ -488,7 +500,8 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
                                                                                            FirstParams prm) {
   using C = FirstCfg<PO, COUT, KS, TY, TX, ST>;
   static_assert(!MAXOUT || PO == F32 || PO == BF16, "max-out first layers are FP32 or BF16");
-  __shared__ __attribute__((aligned(16))) unsigned char tile[C::LDS];
+  using AT = typename std::conditional<PO == F32, float, unsigned short>::type;  // float or bf16 bits
+  __shared__ __attribute__((aligned(16))) AT tile[C::LR * C::LCP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n16 = lane & 15;
   constexpr int MCOLS = TX / 16;
@@ -523,7 +536,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int k = PO == F32 ? 4 * t + g : 8 * g + t;
-    toff[t] = k < KS * KS ? (k / KS) * C::LC + k % KS : 0;
+    toff[t] = k < KS * KS ? (k / KS) * C::LCP + k % KS : 0;
   }
 
   const ItemRange rg = item_range(js.total_items);
@@ -540,26 +553,61 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
     const int y0 = by * TY, x0 = bx * TX;
     const gbyte* in = gin(J.in) + (int64_t)zz * J.in_zs;
     __syncthreads();
-    for (int t = tid; t < C::LR * C::LC; t += C::THREADS) {
-      const int r = t / C::LC, c = t % C::LC;
-      const int y = min(ST * y0 + r, J.hin - 1), x = min(ST * x0 + c, J.win - 1);
-      tile[t] = in[(int64_t)y * J.in_rs + x];
+    {
+      // chunk (r, k): tile row r, columns 16k .. 16k + 15 (clamped to the
+      // image). Whole chunks inside the image of a 16-byte aligned row are one
+      // vector load; the others (right edge, unaligned rows) go byte by byte.
+      const bool al16 = ((reinterpret_cast<uintptr_t>(in) | (uintptr_t)J.in_rs) & 15) == 0;
+      for (int t = tid; t < C::LR * C::NCK; t += C::THREADS) {
+        const int r = t / C::NCK, k = t % C::NCK;
+        const int y = min(ST * y0 + r, J.hin - 1), xs = ST * x0 + 16 * k;
+        const gbyte* row = in + (int64_t)y * J.in_rs;
+        unsigned char b[16];
+        if (al16 && xs + 15 < J.win) {
+          const i4v v = ld<i4v>(row + xs);
+#pragma unroll
+          for (int e = 0; e < 16; ++e) b[e] = (unsigned char)(v[e >> 2] >> (8 * (e & 3)));
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) b[e] = row[min(xs + e, J.win - 1)];
+        }
+        AT* dst = tile + r * C::LCP + 16 * k;
+        if constexpr (PO == F32) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<f4*>(dst + 4 * q) =
+                f4{(float)b[4 * q], (float)b[4 * q + 1], (float)b[4 * q + 2], (float)b[4 * q + 3]};
+        } else {
+          // the bf16 of a uint8 is the high half of its float (the low half is zero)
+          uint32_t hb[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            hb[q] = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, (float)b[2 * q + 1]),
+                                          __builtin_bit_cast(uint32_t, (float)b[2 * q]), 0x07060302u);
+          *reinterpret_cast<i4v*>(dst) = i4v{(int)hb[0], (int)hb[1], (int)hb[2], (int)hb[3]};
+          *reinterpret_cast<i4v*>(dst + 8) = i4v{(int)hb[4], (int)hb[5], (int)hb[6], (int)hb[7]};
+        }
+      }
     }
     __syncthreads();
     constexpr int CST = MAXOUT ? COUT / 2 : COUT;  // stored channels
     gbyte* oslice = gout(J.out) + (int64_t)zz * J.out_zs * CST * C::ESZ;
+    // channel-blocked output: this lane's bytes of its pixel in the wave's
+    // first m-block, and the strides of a tile row and of a plane
+    const int wrow = wave * (C::MW / MCOLS);  // the wave's first tile row
+    gbyte* const obase = oslice + ((int64_t)(y0 + wrow) * J.out_rs + x0 + n16) * 16 * C::ESZ + 4 * g * C::ESZ;
+    const int64_t orow_b = (int64_t)J.out_rs * 16 * C::ESZ, oplane_b = (int64_t)J.out_zs * 16 * C::ESZ;
 #pragma unroll
     for (int u = 0; u < C::MW; ++u) {
-      const int mb = wave * C::MW + u;
-      const int mrow = mb / MCOLS, mcol = mb % MCOLS;
-      const unsigned char* a0 = tile + ST * (mrow * C::LC + mcol * 16 + n16);
+      const int mrow = wrow + u / MCOLS, mcol = u % MCOLS;
+      const AT* a0 = tile + ST * (mrow * C::LCP + mcol * 16 + n16);
       f4 acc[C::NB];
 #pragma unroll
       for (int nb = 0; nb < C::NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
       if constexpr (PO == F32) {
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s) {
-          const float a = (float)a0[toff[s]];
+          const float a = a0[toff[s]];
 #pragma unroll
           for (int nb = 0; nb < C::NB; ++nb)
             acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wf[s][nb].v[0], a, acc[nb], 0, 0, 0);
@@ -567,7 +615,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
       } else {
         bf16x8 a;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) a[t] = (__bf16)(float)a0[toff[t]];  // exact: uint8 fits in bf16
+        for (int t = 0; t < 8; ++t) a[t] = __builtin_bit_cast(__bf16, a0[toff[t]]);
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb)
           acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][nb].v, a, acc[nb], 0, 0, 0);
@@ -607,13 +655,44 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
         __builtin_amdgcn_wave_barrier();
         continue;
       }
-      {
-        // bias + ReLU. The m-block's output (16 pixels x COUT channels, laid out
-        // as stored: NHWC for FP32; for BF16 / FP8 one 16-channel plane after
-        // another, 16 consecutive pixels each) passes through this wave's LDS
-        // scratch, so that each lane stores 16 contiguous bytes.
-        constexpr int BLK = 16 * COUT * C::ESZ;  // bytes of the m-block
-        constexpr int PLB = 16 * 16 * C::ESZ;    // bytes of one plane of it (BF16 / FP8)
+      if constexpr (C::BLOCKED) {
+        // bias + ReLU, stored from registers: lane (g, n16) writes channels
+        // 4g .. 4g + 3 of plane nb at pixel n16, bytes 4g * ESZ .. of the
+        // pixel's 16 * ESZ, so each n-block's 64 lanes cover the plane's 16
+        // pixels as one contiguous run.
+        if (y < J.hout && x < J.wout) {
+          gbyte* dst = obase + (u / MCOLS) * orow_b + mcol * 16 * 16 * C::ESZ;
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) {
+            gbyte* d = dst + nb * oplane_b;
+            if constexpr (PO == BF16) {
+              float v[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
+              st<u2v>(d, u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])});
+            } else {
+              // relu(t) * s clamped to [0, 448] is the median of (t * s, 0, 448)
+              // for s > 0; a negative t can give -0 there, whose code has the
+              // sign bit set: clearing bit 7 of each code maps it to +0 and
+              // leaves every other (non-negative) code as it is
+              const float inv = prm.out_inv_scale;
+              float v[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                v[k] = __builtin_amdgcn_fmed3f((acc[nb][k] + bias[nb][k]) * inv, 0.0f, 448.0f);
+              // (the first conversion's high half is any value: the second overwrites it)
+              int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], __builtin_bit_cast(int, v[0]), false);
+              w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+              st<uint32_t>(d, (uint32_t)w & 0x7f7f7f7fu);
+            }
+          }
+        }
+      } else {
+        // bias + ReLU. The m-block's output (16 pixels x COUT channels, NHWC)
+        // passes through this wave's LDS scratch, so that each lane stores 16
+        // contiguous bytes.
+        static_assert(PO == F32, "BF16 / FP8 output is stored from registers");
+        constexpr int BLK = 16 * COUT * 4;  // bytes of the m-block
         __shared__ __attribute__((aligned(16))) unsigned char scr_all[C::WAVES * BLK];
         unsigned char* scr = scr_all + wave * BLK;
 #pragma unroll
@@ -621,18 +700,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
           float v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
-          if constexpr (PO == F32) {
-            *reinterpret_cast<f4*>(scr + (n16 * COUT + nb * 16 + 4 * g) * 4) = f4{v[0], v[1], v[2], v[3]};
-          } else {
-            unsigned char* dst = scr + nb * PLB + (n16 * 16 + 4 * g) * C::ESZ;
-            if constexpr (PO == BF16) {
-              *reinterpret_cast<u2v*>(dst) = u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])};
-            } else {
-              const float inv = prm.out_inv_scale;
-              *reinterpret_cast<uint32_t*>(dst) =
-                  pack_e4m3x2(v[0] * inv, v[1] * inv) | (pack_e4m3x2(v[2] * inv, v[3] * inv) << 16);
-            }
-          }
+          *reinterpret_cast<f4*>(scr + (n16 * COUT + nb * 16 + 4 * g) * 4) = f4{v[0], v[1], v[2], v[3]};
         }
         __builtin_amdgcn_wave_barrier();
         const int xb = x0 + mcol * 16;  // the m-block's first pixel
@@ -642,16 +710,8 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
           const int c = h * 64 + lane;  // 16-byte chunk of the block
           if (c < BLK / 16) {
             const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
-            int pp;
-            gbyte* dst;
-            if constexpr (PO == F32) {
-              pp = c / (COUT / 4);  // COUT / 4 chunks per pixel
-              dst = oslice + (pix0 + pp) * COUT * 4 + (c % (COUT / 4)) * 16;
-            } else {
-              const int pl = c / (PLB / 16), cc = c % (PLB / 16);
-              pp = cc / C::ESZ;  // ESZ chunks per plane pixel
-              dst = oslice + ((int64_t)pl * J.out_zs + pix0) * 16 * C::ESZ + cc * 16;
-            }
+            const int pp = c / (COUT / 4);  // COUT / 4 chunks per pixel
+            gbyte* dst = oslice + (pix0 + pp) * COUT * 4 + (c % (COUT / 4)) * 16;
             if (y < J.hout && xb + pp < J.wout) st<i4v>(dst, o);
           }
         }
