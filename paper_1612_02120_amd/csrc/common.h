@@ -97,7 +97,53 @@ struct VariantInfo {
                         // occupancy take the kernel's own static LDS, epilogue scratch included)
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
   const char* name;
+  int rowq = 0;         // 1: row-quad K order (k_slot); 0: flattened
 };
+
+// K order of the implicit-GEMM convs over one channel block. K slot c is read
+// by lane group c % 4 of the (c / 4)-th quad of slots, and holds 16-byte chunk
+// cg of tap (i, j) of the block's pixels.
+// * Flattened: chunk c of the block's KS x KS x NCHB chunks, row-major over
+//   (i, j, cg); slots past the last chunk carry zero weights.
+// * Row quads (conv_ws, whose LDS pixels are unpadded, so a filter row's
+//   KS x NCHB chunks of a pixel run are one contiguous run): quad q covers 4
+//   consecutive chunks e .. e + 3 of filter row q / QR (QR = quads per row),
+//   e = 4 (q % QR) except that a row's last quad ends at its last chunk.
+//   Chunks a quad repeats, and quads past the last row (which read row 0's
+//   first quad), carry zero weights. Lane group g then reads 16 g bytes past
+//   its quad's first chunk, whatever the quad.
+struct KSlot {
+  int i, j, cg;
+  bool live;  // false: the slot's weights are zero
+};
+__host__ __device__ constexpr int rowq_quads(int ks, int nchb) { return (ks * nchb + 3) / 4; }
+__host__ __device__ inline KSlot k_slot(int c, int ks, int nchb, bool rowq) {
+  const int nrow = ks * nchb;  // chunks of one filter row
+  KSlot k{0, 0, 0, false};
+  int i, e;
+  if (!rowq) {
+    k.live = c < ks * nrow;
+    const int cc = k.live ? c : ks * nrow - 1;  // a padded slot reads real (finite) data
+    i = cc / nrow;
+    e = cc % nrow;
+  } else {
+    const int qr_n = rowq_quads(ks, nchb), q = c / 4, g = c % 4;
+    i = q / qr_n;
+    const int qr = q % qr_n;
+    int e0 = 4 * qr;
+    if (e0 + 4 > nrow) e0 = nrow - 4;  // the row's last quad (nrow >= 4)
+    e = e0 + g;
+    k.live = i < ks && e >= 4 * qr;
+    if (i >= ks) {
+      i = 0;
+      e = g;
+    }
+  }
+  k.i = i;
+  k.j = e / nchb;
+  k.cg = e % nchb;
+  return k;
+}
 
 struct FirstInfo {
   int prec_out, cout, ks;

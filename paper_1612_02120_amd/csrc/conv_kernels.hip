@@ -1417,6 +1417,7 @@ __global__ __launch_bounds__(TX) void head_1x1(JobSet js, ConvParams prm) {
 template <int P, int CIN, int COUT, int KS, int TY, int TX, int NCW, int NPW, int K1 = 0>
 struct CfgWS {
   using T = PT<P>;
+  static constexpr int KSZ = KS;
   // channels per stage: 16 (one plane) for BF16; all of CIN for FP8, whose
   // 128-deep MFMA needs the longer K of a stage to stay filled
   static constexpr int CB = P == FP8 ? CIN : 16;
@@ -1437,6 +1438,12 @@ struct CfgWS {
   // L1 kept the texture addresser ~80 % busy (6 % slower conv2 despite fewer
   // LDS bank conflicts)
   static constexpr int PSB = P == FP8 ? CB * T::BYTES : pad_words(CB * T::BYTES / 4) * 4;
+  // Row-quad K order (k_slot) where a pixel's chunks are unpadded and it takes
+  // no more group-steps than the flattened order: each lane then reads at a
+  // fixed offset from a uniform per-slot address (FP8 5x5: 15 chunks a filter
+  // row, 16 slots a row, the same 80 slots as flattened).
+  static constexpr bool ROWK = PSB == NCHB * 16 && KS * NCHB >= 4 &&
+                               KS * rowq_quads(KS, NCHB) * 4 <= NGS * SLOTS;
   static constexpr int BUF = LR * LC * PSB;                // one operand buffer
   static constexpr int WB = NGS * NB * 64 * T::U * 16;     // packed weights of one stage
   static constexpr int LDS_MAX = 160 * 1024;
@@ -1473,6 +1480,17 @@ struct CfgWS {
   static_assert(LDS <= LDS_MAX, "LDS budget of a gfx950 workgroup");
   static_assert(K1 == 0 || K1 * K1 <= 32, "fused first layer: one 16x16x32 MFMA per block");
 };
+
+// LDS offset, from the lane's pixel, of the chunk that lane group g reads for
+// operand chunk uu of group-step s (slot 4U s + 4 uu + g, see k_slot). Row
+// quads: a uniform offset plus 16 g bytes; the caller adds the 16 g (the
+// lane's base carries it), so the offset is the same for every lane.
+template <class C>
+__device__ __forceinline__ int slot_off(int s, int uu, int g) {
+  const int c = s * (4 * C::T::U) + 4 * uu + (C::ROWK ? 0 : g);
+  const KSlot k = k_slot(c, C::KSZ, C::NCHB, C::ROWK);
+  return (k.i * C::LC + k.j) * C::PSB + k.cg * 16;
+}
 
 // Walk of the work items of one workgroup (see item_range), skipping items
 // of gated-off jobs. Every wave of the workgroup walks the same sequence.
@@ -1974,7 +1992,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) acc[u][nb] = f4{0.f, 0.f, 0.f, 0.f};
     }
-    const unsigned char* abase = lds + sel * C::BUF + (wrow0 * C::LC + n16) * C::PSB;
+    const unsigned char* abase = lds + sel * C::BUF + (wrow0 * C::LC + n16) * C::PSB + (C::ROWK ? 16 * g : 0);
     // implicit GEMM over the stage's (tap, chunk) slots; B fragments from
     // LDS (BF16) or global memory (FP8)
     auto kloop = [&](auto wl) __attribute__((always_inline)) {
@@ -1988,15 +2006,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
         }
         int off[T::U];
 #pragma unroll
-        for (int uu = 0; uu < T::U; ++uu) {
-          // slot order: chunk s*4U + 4uu + g (lane group g, uu-th 16 bytes of its operand)
-          int c = s * (4 * T::U) + 4 * uu + g;
-          c = c < C::NCHK ? c : C::NCHK - 1;  // padded slot: any finite data, weights are 0
-          const int i = c / (KS * C::NCHB);
-          const int rem = c % (KS * C::NCHB);
-          const int j = rem / C::NCHB, cg = rem % C::NCHB;
-          off[uu] = (i * C::LC + j) * C::PSB + cg * 16;
-        }
+        for (int uu = 0; uu < T::U; ++uu) off[uu] = slot_off<C>(s, uu, g);
         const unsigned char* a0 = abase + off[0];
         const unsigned char* a1 = abase + off[T::U - 1];
 #pragma unroll
@@ -2016,14 +2026,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
       auto mstep = [&](int s, const Frag<P>* cur) __attribute__((always_inline)) {
         int off[T::U];
 #pragma unroll
-        for (int uu = 0; uu < T::U; ++uu) {
-          int c = s * (4 * T::U) + 4 * uu + g;
-          c = c < C::NCHK ? c : C::NCHK - 1;
-          const int i = c / (KS * C::NCHB);
-          const int rem = c % (KS * C::NCHB);
-          const int j = rem / C::NCHB, cg = rem % C::NCHB;
-          off[uu] = (i * C::LC + j) * C::PSB + cg * 16;
-        }
+        for (int uu = 0; uu < T::U; ++uu) off[uu] = slot_off<C>(s, uu, g);
         const unsigned char* a0 = abase + off[0];
         const unsigned char* a1 = abase + off[T::U - 1];
 #pragma unroll
@@ -2193,7 +2196,8 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::LDS,                                     \
               reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, K1>), \
               "conv_ws<" #P "," #CIN "," #COUT "," #KS "," #POOL "," #HEAD "," #TY "," #TX "," #NCW "," #NPW \
-              "," #K1 ">"}
+              "," #K1 ">",                                                                            \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::ROWK}
 #define EMCNN_WS_PHASE(P, CIN, COUT, KS, TY, TX, NCW, NPW)                                           \
   VariantInfo{P, CIN, COUT, KS, 1, 0, TY, TX,                                                         \
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::MW,                                       \
@@ -2205,7 +2209,8 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               0, 0, 1,                                                                                \
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::LDS + NCW * 1024,                         \
               reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, true, false, TY, TX, NCW, NPW, 0, 1>), \
-              "conv_ws_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #NCW "," #NPW ">"}
+              "conv_ws_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #NCW "," #NPW ">",        \
+              CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::ROWK}
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
   EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
 
@@ -2275,8 +2280,10 @@ static const VariantInfo kConv[] = {
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
     EMCNN_WS_W4(FP8, 48, 48, 5, true, false),
-    EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
-    EMCNN_WS_W4(FP8, 48, 48, 3, true, true),
+    // FP8 conv3: 16 x 48 tiles (6 m-blocks per consumer wave) carry 1.5x the
+    // MFMA work of an 8 x 64 tile per stage barrier, with a smaller halo
+    EMCNN_WS(FP8, 48, 48, 3, true, true, 16, 48, 8, 4), EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
+    EMCNN_WS_W4(FP8, 48, 48, 3, true, true), EMCNN_WS(FP8, 48, 48, 3, true, true, 12, 64, 6, 4),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)

@@ -111,7 +111,7 @@ static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b
                      double in_scale, double next_scale) {
   const VariantInfo* v = conv_variant(variant);
   const int cin = v->cin, cout = v->cout, ks = v->ks, cb = v->cb, chb = v->chb, u = v->u, ngs = v->ngs;
-  const int ncb = cin / cb, nchb = cb / chb, nchk = ks * ks * nchb, nb = cout / 16;
+  const int ncb = cin / cb, nchb = cb / chb, nb = cout / 16;
   const int esz = act_bytes(v->prec);
   // flattened K: [cb][s][nb][u][lane]; row reuse: [cb][i][rs][nb][u][lane]. The
   // 16-byte chunk uu of all 64 lanes is contiguous, so each fragment load of a
@@ -152,12 +152,12 @@ static int pack_conv(ExecLayer& L, int variant, const double* w, const double* b
               j = c / nchb;
               cg = c % nchb;
             } else {
-              const int c = s * 4 * u + 4 * uu + g;  // the kernels' chunk-slot order
-              if (c >= nchk) continue;
-              i = c / (ks * nchb);
-              const int rem = c % (ks * nchb);
-              j = rem / nchb;
-              cg = rem % nchb;
+              // the kernels' chunk-slot order
+              const KSlot k = k_slot(s * 4 * u + 4 * uu + g, ks, nchb, v->rowq != 0);
+              if (!k.live) continue;
+              i = k.i;
+              j = k.j;
+              cg = k.cg;
             }
             uint8_t* dst = pk.data() + ((((size_t)(c0 * nsteps + s) * nb + n_b) * u + uu) * 64 + lane) * 16;
             for (int t = 0; t < chb; ++t) {
