@@ -368,10 +368,10 @@ int student_infer_with_fallback(cnn_student* s, cnn_net* teacher, const uint8_t*
  * The labelling is unique; it is an over-segmentation whose seeded basins are
  * the cells when the map separates them.
  * prob: device Z x H x W float32, finite; labels_out: device int32, same
- * shape; work: device int32[Z H W + 1] scratch (caller-owned, overwritten);
- * Z H W < 2^31 - 1. The call synchronises `stream` once per round of the seed
- * components (typically a few rounds) and returns with the labelling
- * enqueued. */
+ * shape; work: device int32[Z H W + 1] scratch (caller-owned, overwritten;
+ * its last word is not used); Z H W < 2^31 - 1. The call only enqueues three
+ * kernels on `stream` (descent pointers, one lock-free union-find pass over
+ * the seeds, root finding with path halving) and never waits on the host. */
 int watershed_3d(const float* prob, const int64_t dims[3], float seed_threshold, int32_t* labels_out,
                  int32_t* work, void* stream);
 

@@ -8,18 +8,22 @@
 //   label   of v: the seed component's label where the descent from v ends
 //           in S, else 1 + the index of the local minimum it ends at.
 // The result is unique (a total order, no flooding order to choose), so the
-// kernels reproduce it exactly whatever the scheduling:
-//   ws_init      one pass: a[v] = v on S, else next(v)
-//   ws_hook      seed components by hooking: for each pair of 6-adjacent
-//                seeds in different trees, the larger root is pointed at the
-//                smaller one (atomicMin); a[] only ever decreases and a[v] <= v,
-//                so the forest stays valid under any interleaving, and the
-//                least index of a component is its final root
-//   ws_compress  path compression, a[v] = root, between hooking rounds
-//   ws_label     every voxel follows a[] to a seed (then takes its root) or to
-//                a non-seed fixed point (a local minimum of the order)
-// Rounds repeat until a hooking round changes nothing; each round reads a
-// one-word flag back to the host.
+// kernels reproduce it exactly whatever the scheduling. One forest a[] holds
+// both parts: a non-seed points along its descent, a seed into its
+// component's tree. Roots are fixed points: component minima and non-seed
+// local minima.
+//   ws_init   one pass: a[v] = v on S, else next(v)
+//   ws_union  one pass over the seeds: each 6-adjacent pair of seeds is
+//             united by a lock-free union-find (the structure of ECL-CC):
+//             find both roots, hook the larger root under the smaller with a
+//             compare-and-swap that only succeeds while it is still a root,
+//             and retry from the new roots when another thread hooked it
+//             first. A seed's parent index only decreases, so every
+//             component ends rooted at its least index.
+//   ws_label  every voxel finds its root (a component minimum or a local
+//             minimum), halving the path as it goes, and takes root + 1.
+// Path halving points a node at its grandparent, an ancestor in the same
+// tree, so concurrent finds stay valid; it never writes a root.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -40,86 +44,85 @@ __device__ __forceinline__ int32_t wa(const int32_t* a, int64_t v) {
   return __atomic_load_n(a + v, __ATOMIC_RELAXED);
 }
 
+// Work split: one row (z, y) of W voxels per block iteration, x over the
+// threads; indices fit in 32 bits (Z H W < 2^31 - 1).
 __global__ __launch_bounds__(256) void ws_init(const float* __restrict__ p, Vol3 g, float t, int32_t* __restrict__ a) {
-  const int64_t HW = (int64_t)g.H * g.W;
-  for (int64_t v = blockIdx.x * 256ll + threadIdx.x; v < g.N; v += (int64_t)gridDim.x * 256) {
-    const float pv = wp(p, v);
-    if (pv < t) {
-      a[v] = (int32_t)v;
-      continue;
-    }
-    const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)(v / HW);
-    int64_t best = v;
-    float pb = pv;
-    // candidates in ascending index order: a later candidate wins only if strictly lower
-    const int64_t cand[6] = {z > 0 ? v - HW : -1, y > 0 ? v - g.W : -1, x > 0 ? v - 1 : -1,
-                             x < g.W - 1 ? v + 1 : -1, y < g.H - 1 ? v + g.W : -1, z < g.Z - 1 ? v + HW : -1};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int64_t u = cand[k];
-      if (u < 0) continue;
-      const float pu = wp(p, u);
-      if (pu < pb || (pu == pb && u < best)) {
-        pb = pu;
-        best = u;
+  const int HW = g.H * g.W;
+  for (int row = blockIdx.x; row < g.Z * g.H; row += gridDim.x) {
+    const int z = row / g.H, y = row - z * g.H, base = row * g.W;
+    for (int x = threadIdx.x; x < g.W; x += 256) {
+      const int v = base + x;
+      const float pv = wp(p, v);
+      if (pv < t) {
+        a[v] = v;
+        continue;
       }
+      int best = v;
+      float pb = pv;
+      // candidates in ascending index order: a later candidate wins only if strictly lower
+      const int cand[6] = {z > 0 ? v - HW : -1, y > 0 ? v - g.W : -1, x > 0 ? v - 1 : -1,
+                           x < g.W - 1 ? v + 1 : -1, y < g.H - 1 ? v + g.W : -1, z < g.Z - 1 ? v + HW : -1};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int u = cand[k];
+        if (u < 0) continue;
+        const float pu = wp(p, u);
+        if (pu < pb || (pu == pb && u < best)) {
+          pb = pu;
+          best = u;
+        }
+      }
+      a[v] = best;
     }
-    a[v] = (int32_t)best;
   }
 }
 
-__device__ __forceinline__ int32_t ws_find(const int32_t* a, int32_t r) {
-  int32_t q = wa(a, r);
-  while (q != r) {
-    r = q;
-    q = wa(a, r);
+// Root of r with path halving (any node may be passed; roots are fixed points).
+__device__ __forceinline__ int32_t ws_find(int32_t* a, int32_t r) {
+  int32_t par = wa(a, r);
+  while (par != r) {
+    const int32_t gp = wa(a, par);
+    if (gp == par) return par;
+    __atomic_store_n(a + r, gp, __ATOMIC_RELAXED);  // r is not a root: an ancestor is a valid parent
+    r = gp;
+    par = wa(a, r);
   }
   return r;
 }
 
-__global__ __launch_bounds__(256) void ws_hook(const float* __restrict__ p, Vol3 g, float t, int32_t* a,
-                                               int32_t* flag) {
-  const int64_t HW = (int64_t)g.H * g.W;
-  int changed = 0;
-  for (int64_t v = blockIdx.x * 256ll + threadIdx.x; v < g.N; v += (int64_t)gridDim.x * 256) {
-    if (!(wp(p, v) < t)) continue;
-    const int x = (int)(v % g.W), y = (int)((v / g.W) % g.H), z = (int)(v / HW);
-    const int64_t fwd[3] = {x < g.W - 1 ? v + 1 : -1, y < g.H - 1 ? v + g.W : -1, z < g.Z - 1 ? v + HW : -1};
+__device__ __forceinline__ void ws_unite(int32_t* a, int32_t u, int32_t v) {
+  int32_t ru = ws_find(a, u), rv = ws_find(a, v);
+  while (ru != rv) {
+    const int32_t hi = ru > rv ? ru : rv, lo = ru < rv ? ru : rv;
+    const int32_t old = atomicCAS(a + hi, hi, lo);
+    if (old == hi) return;  // hooked while hi was still a root
+    // hi was hooked meanwhile: continue from the current roots
+    ru = ws_find(a, hi);
+    rv = ws_find(a, lo);
+  }
+}
+
+__global__ __launch_bounds__(256) void ws_union(const float* __restrict__ p, Vol3 g, float t, int32_t* a) {
+  const int HW = g.H * g.W;
+  for (int row = blockIdx.x; row < g.Z * g.H; row += gridDim.x) {
+    const int z = row / g.H, y = row - z * g.H, base = row * g.W;
+    for (int x = threadIdx.x; x < g.W; x += 256) {
+      const int v = base + x;
+      if (!(wp(p, v) < t)) continue;
+      const int fwd[3] = {x < g.W - 1 ? v + 1 : -1, y < g.H - 1 ? v + g.W : -1, z < g.Z - 1 ? v + HW : -1};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int64_t u = fwd[k];
-      if (u < 0 || !(wp(p, u) < t)) continue;
-      const int32_t rv = ws_find(a, (int32_t)v), ru = ws_find(a, (int32_t)u);
-      if (rv != ru) {
-        atomicMin(a + (rv > ru ? rv : ru), rv < ru ? rv : ru);
-        changed = 1;
+      for (int k = 0; k < 3; ++k) {
+        const int u = fwd[k];
+        if (u < 0 || !(wp(p, u) < t)) continue;
+        ws_unite(a, v, u);
       }
     }
   }
-  if (__any(changed) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-__global__ __launch_bounds__(256) void ws_compress(const float* __restrict__ p, Vol3 g, float t, int32_t* a) {
-  for (int64_t v = blockIdx.x * 256ll + threadIdx.x; v < g.N; v += (int64_t)gridDim.x * 256)
-    if (wp(p, v) < t) a[v] = ws_find(a, (int32_t)v);
-}
-
-__global__ __launch_bounds__(64) void ws_clear(int32_t* flag) {
-  if (threadIdx.x == 0) *flag = 0;
-}
-
-__global__ __launch_bounds__(256) void ws_label(const float* __restrict__ p, Vol3 g, float t,
-                                                const int32_t* __restrict__ a, int32_t* __restrict__ out) {
-  for (int64_t v = blockIdx.x * 256ll + threadIdx.x; v < g.N; v += (int64_t)gridDim.x * 256) {
-    int32_t u = (int32_t)v;
-    // descend until a seed or a fixed point; on a seed a[] is its root
-    while (!(wp(p, u) < t)) {
-      const int32_t n = a[u];
-      if (n == u) break;
-      u = n;
-    }
-    out[v] = (wp(p, u) < t ? a[u] : u) + 1;
-  }
+__global__ __launch_bounds__(256) void ws_label(Vol3 g, int32_t* a, int32_t* __restrict__ out) {
+  const int n = (int)g.N;
+  for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) out[v] = ws_find(a, v) + 1;
 }
 
 }  // namespace emcnn
@@ -136,24 +139,14 @@ extern "C" int watershed_3d(const float* prob, const int64_t dims[3], float seed
   if (seed_threshold != seed_threshold) return fail(CNN_EINVAL, "watershed_3d: NaN threshold");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Vol3 g{(int)Z, (int)H, (int)W, Z * H * W};
-  int32_t* flag = work + g.N;
   const int grid = (int)std::min<int64_t>((g.N + 255) / 256, 2048 * 8);
+  const int rows = (int)std::min<int64_t>(Z * H, 2048 * 8);  // row-per-block kernels
   hipError_t e;
-  hipLaunchKernelGGL(ws_init, dim3(grid), dim3(256), 0, st, prob, g, seed_threshold, work);
+  hipLaunchKernelGGL(ws_init, dim3(rows), dim3(256), 0, st, prob, g, seed_threshold, work);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "watershed_3d: init");
-  for (int round = 0;; ++round) {
-    if (round >= 4096) return fail(CNN_EHIP, "watershed_3d: seed components did not converge");
-    hipLaunchKernelGGL(ws_clear, dim3(1), dim3(64), 0, st, flag);
-    hipLaunchKernelGGL(ws_hook, dim3(grid), dim3(256), 0, st, prob, g, seed_threshold, work, flag);
-    hipLaunchKernelGGL(ws_compress, dim3(grid), dim3(256), 0, st, prob, g, seed_threshold, work);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "watershed_3d: hook");
-    int32_t h = 0;
-    if ((e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
-      return hip_fail(e, "watershed_3d: flag");
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "watershed_3d: sync");
-    if (!h) break;
-  }
-  hipLaunchKernelGGL(ws_label, dim3(grid), dim3(256), 0, st, prob, g, seed_threshold, work, labels_out);
+  hipLaunchKernelGGL(ws_union, dim3(rows), dim3(256), 0, st, prob, g, seed_threshold, work);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "watershed_3d: union");
+  hipLaunchKernelGGL(ws_label, dim3(grid), dim3(256), 0, st, g, work, labels_out);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "watershed_3d: label");
   return CNN_OK;
 }
