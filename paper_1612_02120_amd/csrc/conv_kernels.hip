@@ -1442,6 +1442,8 @@ struct CfgWS {
   // no more group-steps than the flattened order: each lane then reads at a
   // fixed offset from a uniform per-slot address (FP8 5x5: 15 chunks a filter
   // row, 16 slots a row, the same 80 slots as flattened).
+  // group-steps per unrolled body of the consumer loop
+  static constexpr int KUNROLL = P == FP8 ? 1 : 2;
   static constexpr bool ROWK = PSB == NCHB * 16 && KS * NCHB >= 4 &&
                                KS * rowq_quads(KS, NCHB) * 4 <= NGS * SLOTS;
   static constexpr int BUF = LR * LC * PSB;                // one operand buffer
@@ -1995,8 +1997,11 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
     const unsigned char* abase = lds + sel * C::BUF + (wrow0 * C::LC + n16) * C::PSB + (C::ROWK ? 16 * g : 0);
     // implicit GEMM over the stage's (tap, chunk) slots; B fragments from
     // LDS (BF16) or global memory (FP8)
+    // FP8: not unrolled, so the accumulators stay in place (unrolled twice,
+    // the allocator alternates them between two register sets, which spills
+    // the 6-m-block shapes); BF16: unrolled twice, measured faster
     auto kloop = [&](auto wl) __attribute__((always_inline)) {
-#pragma unroll 2
+#pragma unroll C::KUNROLL
       for (int s = 0; s < C::NGS; ++s) {
         Frag<P> bfr[C::NB];
 #pragma unroll
@@ -2269,22 +2274,25 @@ static const VariantInfo kConv[] = {
     EMCNN_RR_SHAPES(F32, 48, 48, 5, true, false, 0),
     EMCNN_SHAPES(F32, 48, 48, 3, true, true),
     EMCNN_RR_SHAPES(F32, 48, 48, 3, true, true, 0),
-    // conv2: separate first layer (default), then with the first layer computed inside
-    EMCNN_WS(BF16, 48, 48, 5, true, false, 16, 32, 8, 4), EMCNN_WS_NARROW(BF16, 48, 48, 5, true, false),
+    // conv2: separate first layer (defaults first), then with the first layer computed inside
+    EMCNN_WS(BF16, 48, 48, 5, true, false, 24, 32, 8, 4), EMCNN_WS(BF16, 48, 48, 5, true, false, 16, 32, 8, 4),
+    EMCNN_WS_NARROW(BF16, 48, 48, 5, true, false),
     EMCNN_WSK(BF16, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
     EMCNN_WSK(BF16, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
     EMCNN_WS_W4(BF16, 48, 48, 5, true, false),
     EMCNN_WS_SHAPES(BF16, 48, 48, 3, true, true),
     EMCNN_WS_W4(BF16, 48, 48, 3, true, true),
-    // conv2 BF16 / FP8: 16 x 32 tiles (halo 1.41x, against 1.59x for 8 x 64)
-    EMCNN_WS(FP8, 48, 48, 5, true, false, 16, 32, 8, 4), EMCNN_WS_NARROW(FP8, 48, 48, 5, true, false),
+    // conv2 BF16 / FP8: 24 x 32 tiles, 6 m-blocks per consumer wave (halo
+    // 1.31x, against 1.59x for 8 x 64; B fragments shared by 6 m-blocks)
+    EMCNN_WS(FP8, 48, 48, 5, true, false, 24, 32, 8, 4), EMCNN_WS(FP8, 48, 48, 5, true, false, 16, 32, 8, 4),
+    EMCNN_WS_NARROW(FP8, 48, 48, 5, true, false),
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 64, 8, 4, 5),
     EMCNN_WSK(FP8, 48, 48, 5, true, false, 8, 48, 8, 4, 5),
     EMCNN_WS_W4(FP8, 48, 48, 5, true, false),
     // FP8 conv3: 16 x 48 tiles (6 m-blocks per consumer wave) carry 1.5x the
     // MFMA work of an 8 x 64 tile per stage barrier, with a smaller halo
     EMCNN_WS(FP8, 48, 48, 3, true, true, 16, 48, 8, 4), EMCNN_WS_NARROW(FP8, 48, 48, 3, true, true),
-    EMCNN_WS_W4(FP8, 48, 48, 3, true, true), EMCNN_WS(FP8, 48, 48, 3, true, true, 12, 64, 6, 4),
+    EMCNN_WS_W4(FP8, 48, 48, 3, true, true), EMCNN_WS(FP8, 48, 48, 3, true, true, 24, 32, 8, 4),
     // net A body: 16 -> 16, 5x5, no pool, head fused (FP32)
     EMCNN_SHAPES(F32, 16, 16, 5, false, true),
     // same layer shapes without the pool / with the head elsewhere (generic specs)
