@@ -212,6 +212,44 @@ __device__ __forceinline__ uint32_t max_u7x4(uint32_t a, uint32_t b) {
   const uint32_t m = hm | (hm - (hm >> 7));                   // 0xff per byte where a >= b
   return (a & m) | (b & ~m);
 }
+// The 2x2 max filter of a 3x3 neighbourhood of FP8 chunks (q row-major) into
+// its four outputs (o[2d + e] = max over rows d, d+1 and columns e, e+1), per
+// byte. A packed u16 max orders each half by its high byte first, so on the
+// raw words it gives the odd bytes' max; the even bytes take a packed u16 max
+// of the words masked to them. 9 masks, 20 packed maxes and 4 bit-field
+// inserts per dword, against 10 SWAR maxes of 7 operations each.
+typedef unsigned short u16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pkmax_u16(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_max(__builtin_bit_cast(u16x2v, a), __builtin_bit_cast(u16x2v, b)));
+}
+__device__ __forceinline__ void max_filter_fp8(const i4v (&q)[9], i4v (&o)[4]) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t hi[9], lo[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      hi[j] = (uint32_t)q[j][w];
+      lo[j] = hi[j] & 0x00ff00ffu;
+    }
+    uint32_t hh[3][2], hl[3][2];  // horizontal maxes of each row
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        hh[r][e] = pkmax_u16(hi[3 * r + e], hi[3 * r + e + 1]);
+        hl[r][e] = pkmax_u16(lo[3 * r + e], lo[3 * r + e + 1]);
+      }
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const uint32_t mh = pkmax_u16(hh[d][e], hh[d + 1][e]), ml = pkmax_u16(hl[d][e], hl[d + 1][e]);
+        o[2 * d + e][w] = (int)((mh & 0xff00ff00u) | ml);
+      }
+  }
+}
+
 template <>
 __device__ __forceinline__ i4v chunk_max<FP8>(i4v a, i4v b) {
   i4v r;
@@ -1600,14 +1638,22 @@ struct AStage {
         const int cg = t % NCHB, it = t / NCHB;
         if constexpr (POOL) {
           const int r = 2 * (it / (LC / 2)), cc = 2 * (it % (LC / 2));
+          i4v mo[4];
+          if constexpr (P == FP8) {
+            max_filter_fp8(q[k], mo);
+          } else {
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+#pragma unroll
+              for (int e = 0; e < 2; ++e)
+                mo[2 * d + e] = chunk_max<P>(chunk_max<P>(q[k][d * 3 + e], q[k][d * 3 + e + 1]),
+                                             chunk_max<P>(q[k][(d + 1) * 3 + e], q[k][(d + 1) * 3 + e + 1]));
+          }
 #pragma unroll
           for (int d = 0; d < 2; ++d)
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-              const i4v v = chunk_max<P>(chunk_max<P>(q[k][d * 3 + e], q[k][d * 3 + e + 1]),
-                                         chunk_max<P>(q[k][(d + 1) * 3 + e], q[k][(d + 1) * 3 + e + 1]));
-              *reinterpret_cast<i4v*>(lds + ((r + d) * LC + cc + e) * PSB + cg * 16) = v;
-            }
+            for (int e = 0; e < 2; ++e)
+              *reinterpret_cast<i4v*>(lds + ((r + d) * LC + cc + e) * PSB + cg * 16) = mo[2 * d + e];
         } else {
           *reinterpret_cast<i4v*>(lds + it * PSB + cg * 16) = q[k][0];
         }
@@ -1682,33 +1728,6 @@ struct PhStage {
     }
   }
 };
-
-// Store one (m-block, n-block) accumulator tile in the channel-blocked layout.
-// Lane (g, n) holds channel n of pixels 4g..4g+3. Two quad exchanges leave
-// lane (g, n) with channels 4(n/4)..4(n/4)+3 of pixel 4g + n%4, so the 64
-// lanes write 16 consecutive plane pixels (one contiguous run).
-template <int P, class B>
-__device__ __forceinline__ void store_block_tile(B* plane_row, int pm_ok, const float (&v)[4], int n16,
-                                                 float inv) {
-  const int b0 = n16 & 1, b1 = (n16 >> 1) & 1, q = n16 >> 2;
-  const float s0 = b0 ? v[0] : v[1], s1 = b0 ? v[2] : v[3];
-  const float r0 = __builtin_bit_cast(float, quad_perm<kQuadXor1>(__builtin_bit_cast(int, s0)));
-  const float r1 = __builtin_bit_cast(float, quad_perm<kQuadXor1>(__builtin_bit_cast(int, s1)));
-  // pixel 4g + b0 and pixel 4g + 2 + b0, channels (n & ~1, n | 1)
-  const float alo = b0 ? r0 : v[0], ahi = b0 ? v[1] : r0;
-  const float blo = b0 ? r1 : v[2], bhi = b0 ? v[3] : r1;
-  if constexpr (P == BF16) {
-    const uint32_t wa = pack_bf16x2(alo, ahi), wb = pack_bf16x2(blo, bhi);
-    const uint32_t rw = (uint32_t)quad_perm<kQuadXor2>((int)(b1 ? wa : wb));
-    const uint32_t lo = b1 ? rw : wa, hi = b1 ? wb : rw;
-    if (pm_ok) st<u2v>(plane_row + q * 8, u2v{lo, hi});
-  } else {
-    const uint32_t wa = pack_e4m3x2(alo * inv, ahi * inv), wb = pack_e4m3x2(blo * inv, bhi * inv);
-    const uint32_t rw = (uint32_t)quad_perm<kQuadXor2>((int)(b1 ? wa : wb));
-    const uint32_t word = b1 ? (rw | (wb << 16)) : (wa | (rw << 16));
-    if (pm_ok) st<uint32_t>(plane_row + q * 4, word);
-  }
-}
 
 // PH = 1: a spaced conv of a stride-2 pool net (the work of conv_phase with
 // max-out, BF16): NHWC keyed input, operand pixels are the spaced 2x2 max
@@ -1970,6 +1989,11 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   // per-m-block LDS and global addresses are immediates on one lane base.
   const int g = lane >> 4, n16 = lane & 15;
   const int wrow0 = wave * C::WROWS;
+  // TRANS: weights as the MFMA's A operand and pixels as B, so lane (g, n16)
+  // accumulates channels 4g .. 4g + 3 of pixel n16 (4 consecutive stored
+  // channels); otherwise (the head and the spaced form) channel n16 of
+  // pixels 4g .. 4g + 3
+  constexpr bool TRANS = !HEAD && !PH;
   __syncthreads();  // the first stage is ready
   int cb = 0, sel = 0;
   f4 acc[C::MW][C::NB];
@@ -2020,7 +2044,12 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
           Frag<P> afr;
           load_frag<P>(afr, a0 + mo, a1 + mo);
 #pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[u][nb], afr, bfr[nb]);
+          for (int nb = 0; nb < C::NB; ++nb) {
+            if constexpr (TRANS)
+              mma<P>(acc[u][nb], bfr[nb], afr);
+            else
+              mma<P>(acc[u][nb], afr, bfr[nb]);
+          }
         }
       }
     };
@@ -2040,7 +2069,12 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
           Frag<P> afr;
           load_frag<P>(afr, a0 + mo, a1 + mo);
 #pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) mma<P>(acc[u][nb], afr, cur[nb]);
+          for (int nb = 0; nb < C::NB; ++nb) {
+            if constexpr (TRANS)
+              mma<P>(acc[u][nb], cur[nb], afr);
+            else
+              mma<P>(acc[u][nb], afr, cur[nb]);
+          }
         }
       };
       {
@@ -2131,20 +2165,44 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
             },
             bias, osc, hw, prm.head_b, g, n16, gout(J.out), (int64_t)zz * J.out_zs, J.out_rs, J.hout, J.wout);
       } else {
+        // TRANS: a lane's 4 channels of an n-block are 4 (FP8) / 8 (BF16)
+        // contiguous bytes of its pixel's entry in that 16-channel plane, and
+        // an n-block's 64 lanes cover 16 pixels x 16 channels, one contiguous
+        // run, stored straight from the accumulators
+        static_assert(TRANS, "non-head epilogue of the plain form");
+        f4 bs[C::NB], sc[C::NB];
+#pragma unroll
+        for (int nb = 0; nb < C::NB; ++nb) {
+          bs[nb] = ld<f4>(gin(prm.bias) + (nb * 16 + 4 * g) * 4);
+          sc[nb] = prm.oscale ? ld<f4>(gin(prm.oscale) + (nb * 16 + 4 * g) * 4) : f4{1.f, 1.f, 1.f, 1.f};
+        }
+        const float inv = prm.out_inv_scale;
+        gbyte* const obase = gout(J.out) + (int64_t)zz * J.out_zs * COUT * T::BYTES + (int64_t)(4 * g) * T::BYTES;
 #pragma unroll
         for (int u = 0; u < C::MW; ++u) {
           const int y = ty0 + u / MCOLS;
-          const int xb = x0 + (u % MCOLS) * 16;
-          const int pm = 4 * g + (n16 & 3);
-          const int ok = (y < J.hout) && (xb + pm < J.wout);
-          gbyte* orow = gout(J.out) + ((int64_t)zz * J.out_zs * COUT + ((int64_t)y * J.out_rs + xb) * 16) * T::BYTES +
-                        pm * PB;
+          const int x = x0 + (u % MCOLS) * 16 + n16;
+          if (y < J.hout && x < J.wout) {
+            gbyte* const d0 = obase + ((int64_t)y * J.out_rs + x) * PB;
 #pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb) {
-            float v[4];
+            for (int nb = 0; nb < C::NB; ++nb) {
+              gbyte* const d = d0 + (int64_t)nb * J.out_zs * PB;
+              float t[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = relu(fmaf(acc[u][nb][k], osc[nb], bias[nb]));
-            store_block_tile<P>(orow + (int64_t)nb * J.out_zs * PB, ok, v, n16, prm.out_inv_scale);
+              for (int k = 0; k < 4; ++k) t[k] = fmaf(acc[u][nb][k], sc[nb][k], bs[nb][k]);
+              if constexpr (P == BF16) {
+                st<u2v>(d, u2v{pack_bf16x2(relu(t[0]), relu(t[1])), pack_bf16x2(relu(t[2]), relu(t[3]))});
+              } else {
+                // relu(t) * s clamped to [0, 448] is the median of (t * s, 0, 448)
+                // for s > 0; clearing bit 7 of each code maps a -0 to +0
+                float v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_fmed3f(t[k] * inv, 0.0f, 448.0f);
+                int wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], __builtin_bit_cast(int, v[0]), false);
+                wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], wd, true);
+                st<uint32_t>(d, (uint32_t)wd & 0x7f7f7f7fu);
+              }
+            }
           }
         }
       }
