@@ -52,9 +52,11 @@ def log(*a):
 
 
 def kernel_source_sha():
+    """sha1 of the conv kernels' source and of the build script (its per-file
+    compiler flags change the code of the same source)."""
     h = hashlib.sha1()
-    for f in ("conv_kernels.hip",):
-        with open(os.path.join(ROOT, "paper_1612_02120_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/conv_kernels.hip", "build_lib.py"):
+        with open(os.path.join(ROOT, "paper_1612_02120_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
