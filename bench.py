@@ -504,10 +504,6 @@ def main():
         pool = em_volume(4, 8, 1040, 1040)
         hb = emcnn.cnn_create(p, NET_B, "bf16")
         t_tune = 0.0
-        if not args.no_batch_autotune:  # tile shapes picked by the autotuner on a 1024^2 slice
-            t0 = time.perf_counter()
-            emcnn.cnn_autotune(hb, 1024, 1024, args.tune_cache, stream)
-            t_tune = time.perf_counter() - t0
         tiles, nv = [], 0
         for t in tl:
             y = int(rng.integers(0, 1040 - t["h"] + 1))
@@ -517,6 +513,10 @@ def main():
             out = torch.empty((t["z"], L, L), dtype=torch.float32, device=dev)
             tiles.append((inp, t["halo"], out))
             nv += t["z"] * L * L
+        if not args.no_batch_autotune:  # tile shapes per tile class, tuned on these tiles
+            t0 = time.perf_counter()
+            emcnn.cnn_autotune_batch(hb, tiles, stream)
+            t_tune = time.perf_counter() - t0
         with torch.cuda.stream(stream):
             for _ in range(2):
                 emcnn.cnn_infer_batch(hb, tiles, stream=stream)
@@ -547,7 +547,7 @@ def main():
                           "per_tile_loop": "cnn_infer per tile (input cropped to a halo of R/2), 3 direct "
                                            "launches per tile, no host waits",
                           "path_mfma_frac": nv * NET_B_FLOP_PER_VOXEL / (msb * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"],
-                          "autotuned": not args.no_batch_autotune, "autotune_s": t_tune,
+                          "autotuned": "per tile class" if not args.no_batch_autotune else False, "autotune_s": t_tune,
                           "tiles": emcnn.cnn_describe(hb)}
         log("batch", json.dumps(forms["batch"]))
         del tiles, hb

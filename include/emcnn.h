@@ -210,6 +210,21 @@ int cnn_infer_batch(cnn_net* net, const cnn_tile* tiles, int32_t n, void* stream
  * text file of earlier choices, read first and updated. */
 int cnn_autotune(cnn_net* net, int64_t H, int64_t W, const char* cache_path, void* stream);
 
+/* Per tile class tile shapes for cnn_infer_batch (Section 2.2: the volume is
+ * processed as independent blocks, of varied sizes). Tiles are classed by
+ * their smaller output side, with representative sides 64, 128, 256, 512 and
+ * 1024 (class edges at their geometric means, 91, 181, 362 and 724). For each
+ * class present in `tiles` (the same descriptors cnn_infer_batch takes), every
+ * layer's candidates are timed, greedily layer by layer, on submissions of
+ * that class's tiles; a candidate is accepted only if every output of the class
+ * is bitwise equal to the default variants' output. cnn_infer_batch then plans
+ * each class with its own variants (classes with equal choices together);
+ * cnn_infer keeps the handle's selected variants, and cnn_set_variant drops the
+ * per-class choice. The tiles' output buffers are overwritten (their content
+ * afterwards is unspecified). Synchronous; allocates a copy of the largest
+ * class's outputs while it runs. */
+int cnn_autotune_batch(cnn_net* net, const cnn_tile* tiles, int32_t n, void* stream);
+
 /* Batched submissions are captured as a HIP graph by default; enable = 0
  * launches the same kernels directly instead (a per-call launch sequence). */
 int cnn_set_batch_graph(cnn_net* net, int32_t enable);

@@ -61,7 +61,7 @@ EXPORTS = [
     "student_train_step", "student_infer", "student_infer_with_fallback", "cnn_last_error",
     "cnn_profile", "cnn_profile_read", "cnn_variant_name", "cnn_set_variant",
     "cnn_infer_noalloc", "student_gather", "cnn_read_activation", "cnn_mfma_probe", "cnn_mfma_bench",
-    "cnn_output_dims", "watershed_3d", "cnn_infer_maps",
+    "cnn_output_dims", "watershed_3d", "cnn_infer_maps", "cnn_autotune_batch",
 ]
 
 
@@ -84,6 +84,7 @@ def _load():
         "cnn_mfma_bench": [i32, i32, i32, vp, vp, vp, vp],
         "cnn_infer_batch": [vp, vp, i32, vp],
         "cnn_autotune": [vp, i64, i64, ctypes.c_char_p, vp],
+        "cnn_autotune_batch": [vp, vp, i32, vp],
         "cnn_describe": [vp, ctypes.c_char_p, i32],
         "cnn_set_batch_graph": [vp, i32],
         "cnn_set_workspace_limit": [vp, i64],
@@ -288,9 +289,7 @@ def cnn_infer_noalloc(net: Net, volume, out, stream=None):
     return out
 
 
-def cnn_infer_batch(net: Net, tiles, stream=None):
-    """tiles: list of (input uint8 CUDA tensor z x h x w, halo, output float32 CUDA tensor
-    z x (h-2 halo) x (w-2 halo))."""
+def _tile_array(tiles):
     import torch
     arr = (_Tile * len(tiles))()
     for i, (inp, halo, out) in enumerate(tiles):
@@ -300,6 +299,13 @@ def cnn_infer_batch(net: Net, tiles, stream=None):
         if tuple(out.shape) != (z, h - 2 * halo, w - 2 * halo):
             raise ValueError("tile %d: output must be z x (h-2 halo) x (w-2 halo)" % i)
         arr[i] = _Tile(inp.data_ptr(), z, h, w, int(halo), out.data_ptr())
+    return arr
+
+
+def cnn_infer_batch(net: Net, tiles, stream=None):
+    """tiles: list of (input uint8 CUDA tensor z x h x w, halo, output float32 CUDA tensor
+    z x (h-2 halo) x (w-2 halo))."""
+    arr = _tile_array(tiles)
     _check(_lib.cnn_infer_batch(net.ptr, arr, len(tiles), _stream(stream)), "cnn_infer_batch")
 
 
@@ -307,6 +313,13 @@ def cnn_autotune(net: Net, H: int, W: int, cache_path=None, stream=None):
     _check(_lib.cnn_autotune(net.ptr, int(H), int(W),
                              None if cache_path is None else str(cache_path).encode(),
                              _stream(stream)), "cnn_autotune")
+
+
+def cnn_autotune_batch(net: Net, tiles, stream=None):
+    """Per tile class tile shapes for cnn_infer_batch, tuned on these tiles
+    (as cnn_infer_batch takes them; their outputs are overwritten)."""
+    arr = _tile_array(tiles)
+    _check(_lib.cnn_autotune_batch(net.ptr, arr, len(tiles), _stream(stream)), "cnn_autotune_batch")
 
 
 def cnn_describe(net: Net) -> str:

@@ -444,6 +444,8 @@ int plan_regions(Net* net, const std::vector<Region>& in_regions, size_t job_off
       }
       Launch la;
       la.layer = l;
+      la.variant = L.variant;
+      la.wpack = L.wpack;
       std::memset(&la.js, 0, sizeof(la.js));
       la.js.table = reinterpret_cast<const LayerJob*>(A.tab_dev) + first;
       la.js.njobs = (int)(pos - first);
@@ -483,7 +485,7 @@ int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t
     if ((e = hipMemcpyAsync(dsrc, hsrc, tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
       return hip_fail(e, "job table upload");
     for (auto& la : launches) {
-      int rc = launch_layer(net, net->layers[la.layer], la.js, la.grid, st);
+      int rc = launch_planned(net, la, st);
       if (rc) return rc;
     }
   } else {
@@ -500,8 +502,7 @@ int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t
       put(&la.js.table, sizeof(void*));
       put(&la.js.njobs, sizeof(int));
       put(&la.js.total_items, sizeof(int64_t));
-      const int v = net->layers[la.layer].variant;
-      put(&v, sizeof(int));
+      put(&la.variant, sizeof(int));
     }
     if (!A.graph_exec || key != A.graph_key) {
       if (A.graph_exec) hipGraphExecDestroy(A.graph_exec);
@@ -518,7 +519,7 @@ int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t
         crc = hip_fail(e, "capture: job table upload");
       for (auto& la : launches) {
         if (crc) break;
-        crc = launch_layer(net, net->layers[la.layer], la.js, la.grid, net->cap_stream);
+        crc = launch_planned(net, la, net->cap_stream);
       }
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(net->cap_stream, &g);
@@ -540,6 +541,20 @@ int submit(Net* net, const std::vector<Launch>& launches, size_t job_off, size_t
   if ((e = hipEventRecord(A.done, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
   A.done_pending = true;
   return CNN_OK;
+}
+
+int launch_planned(Net* net, const Launch& la, hipStream_t st) {
+  ExecLayer& L = net->layers[la.layer];
+  const int v0 = L.variant;
+  void* w0 = L.wpack;
+  if (la.variant >= 0) {
+    L.variant = la.variant;
+    L.wpack = la.wpack;
+  }
+  const int rc = launch_layer(net, L, la.js, la.grid, st);
+  L.variant = v0;
+  L.wpack = w0;
+  return rc;
 }
 
 int check_device(const Net* net) {
@@ -676,24 +691,22 @@ extern "C" int cnn_set_workspace_limit(cnn_net* h, int64_t bytes) {
   return CNN_OK;
 }
 
-extern "C" int cnn_infer_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, void* stream) {
-  clear_error();
-  if (!h || !tiles || n < 1) return fail(CNN_EINVAL, "cnn_infer_batch: null argument or n < 1");
-  Net* net = reinterpret_cast<Net*>(h);
-  int rc = check_device(net);
-  if (rc) return rc;
+namespace emcnn {
+
+// Regions of a batch's tiles, the halo surplus beyond R/2 dropped (a tile's
+// interior is then exactly the valid output); validates every tile.
+static int batch_regions(const Net* net, const cnn_tile* tiles, int32_t n, const char* who, std::vector<Region>& regs) {
   if (net->R % 2 || net->out_stride != 1 || net->in_channels != 1)
     return fail(CNN_EUNSUPPORTED,
-                "cnn_infer_batch: blocks need an odd field of view, a full-resolution output and uint8 input");
+                std::string(who) + ": blocks need an odd field of view, a full-resolution output and uint8 input");
   const int R2 = net->R / 2;
-  std::vector<Region> regs(n);
+  regs.assign(n, Region());
   for (int t = 0; t < n; ++t) {
     const cnn_tile& T = tiles[t];
-    if (!T.in || !T.out) return fail(CNN_EINVAL, "cnn_infer_batch: tile " + std::to_string(t) + " has a null pointer");
+    if (!T.in || !T.out) return fail(CNN_EINVAL, std::string(who) + ": tile " + std::to_string(t) + " has a null pointer");
     if (T.z < 1 || T.halo < R2 || T.h <= 2 * (int64_t)T.halo || T.w <= 2 * (int64_t)T.halo || T.h >= (1 << 30) ||
         T.w >= (1 << 30) || T.z >= (1 << 30))
-      return fail(CNN_EINVAL, "cnn_infer_batch: tile " + std::to_string(t) + " has bad dims or halo < R/2");
-    // drop the halo surplus beyond R/2: the tile's interior is then exactly the valid output
+      return fail(CNN_EINVAL, std::string(who) + ": tile " + std::to_string(t) + " has bad dims or halo < R/2");
     const int e = T.halo - R2;
     Region& r = regs[t];
     r.in = T.in + (int64_t)e * T.w + e;
@@ -707,12 +720,76 @@ extern "C" int cnn_infer_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, voi
     r.out_zs = (T.h - 2 * T.halo) * (T.w - 2 * T.halo);
     r.gate = nullptr;
   }
+  return CNN_OK;
+}
+
+// Tile class of a region (its smaller output side).
+static int region_class(const Net* net, const Region& r) { return tile_class(std::min(r.h, r.w) - net->R); }
+
+}  // namespace emcnn
+
+extern "C" int cnn_infer_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, void* stream) {
+  clear_error();
+  if (!h || !tiles || n < 1) return fail(CNN_EINVAL, "cnn_infer_batch: null argument or n < 1");
+  Net* net = reinterpret_cast<Net*>(h);
+  int rc = check_device(net);
+  if (rc) return rc;
+  std::vector<Region> regs;
+  rc = batch_regions(net, tiles, n, "cnn_infer_batch", regs);
+  if (rc) return rc;
   rc = arena_reserve(net, count_region_jobs(net, regs));
   if (rc) return rc;
   std::vector<Launch> launches;
   size_t used = 0, ws_need = 0;
-  rc = plan_regions(net, regs, 0, launches, used, ws_need);
-  if (rc) return rc;
+  if (net->class_variants.empty()) {
+    rc = plan_regions(net, regs, 0, launches, used, ws_need);
+    if (rc) return rc;
+  } else {
+    // each tile class with its own variants, planned one class after another;
+    // classes that chose the same variants share one plan (one launch per
+    // layer over all their tiles)
+    const int nl = (int)net->layers.size();
+    std::vector<std::vector<Region>> byc(kTileClasses);
+    for (const Region& r : regs) {
+      int c = region_class(net, r);
+      for (int k = 0; k < c; ++k)
+        if (net->class_variants[k] == net->class_variants[c]) {
+          c = k;  // the first class with the same choice
+          break;
+        }
+      byc[c].push_back(r);
+    }
+    std::vector<int> defaults(nl);
+    for (int l = 0; l < nl; ++l) defaults[l] = net->layers[l].variant;
+    auto use = [&](const std::vector<int>& v) {
+      for (int l = 0; l < nl; ++l) select_variant(net->layers[l], v[l]);
+    };
+    // the workspace for every class first: growing it while planning a later
+    // class would free it under the jobs of an earlier one
+    size_t ws_max = 0;
+    for (int c = 0; c < kTileClasses && !rc; ++c) {
+      if (byc[c].empty()) continue;
+      use(net->class_variants[c]);
+      std::vector<Launch> none;
+      size_t u = 0, wn = 0;
+      rc = plan_regions(net, byc[c], 0, none, u, wn, true);
+      ws_max = std::max(ws_max, wn);
+    }
+    use(defaults);
+    if (!rc) rc = ensure_ws(net, ws_max);
+    if (rc) return rc;
+    const void* ws_before = net->ws;
+    for (int c = 0; c < kTileClasses && !rc; ++c) {
+      if (byc[c].empty()) continue;
+      use(net->class_variants[c]);
+      size_t u = 0;
+      rc = plan_regions(net, byc[c], used, launches, u, ws_need);
+      used += u;
+    }
+    use(defaults);
+    if (rc) return rc;
+    if (net->ws != ws_before) return fail(CNN_EHIP, "cnn_infer_batch: internal: workspace moved during planning");
+  }
   return submit(net, launches, 0, used, reinterpret_cast<hipStream_t>(stream), net->use_graph != 0);
 }
 
@@ -914,6 +991,159 @@ extern "C" int cnn_autotune(cnn_net* h, int64_t H, int64_t W, const char* cache_
   return CNN_OK;
 }
 
+namespace emcnn {
+
+// Number of 32-bit words that differ between a and b (n words), added to *cnt.
+__global__ __launch_bounds__(256) void count_mismatch(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                                                      int64_t n, unsigned int* cnt) {
+  unsigned int c = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) c += a[i] != b[i];
+  if (c) atomicAdd(cnt, c);
+}
+
+}  // namespace emcnn
+
+extern "C" int cnn_autotune_batch(cnn_net* h, const cnn_tile* tiles, int32_t n, void* stream) {
+  clear_error();
+  if (!h || !tiles || n < 1) return fail(CNN_EINVAL, "cnn_autotune_batch: null argument or n < 1");
+  Net* net = reinterpret_cast<Net*>(h);
+  int rc = check_device(net);
+  if (rc) return rc;
+  std::vector<Region> regs;
+  rc = batch_regions(net, tiles, n, "cnn_autotune_batch", regs);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int nl = (int)net->layers.size();
+  std::vector<int> defaults(nl);
+  for (int l = 0; l < nl; ++l) defaults[l] = net->layers[l].variant;
+  auto use = [&](const std::vector<int>& v) {
+    for (int l = 0; l < nl; ++l) select_variant(net->layers[l], v[l]);
+  };
+  std::vector<std::vector<int>> byc(kTileClasses);
+  for (int t = 0; t < n; ++t) byc[region_class(net, regs[t])].push_back(t);
+  std::vector<std::vector<int>> cv(kTileClasses, defaults);
+  net->class_variants.clear();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  void* ref = nullptr;
+  unsigned int* cnt = nullptr;
+  auto cleanup = [&]() {
+    use(defaults);
+    if (ref) hipFree(ref);
+    if (cnt) hipFree(cnt);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess ||
+      (e = hipMalloc(&cnt, sizeof(unsigned int))) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "cnn_autotune_batch: setup");
+  }
+  for (int c = 0; c < kTileClasses && !rc; ++c) {
+    if (byc[c].empty()) continue;
+    std::vector<Region> rc_regs;
+    std::vector<size_t> off;  // each tile's output, in 32-bit words, inside the reference copy
+    size_t words = 0;
+    for (int t : byc[c]) {
+      rc_regs.push_back(regs[t]);
+      off.push_back(words);
+      words += (size_t)tiles[t].z * (tiles[t].h - 2 * tiles[t].halo) * (tiles[t].w - 2 * tiles[t].halo);
+    }
+    if (ref) hipFree(ref);
+    ref = nullptr;
+    if ((e = hipMalloc(&ref, words * 4)) != hipSuccess) {
+      rc = fail(CNN_ENOMEM, "cnn_autotune_batch: reference outputs");
+      break;
+    }
+    // one submission of this class's tiles with variants v (direct launches)
+    auto pass = [&](const std::vector<int>& v) -> int {
+      use(v);
+      int r = arena_reserve(net, count_region_jobs(net, rc_regs));
+      std::vector<Launch> launches;
+      size_t used = 0, wn = 0;
+      if (!r) r = plan_regions(net, rc_regs, 0, launches, used, wn);
+      if (!r) r = submit(net, launches, 0, used, st, false);
+      return r;
+    };
+    // timed passes: one untimed, then enough for ~10 ms
+    auto timed = [&](const std::vector<int>& v, float& ms) -> int {
+      int r = pass(v);
+      if (!r && (e = hipEventRecord(e0, st)) != hipSuccess) r = hip_fail(e, "cnn_autotune_batch: timing");
+      if (!r) r = pass(v);
+      if (!r && (e = hipEventRecord(e1, st)) != hipSuccess) r = hip_fail(e, "cnn_autotune_batch: timing");
+      if (!r && (e = hipEventSynchronize(e1)) != hipSuccess) r = hip_fail(e, "cnn_autotune_batch: timing");
+      float ms1 = 0.f;
+      if (!r) hipEventElapsedTime(&ms1, e0, e1);
+      const int reps = (int)std::min(20.0f, std::max(2.0f, 10.0f / std::max(ms1, 1e-3f)));
+      if (!r && (e = hipEventRecord(e0, st)) != hipSuccess) r = hip_fail(e, "cnn_autotune_batch: timing");
+      for (int k = 0; k < reps && !r; ++k) r = pass(v);
+      if (!r && (e = hipEventRecord(e1, st)) != hipSuccess) r = hip_fail(e, "cnn_autotune_batch: timing");
+      if (!r && (e = hipEventSynchronize(e1)) != hipSuccess) r = hip_fail(e, "cnn_autotune_batch: timing");
+      if (!r) {
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+      }
+      return r;
+    };
+    // the reference: the class's outputs with the default variants
+    float best_ms = 0.f;
+    rc = timed(defaults, best_ms);
+    for (size_t k = 0; k < byc[c].size() && !rc; ++k) {
+      const cnn_tile& T = tiles[byc[c][k]];
+      const size_t bytes = (size_t)T.z * (T.h - 2 * T.halo) * (T.w - 2 * T.halo) * 4;
+      if ((e = hipMemcpyAsync(reinterpret_cast<uint32_t*>(ref) + off[k], T.out, bytes, hipMemcpyDeviceToDevice, st)) !=
+          hipSuccess)
+        rc = hip_fail(e, "cnn_autotune_batch: reference copy");
+    }
+    if (rc) break;
+    std::vector<int> best = defaults;
+    for (int l = 0; l < nl && !rc; ++l) {
+      const ExecLayer& L = net->layers[l];
+      for (int cand : L.candidates) {
+        if (cand == best[l]) continue;
+        // only candidates with the default's accumulation order
+        if (!L.first && (conv_variant(cand)->rr != conv_variant(defaults[l])->rr ||
+                         conv_variant(cand)->cb != conv_variant(defaults[l])->cb ||
+                         conv_variant(cand)->fused != conv_variant(defaults[l])->fused))
+          continue;
+        std::vector<int> trial = best;
+        trial[l] = cand;
+        float ms = 0.f;
+        rc = timed(trial, ms);
+        if (rc) break;
+        // bitwise check of every tile's output against the reference
+        if ((e = hipMemsetAsync(cnt, 0, sizeof(unsigned int), st)) != hipSuccess) {
+          rc = hip_fail(e, "cnn_autotune_batch: check");
+          break;
+        }
+        for (size_t k = 0; k < byc[c].size(); ++k) {
+          const cnn_tile& T = tiles[byc[c][k]];
+          const int64_t w = (int64_t)T.z * (T.h - 2 * T.halo) * (T.w - 2 * T.halo);
+          const int grid = (int)std::min<int64_t>((w + 255) / 256, 4096);
+          hipLaunchKernelGGL(count_mismatch, dim3(grid), dim3(256), 0, st,
+                             reinterpret_cast<const uint32_t*>(T.out), reinterpret_cast<const uint32_t*>(ref) + off[k],
+                             w, cnt);
+        }
+        unsigned int bad = 1;
+        if ((e = hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess) {
+          rc = hip_fail(e, "cnn_autotune_batch: check");
+          break;
+        }
+        if (bad == 0 && ms < best_ms) {
+          best_ms = ms;
+          best = trial;
+        }
+      }
+    }
+    cv[c] = best;
+  }
+  cleanup();
+  if (rc) return rc;
+  net->class_variants = cv;
+  return CNN_OK;
+}
+
 extern "C" int cnn_profile(cnn_net* h, int32_t enable) {
   clear_error();
   if (!h) return fail(CNN_EINVAL, "cnn_profile: null net");
@@ -956,6 +1186,7 @@ extern "C" int cnn_set_variant(cnn_net* h, int32_t layer, const char* name) {
   ExecLayer& L = net->layers[layer];
   const int c = candidate_name_index(L, name);
   if (c < 0 || !select_variant(L, c)) return fail(CNN_EINVAL, std::string("cnn_set_variant: no candidate ") + name);
+  net->class_variants.clear();  // an explicit choice applies to batches too
   return CNN_OK;
 }
 

@@ -92,7 +92,22 @@ struct Net {
   };
   std::vector<Timed> timed;
   std::vector<hipEvent_t> event_pool;
+  // per tile class (kTileClasses), the variant of every layer that batched
+  // submissions use for that class's tiles; empty: the selected variants
+  std::vector<std::vector<int>> class_variants;
 };
+
+// Tile classes of the batched form, by the smaller output side of a tile:
+// representative sides 64, 128, 256, 512, 1024 (class edges at their
+// geometric means).
+constexpr int kTileClasses = 5;
+inline int tile_class(int64_t side) {
+  const int64_t edges[kTileClasses - 1] = {91, 181, 362, 724};
+  int c = 0;
+  while (c < kTileClasses - 1 && side >= edges[c]) ++c;
+  return c;
+}
+inline int tile_class_side(int c) { return 64 << c; }
 
 // Conv output dims of every executed layer for an input region of h x w.
 struct Dims {
@@ -114,7 +129,13 @@ struct Launch {
   int layer;
   int grid;
   JobSet js;
+  // the layer's variant (and its packed weights) when the launch was planned;
+  // batches plan tile classes with different variants
+  int variant = -1;
+  void* wpack = nullptr;
 };
+// Launch la with the variant it was planned with.
+int launch_planned(Net* net, const Launch& la, hipStream_t st);
 
 Dims layer_dims(const Net* net, int h, int w);
 inline int stored_channels(const ExecLayer& L) { return L.cstore ? L.cstore : L.cout; }

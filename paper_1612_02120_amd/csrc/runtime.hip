@@ -781,6 +781,15 @@ extern "C" int cnn_describe(const cnn_net* h, char* buf, int32_t len) {
     s += layer_name(net->layers[l]);
     if (l == 0 && fused) s += " (computed inside layer 1)";
   }
+  // per tile class choices of batched submissions (cnn_autotune_batch)
+  for (size_t c = 0; c < net->class_variants.size(); ++c) {
+    s += c == 0 ? " || batch classes: " : "; ";
+    s += std::to_string(tile_class_side((int)c)) + ":";
+    for (size_t l = 0; l < net->layers.size(); ++l) {
+      const int v = net->class_variants[c][l];
+      s += std::string(l ? " " : " ") + (net->layers[l].first ? first_variant(v)->name : conv_variant(v)->name);
+    }
+  }
   std::snprintf(buf, len, "%s", s.c_str());
   return CNN_OK;
 }

@@ -105,6 +105,7 @@ def test_null_handles_are_rejected():
     assert m._lib.cnn_destroy(None) == m.CNN_OK
     assert m._lib.student_train_step(None, None, None, 1, 128, None, None, None, None) == m.CNN_EINVAL
     assert m._lib.cnn_geometry(None, None, None) == m.CNN_EINVAL
+    assert m._lib.cnn_autotune_batch(None, None, 0, None) == m.CNN_EINVAL
 
 
 def test_binding_checks_caller_buffers_before_the_library():
