@@ -644,7 +644,8 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
       const AT* a0 = tile + ST * (mrow * C::LCP + mcol * 16 + n16);
       f4 acc[C::NB];
 #pragma unroll
-      for (int nb = 0; nb < C::NB; ++nb) acc[nb] = f4{0.f, 0.f, 0.f, 0.f};
+      // the accumulators start at the bias: the MFMA adds the taps to it
+      for (int nb = 0; nb < C::NB; ++nb) acc[nb] = f4{bias[nb][0], bias[nb][1], bias[nb][2], bias[nb][3]};
       if constexpr (PO == F32) {
 #pragma unroll
         for (int s = 0; s < C::NSTEP; ++s) {
@@ -674,8 +675,8 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
         unsigned char* scr = scr_all + wave * 16 * PIXB;
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
-          const float m0 = fmaxf(acc[nb][0] + bias[nb][0], acc[nb][1] + bias[nb][1]);
-          const float m1 = fmaxf(acc[nb][2] + bias[nb][2], acc[nb][3] + bias[nb][3]);
+          const float m0 = fmaxf(acc[nb][0], acc[nb][1]);
+          const float m1 = fmaxf(acc[nb][2], acc[nb][3]);
           unsigned char* dst = scr + n16 * PIXB + (nb * 8 + 2 * g) * C::ESZ;
           if constexpr (PO == F32)
             *reinterpret_cast<f2*>(dst) = f2{m0, m1};
@@ -709,14 +710,14 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
           if constexpr (PO == BF16) {
             float v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
+            for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k]);
             *reinterpret_cast<u2v*>(d) = u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])};
           } else {
             const float inv = prm.out_inv_scale;
             float v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-              v[k] = __builtin_amdgcn_fmed3f((acc[nb][k] + bias[nb][k]) * inv, 0.0f, 448.0f);
+              v[k] = __builtin_amdgcn_fmed3f(acc[nb][k] * inv, 0.0f, 448.0f);
             int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], __builtin_bit_cast(int, v[0]), false);
             w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
             *reinterpret_cast<uint32_t*>(d) = (uint32_t)w & 0x7f7f7f7fu;
@@ -749,7 +750,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
             if constexpr (PO == BF16) {
               float v[4];
 #pragma unroll
-              for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
+              for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k]);
               st<u2v>(d, u2v{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])});
             } else {
               // relu(t) * s clamped to [0, 448] is the median of (t * s, 0, 448)
@@ -760,7 +761,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
               float v[4];
 #pragma unroll
               for (int k = 0; k < 4; ++k)
-                v[k] = __builtin_amdgcn_fmed3f((acc[nb][k] + bias[nb][k]) * inv, 0.0f, 448.0f);
+                v[k] = __builtin_amdgcn_fmed3f(acc[nb][k] * inv, 0.0f, 448.0f);
               // (the first conversion's high half is any value: the second overwrites it)
               int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], __builtin_bit_cast(int, v[0]), false);
               w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
@@ -780,7 +781,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
         for (int nb = 0; nb < C::NB; ++nb) {
           float v[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k] + bias[nb][k]);
+          for (int k = 0; k < 4; ++k) v[k] = relu(acc[nb][k]);
           *reinterpret_cast<f4*>(scr + (n16 * COUT + nb * 16 + 4 * g) * 4) = f4{v[0], v[1], v[2], v[3]};
         }
         __builtin_amdgcn_wave_barrier();
@@ -1905,11 +1906,13 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
           float hprev[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int rr = 0; rr <= C::RPW; ++rr) {
-            const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[nb1], xb[rr], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            // started at the bias, as the separate first layer does
+            const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                wfr[nb1], xb[rr], f4{b4[nb1][0], b4[nb1][1], b4[nb1][2], b4[nb1][3]}, 0, 0, 0);
             float h[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-              const float t = relu(acc[k] + b4[nb1][k]);
+              const float t = relu(acc[k]);
               // pixel n + 1 (lane n + 1 of the row; lane 15's value is never stored)
               const float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, t),
                                                                                     0x101, 0xF, 0xF, false));
