@@ -1324,12 +1324,13 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
 }
 
 // The two-class softmax layer of a stride-2 pool net on the VALU. Its two
-// output channels would fill 2 of an MFMA's 16 columns; as FP32 FMAs its
-// 2 x KS^2 x CIN multiply-adds per pixel need no padding. The operand tile is
-// conv_phase's (all CIN channels in one stage); one output pixel per thread,
-// reading operand pixels along a row, which is conflict-free with the
-// 8 (mod 16) dword pixel stride. Weights are laid out
-// [i][cg][j][class][4 channels] and read with wave-uniform (scalar) loads.
+// output channels would fill 2 of an MFMA's 16 columns; on the VALU the
+// class-1 probability needs only the logit difference, KS^2 x CIN FP32
+// multiply-adds per pixel with the weight difference W[1] - W[0]. The operand
+// tile is conv_phase's (all CIN channels in one stage); one output pixel per
+// thread, reading operand pixels along a row, which is conflict-free with the
+// 8 (mod 16) dword pixel stride. The weight differences are laid out
+// [i][cg][j][4 channels] and read with wave-uniform (scalar) loads.
 template <int CIN, int KS, int TY, int TX>
 struct CfgHead {
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
@@ -1405,13 +1406,15 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
     const int py = ph / d, px = ph % d;
     const int y0 = by * TY, x0 = bx * TX;
     const FragTile ft = frag_tile(gin(J.in) + (int64_t)zz * J.in_zs * ELB, ELB, J, py, px);
+    // the class-1 probability of a two-class softmax is the sigmoid of the
+    // logit difference: one dot product with the weight difference
     __syncthreads();
     if constexpr (P == F32)
       stage_phase_tile<F32, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, ft, 0, ELB, y0, x0, tid);
     else
       stage_phase_tile_widen<C::LR, C::LC, CIN / 8, C::PSB, C::THREADS>(lds, ft, ELB, y0, x0, tid);
     __syncthreads();
-    float z0 = 0.f, z1 = 0.f;
+    float z = 0.f;
 #pragma unroll
     for (int i = 0; i < KS; ++i)
 #pragma unroll
@@ -1419,17 +1422,14 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
 #pragma unroll
         for (int j = 0; j < KS; ++j) {
           const f4 x = *reinterpret_cast<const f4*>(lds + ((r + i) * C::LC + c + j) * C::PSB + cg * 16);
-          const __attribute__((address_space(4))) float* w = wk + (((i * C::NCHB + cg) * KS + j) * 2) * 4;
+          const __attribute__((address_space(4))) float* w = wk + ((i * C::NCHB + cg) * KS + j) * 4;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            z0 = fmaf(x[e], w[e], z0);
-            z1 = fmaf(x[e], w[4 + e], z1);
-          }
+          for (int e = 0; e < 4; ++e) z = fmaf(x[e], w[e], z);
         }
     const int y = py + d * (y0 + r), x = px + d * (x0 + c);
     if (y < J.hout && x < J.wout)
       st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, (J.geom >> 16) & 0xf, J.out_rs, J.out_zs)) * 4,
-                sigmoid_f((z1 + b1) - (z0 + b0)));
+                sigmoid_f(z + (b1 - b0)));
   }
 }
 
@@ -2338,7 +2338,6 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   VariantInfo{P, CIN, 2, KS, 1, 0, TY, TX, 0, CfgHead<CIN, KS, TY, TX>::THREADS, CIN, PT<F32>::CHB, 1, 0, 0, 0, 3, \
               CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<P, CIN, KS, TY, TX>),       \
               "head_phase<" #P "," #CIN "," #KS "," #TY "," #TX ">"}
-
 #define EMCNN_HEAD1(P, CIN, NCLS, TX)                                                                    \
   VariantInfo{P, CIN, NCLS, 1, 0, 0, 1, TX, 0, TX, CIN, PT<F32>::CHB, 1, 0, 0, 0, 4, 0,                     \
               reinterpret_cast<const void*>(&head_1x1<CIN, NCLS, TX>), "head_1x1<" #CIN "," #NCLS "," #TX ">"}

@@ -255,20 +255,23 @@ static int pack_first(ExecLayer& L, int variant, const double* w, const double* 
   return CNN_OK;
 }
 
-// Weights of the VALU two-class layer (head_phase): W[class][ci][i][j] as
-// [i][ci / 4][j][class][ci % 4], FP32; the bias is stored padded to 16 floats
-// (the MFMA candidate of the same layer reads 16).
+// Weights of the VALU two-class layer (head_phase). A two-class softmax is
+// the sigmoid of the logit difference, so the layer needs only the weight
+// difference W[1] - W[0] (taken in FP64, rounded once), as [i][ci / 4][j][ci % 4],
+// FP32; the bias is stored padded to 16 floats (the MFMA candidate of the same
+// layer reads 16), and the kernel takes b1 - b0.
 static int pack_head_valu(ExecLayer& L, int variant, const double* w, const double* b) {
   const VariantInfo* v = conv_variant(variant);
   const int cin = v->cin, ks = v->ks, ncg = cin / 4;
-  std::vector<float> pk((size_t)ks * ncg * ks * 2 * 4);
+  std::vector<float> pk((size_t)ks * ncg * ks * 4);
   for (int i = 0; i < ks; ++i)
     for (int cg = 0; cg < ncg; ++cg)
       for (int j = 0; j < ks; ++j)
-        for (int cls = 0; cls < 2; ++cls)
-          for (int e = 0; e < 4; ++e)
-            pk[((((size_t)i * ncg + cg) * ks + j) * 2 + cls) * 4 + e] =
-                (float)w[(((size_t)cls * cin + 4 * cg + e) * ks + i) * ks + j];
+        for (int e = 0; e < 4; ++e) {
+          const size_t k0 = (((size_t)0 * cin + 4 * cg + e) * ks + i) * ks + j;
+          const size_t k1 = (((size_t)1 * cin + 4 * cg + e) * ks + i) * ks + j;
+          pk[(((size_t)i * ncg + cg) * ks + j) * 4 + e] = (float)(w[k1] - w[k0]);
+        }
   hipError_t err;
   void* wdev = nullptr;
   if ((err = hipMalloc(&wdev, pk.size() * 4)) != hipSuccess) return hip_fail(err, "hipMalloc(head weights)");
