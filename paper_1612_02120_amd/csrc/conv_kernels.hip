@@ -1433,6 +1433,133 @@ __global__ __launch_bounds__((CfgHead<CIN, KS, TY, TX>::THREADS)) void head_phas
   }
 }
 
+// The two-class softmax layer of a stride-2 pool net as one small GEMM per
+// operand pixel. With Wd = W[1] - W[0], the logit difference at output (r, c)
+// of a phase tile is the sum over taps (i, j) of D[(r + i, c + j)][(i, j)],
+// where D[p][t] = sum over channels of X[p][ch] Wd[t][ch]: one 16-column
+// n-block over the KS^2 = 16 taps. Each operand pixel (the 2x2 max filter)
+// thus goes through the MFMA once, against once per tap with 14 of 16
+// columns zero in the padded implicit GEMM. D leaves the accumulators for LDS
+// as planes E[t][pixel]; each thread then sums its output pixel's 16 taps from
+// 16 planes and stores the class-1 probability, the sigmoid of the sum plus
+// b1 - b0.
+//
+// Operand tile: LR = TY + KS - 1 rows of LCP = 16 NBC columns (whole
+// m-blocks), TX = LCP - KS + 1 outputs a row. Lane (n16, g) of an m-block
+// loads 16-byte chunk 4t + g of pixel n16 for MFMA step t; the packed B
+// fragment of step t holds, in lane (n16, g), tap n16's differences for the
+// same chunk's channels. Plane stride PS = 8 (mod 16) dwords: the sixteen
+// planes one 16-byte accumulator store spans land on distinct banks.
+template <int P, int CIN, int KS, int TY, int NBC, int NW>
+struct CfgTaps {
+  static constexpr int LR = TY + KS - 1, LCP = 16 * NBC, TX = LCP - KS + 1;
+  static constexpr int MB = LR * NBC;                      // m-blocks of the operand tile
+  static constexpr int NK = CIN * PT<P>::BYTES / 64;       // MFMA steps (16-byte chunks per lane group)
+  static constexpr int PS = pad_words(LR * LCP);
+  static constexpr int LDS = 16 * PS * 4;
+  static constexpr int THREADS = NW * 64;
+  static constexpr int UB = 4;                             // m-blocks a wave loads at once
+  static_assert(KS * KS == 16, "the taps fill one 16-column n-block");
+  static_assert(NK * 64 == CIN * PT<P>::BYTES, "whole 16-byte chunks per lane group");
+  static_assert(LDS <= 160 * 1024, "LDS budget of a gfx950 workgroup");
+};
+
+template <int P, int CIN, int KS, int TY, int NBC, int NW>
+__global__ __launch_bounds__(NW * 64) void head_taps(JobSet js, ConvParams prm) {
+  using C = CfgTaps<P, CIN, KS, TY, NBC, NW>;
+  static_assert(P == F32 || P == BF16, "FP32 or keyed BF16 input activations (NHWC)");
+  __shared__ __attribute__((aligned(16))) float E[16 * C::PS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  constexpr int ELB = CIN * PT<P>::BYTES;
+  Frag<P> wf[C::NK];
+#pragma unroll
+  for (int t = 0; t < C::NK; ++t) {
+    const gbyte* p = gin(prm.wpack) + ((size_t)t * 64 + lane) * 16;
+    load_frag<P>(wf[t], p, p);
+  }
+  const float bd = ldf(prm.bias, 1) - ldf(prm.bias, 0);
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
+    // item order and phase decomposition as conv_phase
+    const int d = max(J.geom & 0xff, 1);
+    const int tpy = J.tiles_y / (d * d);
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int ph = (int)(t2 % (d * d));
+    const int64_t t3 = t2 / (d * d);
+    const int by = (int)(t3 % tpy);
+    const int zz = (int)(t3 / tpy);
+    const int py = ph / d, px = ph % d;
+    const int y0 = by * TY, x0 = bx * C::TX;
+    const FragTile ft = frag_tile(gin(J.in) + (int64_t)zz * J.in_zs * ELB, ELB, J, py, px);
+    __syncthreads();  // every thread is done reading the previous item's planes
+    // ---- D = X Wd, m-blocks round-robin over the waves, UB loaded at once
+    for (int mb0 = wave; mb0 < C::MB; mb0 += NW * C::UB) {
+      i4v q[C::UB][C::NK][4];
+#pragma unroll
+      for (int u = 0; u < C::UB; ++u) {
+        const int mb = mb0 + u * NW;
+        if (mb < C::MB) {
+          const int rr = mb / NBC, cc = (mb % NBC) * 16 + n16;
+          const gbyte* p = ft.at(y0 + rr, x0 + cc, ELB) + g * 16;
+#pragma unroll
+          for (int t = 0; t < C::NK; ++t) {
+            q[u][t][0] = ld<i4v>(p + t * 64);
+            q[u][t][1] = ld<i4v>(p + t * 64 + ft.o01);
+            q[u][t][2] = ld<i4v>(p + t * 64 + ft.o10);
+            q[u][t][3] = ld<i4v>(p + t * 64 + ft.o11);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < C::UB; ++u) {
+        const int mb = mb0 + u * NW;
+        if (mb < C::MB) {
+          f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int t = 0; t < C::NK; ++t) {
+            i4v m = chunk_max_signed<P>(chunk_max_signed<P>(q[u][t][0], q[u][t][1]),
+                                        chunk_max_signed<P>(q[u][t][2], q[u][t][3]));
+            if constexpr (P == BF16) {
+#pragma unroll
+              for (int w = 0; w < 4; ++w) m[w] = (int)bf16_unkey((uint32_t)m[w]);
+            }
+            Frag<P> a;
+            if constexpr (P == BF16) a.v = __builtin_bit_cast(bf16x8, m);
+            else a.v = __builtin_bit_cast(f4, m);
+            mma<P>(acc, a, wf[t]);
+          }
+          const int rr = mb / NBC;
+          // lane (n16, g) holds taps n16 of pixels 4g .. 4g + 3 of the m-block
+          *reinterpret_cast<f4*>(&E[n16 * C::PS + rr * C::LCP + (mb % NBC) * 16 + 4 * g]) = acc;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- tap sums, one output pixel per thread and pass
+    const int lgo = (J.geom >> 16) & 0xf;
+    for (int o = tid; o < TY * C::TX; o += C::THREADS) {
+      const int r = o / C::TX, c = o % C::TX;
+      float z = 0.f;
+#pragma unroll
+      for (int i = 0; i < KS; ++i)
+#pragma unroll
+        for (int j = 0; j < KS; ++j) z += E[(i * KS + j) * C::PS + (r + i) * C::LCP + c + j];
+      const int y = py + d * (y0 + r), x = px + d * (x0 + c);
+      if (y < J.hout && x < J.wout)
+        st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * 4,
+                  sigmoid_f(z + bd));
+    }
+  }
+}
+
 // A 1x1 conv to NCLS classes with a softmax, keeping class 0's probability:
 // the output layer of a multi-class net (MaskExtend), on the VALU, one output
 // pixel per thread. Input: row-major NHWC FP32 maps of CIN channels, read as
@@ -2036,10 +2163,10 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   const int g = lane >> 4, n16 = lane & 15;
   const int wrow0 = wave * C::WROWS;
   // TRANS: weights as the MFMA's A operand and pixels as B, so lane (g, n16)
-  // accumulates channels 4g .. 4g + 3 of pixel n16 (4 consecutive stored
-  // channels); otherwise (the head and the spaced form) channel n16 of
-  // pixels 4g .. 4g + 3
-  constexpr bool TRANS = !HEAD && !PH;
+  // accumulates channels 4g .. 4g + 3 of pixel n16 (4 consecutive channels:
+  // stored ones, or two max-out pairs); otherwise (the fused head) channel n16
+  // of pixels 4g .. 4g + 3
+  constexpr bool TRANS = !HEAD;
   __syncthreads();  // the first stage is ready
   int cb = 0, sel = 0;
   f4 acc[C::MW][C::NB];
@@ -2145,9 +2272,11 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 
     if constexpr (PH) {
       if (cb == C::NCB - 1) {
-        // ---- spaced-form epilogue: lane (g, n16) holds channel n16 of pixels 4g + k.
-        // An m-block's 16 pixels x 32 stored channels (1 KB) pass through this
-        // wave's LDS scratch, so that each lane stores 16 contiguous bytes.
+        // ---- spaced-form epilogue: lane (g, n16) holds channels nb*16 + 4g + k
+        // of pixel n16, two max-out pairs whose maxima are stored channels
+        // nb*8 + 2g, +1 (one dword). An m-block's 16 pixels x 32 stored
+        // channels (1 KB) pass through this wave's LDS scratch, so that each
+        // lane stores 16 contiguous bytes.
         static_assert(C::NB == 4, "64 channels, 32 stored: 64 bytes per pixel");
         __shared__ __attribute__((aligned(16))) unsigned char scr_all[NCW * 1024];
         unsigned char* scr = scr_all + wave * 1024;
@@ -2155,28 +2284,19 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
         w.phase_coords<TY, TX>(zz, py, px, y0, x0);
         const LayerJob& J = w.J;
         const int d = max(J.geom & 0xff, 1), lgo = (J.geom >> 16) & 0xf;
-        float bias[C::NB];
+        f4 bs[C::NB];
 #pragma unroll
-        for (int nb = 0; nb < C::NB; ++nb) bias[nb] = ldf(prm.bias, nb * 16 + n16);
-        const int j = n16 & 3, q = n16 >> 2;
+        for (int nb = 0; nb < C::NB; ++nb) bs[nb] = ld<f4>(gin(prm.bias) + (nb * 16 + 4 * g) * 4);
 #pragma unroll
         for (int u = 0; u < C::MW; ++u) {
-          // the dword of stored channels nb*8 + 2q, +1 of pixel 4g + k reaches all
-          // four lanes of quad q; lane (g, 4q + j) keeps pixel 4g + j's
-          uint32_t keep[C::NB];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
+          for (int nb = 0; nb < C::NB; ++nb) {
+            float v[4];
 #pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb) {
-              const float v = acc[u][nb][k] + bias[nb];
-              const float m = fmaxf(v, dpp_f<kQuadXor1>(v));  // channel pair (n16 & ~1, n16 | 1)
-              const float m2 = dpp_f<kQuadXor2>(m);          // the quad's other pair
-              const uint32_t dw = bf16_key((n16 & 2) ? pack_bf16x2(m2, m) : pack_bf16x2(m, m2));
-              keep[nb] = (k == 0 || j == k) ? dw : keep[nb];
-            }
-#pragma unroll
-          for (int nb = 0; nb < C::NB; ++nb)
-            *reinterpret_cast<uint32_t*>(scr + (4 * g + j) * 64 + nb * 16 + q * 4) = keep[nb];
+            for (int k = 0; k < 4; ++k) v[k] = acc[u][nb][k] + bs[nb][k];
+            *reinterpret_cast<uint32_t*>(scr + n16 * 64 + nb * 16 + g * 4) =
+                bf16_key(pack_bf16x2(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+          }
           __builtin_amdgcn_wave_barrier();
           // lane l: stored channels 8 (l % 4) .. + 7 of pixel l / 4
           const i4v o = *reinterpret_cast<const i4v*>(scr + lane * 16);
@@ -2338,6 +2458,11 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   VariantInfo{P, CIN, 2, KS, 1, 0, TY, TX, 0, CfgHead<CIN, KS, TY, TX>::THREADS, CIN, PT<F32>::CHB, 1, 0, 0, 0, 3, \
               CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<P, CIN, KS, TY, TX>),       \
               "head_phase<" #P "," #CIN "," #KS "," #TY "," #TX ">"}
+#define EMCNN_HEAD_TAPS(P, CIN, KS, TY, NBC, NW)                                                          \
+  VariantInfo{P, CIN, 2, KS, 1, 0, TY, CfgTaps<P, CIN, KS, TY, NBC, NW>::TX, 0,                            \
+              CfgTaps<P, CIN, KS, TY, NBC, NW>::THREADS, CIN, PT<P>::CHB, 1, 0, 0, 0, 5,                     \
+              CfgTaps<P, CIN, KS, TY, NBC, NW>::LDS, reinterpret_cast<const void*>(&head_taps<P, CIN, KS, TY, NBC, NW>), \
+              "head_taps<" #P "," #CIN "," #KS "," #TY "," #NBC "," #NW ">"}
 #define EMCNN_HEAD1(P, CIN, NCLS, TX)                                                                    \
   VariantInfo{P, CIN, NCLS, 1, 0, 0, 1, TX, 0, TX, CIN, PT<F32>::CHB, 1, 0, 0, 0, 4, 0,                     \
               reinterpret_cast<const void*>(&head_1x1<CIN, NCLS, TX>), "head_1x1<" #CIN "," #NCLS "," #TX ">"}
@@ -2416,6 +2541,8 @@ static const VariantInfo kConv[] = {
     // the softmax layer: on the VALU (default; 2 classes, no padding), or on
     // MFMA with 14 zero columns
     EMCNN_HEAD_PHASE(F32, 32, 4, 8, 64), EMCNN_HEAD_PHASE(F32, 32, 4, 4, 64),
+    EMCNN_HEAD_TAPS(F32, 32, 4, 13, 4, 8), EMCNN_HEAD_TAPS(F32, 32, 4, 8, 4, 4), EMCNN_HEAD_TAPS(F32, 32, 4, 5, 4, 4),
+    EMCNN_HEAD_TAPS(F32, 32, 4, 8, 8, 8),
     EMCNN_PHASE(F32, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_PHASE(F32, 32, 16, 4, 16, 64, 8, 2, 16),
     // FastMemb BF16: bf16 activations (NHWC, 64 B per pixel) and weights, FP32
     // accumulation; the softmax layer reads bf16 and computes in FP32
@@ -2426,6 +2553,8 @@ static const VariantInfo kConv[] = {
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 16),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(BF16, 32, 64, 4, 16, 64, 8, 1, 32),
     EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
+    EMCNN_HEAD_TAPS(BF16, 32, 4, 13, 4, 8), EMCNN_HEAD_TAPS(BF16, 32, 4, 8, 4, 4), EMCNN_HEAD_TAPS(BF16, 32, 4, 5, 4, 4),
+    EMCNN_HEAD_TAPS(BF16, 32, 4, 8, 8, 8),
     // MaskExtend (FP32): twelve input maps, max-out convs to 32, 40, 48, 56, 64
     // features (channels staged per LDS pass chosen to fit 160 KB with the
     // 8 (mod 16) dword pixel stride), the 1x1 three-class softmax on the VALU

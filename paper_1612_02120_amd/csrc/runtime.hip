@@ -288,6 +288,49 @@ static int pack_head_valu(ExecLayer& L, int variant, const double* w, const doub
   return CNN_OK;
 }
 
+// Weights of the two-class layer as a tap GEMM (head_taps): the weight
+// difference W[1] - W[0] (FP64, rounded once to the operand type) as MFMA B
+// fragments [step t][lane][16 bytes], lane (n16, g) holding tap n16 = KS i + j
+// for the CHB channels of 16-byte chunk 4t + g. Bias as for head_phase.
+static int pack_head_taps(ExecLayer& L, int variant, const double* w, const double* b) {
+  const VariantInfo* v = conv_variant(variant);
+  const int cin = v->cin, ks = v->ks, chb = v->chb, esz = act_bytes(v->prec);
+  const int nk = cin * esz / 64;
+  std::vector<unsigned char> pk((size_t)nk * 64 * 16, 0);
+  for (int t = 0; t < nk; ++t)
+    for (int lane = 0; lane < 64; ++lane)
+      for (int e = 0; e < chb; ++e) {
+        const int tap = lane & 15, ch = chb * (4 * t + (lane >> 4)) + e;
+        const int i = tap / ks, j = tap % ks;
+        const double dw = w[(((size_t)1 * cin + ch) * ks + i) * ks + j] - w[(((size_t)0 * cin + ch) * ks + i) * ks + j];
+        unsigned char* dst = pk.data() + ((size_t)t * 64 + lane) * 16 + (size_t)e * esz;
+        if (v->prec == F32) {
+          const float f = (float)dw;
+          std::memcpy(dst, &f, 4);
+        } else {
+          const float f = bf16_rne((float)dw);
+          uint32_t bits;
+          std::memcpy(&bits, &f, 4);
+          const uint16_t h = (uint16_t)(bits >> 16);
+          std::memcpy(dst, &h, 2);
+        }
+      }
+  hipError_t err;
+  void* wdev = nullptr;
+  if ((err = hipMalloc(&wdev, pk.size())) != hipSuccess) return hip_fail(err, "hipMalloc(head weights)");
+  L.wpacks.push_back(wdev);
+  if ((err = hipMemcpy(wdev, pk.data(), pk.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "hipMemcpy(head weights)");
+  if (L.bias) return CNN_OK;
+  std::vector<float> bf(16, 0.f);
+  bf[0] = (float)b[0];
+  bf[1] = (float)b[1];
+  if ((err = hipMalloc(&L.bias, 16 * sizeof(float))) != hipSuccess) return hip_fail(err, "hipMalloc(head bias)");
+  if ((err = hipMemcpy(L.bias, bf.data(), 16 * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(err, "hipMemcpy(head bias)");
+  return CNN_OK;
+}
+
 // Weights of a 1x1 multi-class output conv (head_1x1): W[class][cin] and the
 // biases, FP32 as given.
 static int pack_head1(ExecLayer& L, int variant, const double* w, const double* b) {
@@ -434,16 +477,17 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       }
       E.dil = sp;
       if (l.act == CNN_ACT_SOFTMAX) {
-        // the two-class layer: FP32 VALU kernels, or MFMA kernels that run it
-        // as 16 columns with zero weights and bias for classes >= 2. FP32
-        // nets default to the VALU form (MFMA would pay 8x padding at the FP32
-        // rate); BF16 nets to the bf16 MFMA form, like their other convs.
+        // the two-class layer: first the tap-GEMM kernels (one MFMA column
+        // per tap of the weight difference), then the VALU kernels and the
+        // MFMA kernels that run it as 16 columns with zero weights and bias
+        // for classes >= 2 (BF16 nets: those two the other way round).
         E.cout = l.cout;
         E.cstore = 1;
         std::vector<int> va = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 3);
         std::vector<int> mf = find_conv_variants(prec, l.cin, 16, l.k, 1, 0, 2);
         if (prec == CNN_PREC_BF16) va.swap(mf);
-        E.candidates = va;
+        E.candidates = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 5);
+        E.candidates.insert(E.candidates.end(), va.begin(), va.end());
         E.candidates.insert(E.candidates.end(), mf.begin(), mf.end());
         if (!E.candidates.empty()) E.epi = conv_variant(E.candidates[0])->epi;
         if (E.candidates.empty()) return unsupported("no kernel for the softmax layer");
@@ -452,8 +496,10 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
         std::copy(b, b + l.cout, bpad.begin());
         for (int v : E.candidates) {
           if (rc != CNN_OK) break;
-          rc = conv_variant(v)->epi == 3 ? pack_head_valu(E, v, w, b)
-                                        : pack_conv(E, v, wpad.data(), bpad.data(), nullptr, 0.0, 1.0, 0.0);
+          const int ep = conv_variant(v)->epi;
+          rc = ep == 3   ? pack_head_valu(E, v, w, b)
+               : ep == 5 ? pack_head_taps(E, v, w, b)
+                         : pack_conv(E, v, wpad.data(), bpad.data(), nullptr, 0.0, 1.0, 0.0);
         }
       } else {
         E.cout = l.cout;

@@ -66,8 +66,10 @@ def test_every_fastmemb_candidate_matches_reference(emcnn):
     ref = oracle.forward(vol, NET_FM, p)
     n_layers = 4
     defaults = [emcnn.cnn_variant_names(h, l)[0] for l in range(n_layers)]
-    assert "conv_phase" in defaults[1] and "head_phase" in defaults[3]
-    assert any("conv_phase" in n for n in emcnn.cnn_variant_names(h, 3))  # the MFMA form of the softmax layer
+    assert "conv_phase" in defaults[1] and "head_taps" in defaults[3]
+    heads = emcnn.cnn_variant_names(h, 3)
+    # the VALU form and the padded MFMA form of the softmax layer
+    assert any("head_phase" in n for n in heads) and any("conv_phase" in n for n in heads)
     for layer in range(n_layers):
         for name in emcnn.cnn_variant_names(h, layer):
             emcnn.cnn_set_variant(h, layer, name)
