@@ -93,7 +93,8 @@ struct VariantInfo {
                         // 2 bias + two-class softmax of channels 0, 1 (stores the class-1 probability),
                         // 3 the two-class softmax layer on the VALU (head_phase),
                         // 4 a 1x1 conv to cout classes with a softmax, storing class 0 (head_1x1),
-                        // 5 the two-class softmax layer as a GEMM over its 16 taps (head_taps)
+                        // 5 the two-class softmax layer as a GEMM over its 16 taps (head_taps),
+                        // 6 the same over groups of four phases (head_taps4)
   int lds_bytes;        // LDS of the staged operand tiles and weights (descriptive; launches and
                         // occupancy take the kernel's own static LDS, epilogue scratch included)
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)

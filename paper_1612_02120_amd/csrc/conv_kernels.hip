@@ -20,10 +20,12 @@
 //                 MFMA) over channel-blocked activations; in its spaced mode the
 //                 BF16 body convs of nets with stride-2 pools.
 //   conv_phase  - the convs of nets with stride-2 pools (FastMemb): taps spaced
-//   head_phase    d apart, tiled per phase sub-lattice (the paper's fragments,
+//   head_*        d apart, tiled per phase sub-lattice (the paper's fragments,
 //                 which the maps between layers store as separate blocks);
-//                 max-out or two-class softmax epilogues; head_phase is the
-//                 two-class layer on the VALU.
+//                 max-out or two-class softmax epilogues. The two-class layer
+//                 also as a GEMM over its taps (head_taps, and over groups of
+//                 four phases head_taps4 / head_strip) and on the VALU
+//                 (head_phase).
 //
 // All are persistent: a grid of a multiple of 8 workgroups walks the work
 // items (z, tile_y, tile_x) of one or many jobs. Workgroups are dispatched to
@@ -1560,6 +1562,315 @@ __global__ __launch_bounds__(NW * 64) void head_taps(JobSet js, ConvParams prm) 
   }
 }
 
+// head_taps over phase groups. The 2x2 max filter before a conv at spacing d
+// has spacing h = d / 2, so the filters of the four phases (gy + a h, gx + b h),
+// a, b in {0, 1}, read the same four fragments F[a][b] (fragment of phase
+// (gy + a h, gx + b h)): operand pixel (R, C) of member (a, b) is the max of
+// F[a ^ a'][b ^ b'][R + (a & a')][C + (b & b')] over a', b'. One work item is
+// a group's tile: each lane loads the nine distinct (fragment, shift) chunks
+// of its pixel once (against sixteen for four separate phase tiles, and the
+// shifted ones mostly hit lines the same wave just brought into the L1), forms
+// all four members' operand pixels and runs four MFMAs. The members' D stay in
+// registers; their tap sums then pass through the LDS planes one member at a
+// time. Needs a max filter at h = d / 2 >= 1 (the host offers it only then).
+template <int P, int CIN, int KS, int TY, int NBC, int NW>
+struct CfgTaps4 : CfgTaps<P, CIN, KS, TY, NBC, NW> {
+  using B = CfgTaps<P, CIN, KS, TY, NBC, NW>;
+  static_assert(B::MB % NW == 0, "m-blocks split evenly over the waves");
+  static constexpr int MBW = B::MB / NW;  // m-blocks of a wave
+  static constexpr bool PF = P == BF16;   // prefetch the next m-block's chunks
+};
+
+template <int P, int CIN, int KS, int TY, int NBC, int NW>
+__global__ __launch_bounds__(NW * 64) void head_taps4(JobSet js, ConvParams prm) {
+  using C = CfgTaps4<P, CIN, KS, TY, NBC, NW>;
+  static_assert(P == F32 || P == BF16, "FP32 or keyed BF16 input activations (NHWC)");
+  __shared__ __attribute__((aligned(16))) float E[16 * C::PS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  constexpr int ELB = CIN * PT<P>::BYTES;
+  Frag<P> wf[C::NK];
+#pragma unroll
+  for (int t = 0; t < C::NK; ++t) {
+    const gbyte* p = gin(prm.wpack) + ((size_t)t * 64 + lane) * 16;
+    load_frag<P>(wf[t], p, p);
+  }
+  const float bd = ldf(prm.bias, 1) - ldf(prm.bias, 0);
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
+    // item order: tile column, then phase group, then tile row, then slice
+    const int d = J.geom & 0xff, h = d >> 1, lg = __builtin_ctz(d);
+    const int tpy = J.tiles_y / (h * h);
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int grp = (int)(t2 % (h * h));
+    const int64_t t3 = t2 / (h * h);
+    const int by = (int)(t3 % tpy);
+    const int zz = (int)(t3 / tpy);
+    const int gy = grp / h, gx = grp % h;
+    const int y0 = by * TY, x0 = bx * C::TX;
+    const int64_t plane = (J.in_zs >> (2 * lg)) * ELB;  // bytes per fragment
+    const int64_t rowb = J.in_rs * ELB;
+    const gbyte* f00 = gin(J.in) + (int64_t)zz * J.in_zs * ELB + (int64_t)(gy * d + gx) * plane;
+    const int64_t o01 = h * plane, o10 = (int64_t)h * d * plane;  // fragments (gy, gx + h), (gy + h, gx)
+    // last valid row / column of the fragments with fy = gy (A) or gy + h (B), fx = gx or gx + h
+    const int rvA = (J.hin - 1 - gy) >> lg, rvB = (J.hin - 1 - gy - h) >> lg;
+    const int cvA = (J.win - 1 - gx) >> lg, cvB = (J.win - 1 - gx - h) >> lg;
+
+    // the nine chunks of m-block k (of this wave) per MFMA step
+    auto load_mb = [&](int k, i4v (&q)[C::NK][9]) __attribute__((always_inline)) {
+      const int mb = wave + k * NW;
+      const int R = y0 + mb / NBC, Cc = x0 + (mb % NBC) * 16 + n16;
+      const int rA = min(R, rvA), rB = min(R, rvB), rA1 = min(R + 1, rvA);
+      const int cA = min(Cc, cvA), cB = min(Cc, cvB), cA1 = min(Cc + 1, cvA);
+#pragma unroll
+      for (int t = 0; t < C::NK; ++t) {
+        const gbyte* b = f00 + g * 16 + t * 64;
+        q[t][0] = ld<i4v>(b + rA * rowb + cA * ELB);              // F00[R][C]
+        q[t][1] = ld<i4v>(b + o01 + rA * rowb + cB * ELB);        // F01[R][C]
+        q[t][2] = ld<i4v>(b + o10 + rB * rowb + cA * ELB);        // F10[R][C]
+        q[t][3] = ld<i4v>(b + o10 + o01 + rB * rowb + cB * ELB);  // F11[R][C]
+        q[t][4] = ld<i4v>(b + rA * rowb + cA1 * ELB);             // F00[R][C+1]
+        q[t][5] = ld<i4v>(b + o10 + rB * rowb + cA1 * ELB);       // F10[R][C+1]
+        q[t][6] = ld<i4v>(b + rA1 * rowb + cA * ELB);             // F00[R+1][C]
+        q[t][7] = ld<i4v>(b + o01 + rA1 * rowb + cB * ELB);       // F01[R+1][C]
+        q[t][8] = ld<i4v>(b + rA1 * rowb + cA1 * ELB);            // F00[R+1][C+1]
+      }
+    };
+    f4 dacc[C::MBW][4];
+    auto mma_mb = [&](int k, const i4v (&q)[C::NK][9]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) dacc[k][m] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < C::NK; ++t) {
+        const i4v* v = q[t];
+        i4v op[4];
+        op[0] = chunk_max_signed<P>(chunk_max_signed<P>(v[0], v[1]), chunk_max_signed<P>(v[2], v[3]));  // (0, 0)
+        op[1] = chunk_max_signed<P>(chunk_max_signed<P>(v[1], v[4]), chunk_max_signed<P>(v[3], v[5]));  // (0, 1)
+        op[2] = chunk_max_signed<P>(chunk_max_signed<P>(v[2], v[3]), chunk_max_signed<P>(v[6], v[7]));  // (1, 0)
+        op[3] = chunk_max_signed<P>(chunk_max_signed<P>(v[3], v[5]), chunk_max_signed<P>(v[7], v[8]));  // (1, 1)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if constexpr (P == BF16) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) op[m][w] = (int)bf16_unkey((uint32_t)op[m][w]);
+          }
+          Frag<P> a;
+          if constexpr (P == BF16) a.v = __builtin_bit_cast(bf16x8, op[m]);
+          else a.v = __builtin_bit_cast(f4, op[m]);
+          mma<P>(dacc[k][m], a, wf[t]);
+        }
+      }
+    };
+    // BF16: the loads of m-block k + 1 are issued before the work of m-block
+    // k; FP32 (twice the chunks) one m-block at a time
+    if constexpr (C::PF) {
+      i4v qa[C::NK][9], qb[C::NK][9];
+      load_mb(0, qa);
+#pragma unroll
+      for (int k = 0; k < C::MBW; k += 2) {
+        if (k + 1 < C::MBW) load_mb(k + 1, qb);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_mb(k, qa);
+        if (k + 1 < C::MBW) {
+          if (k + 2 < C::MBW) load_mb(k + 2, qa);
+          __builtin_amdgcn_sched_barrier(0);
+          mma_mb(k + 1, qb);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < C::MBW; ++k) {
+        i4v q[C::NK][9];
+        load_mb(k, q);
+        mma_mb(k, q);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    const int lgo = (J.geom >> 16) & 0xf;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      __syncthreads();  // the previous member's (or item's) tap sums are done
+#pragma unroll
+      for (int k = 0; k < C::MBW; ++k) {
+        const int mb = wave + k * NW;
+        // lane (n16, g) holds taps n16 of pixels 4g .. 4g + 3 of the m-block
+        *reinterpret_cast<f4*>(&E[n16 * C::PS + (mb / NBC) * C::LCP + (mb % NBC) * 16 + 4 * g]) = dacc[k][m];
+      }
+      __syncthreads();
+      const int py = gy + (m >> 1) * h, px = gx + (m & 1) * h;
+      for (int o = tid; o < TY * C::TX; o += C::THREADS) {
+        const int r = o / C::TX, c = o % C::TX;
+        float z = 0.f;
+#pragma unroll
+        for (int i = 0; i < KS; ++i)
+#pragma unroll
+          for (int j = 0; j < KS; ++j) z += E[(i * KS + j) * C::PS + (r + i) * C::LCP + c + j];
+        const int y = py + d * (y0 + r), x = px + d * (x0 + c);
+        if (y < J.hout && x < J.wout)
+          st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * 4,
+                    sigmoid_f(z + bd));
+      }
+    }
+  }
+}
+
+// head_taps4 without LDS: one wave walks a vertical strip of a phase group,
+// TY output rows x 13 columns of each of the four members. At operand row R
+// it computes, for pixels C .. C + 15 (lane n16: pixel C + n16), each member's
+// D^T = Wd^T X^T in the transposed MFMA form: lane (g, n16) holds taps
+// (i = g, j = 0 .. 3) of pixel n16. Three DPP row shifts sum j into lane
+// n16's output column (pixels n16 + j; columns 13 .. 15 lack their right
+// neighbours and are not stored), leaving row i = g's share of output row
+// R - g. Output row r accumulates in lane group r mod 4, so one ds_bpermute
+// routes each share to its row; after row R, output row R - 3 is complete
+// and its lane group stores it. The chunks of the first two fragments at row
+// R + 1 (loaded for the members one phase row down) are carried to the next
+// row, so a row costs six new chunk loads per MFMA step.
+template <int P, int CIN, int KS, int TY>
+__global__ __launch_bounds__(64) void head_strip(JobSet js, ConvParams prm) {
+  static_assert(P == F32 || P == BF16, "FP32 or keyed BF16 input activations (NHWC)");
+  static_assert(KS == 4, "sixteen taps: one MFMA tile, four per lane");
+  constexpr int NK = CIN * PT<P>::BYTES / 64;  // MFMA steps (16-byte chunks per lane group)
+  static_assert(NK * 64 == CIN * PT<P>::BYTES, "whole 16-byte chunks per lane group");
+  constexpr int TXS = 16 - KS + 1;             // output columns of a strip
+  constexpr int NS = TY + KS - 1;              // operand rows of a strip
+  constexpr int ELB = CIN * PT<P>::BYTES;
+  const int lane = threadIdx.x, g = lane >> 4, n16 = lane & 15;
+  Frag<P> wf[NK];
+#pragma unroll
+  for (int t = 0; t < NK; ++t) {
+    const gbyte* p = gin(prm.wpack) + ((size_t)t * 64 + lane) * 16;
+    load_frag<P>(wf[t], p, p);
+  }
+  const float bd = ldf(prm.bias, 1) - ldf(prm.bias, 0);
+
+  const ItemRange rg = item_range(js.total_items);
+  int cur = 0;
+  if (js.table && rg.begin < rg.end) cur = find_job(js.table, js.njobs, rg.begin);
+  for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
+    const LayerJob J = job_at(js, cur, item);
+    if (gated_off(J)) continue;
+    // item order: strip column, then phase group, then strip row, then slice
+    const int d = J.geom & 0xff, h = d >> 1, lg = __builtin_ctz(d);
+    const int tpy = J.tiles_y / (h * h);
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int grp = (int)(t2 % (h * h));
+    const int64_t t3 = t2 / (h * h);
+    const int by = (int)(t3 % tpy);
+    const int zz = (int)(t3 / tpy);
+    const int gy = grp / h, gx = grp % h;
+    const int y0 = by * TY, x0 = bx * TXS;
+    const int64_t plane = (J.in_zs >> (2 * lg)) * ELB;  // bytes per fragment
+    const int64_t rowb = J.in_rs * ELB;
+    const int64_t o01 = h * plane;  // fragment (gy, gx + h) from (gy, gx); (gy + h, .) at o10
+    const gbyte* bA = gin(J.in) + (int64_t)zz * J.in_zs * ELB + (int64_t)(gy * d + gx) * plane + g * 16;
+    const gbyte* bB = bA + (int64_t)h * d * plane;
+    // last valid row / column of the fragments with fy = gy (A) or gy + h (B), fx = gx or gx + h
+    const int rvA = (J.hin - 1 - gy) >> lg, rvB = (J.hin - 1 - gy - h) >> lg;
+    const int cvA = (J.win - 1 - gx) >> lg, cvB = (J.win - 1 - gx - h) >> lg;
+    const int Cc = x0 + n16;
+    const int64_t xA = (int64_t)min(Cc, cvA) * ELB, xB = (int64_t)min(Cc, cvB) * ELB;
+    const int64_t xA1 = (int64_t)min(Cc + 1, cvA) * ELB;
+    // new chunks of operand row R: F10[R][C], F11[R][C], F10[R][C+1], F00[R+1][C], F01[R+1][C], F00[R+1][C+1]
+    auto load_row = [&](int R, i4v (&q)[NK][6]) __attribute__((always_inline)) {
+      const int64_t ra1 = (int64_t)min(R + 1, rvA) * rowb, rb = (int64_t)min(R, rvB) * rowb;
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        q[t][0] = ld<i4v>(bB + rb + xA + t * 64);
+        q[t][1] = ld<i4v>(bB + o01 + rb + xB + t * 64);
+        q[t][2] = ld<i4v>(bB + rb + xA1 + t * 64);
+        q[t][3] = ld<i4v>(bA + ra1 + xA + t * 64);
+        q[t][4] = ld<i4v>(bA + o01 + ra1 + xB + t * 64);
+        q[t][5] = ld<i4v>(bA + ra1 + xA1 + t * 64);
+      }
+    };
+    // carried chunks of row R of fragments F00, F01: F00[R][C], F01[R][C], F00[R][C+1]
+    i4v cr[NK][3];
+    {
+      const int64_t ra = (int64_t)min(y0, rvA) * rowb;
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        cr[t][0] = ld<i4v>(bA + ra + xA + t * 64);
+        cr[t][1] = ld<i4v>(bA + o01 + ra + xB + t * 64);
+        cr[t][2] = ld<i4v>(bA + ra + xA1 + t * 64);
+      }
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};  // output row (strip row) = lane group mod 4, per member
+    const int lgo = (J.geom >> 16) & 0xf;
+    auto row = [&](int s, const i4v (&q)[NK][6]) __attribute__((always_inline)) {
+      f4 dm[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) dm[m] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        // v[0..8] as in head_taps4: F00, F01, F10, F11 at (R, C); F00, F10 at C + 1;
+        // F00, F01 at R + 1; F00 at (R + 1, C + 1)
+        const i4v v0 = cr[t][0], v1 = cr[t][1], v2 = q[t][0], v3 = q[t][1], v4 = cr[t][2], v5 = q[t][2];
+        const i4v v6 = q[t][3], v7 = q[t][4], v8 = q[t][5];
+        i4v op[4];
+        op[0] = chunk_max_signed<P>(chunk_max_signed<P>(v0, v1), chunk_max_signed<P>(v2, v3));  // (0, 0)
+        op[1] = chunk_max_signed<P>(chunk_max_signed<P>(v1, v4), chunk_max_signed<P>(v3, v5));  // (0, 1)
+        op[2] = chunk_max_signed<P>(chunk_max_signed<P>(v2, v3), chunk_max_signed<P>(v6, v7));  // (1, 0)
+        op[3] = chunk_max_signed<P>(chunk_max_signed<P>(v3, v5), chunk_max_signed<P>(v7, v8));  // (1, 1)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if constexpr (P == BF16) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) op[m][w] = (int)bf16_unkey((uint32_t)op[m][w]);
+          }
+          Frag<P> a;
+          if constexpr (P == BF16) a.v = __builtin_bit_cast(bf16x8, op[m]);
+          else a.v = __builtin_bit_cast(f4, op[m]);
+          mma<P>(dm[m], wf[t], a);  // weights as A: lane (g, n16) gets taps 4g .. 4g + 3 of pixel n16
+        }
+        cr[t][0] = v6;
+        cr[t][1] = v7;
+        cr[t][2] = v8;
+      }
+      const int src = ((((s - g) & 3) << 4) + n16) << 2;  // lane holding row s - (row of this group)'s share
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float sh = dm[m][0] + dpp_f<0x101>(dm[m][1]) + dpp_f<0x102>(dm[m][2]) + dpp_f<0x103>(dm[m][3]);
+        acc[m] += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, sh)));
+      }
+      if (g == ((s + 1) & 3)) {  // this lane group holds output row s - 3, now complete
+        if (s >= KS - 1 && n16 < TXS) {
+          const int r = y0 + s - (KS - 1), x_ = x0 + n16;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int y = gy + (m >> 1) * h + d * r, x = gx + (m & 1) * h + d * x_;
+            if (y < J.hout && x < J.wout)
+              st<float>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * 4,
+                        sigmoid_f(acc[m] + bd));
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m] = 0.f;
+      }
+    };
+    i4v qa[NK][6], qb[NK][6];
+    load_row(y0, qa);
+#pragma unroll 1
+    for (int s = 0; s < NS; s += 2) {
+      if (s + 1 < NS) load_row(y0 + s + 1, qb);
+      row(s, qa);
+      if (s + 1 < NS) {
+        if (s + 2 < NS) load_row(y0 + s + 2, qa);
+        row(s + 1, qb);
+      }
+    }
+  }
+}
+
 // A 1x1 conv to NCLS classes with a softmax, keeping class 0's probability:
 // the output layer of a multi-class net (MaskExtend), on the VALU, one output
 // pixel per thread. Input: row-major NHWC FP32 maps of CIN channels, read as
@@ -2463,6 +2774,14 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               CfgTaps<P, CIN, KS, TY, NBC, NW>::THREADS, CIN, PT<P>::CHB, 1, 0, 0, 0, 5,                     \
               CfgTaps<P, CIN, KS, TY, NBC, NW>::LDS, reinterpret_cast<const void*>(&head_taps<P, CIN, KS, TY, NBC, NW>), \
               "head_taps<" #P "," #CIN "," #KS "," #TY "," #NBC "," #NW ">"}
+#define EMCNN_HEAD_TAPS4(P, CIN, KS, TY, NBC, NW)                                                         \
+  VariantInfo{P, CIN, 2, KS, 1, 0, TY, CfgTaps<P, CIN, KS, TY, NBC, NW>::TX, 0,                            \
+              CfgTaps<P, CIN, KS, TY, NBC, NW>::THREADS, CIN, PT<P>::CHB, 1, 0, 0, 0, 6,                     \
+              CfgTaps<P, CIN, KS, TY, NBC, NW>::LDS, reinterpret_cast<const void*>(&head_taps4<P, CIN, KS, TY, NBC, NW>), \
+              "head_taps4<" #P "," #CIN "," #KS "," #TY "," #NBC "," #NW ">"}
+#define EMCNN_HEAD_STRIP(P, CIN, KS, TY)                                                                   \
+  VariantInfo{P, CIN, 2, KS, 1, 0, TY, 16 - KS + 1, 0, 64, CIN, PT<P>::CHB, 1, 0, 0, 0, 6, 0,               \
+              reinterpret_cast<const void*>(&head_strip<P, CIN, KS, TY>), "head_strip<" #P "," #CIN "," #KS "," #TY ">"}
 #define EMCNN_HEAD1(P, CIN, NCLS, TX)                                                                    \
   VariantInfo{P, CIN, NCLS, 1, 0, 0, 1, TX, 0, TX, CIN, PT<F32>::CHB, 1, 0, 0, 0, 4, 0,                     \
               reinterpret_cast<const void*>(&head_1x1<CIN, NCLS, TX>), "head_1x1<" #CIN "," #NCLS "," #TX ">"}
@@ -2538,23 +2857,32 @@ static const VariantInfo kConv[] = {
     // (all 32 channels per stage use a whole 128-byte pixel line at once)
     EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 8, 1, 32),
     EMCNN_PHASE(F32, 32, 64, 4, 16, 64, 8, 1, 16), EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 4, 1, 16),
-    // the softmax layer: on the VALU (default; 2 classes, no padding), or on
-    // MFMA with 14 zero columns
+    // the softmax layer (the host orders its candidates: phase-group kernels
+    // first, head_strip's 61-row strips the default): as a GEMM over the 16
+    // taps of the weight difference per phase group (head_strip, head_taps4)
+    // or per phase (head_taps), on the VALU (head_phase), or as a conv with
+    // 14 zero MFMA columns (conv_phase)
     EMCNN_HEAD_PHASE(F32, 32, 4, 8, 64), EMCNN_HEAD_PHASE(F32, 32, 4, 4, 64),
     EMCNN_HEAD_TAPS(F32, 32, 4, 13, 4, 8), EMCNN_HEAD_TAPS(F32, 32, 4, 8, 4, 4), EMCNN_HEAD_TAPS(F32, 32, 4, 5, 4, 4),
     EMCNN_HEAD_TAPS(F32, 32, 4, 8, 8, 8),
+    EMCNN_HEAD_STRIP(F32, 32, 4, 61), EMCNN_HEAD_STRIP(F32, 32, 4, 41), EMCNN_HEAD_STRIP(F32, 32, 4, 31),
+    EMCNN_HEAD_TAPS4(F32, 32, 4, 13, 4, 8), EMCNN_HEAD_TAPS4(F32, 32, 4, 5, 4, 4), EMCNN_HEAD_TAPS4(F32, 32, 4, 6, 4, 4),
     EMCNN_PHASE(F32, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_PHASE(F32, 32, 16, 4, 16, 64, 8, 2, 16),
     // FastMemb BF16: bf16 activations (NHWC, 64 B per pixel) and weights, FP32
-    // accumulation; the softmax layer reads bf16 and computes in FP32
+    // accumulation; the softmax layer's kernels as for FP32, on bf16 MFMA
+    // (head_phase: FP32 on the VALU)
     // body convs: warp-specialised (16-channel stages, weights resident in
     // LDS; default), conv_phase with the same 16-channel stages (the same MFMA
     // sequence), and conv_phase staging all 32 channels at once
     EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 8, 4), EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 4, 4),
+    EMCNN_WS_PHASE(BF16, 32, 64, 4, 16, 32, 8, 4),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 16),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(BF16, 32, 64, 4, 16, 64, 8, 1, 32),
     EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
     EMCNN_HEAD_TAPS(BF16, 32, 4, 13, 4, 8), EMCNN_HEAD_TAPS(BF16, 32, 4, 8, 4, 4), EMCNN_HEAD_TAPS(BF16, 32, 4, 5, 4, 4),
     EMCNN_HEAD_TAPS(BF16, 32, 4, 8, 8, 8),
+    EMCNN_HEAD_STRIP(BF16, 32, 4, 61), EMCNN_HEAD_STRIP(BF16, 32, 4, 41), EMCNN_HEAD_STRIP(BF16, 32, 4, 31),
+    EMCNN_HEAD_TAPS4(BF16, 32, 4, 13, 4, 8), EMCNN_HEAD_TAPS4(BF16, 32, 4, 5, 4, 4), EMCNN_HEAD_TAPS4(BF16, 32, 4, 6, 4, 4),
     // MaskExtend (FP32): twelve input maps, max-out convs to 32, 40, 48, 56, 64
     // features (channels staged per LDS pass chosen to fit 160 KB with the
     // 8 (mod 16) dword pixel stride), the 1x1 three-class softmax on the VALU

@@ -87,8 +87,10 @@ static LayerJob make_job(const ExecLayer& L, const void* in, void* out, int z, i
     // d^2 phase sub-lattices, each tiled on its own (the largest phase has
     // ceil(hout / d) x ceil(wout / d) positions)
     const int d = L.dil, hs = (hout + d - 1) / d, wsub = (wout + d - 1) / d;
+    // kernels over phase groups (four phases whose max filters share fragments) tile d^2 / 4 groups
+    const int phases = layer_phase_groups(L) ? d * d / 4 : d * d;
     j.tiles_x = (wsub + layer_tx(L) - 1) / layer_tx(L);
-    j.tiles_y = d * d * ((hs + layer_ty(L) - 1) / layer_ty(L));
+    j.tiles_y = phases * ((hs + layer_ty(L) - 1) / layer_ty(L));
     j.geom = d | (L.pd << 8) | (L.out_lg << 16);
   } else {
     j.geom = L.out_lg << 16;

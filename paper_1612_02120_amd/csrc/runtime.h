@@ -163,6 +163,7 @@ uint8_t e4m3_code(double x);
 int layer_threads(const ExecLayer& L);
 int layer_ty(const ExecLayer& L);
 int layer_tx(const ExecLayer& L);
+bool layer_phase_groups(const ExecLayer& L);  // work items are groups of four phases (head_taps4)
 const void* layer_fn(const ExecLayer& L);
 const char* layer_name(const ExecLayer& L);
 int persistent_grid(Net* net, const ExecLayer& L, int64_t total_items);

@@ -478,7 +478,8 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       E.dil = sp;
       if (l.act == CNN_ACT_SOFTMAX) {
         // the two-class layer: first the tap-GEMM kernels (one MFMA column
-        // per tap of the weight difference), then the VALU kernels and the
+        // per tap of the weight difference; over phase groups where the max
+        // filter before it has half its spacing), then the VALU kernels and the
         // MFMA kernels that run it as 16 columns with zero weights and bias
         // for classes >= 2 (BF16 nets: those two the other way round).
         E.cout = l.cout;
@@ -486,7 +487,11 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
         std::vector<int> va = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 3);
         std::vector<int> mf = find_conv_variants(prec, l.cin, 16, l.k, 1, 0, 2);
         if (prec == CNN_PREC_BF16) va.swap(mf);
-        E.candidates = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 5);
+        E.candidates.clear();
+        if (E.pd >= 1 && 2 * E.pd == E.dil)  // phase groups share the max filter's fragments
+          E.candidates = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 6);
+        const std::vector<int> tp = find_conv_variants(prec, l.cin, 2, l.k, 1, 0, 5);
+        E.candidates.insert(E.candidates.end(), tp.begin(), tp.end());
         E.candidates.insert(E.candidates.end(), va.begin(), va.end());
         E.candidates.insert(E.candidates.end(), mf.begin(), mf.end());
         if (!E.candidates.empty()) E.epi = conv_variant(E.candidates[0])->epi;
@@ -498,7 +503,7 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
           if (rc != CNN_OK) break;
           const int ep = conv_variant(v)->epi;
           rc = ep == 3   ? pack_head_valu(E, v, w, b)
-               : ep == 5 ? pack_head_taps(E, v, w, b)
+               : ep >= 5 ? pack_head_taps(E, v, w, b)
                          : pack_conv(E, v, wpad.data(), bpad.data(), nullptr, 0.0, 1.0, 0.0);
         }
       } else {
@@ -539,6 +544,7 @@ int layer_threads(const ExecLayer& L) {
 }
 int layer_ty(const ExecLayer& L) { return L.first ? first_variant(L.variant)->ty : conv_variant(L.variant)->ty; }
 int layer_tx(const ExecLayer& L) { return L.first ? first_variant(L.variant)->tx : conv_variant(L.variant)->tx; }
+bool layer_phase_groups(const ExecLayer& L) { return !L.first && conv_variant(L.variant)->epi == 6; }
 const void* layer_fn(const ExecLayer& L) {
   return L.first ? first_variant(L.variant)->fn : conv_variant(L.variant)->fn;
 }

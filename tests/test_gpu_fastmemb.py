@@ -66,7 +66,7 @@ def test_every_fastmemb_candidate_matches_reference(emcnn):
     ref = oracle.forward(vol, NET_FM, p)
     n_layers = 4
     defaults = [emcnn.cnn_variant_names(h, l)[0] for l in range(n_layers)]
-    assert "conv_phase" in defaults[1] and "head_taps" in defaults[3]
+    assert "conv_phase" in defaults[1] and defaults[3].startswith("head_strip<")
     heads = emcnn.cnn_variant_names(h, 3)
     # the VALU form and the padded MFMA form of the softmax layer
     assert any("head_phase" in n for n in heads) and any("conv_phase" in n for n in heads)
@@ -164,7 +164,7 @@ def test_fastmemb_bf16_warp_specialised_equals_plain_staging(emcnn, shape):
     plain16 = "conv_phase<BF16,32,64,4,8,64,4,1,16>"
     for layer in (1, 2):
         names = emcnn.cnn_variant_names(h, layer)
-        assert plain16 in names and sum(n.startswith("conv_ws_phase<") for n in names) == 2, names
+        assert plain16 in names and sum(n.startswith("conv_ws_phase<") for n in names) >= 2, names
         emcnn.cnn_set_variant(h, layer, plain16)
     base = _run(emcnn, h, vol)
     for layer in (1, 2):
