@@ -100,8 +100,10 @@ typedef struct cnn_net cnn_net;
  * Two families of nets are supported: the ReLU nets described below, and the
  * FastMemb family (Section 2.2), FP32 or BF16 (bf16 weights and stored
  * activations with FP32 accumulation in every conv, the first conv with
- * bf16(w / 255) weights; the softmax layer's default kernel is a bf16 MFMA, its
- * VALU candidate reads bf16 activations with FP32 weights):
+ * bf16(w / 255) weights; the two-class softmax layer takes the weight
+ * difference W[1] - W[0], rounded once to the form's type, by default on MFMA
+ * with FP32 accumulation, and its VALU candidate reads bf16 activations with
+ * FP32 weights):
  * conv(k=4, 1 -> 64, MAXOUT), then
  * one or more pairs { MAXPOOL_S2, conv(k=4, 32 -> 64, MAXOUT) }, then
  * MAXPOOL_S2 and conv(k=4, 32 -> 2, SOFTMAX); no other transfer function.
