@@ -100,6 +100,8 @@ struct VariantInfo {
   const void* fn;       // kernel symbol (host pointer for hipLaunchKernel)
   const char* name;
   int rowq = 0;         // 1: row-quad K order (k_slot); 0: flattened
+  int groups = 0;       // 1: a work item is a tile of four phases whose max filters share
+                        // fragments (spaced layers whose max filter has half their spacing)
 };
 
 // K order of the implicit-GEMM convs over one channel block. K slot c is read

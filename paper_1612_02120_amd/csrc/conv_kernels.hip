@@ -1934,7 +1934,9 @@ __global__ __launch_bounds__(TX) void head_1x1(JobSet js, ConvParams prm) {
 // and the producers issue the global loads of stage k+1 before that barrier,
 // so the load latency overlaps a whole stage of MFMA work.
 
-template <int P, int CIN, int COUT, int KS, int TY, int TX, int NCW, int NPW, int K1 = 0>
+// NMEM > 1 (grouped spaced form): the operand tiles of NMEM phases stacked
+// row-wise in one buffer, and the tile's m-blocks NMEM times TY x TX / 16.
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int NCW, int NPW, int K1 = 0, int NMEM = 1>
 struct CfgWS {
   using T = PT<P>;
   static constexpr int KSZ = KS;
@@ -1966,7 +1968,7 @@ struct CfgWS {
   static constexpr int KUNROLL = P == FP8 ? 1 : 2;
   static constexpr bool ROWK = PSB == NCHB * 16 && KS * NCHB >= 4 &&
                                KS * rowq_quads(KS, NCHB) * 4 <= NGS * SLOTS;
-  static constexpr int BUF = LR * LC * PSB;                // one operand buffer
+  static constexpr int BUF = NMEM * LR * LC * PSB;         // one operand buffer
   static constexpr int WB = NGS * NB * 64 * T::U * 16;     // packed weights of one stage
   static constexpr int LDS_MAX = 160 * 1024;
   // BF16 consumers read B fragments from LDS: resident for the workgroup's
@@ -1991,12 +1993,13 @@ struct CfgWS {
   static constexpr int U8PL = (U8W + 63) / 64;    // per lane
   static constexpr int U8OFF = WOFF + WLDS;
   static constexpr int LDS = U8OFF + NPW * U8W;
-  static constexpr int MBLK = TY * TX / 16;
+  static constexpr int MBLK = NMEM * TY * TX / 16;
   static_assert(TX % 16 == 0, "TX must be a multiple of 16");
   static_assert(MBLK % NCW == 0, "m-blocks must split evenly over consumer waves");
   static constexpr int MW = MBLK / NCW;
   static_assert(MW % (TX / 16) == 0, "each consumer wave owns whole tile rows");
   static constexpr int WROWS = MW / (TX / 16);  // tile rows per consumer wave
+  static_assert(NMEM == 1 || TY % WROWS == 0, "a consumer wave's rows lie in one member's tile");
   static constexpr int THREADS = (NCW + NPW) * 64;
   static_assert(THREADS <= 1024, "workgroup size limit");
   static_assert(LDS <= LDS_MAX, "LDS budget of a gfx950 workgroup");
@@ -2044,6 +2047,24 @@ struct TileWalk {
     y0 = (int)(t2 % J.tiles_y) * TY;
     x0 = bx * TX;
     zz = (int)(t2 / J.tiles_y);
+  }
+  // items over groups of four phases (head_taps4's order: tile column, then
+  // group, then tile row, then slice); the group's first phase (gy, gx), gy,
+  // gx < d / 2; (y0, x0) in sub-lattice coordinates
+  template <int TY, int TX>
+  __device__ void group_coords(int& zz, int& gy, int& gx, int& y0, int& x0) const {
+    const int h = (J.geom & 0xff) >> 1;
+    const int tpy = J.tiles_y / (h * h);
+    const int64_t local = item - J.item0;
+    const int bx = (int)(local % J.tiles_x);
+    const int64_t t2 = local / J.tiles_x;
+    const int grp = (int)(t2 % (h * h));
+    const int64_t t3 = t2 / (h * h);
+    y0 = (int)(t3 % tpy) * TY;
+    x0 = bx * TX;
+    zz = (int)(t3 / tpy);
+    gy = grp / h;
+    gx = grp % h;
   }
   // phase-tiled items of a spaced conv (the order of conv_phase: tile column,
   // then phase, then tile row, then slice); (y0, x0) in sub-lattice coordinates
@@ -2211,19 +2232,83 @@ struct PhStage {
   }
 };
 
+// One stage's operand tiles of the four phases of a group (PH = 2) held in
+// producer registers: for operand position (R, C) and chunk cg, the nine
+// distinct (fragment, shift) chunks that the four members' max filters read
+// (see head_taps4). The store forms the members' operand pixels (max on keys,
+// then bf16) and writes member m's tile at rows m LR .. m LR + LR - 1.
+template <int LR, int LC, int NCHB, int PSB, int NPT>
+struct GrpStage {
+  static constexpr int NST = LR * LC * NCHB;
+  static constexpr int NIT = (NST + NPT - 1) / NPT;
+  i4v q[NIT][9];
+
+  // f00: fragment (gy, gx) of the slice plus the stage's channel offset;
+  // o01 / o10: offsets of fragments (gy, gx + h) / (gy + h, gx); rv / cv: last
+  // valid row / column of the fragments at gy, gy + h / gx, gx + h
+  __device__ __forceinline__ void load(const gbyte* f00, int64_t o01, int64_t o10, int64_t rowb, int elb, int rvA,
+                                       int rvB, int cvA, int cvB, int y0, int x0, int ptid) {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < NST) {
+        const int cg = t % NCHB, pix = t / NCHB;
+        const int R = y0 + pix / LC, Cc = x0 + pix % LC;
+        const int64_t rA = (int64_t)min(R, rvA) * rowb, rB = (int64_t)min(R, rvB) * rowb;
+        const int64_t rA1 = (int64_t)min(R + 1, rvA) * rowb;
+        const int64_t cA = (int64_t)min(Cc, cvA) * elb, cB = (int64_t)min(Cc, cvB) * elb;
+        const int64_t cA1 = (int64_t)min(Cc + 1, cvA) * elb;
+        const gbyte* b = f00 + cg * 16;
+        q[k][0] = ld<i4v>(b + rA + cA);              // F00[R][C]
+        q[k][1] = ld<i4v>(b + o01 + rA + cB);        // F01[R][C]
+        q[k][2] = ld<i4v>(b + o10 + rB + cA);        // F10[R][C]
+        q[k][3] = ld<i4v>(b + o10 + o01 + rB + cB);  // F11[R][C]
+        q[k][4] = ld<i4v>(b + rA + cA1);             // F00[R][C+1]
+        q[k][5] = ld<i4v>(b + o10 + rB + cA1);       // F10[R][C+1]
+        q[k][6] = ld<i4v>(b + rA1 + cA);             // F00[R+1][C]
+        q[k][7] = ld<i4v>(b + o01 + rA1 + cB);       // F01[R+1][C]
+        q[k][8] = ld<i4v>(b + rA1 + cA1);            // F00[R+1][C+1]
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(unsigned char* lds, int ptid) const {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int t = ptid + k * NPT;
+      if (t < NST) {
+        const int cg = t % NCHB, pix = t / NCHB;
+        const i4v* v = q[k];
+        i4v op[4];
+        op[0] = chunk_max<BF16>(chunk_max<BF16>(v[0], v[1]), chunk_max<BF16>(v[2], v[3]));  // (0, 0)
+        op[1] = chunk_max<BF16>(chunk_max<BF16>(v[1], v[4]), chunk_max<BF16>(v[3], v[5]));  // (0, 1)
+        op[2] = chunk_max<BF16>(chunk_max<BF16>(v[2], v[3]), chunk_max<BF16>(v[6], v[7]));  // (1, 0)
+        op[3] = chunk_max<BF16>(chunk_max<BF16>(v[3], v[5]), chunk_max<BF16>(v[7], v[8]));  // (1, 1)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) op[m][w] = (int)bf16_unkey((uint32_t)op[m][w]);
+          *reinterpret_cast<i4v*>(lds + (m * LR * LC + pix) * PSB + cg * 16) = op[m];
+        }
+      }
+    }
+  }
+};
+
 // PH = 1: a spaced conv of a stride-2 pool net (the work of conv_phase with
 // max-out, BF16): NHWC keyed input, operand pixels are the spaced 2x2 max
 // filter, items are phase tiles, and the epilogue is bias + max-out over
 // channel pairs, stored as NHWC keys.
 template <int P, int CIN, int COUT, int KS, bool POOL, bool HEAD, int TY, int TX, int NCW, int NPW, int K1, int PH = 0>
-__global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THREADS)) void conv_ws(
+__global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH == 2 ? 4 : 1>::THREADS)) void conv_ws(
     JobSet js, ConvParams prm) {
-  using C = CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>;
+  using C = CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH == 2 ? 4 : 1>;
   static_assert(K1 == 0 || POOL, "the fused first layer feeds a max filter");
   using T = PT<P>;
   static_assert(P != F32, "conv_ws reads and writes the channel-blocked BF16 / FP8 layout");
   static_assert(!PH || (P == BF16 && POOL && !HEAD && K1 == 0 && C::WRES),
                 "spaced form: BF16 max-out conv with all weights resident in LDS");
+  static_assert(PH != 2 || TX == 16, "grouped form: one m-block column per member tile");
   __shared__ __attribute__((aligned(16))) unsigned char lds[C::LDS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform role
@@ -2393,7 +2478,46 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
     return;
   }
 
-  if constexpr (PH) if (wave >= NCW) {
+  if constexpr (PH == 2) if (wave >= NCW) {
+    // ---------------- producer waves, spaced max filter over a phase group
+    const int ptid = tid - NCW * 64;
+    constexpr int ELB = CIN * T::BYTES;  // bytes per stored input pixel (NHWC)
+    GrpStage<C::LR, C::LC, C::NCHB, C::PSB, NPW * 64> a;
+    int cb = 0;
+    auto issue = [&]() __attribute__((always_inline)) {
+      int zz, gy, gx, y0, x0;
+      w.group_coords<TY, TX>(zz, gy, gx, y0, x0);
+      const LayerJob& J = w.J;
+      const int d = J.geom & 0xff, h = d >> 1, lg = __builtin_ctz(d);
+      const int64_t plane = (J.in_zs >> (2 * lg)) * ELB;  // bytes per fragment
+      const gbyte* f00 = gin(J.in) + (int64_t)zz * J.in_zs * ELB + (int64_t)(gy * d + gx) * plane +
+                         cb * C::CB * T::BYTES;
+      a.load(f00, h * plane, (int64_t)h * d * plane, J.in_rs * ELB, ELB, (J.hin - 1 - gy) >> lg,
+             (J.hin - 1 - gy - h) >> lg, (J.win - 1 - gx) >> lg, (J.win - 1 - gx - h) >> lg, y0, x0, ptid);
+    };
+    auto advance = [&]() __attribute__((always_inline)) -> bool {
+      if (++cb < C::NCB) return true;
+      cb = 0;
+      return w.next(js);
+    };
+    issue();
+    a.store(lds, ptid);
+    bool more = advance();
+    if (more) issue();
+    __syncthreads();  // stage 0 ready
+    int sel = 1;
+    while (more) {
+      a.store(lds + sel * C::BUF, ptid);  // the consumers finished this buffer's previous stage
+      more = advance();
+      if (more) issue();
+      __syncthreads();  // this stage ready; the consumers finished the previous one
+      sel ^= 1;
+    }
+    __syncthreads();  // the consumers' last stage
+    return;
+  }
+
+  if constexpr (PH == 1) if (wave >= NCW) {
     // ---------------- producer waves, spaced max filter
     const int ptid = tid - NCW * 64;
     constexpr int ELB = CIN * T::BYTES;  // bytes per stored input pixel (NHWC)
@@ -2472,7 +2596,11 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   // m-block offsets inside a wave's rows are compile-time constants, so the
   // per-m-block LDS and global addresses are immediates on one lane base.
   const int g = lane >> 4, n16 = lane & 15;
-  const int wrow0 = wave * C::WROWS;
+  // the wave's first tile row; grouped form: member wmem's rows, stacked
+  // after the LR operand rows of each earlier member in LDS
+  const int wrow0 = PH == 2 ? (wave * C::WROWS) % TY : wave * C::WROWS;
+  const int wmem = PH == 2 ? (wave * C::WROWS) / TY : 0;
+  const int lrow0 = wmem * C::LR + wrow0;
   // TRANS: weights as the MFMA's A operand and pixels as B, so lane (g, n16)
   // accumulates channels 4g .. 4g + 3 of pixel n16 (4 consecutive channels:
   // stored ones, or two max-out pairs); otherwise (the fused head) channel n16
@@ -2502,7 +2630,7 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) acc[u][nb] = f4{0.f, 0.f, 0.f, 0.f};
     }
-    const unsigned char* abase = lds + sel * C::BUF + (wrow0 * C::LC + n16) * C::PSB + (C::ROWK ? 16 * g : 0);
+    const unsigned char* abase = lds + sel * C::BUF + (lrow0 * C::LC + n16) * C::PSB + (C::ROWK ? 16 * g : 0);
     // implicit GEMM over the stage's (tap, chunk) slots; B fragments from
     // LDS (BF16) or global memory (FP8)
     // FP8: not unrolled, so the accumulators stay in place (unrolled twice,
@@ -2592,7 +2720,14 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
         __shared__ __attribute__((aligned(16))) unsigned char scr_all[NCW * 1024];
         unsigned char* scr = scr_all + wave * 1024;
         int zz, py, px, y0, x0;
-        w.phase_coords<TY, TX>(zz, py, px, y0, x0);
+        if constexpr (PH == 2) {
+          w.group_coords<TY, TX>(zz, py, px, y0, x0);
+          const int h = (w.J.geom & 0xff) >> 1;
+          py += (wmem >> 1) * h;  // member (a, b) = (wmem / 2, wmem % 2): phase (gy + a h, gx + b h)
+          px += (wmem & 1) * h;
+        } else {
+          w.phase_coords<TY, TX>(zz, py, px, y0, x0);
+        }
         const LayerJob& J = w.J;
         const int d = max(J.geom & 0xff, 1), lgo = (J.geom >> 16) & 0xf;
         f4 bs[C::NB];
@@ -2751,6 +2886,19 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
               reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, true, false, TY, TX, NCW, NPW, 0, 1>), \
               "conv_ws_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #NCW "," #NPW ">",        \
               CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, 0>::ROWK}
+#define EMCNN_WS_GROUP(P, CIN, COUT, KS, TY, NCW, NPW)                                               \
+  VariantInfo{P, CIN, COUT, KS, 1, 0, TY, 16,                                                         \
+              CfgWS<P, CIN, COUT, KS, TY, 16, NCW, NPW, 0, 4>::MW,                                    \
+              CfgWS<P, CIN, COUT, KS, TY, 16, NCW, NPW, 0, 4>::THREADS,                               \
+              CfgWS<P, CIN, COUT, KS, TY, 16, NCW, NPW, 0, 4>::CB,                                    \
+              PT<P>::CHB,                                                                             \
+              PT<P>::U,                                                                               \
+              CfgWS<P, CIN, COUT, KS, TY, 16, NCW, NPW, 0, 4>::NGS,                                   \
+              0, 0, 1,                                                                                \
+              CfgWS<P, CIN, COUT, KS, TY, 16, NCW, NPW, 0, 4>::LDS + NCW * 1024,                      \
+              reinterpret_cast<const void*>(&conv_ws<P, CIN, COUT, KS, true, false, TY, 16, NCW, NPW, 0, 2>), \
+              "conv_ws_group<" #P "," #CIN "," #COUT "," #KS "," #TY "," #NCW "," #NPW ">",               \
+              CfgWS<P, CIN, COUT, KS, TY, 16, NCW, NPW, 0, 4>::ROWK, 1}
 #define EMCNN_WS(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW) \
   EMCNN_WSK(P, CIN, COUT, KS, POOL, HEAD, TY, TX, NCW, NPW, 0)
 
@@ -2778,10 +2926,11 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1>::THR
   VariantInfo{P, CIN, 2, KS, 1, 0, TY, CfgTaps<P, CIN, KS, TY, NBC, NW>::TX, 0,                            \
               CfgTaps<P, CIN, KS, TY, NBC, NW>::THREADS, CIN, PT<P>::CHB, 1, 0, 0, 0, 6,                     \
               CfgTaps<P, CIN, KS, TY, NBC, NW>::LDS, reinterpret_cast<const void*>(&head_taps4<P, CIN, KS, TY, NBC, NW>), \
-              "head_taps4<" #P "," #CIN "," #KS "," #TY "," #NBC "," #NW ">"}
+              "head_taps4<" #P "," #CIN "," #KS "," #TY "," #NBC "," #NW ">", 0, 1}
 #define EMCNN_HEAD_STRIP(P, CIN, KS, TY)                                                                   \
   VariantInfo{P, CIN, 2, KS, 1, 0, TY, 16 - KS + 1, 0, 64, CIN, PT<P>::CHB, 1, 0, 0, 0, 6, 0,               \
-              reinterpret_cast<const void*>(&head_strip<P, CIN, KS, TY>), "head_strip<" #P "," #CIN "," #KS "," #TY ">"}
+              reinterpret_cast<const void*>(&head_strip<P, CIN, KS, TY>), "head_strip<" #P "," #CIN "," #KS "," #TY ">", \
+              0, 1}
 #define EMCNN_HEAD1(P, CIN, NCLS, TX)                                                                    \
   VariantInfo{P, CIN, NCLS, 1, 0, 0, 1, TX, 0, TX, CIN, PT<F32>::CHB, 1, 0, 0, 0, 4, 0,                     \
               reinterpret_cast<const void*>(&head_1x1<CIN, NCLS, TX>), "head_1x1<" #CIN "," #NCLS "," #TX ">"}
@@ -2872,8 +3021,12 @@ static const VariantInfo kConv[] = {
     // accumulation; the softmax layer's kernels as for FP32, on bf16 MFMA
     // (head_phase: FP32 on the VALU)
     // body convs: warp-specialised (16-channel stages, weights resident in
-    // LDS; default), conv_phase with the same 16-channel stages (the same MFMA
-    // sequence), and conv_phase staging all 32 channels at once
+    // LDS) over groups of four phases (the default where the max filter has
+    // half the conv's spacing: 12 x 16 tiles of each member, 1.93 against
+    // 2.38 ms for one phase's 8 x 64 tile) or one phase, conv_phase with the
+    // same 16-channel stages (the same MFMA sequence), and conv_phase staging
+    // all 32 channels at once
+    EMCNN_WS_GROUP(BF16, 32, 64, 4, 12, 8, 4), EMCNN_WS_GROUP(BF16, 32, 64, 4, 8, 8, 4),
     EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 8, 4), EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 4, 4),
     EMCNN_WS_PHASE(BF16, 32, 64, 4, 16, 32, 8, 4),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 16),

@@ -440,6 +440,9 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
       E.pd = 0;
       E.dil = 1;
       E.candidates = find_conv_variants(prec, l.cin, l.cout, l.k, 1, 0, 1);
+      E.candidates.erase(std::remove_if(E.candidates.begin(), E.candidates.end(),
+                                        [](int v) { return conv_variant(v)->groups != 0; }),
+                         E.candidates.end());  // no max filter: no phase groups
       if (E.candidates.empty()) return unsupported("no kernel for a first conv " + std::to_string(l.cin) + " -> " +
                                                    std::to_string(l.cout));
       for (int v : E.candidates)
@@ -513,6 +516,10 @@ static int build_strided(Net* net, const double* weights, const cnn_layer* Lr, i
         // the spaced kernels take the max filter's spacing from the job: the
         // same kernels serve a conv without a max filter (spacing 0)
         E.candidates = find_conv_variants(prec, l.cin, E.cout, l.k, 1, 0, E.epi);
+        if (!(E.pd >= 1 && 2 * E.pd == E.dil))  // phase groups need a max filter at half the spacing
+          E.candidates.erase(std::remove_if(E.candidates.begin(), E.candidates.end(),
+                                            [](int v) { return conv_variant(v)->groups != 0; }),
+                             E.candidates.end());
         if (E.candidates.empty())
           return unsupported("no MFMA kernel for conv " + std::to_string(c) + " (" + std::to_string(l.cin) + " -> " +
                              std::to_string(l.cout) + ")");
@@ -544,7 +551,7 @@ int layer_threads(const ExecLayer& L) {
 }
 int layer_ty(const ExecLayer& L) { return L.first ? first_variant(L.variant)->ty : conv_variant(L.variant)->ty; }
 int layer_tx(const ExecLayer& L) { return L.first ? first_variant(L.variant)->tx : conv_variant(L.variant)->tx; }
-bool layer_phase_groups(const ExecLayer& L) { return !L.first && conv_variant(L.variant)->epi == 6; }
+bool layer_phase_groups(const ExecLayer& L) { return !L.first && conv_variant(L.variant)->groups != 0; }
 const void* layer_fn(const ExecLayer& L) {
   return L.first ? first_variant(L.variant)->fn : conv_variant(L.variant)->fn;
 }

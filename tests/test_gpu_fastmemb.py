@@ -156,8 +156,9 @@ def test_every_fastmemb_bf16_candidate_matches_reference(emcnn):
 @pytest.mark.parametrize("shape", [(2, 131, 157), (1, 53, 53), (1, 620, 590)])
 def test_fastmemb_bf16_warp_specialised_equals_plain_staging(emcnn, shape):
     # the warp-specialised spaced conv (producer waves stage the next 16-channel
-    # block while consumer waves run the MFMAs) and conv_phase staging the same
-    # 16-channel blocks issue the same MFMAs in the same order: bitwise equal
+    # block while consumer waves run the MFMAs), per phase or per group of four
+    # phases, and conv_phase staging the same 16-channel blocks issue the same
+    # MFMAs in the same order: bitwise equal
     vol = em_volume(90 + shape[1], *shape)
     p = _params()
     h = emcnn.cnn_create(p, NET_FM, "bf16")
@@ -165,11 +166,12 @@ def test_fastmemb_bf16_warp_specialised_equals_plain_staging(emcnn, shape):
     for layer in (1, 2):
         names = emcnn.cnn_variant_names(h, layer)
         assert plain16 in names and sum(n.startswith("conv_ws_phase<") for n in names) >= 2, names
+        assert names[0].startswith("conv_ws_group<"), names
         emcnn.cnn_set_variant(h, layer, plain16)
     base = _run(emcnn, h, vol)
     for layer in (1, 2):
         for name in emcnn.cnn_variant_names(h, layer):
-            if name.startswith("conv_ws_phase<"):
+            if name.startswith(("conv_ws_phase<", "conv_ws_group<")):
                 emcnn.cnn_set_variant(h, layer, name)
                 assert np.array_equal(_run(emcnn, h, vol), base), (layer, name)
         emcnn.cnn_set_variant(h, layer, plain16)
