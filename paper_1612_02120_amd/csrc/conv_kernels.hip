@@ -67,8 +67,10 @@ __host__ __device__ constexpr int pad_words(int w) {
   return (w % 16 == 8) ? w : w + ((24 - (w % 16)) % 16);
 }
 
-// CBO: channels staged per LDS pass (0: the precision's default block)
-template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, bool HEAD = false, int CBO = 0>
+// CBO: channels staged per LDS pass (0: the precision's default block).
+// NMEM > 1: the operand tiles of NMEM phases stacked row-wise (conv_phase over
+// phase groups), NMEM times the m-blocks.
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, bool HEAD = false, int CBO = 0, int NMEM = 1>
 struct Cfg {
   using T = PT<P>;
   static constexpr int CB = CBO ? CBO : (T::CB < CIN) ? T::CB : CIN;
@@ -83,9 +85,9 @@ struct Cfg {
   static_assert(NB * 16 == COUT, "COUT must be a multiple of 16");
   static constexpr int LR = TY + KS - 1, LC = TX + KS - 1;
   static constexpr int PSB = pad_words(CB * T::BYTES / 4) * 4;
-  static constexpr int LDS_IN = LR * LC * PSB;
+  static constexpr int LDS_IN = NMEM * LR * LC * PSB;
   static constexpr int LDS_TILE = LDS_IN;
-  static constexpr int MBLK = TY * TX / 16;
+  static constexpr int MBLK = NMEM * TY * TX / 16;
   static_assert(TX % 16 == 0, "TX must be a multiple of 16");
   static_assert(MBLK % MW == 0, "m-blocks must split evenly over waves");
   static constexpr int WAVES = MBLK / MW;
@@ -1149,10 +1151,60 @@ __device__ __forceinline__ void stage_phase_tile(unsigned char* lds, const FragT
   }
 }
 
-template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI, int CB>
-__global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THREADS)) void conv_phase(
+// Stage the operand tiles of the four phases of a group (channel chunks 0 ..
+// NCHB-1 of the block at byte offset cofs of each pixel; fragments and clamps
+// as in head_taps4): member m = 2a + b's tile at rows m LR .. m LR + LR - 1,
+// its operand pixel (R, C) the max of four of the nine distinct (fragment,
+// shift) chunks of position (R, C). P: the stored activation type.
+template <int P, int LR, int LC, int NCHB, int PSB, int THREADS>
+__device__ __forceinline__ void stage_group_tile(unsigned char* lds, const gbyte* f00, int64_t o01, int64_t o10,
+                                                 int64_t rowb, int elb, int rvA, int rvB, int cvA, int cvB, int y0,
+                                                 int x0, int tid) {
+  constexpr int NST = LR * LC * NCHB;
+  constexpr int NIT = (NST + THREADS - 1) / THREADS;
+#pragma unroll 2
+  for (int k = 0; k < NIT; ++k) {
+    const int t = tid + k * THREADS;
+    if (t < NST) {
+      const int cg = t % NCHB, pix = t / NCHB;
+      const int R = y0 + pix / LC, Cc = x0 + pix % LC;
+      const int64_t rA = (int64_t)min(R, rvA) * rowb, rB = (int64_t)min(R, rvB) * rowb;
+      const int64_t rA1 = (int64_t)min(R + 1, rvA) * rowb;
+      const int64_t cA = (int64_t)min(Cc, cvA) * elb, cB = (int64_t)min(Cc, cvB) * elb;
+      const int64_t cA1 = (int64_t)min(Cc + 1, cvA) * elb;
+      const gbyte* b = f00 + cg * 16;
+      const i4v v0 = ld<i4v>(b + rA + cA), v1 = ld<i4v>(b + o01 + rA + cB);
+      const i4v v2 = ld<i4v>(b + o10 + rB + cA), v3 = ld<i4v>(b + o10 + o01 + rB + cB);
+      const i4v v4 = ld<i4v>(b + rA + cA1), v5 = ld<i4v>(b + o10 + rB + cA1);
+      const i4v v6 = ld<i4v>(b + rA1 + cA), v7 = ld<i4v>(b + o01 + rA1 + cB);
+      const i4v v8 = ld<i4v>(b + rA1 + cA1);
+      i4v op[4];
+      op[0] = chunk_max_signed<P>(chunk_max_signed<P>(v0, v1), chunk_max_signed<P>(v2, v3));  // (0, 0)
+      op[1] = chunk_max_signed<P>(chunk_max_signed<P>(v1, v4), chunk_max_signed<P>(v3, v5));  // (0, 1)
+      op[2] = chunk_max_signed<P>(chunk_max_signed<P>(v2, v3), chunk_max_signed<P>(v6, v7));  // (1, 0)
+      op[3] = chunk_max_signed<P>(chunk_max_signed<P>(v3, v5), chunk_max_signed<P>(v7, v8));  // (1, 1)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if constexpr (P == BF16) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) op[m][w] = (int)bf16_unkey((uint32_t)op[m][w]);
+        }
+        st<i4v>(lds + (m * LR * LC + pix) * PSB + cg * 16, op[m]);
+      }
+    }
+  }
+}
+
+// GRP = 1: the items are groups of four phases whose max filters share
+// fragments (the max filter has half the conv's spacing), each a TY x TX tile
+// of every member, staged together (stage_group_tile); m-block mb belongs to
+// member mb / (TY TX / 16).
+template <int P, int CIN, int COUT, int KS, int TY, int TX, int MW, int EPI, int CB, int GRP = 0>
+__global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB, GRP ? 4 : 1>::THREADS)) void conv_phase(
     JobSet js, ConvParams prm) {
-  using C = Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>;
+  using C = Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB, GRP ? 4 : 1>;
+  static_assert(!GRP || (EPI == 1 && P == F32), "phase groups: the FP32 max-out convs");
+  constexpr int MPM = TY * TX / 16;  // m-blocks of one member's tile
   using T = PT<P>;
   static_assert(P == F32 || P == BF16, "FP32 or BF16 activations (NHWC)");
   static_assert(EPI == 1 || EPI == 2, "max-out or softmax epilogue");
@@ -1173,20 +1225,22 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
   for (int64_t item = rg.begin; item < rg.end; item += rg.step) {
     const LayerJob J = job_at(js, cur, item);
     if (gated_off(J)) continue;
-    const int d = max(J.geom & 0xff, 1);
-    // item order: tile column, then phase, then tile row, then slice. The d^2
-    // phases of one tile row are neighbours in the item range, so the
-    // workgroups of an XCD stage them together: their max filters read each
-    // other's pixels, which then meet in that XCD's L2.
-    const int tpy = J.tiles_y / (d * d);  // tile rows per phase
+    const int d = max(J.geom & 0xff, 1), h = d >> 1;
+    // item order: tile column, then phase (GRP: phase group), then tile row,
+    // then slice. The d^2 phases of one tile row are neighbours in the item
+    // range, so the workgroups of an XCD stage them together: their max
+    // filters read each other's pixels, which then meet in that XCD's L2.
+    const int nph = GRP ? h * h : d * d;
+    const int tpy = J.tiles_y / nph;  // tile rows per phase (group)
     const int64_t local = item - J.item0;
     const int bx = (int)(local % J.tiles_x);
     const int64_t t2 = local / J.tiles_x;
-    const int ph = (int)(t2 % (d * d));
-    const int64_t t3 = t2 / (d * d);
+    const int ph = (int)(t2 % nph);
+    const int64_t t3 = t2 / nph;
     const int by = (int)(t3 % tpy);
     const int zz = (int)(t3 / tpy);
-    const int py = ph / d, px = ph % d;
+    // GRP: (py, px) is the group's first phase (gy, gx); member (a, b) adds (a h, b h)
+    const int py = GRP ? ph / h : ph / d, px = GRP ? ph % h : ph % d;
     const int y0 = by * TY, x0 = bx * TX;  // sub-lattice coordinates of the tile
     // operand pixel (r, c) is the max filter at input (py + d (y0 + r), px + d (x0 + c))
     const FragTile ft = frag_tile(gin(J.in) + (int64_t)zz * J.in_zs * ELB, ELB, J, py, px);
@@ -1200,8 +1254,18 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
 
     for (int cb = 0; cb < C::NCB; ++cb) {
       __syncthreads();
-      stage_phase_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, ft, cb * C::CB * T::BYTES, ELB, y0, x0,
-                                                                      tid);
+      if constexpr (GRP) {
+        const int lg = __builtin_ctz(d);
+        const int64_t plane = (J.in_zs >> (2 * lg)) * ELB;  // bytes per fragment
+        const gbyte* f00 = gin(J.in) + (int64_t)zz * J.in_zs * ELB + (int64_t)(py * d + px) * plane +
+                           cb * C::CB * T::BYTES;
+        stage_group_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(
+            lds, f00, h * plane, (int64_t)h * d * plane, J.in_rs * ELB, ELB, (J.hin - 1 - py) >> lg,
+            (J.hin - 1 - py - h) >> lg, (J.win - 1 - px) >> lg, (J.win - 1 - px - h) >> lg, y0, x0, tid);
+      } else {
+        stage_phase_tile<P, C::LR, C::LC, C::NCHB, C::PSB, C::THREADS>(lds, ft, cb * C::CB * T::BYTES, ELB, y0, x0,
+                                                                        tid);
+      }
       __syncthreads();
       // ---- implicit GEMM over this block's (tap, chunk) slots (as conv_mfma)
       const gbyte* wb = gin(prm.wpack) + (size_t)cb * C::NGS * C::NB * 64 * 16;
@@ -1222,8 +1286,9 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
 #pragma unroll
         for (int u = 0; u < MW; ++u) {
           const int mb = wave * MW + u;
-          const int mrow = mb / MCOLS, mcol = mb % MCOLS;
-          const unsigned char* a0 = lds + (mrow * C::LC + mcol * 16 + n16) * C::PSB;
+          const int mm = mb / MPM, lmb = mb % MPM;  // member, m-block in its tile
+          const int mrow = lmb / MCOLS, mcol = lmb % MCOLS;
+          const unsigned char* a0 = lds + ((mm * C::LR + mrow) * C::LC + mcol * 16 + n16) * C::PSB;
           Frag<P> afr;
           load_frag<P>(afr, a0 + off, a0 + off);
 #pragma unroll
@@ -1268,8 +1333,10 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
 #pragma unroll
         for (int u = 0; u < MW; ++u) {
           const int mb = wave * MW + u;
-          const int mrow = mb / MCOLS, mcol = mb % MCOLS;
-          const int y = py + d * (y0 + mrow);
+          const int mm = mb / MPM, lmb = mb % MPM;
+          const int mrow = lmb / MCOLS, mcol = lmb % MCOLS;
+          const int mpy = py + (mm >> 1) * h, mpx = px + (mm & 1) * h;  // the member's phase
+          const int y = mpy + d * (y0 + mrow);
           // lane parity e keeps pixels 4g + e and 4g + 2 + e
           float keep[2][C::NB];
 #pragma unroll
@@ -1293,7 +1360,7 @@ __global__ __launch_bounds__((Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CB>::THRE
             const int c = h * 64 + lane;  // 16-byte chunk: pixel c / (PIXB / 16)
             if (PIXB % 64 != 0 && c >= PIXB) break;
             const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
-            const int x = px + d * (x0 + mcol * 16 + c / (PIXB / 16));
+            const int x = mpx + d * (x0 + mcol * 16 + c / (PIXB / 16));
             if (y < J.hout && x < J.wout)
               st<i4v>(gout(J.out) + ((int64_t)zz * J.out_zs + frag_pix(y, x, lgo, J.out_rs, J.out_zs)) * PIXB +
                           (c % (PIXB / 16)) * 16,
@@ -2913,6 +2980,17 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH =
               Cfg<P, CIN, COUT, KS, TY, TX, MW, false, CBL>::LDS_TILE,                               \
               reinterpret_cast<const void*>(&conv_phase<P, CIN, COUT, KS, TY, TX, MW, EPI, CBL>),         \
               "conv_phase<" #P "," #CIN "," #COUT "," #KS "," #TY "," #TX "," #MW "," #EPI "," #CBL ">"}
+#define EMCNN_PHASE_GROUP(P, CIN, COUT, KS, TY, MW, CBL)                                                  \
+  VariantInfo{P, CIN, COUT, KS, 1, 0, TY, 16, MW,                                                    \
+              Cfg<P, CIN, COUT, KS, TY, 16, MW, false, CBL, 4>::THREADS,                              \
+              Cfg<P, CIN, COUT, KS, TY, 16, MW, false, CBL, 4>::CB,                                   \
+              PT<P>::CHB,                                                                           \
+              PT<P>::U,                                                                             \
+              Cfg<P, CIN, COUT, KS, TY, 16, MW, false, CBL, 4>::NGS,                                  \
+              0, 0, 1,                                                                              \
+              Cfg<P, CIN, COUT, KS, TY, 16, MW, false, CBL, 4>::LDS_TILE,                             \
+              reinterpret_cast<const void*>(&conv_phase<P, CIN, COUT, KS, TY, 16, MW, 1, CBL, 1>),         \
+              "conv_phase_group<" #P "," #CIN "," #COUT "," #KS "," #TY "," #MW "," #CBL ">", 0, 1}
 #define EMCNN_HEAD_PHASE(P, CIN, KS, TY, TX)                                                              \
   VariantInfo{P, CIN, 2, KS, 1, 0, TY, TX, 0, CfgHead<CIN, KS, TY, TX>::THREADS, CIN, PT<F32>::CHB, 1, 0, 0, 0, 3, \
               CfgHead<CIN, KS, TY, TX>::LDS, reinterpret_cast<const void*>(&head_phase<P, CIN, KS, TY, TX>),       \
@@ -3001,9 +3079,12 @@ static const VariantInfo kConv[] = {
     EMCNN_WS(FP8, 48, 48, 3, false, true, 8, 64, 8, 4),
     EMCNN_CONV(F32, 16, 16, 5, true, true, 8, 32, 4),
     EMCNN_CONV(F32, 16, 16, 5, false, false, 8, 32, 4),
-    // FastMemb body convs (4x4, 32 -> 64, max-out to 32) and its softmax layer
-    // (4x4, 32 -> 2 classes, computed as 16 MFMA columns), spaced form
+    // FastMemb body convs (4x4, 32 -> 64, max-out to 32), spaced form: over
+    // groups of four phases with 16-channel stages (the default where the max
+    // filter has half the conv's spacing; 17.7-17.8 against 18.1-18.2 ms per
+    // conv) or 32 (bitwise the same as one phase's 8 x 64 tile), or per phase
     // (all 32 channels per stage use a whole 128-byte pixel line at once)
+    EMCNN_PHASE_GROUP(F32, 32, 64, 4, 8, 4, 16), EMCNN_PHASE_GROUP(F32, 32, 64, 4, 8, 4, 32),
     EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 8, 1, 32),
     EMCNN_PHASE(F32, 32, 64, 4, 16, 64, 8, 1, 16), EMCNN_PHASE(F32, 32, 64, 4, 8, 64, 4, 1, 16),
     // the softmax layer (the host orders its candidates: phase-group kernels
@@ -3042,11 +3123,15 @@ static const VariantInfo kConv[] = {
     // (the three widest layers: 4 x 64 tiles of 2 m-blocks per wave, 7 or 8
     // n-blocks each, 138-162 registers instead of 192-236: 14-25 % faster than
     // 8 x 64 tiles of 4 m-blocks, bitwise the same)
+    // (the widest over phase groups of 4 x 16 tiles, 15.6 against 16.1 ms;
+    // the others' group candidates measured even)
     EMCNN_PHASE(F32, 12, 64, 4, 8, 64, 4, 1, 12), EMCNN_PHASE(F32, 32, 80, 4, 8, 64, 4, 1, 32),
     EMCNN_PHASE(F32, 40, 96, 4, 4, 64, 2, 1, 40), EMCNN_PHASE(F32, 48, 112, 4, 4, 64, 2, 1, 24),
-    EMCNN_PHASE(F32, 56, 128, 4, 4, 64, 2, 1, 28), EMCNN_HEAD1(F32, 64, 3, 256),
+    EMCNN_PHASE_GROUP(F32, 56, 128, 4, 4, 2, 28), EMCNN_HEAD1(F32, 64, 3, 256),
     EMCNN_PHASE(F32, 32, 80, 4, 4, 64, 2, 1, 32), EMCNN_PHASE(F32, 40, 96, 4, 8, 64, 4, 1, 40),
     EMCNN_PHASE(F32, 48, 112, 4, 8, 64, 4, 1, 24), EMCNN_PHASE(F32, 56, 128, 4, 8, 64, 4, 1, 28),
+    EMCNN_PHASE_GROUP(F32, 32, 80, 4, 4, 2, 32), EMCNN_PHASE_GROUP(F32, 40, 96, 4, 4, 2, 40),
+    EMCNN_PHASE_GROUP(F32, 48, 112, 4, 4, 2, 24), EMCNN_PHASE(F32, 56, 128, 4, 4, 64, 2, 1, 28),
 };
 
 #define EMCNN_FIRSTV(PO, COUT, KS, TY, TX, MX, ST, XS, SUFFIX)                                       \
