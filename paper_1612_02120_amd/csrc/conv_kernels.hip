@@ -642,6 +642,7 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
     const int wrow = wave * (C::MW / MCOLS);  // the wave's first tile row
     gbyte* const obase = oslice + ((int64_t)(y0 + wrow) * J.out_rs + x0 + n16) * 16 * C::ESZ + 4 * g * C::ESZ;
     const int64_t orow_b = (int64_t)J.out_rs * 16 * C::ESZ, oplane_b = (int64_t)J.out_zs * 16 * C::ESZ;
+    int64_t obase_px[MAXOUT ? (COUT / 2) * C::ESZ / 64 : 1];  // max-out stores: see the epilogue
 #pragma unroll
     for (int u = 0; u < C::MW; ++u) {
       const int mrow = wrow + u / MCOLS, mcol = u % MCOLS;
@@ -679,8 +680,9 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
         unsigned char* scr = scr_all + wave * 16 * PIXB;
 #pragma unroll
         for (int nb = 0; nb < C::NB; ++nb) {
-          const float m0 = fmaxf(acc[nb][0], acc[nb][1]);
-          const float m1 = fmaxf(acc[nb][2], acc[nb][3]);
+          // a compare and a select (fmaxf would first quiet each MFMA result)
+          const float m0 = acc[nb][0] > acc[nb][1] ? acc[nb][0] : acc[nb][1];
+          const float m1 = acc[nb][2] > acc[nb][3] ? acc[nb][2] : acc[nb][3];
           unsigned char* dst = scr + n16 * PIXB + (nb * 8 + 2 * g) * C::ESZ;
           if constexpr (PO == F32)
             *reinterpret_cast<f2*>(dst) = f2{m0, m1};
@@ -695,8 +697,11 @@ __global__ __launch_bounds__((FirstCfg<PO, COUT, KS, TY, TX, ST>::THREADS)) void
           const int c = h * 64 + lane;
           const i4v o = *reinterpret_cast<const i4v*>(scr + c * 16);
           const int pp = c / (PIXB / 16), xx = x0 + mcol * 16 + pp;
+          // pixel index of the row's first m-block, then 16 / 2^lgo further per m-block
+          // (the fragment modulus divides 16)
+          if (mcol == 0) obase_px[h] = frag_pix(y, x0 + pp, lgo, J.out_rs, J.out_zs);
           if (y < J.hout && xx < J.wout)
-            st<i4v>(oslice + frag_pix(y, xx, lgo, J.out_rs, J.out_zs) * PIXB + (c % (PIXB / 16)) * 16, o);
+            st<i4v>(oslice + (obase_px[h] + ((mcol * 16) >> lgo)) * PIXB + (c % (PIXB / 16)) * 16, o);
         }
         __builtin_amdgcn_wave_barrier();
         continue;
