@@ -87,3 +87,19 @@ def test_fastmemb_ss_workspace_slabs_and_batch_rejected(emcnn):
     with pytest.raises(emcnn.CnnError) as e:
         emcnn.cnn_infer_batch(h, [(v[:1], 60, torch.empty((1, 70, 50), device="cuda"))])
     assert e.value.code == emcnn.CNN_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fastmemb_ss_phase_group_kernels_offered_only_with_a_half_spacing_filter(emcnn, prec):
+    # the kernels over groups of four phases assume the max filter before the
+    # conv has half its spacing: offered (and the default) after each stride-2
+    # pool, never for the conv right after the subsample (no max filter)
+    h = emcnn.cnn_create(_params(), NET_FMSS, prec)
+    names = [emcnn.cnn_variant_names(h, l) for l in range(5)]
+    grouped = ("conv_phase_group<", "conv_ws_group<", "head_strip<", "head_taps4<")
+    assert not any(n.startswith(grouped) for n in names[1]), names[1]
+    for l in (2, 3):
+        assert names[l][0].startswith(("conv_phase_group<", "conv_ws_group<")), names[l]
+    assert names[4][0].startswith("head_strip<"), names[4]
+    with pytest.raises(emcnn.CnnError):
+        emcnn.cnn_set_variant(h, 1, names[2][0])  # a phase-group kernel on the unfiltered conv
