@@ -111,9 +111,12 @@ __device__ __forceinline__ unsigned char to_e4m3(float v) {
   return (unsigned char)(packed & 0xff);
 }
 
+// Two floats to bf16 (round to nearest even), lo in the low half: one packed
+// conversion (converted one at a time, the compiler adds a shift and an or)
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-  const __bf16 a = (__bf16)lo, b = (__bf16)hi;
-  return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){lo, hi}, bf16x2v));
 }
 
 __device__ __forceinline__ uint32_t pack_e4m3x2(float lo, float hi) {
