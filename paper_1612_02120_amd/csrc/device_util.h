@@ -42,6 +42,13 @@ template <class V>
 __device__ __forceinline__ void st(gbyte* p, V v) {
   *reinterpret_cast<EMCNN_GLOBAL V*>(p) = v;
 }
+// Store with the nontemporal (streaming) hint, for FP32 maps that a layer
+// writes once and the next layer reads only after this one has ended: at
+// hundreds of MB to GB per layer they do not stay in the caches anyway.
+template <class V>
+__device__ __forceinline__ void st_nt(gbyte* p, V v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<EMCNN_GLOBAL V*>(p));
+}
 __device__ __forceinline__ float ldf(const float* p, int i) { return ld<float>(gin(p) + (int64_t)i * 4); }
 
 }  // namespace emcnn
