@@ -3159,17 +3159,24 @@ static const VariantInfo kConv[] = {
 static const FirstInfo kFirst[] = {
     // defaults (first match per signature) are the measured fastest shapes:
     // FP8 output staged through LDS for 16-byte stores (0.39 against 0.53 ms
-    // stored from registers, on 8 x 2048^2), BF16 stored from registers
-    EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 8, 64), EMCNN_FIRSTX(FP8, 48, 5, 16, 128),
-    EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 8, 32),  EMCNN_FIRST(BF16, 48, 5, 4, 64),
-    EMCNN_FIRST(FP8, 48, 5, 8, 64), EMCNN_FIRST(FP8, 48, 5, 4, 64),  EMCNN_FIRST(FP8, 48, 5, 16, 64),
-    EMCNN_FIRSTX(BF16, 48, 5, 8, 64), EMCNN_FIRSTX(FP8, 48, 5, 16, 64), EMCNN_FIRSTX(FP8, 48, 5, 32, 128),
+    // stored from registers, on 8 x 2048^2), BF16 stored from registers. Tall
+    // tiles pay off where the layer is cheap per staged row: 16 x 128 BF16 and
+    // 32 x 128 FP8 against 8 x 64 and 16 x 128 (5 % and 3 % faster); for the
+    // max-out layers 16 x 128 FP32 and 32 x 128 BF16 against 4 x 64 (13 % and
+    // 26 % faster; a 4-row tile stages 7 rows)
+    EMCNN_FIRST(F32, 48, 5, 4, 64),  EMCNN_FIRST(BF16, 48, 5, 16, 128), EMCNN_FIRSTX(FP8, 48, 5, 32, 128),
+    EMCNN_FIRST(F32, 16, 5, 4, 64),  EMCNN_FIRST(F32, 48, 5, 8, 32),   EMCNN_FIRST(F32, 48, 5, 8, 64),
+    EMCNN_FIRST(BF16, 48, 5, 8, 64), EMCNN_FIRST(BF16, 48, 5, 32, 64), EMCNN_FIRST(BF16, 48, 5, 4, 64),
+    EMCNN_FIRST(FP8, 48, 5, 8, 64),  EMCNN_FIRST(FP8, 48, 5, 4, 64),   EMCNN_FIRST(FP8, 48, 5, 16, 64),
+    EMCNN_FIRSTX(BF16, 48, 5, 8, 64), EMCNN_FIRSTX(FP8, 48, 5, 16, 64), EMCNN_FIRSTX(FP8, 48, 5, 16, 128),
+    EMCNN_FIRSTX(FP8, 48, 5, 16, 256),
     // FastMemb first conv: 4x4, 1 -> 64, max-out to 32
-    EMCNN_FIRSTM(F32, 64, 4, 4, 64, true), EMCNN_FIRSTM(F32, 64, 4, 8, 32, true),
-    EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true), EMCNN_FIRSTM(BF16, 64, 4, 8, 64, true),
-    // FastMemb_ss first conv: evaluated only where the 2x subsample after it keeps a pixel
-    EMCNN_FIRSTS(F32, 64, 4, 4, 64, true, 2), EMCNN_FIRSTS(F32, 64, 4, 8, 32, true, 2),
-    EMCNN_FIRSTS(BF16, 64, 4, 4, 64, true, 2), EMCNN_FIRSTS(BF16, 64, 4, 8, 64, true, 2),
+    EMCNN_FIRSTM(F32, 64, 4, 16, 128, true), EMCNN_FIRSTM(F32, 64, 4, 32, 64, true), EMCNN_FIRSTM(F32, 64, 4, 4, 64, true),
+    EMCNN_FIRSTM(BF16, 64, 4, 32, 128, true), EMCNN_FIRSTM(BF16, 64, 4, 16, 256, true), EMCNN_FIRSTM(BF16, 64, 4, 4, 64, true),
+    // FastMemb_ss first conv: evaluated only where the 2x subsample after it
+    // keeps a pixel (16 x 64 FP32 and 8 x 64 BF16: 7 % and 2 % faster than 4 x 64)
+    EMCNN_FIRSTS(F32, 64, 4, 16, 64, true, 2), EMCNN_FIRSTS(F32, 64, 4, 8, 64, true, 2), EMCNN_FIRSTS(F32, 64, 4, 4, 64, true, 2),
+    EMCNN_FIRSTS(BF16, 64, 4, 8, 64, true, 2), EMCNN_FIRSTS(BF16, 64, 4, 16, 64, true, 2), EMCNN_FIRSTS(BF16, 64, 4, 4, 64, true, 2),
 };
 
 int conv_variant_count() { return (int)(sizeof(kConv) / sizeof(kConv[0])); }
