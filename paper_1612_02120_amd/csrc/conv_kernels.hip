@@ -3119,8 +3119,8 @@ static const VariantInfo kConv[] = {
     // same 16-channel stages (the same MFMA sequence), and conv_phase staging
     // all 32 channels at once
     EMCNN_WS_GROUP(BF16, 32, 64, 4, 12, 8, 4), EMCNN_WS_GROUP(BF16, 32, 64, 4, 8, 8, 4),
-    EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 8, 4), EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 4, 4),
-    EMCNN_WS_PHASE(BF16, 32, 64, 4, 16, 32, 8, 4),
+    EMCNN_WS_PHASE(BF16, 32, 64, 4, 16, 32, 8, 4), EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 8, 4),
+    EMCNN_WS_PHASE(BF16, 32, 64, 4, 8, 64, 4, 4),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 16),
     EMCNN_PHASE(BF16, 32, 64, 4, 8, 64, 4, 1, 32), EMCNN_PHASE(BF16, 32, 64, 4, 16, 64, 8, 1, 32),
     EMCNN_PHASE(BF16, 32, 16, 4, 8, 64, 4, 2, 32), EMCNN_HEAD_PHASE(BF16, 32, 4, 8, 64),
@@ -3134,15 +3134,16 @@ static const VariantInfo kConv[] = {
     // (the three widest layers: 4 x 64 tiles of 2 m-blocks per wave, 7 or 8
     // n-blocks each, 138-162 registers instead of 192-236: 14-25 % faster than
     // 8 x 64 tiles of 4 m-blocks, bitwise the same)
-    // (the widest over phase groups of 4 x 16 tiles, 15.6 against 16.1 ms;
-    // the others' group candidates measured even)
+    // (the three widest over phase groups of 4 x 16 tiles: 15.4 against 15.9,
+    // 11.95 against 12.0 and 9.43 against 9.48 ms; the narrowest's group
+    // candidate measured 1 % slower)
     EMCNN_PHASE(F32, 12, 64, 4, 8, 64, 4, 1, 12), EMCNN_PHASE(F32, 32, 80, 4, 8, 64, 4, 1, 32),
-    EMCNN_PHASE(F32, 40, 96, 4, 4, 64, 2, 1, 40), EMCNN_PHASE(F32, 48, 112, 4, 4, 64, 2, 1, 24),
+    EMCNN_PHASE_GROUP(F32, 40, 96, 4, 4, 2, 40), EMCNN_PHASE_GROUP(F32, 48, 112, 4, 4, 2, 24),
     EMCNN_PHASE_GROUP(F32, 56, 128, 4, 4, 2, 28), EMCNN_HEAD1(F32, 64, 3, 256),
     EMCNN_PHASE(F32, 32, 80, 4, 4, 64, 2, 1, 32), EMCNN_PHASE(F32, 40, 96, 4, 8, 64, 4, 1, 40),
     EMCNN_PHASE(F32, 48, 112, 4, 8, 64, 4, 1, 24), EMCNN_PHASE(F32, 56, 128, 4, 8, 64, 4, 1, 28),
-    EMCNN_PHASE_GROUP(F32, 32, 80, 4, 4, 2, 32), EMCNN_PHASE_GROUP(F32, 40, 96, 4, 4, 2, 40),
-    EMCNN_PHASE_GROUP(F32, 48, 112, 4, 4, 2, 24), EMCNN_PHASE(F32, 56, 128, 4, 4, 64, 2, 1, 28),
+    EMCNN_PHASE_GROUP(F32, 32, 80, 4, 4, 2, 32), EMCNN_PHASE(F32, 40, 96, 4, 4, 64, 2, 1, 40),
+    EMCNN_PHASE(F32, 48, 112, 4, 4, 64, 2, 1, 24), EMCNN_PHASE(F32, 56, 128, 4, 4, 64, 2, 1, 28),
 };
 
 #define EMCNN_FIRSTV(PO, COUT, KS, TY, TX, MX, ST, XS, SUFFIX)                                       \
