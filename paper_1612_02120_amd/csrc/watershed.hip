@@ -12,14 +12,18 @@
 // both parts: a non-seed points along its descent, a seed into its
 // component's tree. Roots are fixed points: component minima and non-seed
 // local minima.
-//   ws_init   one pass: a[v] = v on S, else next(v)
-//   ws_union  one pass over the seeds: each 6-adjacent pair of seeds is
-//             united by a lock-free union-find (the structure of ECL-CC):
-//             find both roots, hook the larger root under the smaller with a
+//   ws_init   one pass: a seed points to the first seed of its run along x
+//             (the run's least index; a ballot scan per row), any other
+//             voxel to next(v). The x-links of the seed graph are then made.
+//   ws_union  one pass over the seeds: runs adjacent along y or z are united
+//             by a lock-free union-find (the structure of ECL-CC): find both
+//             roots, hook the larger root under the smaller with a
 //             compare-and-swap that only succeeds while it is still a root,
 //             and retry from the new roots when another thread hooked it
-//             first. A seed's parent index only decreases, so every
-//             component ends rooted at its least index.
+//             first. Two runs that touch are united once, at the first column
+//             where they do (the pair one column left, when both are seeds,
+//             joins the same two runs). A seed's parent index only
+//             decreases, so every component ends rooted at its least index.
 //   ws_label  every voxel finds its root (a component minimum or a local
 //             minimum), halving the path as it goes, and takes root + 1.
 // Path halving points a node at its grandparent, an ancestor in the same
@@ -45,16 +49,37 @@ __device__ __forceinline__ int32_t wa(const int32_t* a, int64_t v) {
 }
 
 // Work split: one row (z, y) of W voxels per block iteration, x over the
-// threads; indices fit in 32 bits (Z H W < 2^31 - 1).
+// threads in chunks of 256 columns; indices fit in 32 bits (Z H W < 2^31 - 1).
 __global__ __launch_bounds__(256) void ws_init(const float* __restrict__ p, Vol3 g, float t, int32_t* __restrict__ a) {
+  __shared__ int wbreak[4];  // per wave: its last non-seed column in the chunk, or -1
   const int HW = g.H * g.W;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int row = blockIdx.x; row < g.Z * g.H; row += gridDim.x) {
     const int z = row / g.H, y = row - z * g.H, base = row * g.W;
-    for (int x = threadIdx.x; x < g.W; x += 256) {
+    int carry = -1;  // the last non-seed column before the chunk
+    for (int x0 = 0; x0 < g.W; x0 += 256) {  // uniform over the block: every thread takes every chunk
+      const int x = x0 + threadIdx.x;
       const int v = base + x;
-      const float pv = wp(p, v);
-      if (pv < t) {
-        a[v] = v;
+      const bool in = x < g.W;
+      const float pv = in ? wp(p, v) : 0.f;
+      const bool seed = in && pv < t;
+      // lb: the last non-seed column at or before x (columns past the row count as non-seeds)
+      const uint64_t brk = __ballot(!seed);
+      const uint64_t upto = brk & ((2ull << lane) - 1);  // lanes 0 .. lane (all 64 bits for lane 63)
+      const int wx = x0 + wv * 64 + 63;                   // the wave's last column
+      int lb = upto ? wx - __builtin_clzll(upto) : -1;
+      if (lane == 0) wbreak[wv] = brk ? wx - __builtin_clzll(brk) : -1;
+      __syncthreads();
+      if (lb < 0) {
+        lb = carry;
+        for (int k = 0; k < wv; ++k) lb = max(lb, wbreak[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) carry = max(carry, wbreak[k]);
+      __syncthreads();  // wbreak is rewritten for the next chunk
+      if (!in) continue;
+      if (seed) {
+        a[v] = base + lb + 1;  // the run's first seed
         continue;
       }
       int best = v;
@@ -109,11 +134,13 @@ __global__ __launch_bounds__(256) void ws_union(const float* __restrict__ p, Vol
     for (int x = threadIdx.x; x < g.W; x += 256) {
       const int v = base + x;
       if (!(wp(p, v) < t)) continue;
-      const int fwd[3] = {x < g.W - 1 ? v + 1 : -1, y < g.H - 1 ? v + g.W : -1, z < g.Z - 1 ? v + HW : -1};
+      const bool left = x > 0 && wp(p, v - 1) < t;  // v is not its run's first seed
+      const int fwd[2] = {y < g.H - 1 ? v + g.W : -1, z < g.Z - 1 ? v + HW : -1};
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 2; ++k) {
         const int u = fwd[k];
         if (u < 0 || !(wp(p, u) < t)) continue;
+        if (left && wp(p, u - 1) < t) continue;  // the pair one column left joins the same two runs
         ws_unite(a, v, u);
       }
     }

@@ -43,6 +43,20 @@ def test_watershed_random_with_ties(emcnn, shape, levels, t, seed):
     assert np.array_equal(_gpu(emcnn, p, t), oracle.watershed(p, t))
 
 
+@pytest.mark.parametrize("shape,frac,seed", [((3, 9, 600), 0.85, 7), ((2, 5, 1030), 0.97, 8), ((2, 3, 700), 1.0, 9),
+                                              ((4, 6, 257), 0.6, 10)])
+def test_watershed_long_seed_runs(emcnn, shape, frac, seed):
+    """Seed runs along x that cross the 256-column chunks of a row (the
+    first-seed scan carries between chunks), rows that are all seeds, and
+    exact ties among the seeds and the rest."""
+    print("watershed runs case", shape, frac, flush=True)
+    rng = np.random.default_rng(seed)
+    p = np.floor(rng.uniform(0, 1, shape) * 5) / 5 + 0.2
+    p = np.where(rng.uniform(0, 1, shape) < frac, 0.1, p).astype(np.float32)
+    t = 0.15
+    assert np.array_equal(_gpu(emcnn, p, t), oracle.watershed(p, t))
+
+
 @pytest.mark.parametrize("sigma,q", [(1.0, 0.1), (2.5, 0.3)])
 def test_watershed_smooth_maps(emcnn, sigma, q):
     rng = np.random.default_rng(11)
