@@ -2095,6 +2095,14 @@ __device__ __forceinline__ int slot_off(int s, int uu, int g) {
   return (k.i * C::LC + k.j) * C::PSB + k.cg * 16;
 }
 
+// Output fields of a job that a conv_ws epilogue needs after the tile walk
+// has moved on to the next item.
+struct EpiJob {
+  void* out;
+  int64_t out_rs, out_zs;
+  int32_t hout, wout;
+};
+
 // Walk of the work items of one workgroup (see item_range), skipping items
 // of gated-off jobs. Every wave of the workgroup walks the same sequence.
 struct TileWalk {
@@ -2684,6 +2692,24 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH =
   // stored ones, or two max-out pairs); otherwise (the fused head) channel n16
   // of pixels 4g .. 4g + 3
   constexpr bool TRANS = !HEAD;
+  // Rolled K loop over the flattened order (FP8 3x3): the lane's LDS offsets
+  // of every (step, chunk) slot, computed once and packed as 16-bit values
+  // (two steps per register), so a step extracts its two offsets with a
+  // select and a shift instead of redoing the divisions of slot_off.
+  constexpr bool OTAB = !C::ROWK && C::KUNROLL == 1 && C::NGS <= 4 && C::BL;
+  constexpr int OTW = OTAB ? (C::NGS + 1) / 2 : 1;
+  uint32_t otab[T::U][OTW];
+  if constexpr (OTAB) {
+    static_assert(((C::KSZ - 1) * (C::LC + 1) + 1) * C::PSB <= 65535, "16-bit slot offsets");
+#pragma unroll
+    for (int uu = 0; uu < T::U; ++uu)
+#pragma unroll
+      for (int q = 0; q < OTW; ++q) {
+        const uint32_t lo = (uint32_t)slot_off<C>(2 * q, uu, g);
+        const uint32_t hi = 2 * q + 1 < C::NGS ? (uint32_t)slot_off<C>(2 * q + 1, uu, g) : 0u;
+        otab[uu][q] = lo | (hi << 16);
+      }
+  }
   __syncthreads();  // the first stage is ready
   int cb = 0, sel = 0;
   f4 acc[C::MW][C::NB];
@@ -2701,7 +2727,91 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH =
     }
   };
   if constexpr (!C::BL) load_b(bq[0], wglob + lane * 16, 0);
+  // Epilogue of the plain form straight from the accumulators, for the tile
+  // at (zz, y0, x0) of the job whose output fields are in J.
+  auto plain_epi = [&](const EpiJob& J, int zz, int y0, int x0) __attribute__((always_inline)) {
+    float bias[C::NB], osc[C::NB], hw[C::NB];
+#pragma unroll
+    for (int nb = 0; nb < C::NB; ++nb) {
+      bias[nb] = ldf(prm.bias, nb * 16 + n16);
+      osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
+      hw[nb] = HEAD ? ldf(prm.head_w, nb * 16 + n16) : 0.f;
+    }
+    const int ty0 = y0 + wrow0;
+    if constexpr (HEAD) {
+      head_epilogue<C::MW, C::NB>(
+          [&](int u, int nb, int k) __attribute__((always_inline)) { return acc[u][nb][k]; },
+          [&](int u, int& y, int& xb) __attribute__((always_inline)) {
+            y = ty0 + u / MCOLS;
+            xb = x0 + (u % MCOLS) * 16;
+          },
+          bias, osc, hw, prm.head_b, g, n16, gout(J.out), (int64_t)zz * J.out_zs, J.out_rs, J.hout, J.wout);
+    } else {
+      // TRANS: a lane's 4 channels of an n-block are 4 (FP8) / 8 (BF16)
+      // contiguous bytes of its pixel's entry in that 16-channel plane, and
+      // an n-block's 64 lanes cover 16 pixels x 16 channels, one contiguous
+      // run, stored straight from the accumulators
+      static_assert(TRANS, "non-head epilogue of the plain form");
+      f4 bs[C::NB], sc[C::NB];
+#pragma unroll
+      for (int nb = 0; nb < C::NB; ++nb) {
+        bs[nb] = ld<f4>(gin(prm.bias) + (nb * 16 + 4 * g) * 4);
+        sc[nb] = prm.oscale ? ld<f4>(gin(prm.oscale) + (nb * 16 + 4 * g) * 4) : f4{1.f, 1.f, 1.f, 1.f};
+      }
+      const float inv = prm.out_inv_scale;
+      gbyte* const obase = gout(J.out) + (int64_t)zz * J.out_zs * COUT * T::BYTES + (int64_t)(4 * g) * T::BYTES;
+#pragma unroll
+      for (int u = 0; u < C::MW; ++u) {
+        const int y = ty0 + u / MCOLS;
+        const int x = x0 + (u % MCOLS) * 16 + n16;
+        if (y < J.hout && x < J.wout) {
+          gbyte* const d0 = obase + ((int64_t)y * J.out_rs + x) * PB;
+#pragma unroll
+          for (int nb = 0; nb < C::NB; ++nb) {
+            gbyte* const d = d0 + (int64_t)nb * J.out_zs * PB;
+            float t[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t[k] = fmaf(acc[u][nb][k], sc[nb][k], bs[nb][k]);
+            if constexpr (P == BF16) {
+              st<u2v>(d, u2v{pack_bf16x2(relu(t[0]), relu(t[1])), pack_bf16x2(relu(t[2]), relu(t[3]))});
+            } else {
+              // relu(t) * s clamped to [0, 448] is the median of (t * s, 0, 448)
+              // for s > 0; clearing bit 7 of each code maps a -0 to +0
+              float v[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_fmed3f(t[k] * inv, 0.0f, 448.0f);
+              int wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], __builtin_bit_cast(int, v[0]), false);
+              wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], wd, true);
+              st<uint32_t>(d, (uint32_t)wd & 0x7f7f7f7fu);
+            }
+          }
+        }
+      }
+    }
+  };
+  // The second half of the consumer waves (one per SIMD beside one of the
+  // first half) defers a tile's epilogue to the start of the next stage: its
+  // epilogue then overlaps the other wave's MFMAs instead of both waves of a
+  // SIMD running theirs after the same barrier. The epilogue reads only
+  // registers and global memory, so the delay needs no extra LDS buffer; the
+  // accumulators are cleared after it. Measured on net B over 8 x 2048^2:
+  // conv2 FP8 1.70 -> 1.63 ms, BF16 2.84 -> 2.78 ms; with the fused head
+  // (conv3) slower (FP8 0.96 -> 1.03 ms, BF16 1.55 -> 1.65 ms), so not there.
+  // The spaced form's epilogue measured no gain from the same delay; those
+  // kernels and the fused head keep the loop without it.
+  constexpr bool DEFER = !PH && !HEAD;
+  const bool defer = DEFER && wave >= NCW / 2;
+  bool pend = false, more = true;
+  EpiJob pj{};
+  int pz = 0, py0 = 0, px0 = 0;
   for (;;) {
+    if constexpr (DEFER) {
+      if (pend) {
+        plain_epi(pj, pz, py0, px0);
+        pend = false;
+      }
+      if (!more) break;
+    }
     if (cb == 0) {
 #pragma unroll
       for (int u = 0; u < C::MW; ++u)
@@ -2725,7 +2835,16 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH =
         }
         int off[T::U];
 #pragma unroll
-        for (int uu = 0; uu < T::U; ++uu) off[uu] = slot_off<C>(s, uu, g);
+        for (int uu = 0; uu < T::U; ++uu) {
+          if constexpr (OTAB) {
+            uint32_t wd = otab[uu][0];
+#pragma unroll
+            for (int q = 1; q < OTW; ++q) wd = s >= 2 * q ? otab[uu][q] : wd;
+            off[uu] = (int)((wd >> ((s & 1) * 16)) & 0xffffu);
+          } else {
+            off[uu] = slot_off<C>(s, uu, g);
+          }
+        }
         const unsigned char* a0 = abase + off[0];
         const unsigned char* a1 = abase + off[T::U - 1];
 #pragma unroll
@@ -2834,67 +2953,17 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH =
         }
       }
     } else if (cb == C::NCB - 1) {
-      // ---- epilogue straight from the accumulators
       int zz, y0, x0;
       w.coords<TY, TX>(zz, y0, x0);
-      const LayerJob& J = w.J;
-      float bias[C::NB], osc[C::NB], hw[C::NB];
-#pragma unroll
-      for (int nb = 0; nb < C::NB; ++nb) {
-        bias[nb] = ldf(prm.bias, nb * 16 + n16);
-        osc[nb] = prm.oscale ? ldf(prm.oscale, nb * 16 + n16) : 1.0f;
-        hw[nb] = HEAD ? ldf(prm.head_w, nb * 16 + n16) : 0.f;
-      }
-      const int ty0 = y0 + wrow0;
-      if constexpr (HEAD) {
-        head_epilogue<C::MW, C::NB>(
-            [&](int u, int nb, int k) __attribute__((always_inline)) { return acc[u][nb][k]; },
-            [&](int u, int& y, int& xb) __attribute__((always_inline)) {
-              y = ty0 + u / MCOLS;
-              xb = x0 + (u % MCOLS) * 16;
-            },
-            bias, osc, hw, prm.head_b, g, n16, gout(J.out), (int64_t)zz * J.out_zs, J.out_rs, J.hout, J.wout);
+      const EpiJob ej{w.J.out, w.J.out_rs, w.J.out_zs, w.J.hout, w.J.wout};
+      if (DEFER && defer) {
+        pj = ej;
+        pz = zz;
+        py0 = y0;
+        px0 = x0;
+        pend = true;
       } else {
-        // TRANS: a lane's 4 channels of an n-block are 4 (FP8) / 8 (BF16)
-        // contiguous bytes of its pixel's entry in that 16-channel plane, and
-        // an n-block's 64 lanes cover 16 pixels x 16 channels, one contiguous
-        // run, stored straight from the accumulators
-        static_assert(TRANS, "non-head epilogue of the plain form");
-        f4 bs[C::NB], sc[C::NB];
-#pragma unroll
-        for (int nb = 0; nb < C::NB; ++nb) {
-          bs[nb] = ld<f4>(gin(prm.bias) + (nb * 16 + 4 * g) * 4);
-          sc[nb] = prm.oscale ? ld<f4>(gin(prm.oscale) + (nb * 16 + 4 * g) * 4) : f4{1.f, 1.f, 1.f, 1.f};
-        }
-        const float inv = prm.out_inv_scale;
-        gbyte* const obase = gout(J.out) + (int64_t)zz * J.out_zs * COUT * T::BYTES + (int64_t)(4 * g) * T::BYTES;
-#pragma unroll
-        for (int u = 0; u < C::MW; ++u) {
-          const int y = ty0 + u / MCOLS;
-          const int x = x0 + (u % MCOLS) * 16 + n16;
-          if (y < J.hout && x < J.wout) {
-            gbyte* const d0 = obase + ((int64_t)y * J.out_rs + x) * PB;
-#pragma unroll
-            for (int nb = 0; nb < C::NB; ++nb) {
-              gbyte* const d = d0 + (int64_t)nb * J.out_zs * PB;
-              float t[4];
-#pragma unroll
-              for (int k = 0; k < 4; ++k) t[k] = fmaf(acc[u][nb][k], sc[nb][k], bs[nb][k]);
-              if constexpr (P == BF16) {
-                st<u2v>(d, u2v{pack_bf16x2(relu(t[0]), relu(t[1])), pack_bf16x2(relu(t[2]), relu(t[3]))});
-              } else {
-                // relu(t) * s clamped to [0, 448] is the median of (t * s, 0, 448)
-                // for s > 0; clearing bit 7 of each code maps a -0 to +0
-                float v[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) v[k] = __builtin_amdgcn_fmed3f(t[k] * inv, 0.0f, 448.0f);
-                int wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], __builtin_bit_cast(int, v[0]), false);
-                wd = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], wd, true);
-                st<uint32_t>(d, (uint32_t)wd & 0x7f7f7f7fu);
-              }
-            }
-          }
-        }
+        plain_epi(ej, zz, y0, x0);
       }
     }
 
@@ -2902,7 +2971,10 @@ __global__ __launch_bounds__((CfgWS<P, CIN, COUT, KS, TY, TX, NCW, NPW, K1, PH =
     sel ^= 1;
     if (++cb == C::NCB) {
       cb = 0;
-      if (!w.next(js)) break;
+      if constexpr (DEFER)
+        more = w.next(js);
+      else if (!w.next(js))
+        break;
     }
   }
 }
