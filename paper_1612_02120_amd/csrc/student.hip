@@ -108,47 +108,68 @@ __global__ __launch_bounds__((TY * TX)) void student_fused(const uint8_t* __rest
 // output channels fill half of the MFMA's 16 rows: lane (g, n) receives
 // channels 4g..4g+3 of pixel n, lanes g >= 2 the zero-weight rows. One
 // workgroup of 4 waves computes a TY x TX output tile:
+//   input: the uint8 tile converted once to bf16 in LDS (the high half of
+//          the float of a byte, whose low half is zero);
 //   conv1: h1 for (TY+2) x (16 ceil((TX+2)/16)) positions, one MFMA per 16
 //          pixels (K = 25 taps padded to 32), bias, ReLU, bf16 -> LDS
-//          (16 bytes per position: 8 channels);
+//          (16 bytes per position: 8 channels); wave w takes the h1 rows
+//          w, w + 4, ..., so its LDS offsets are a per-lane base plus
+//          compile-time immediates;
 //   conv2: K = 9 taps x 8 channels in 3 MFMAs per 16 outputs (taps 4s + g,
 //          padded to 12), one 16-byte LDS read per lane per MFMA;
-//   head:  each lane's 4-channel partial dot, one cross-lane add, sigmoid.
+//   head:  each lane's 4-channel partial dot; the two real lane groups' sums
+//          are gathered for four m-blocks at a time, so that lane group j
+//          holds m-block j's 16 probabilities and one sigmoid and one store
+//          per lane serve four m-blocks.
 template <int TY, int TX>
 __global__ __launch_bounds__(256) void student_mfma(const uint8_t* in, int64_t in_rs, int64_t in_zs, float* out,
                                                     int64_t out_rs, int64_t out_zs, int Ho, int Wo, int crop,
                                                     const float* ww) {
-  constexpr int HR = TY + 2;            // h1 rows
+  constexpr int HR = TY + 2;               // h1 rows
   constexpr int HMC = (TX + 2 + 15) / 16;  // h1 m-blocks per row
-  constexpr int HC = HMC * 16;          // h1 row pitch (positions)
-  constexpr int IR = HR + 4, IC = HC + 4;  // uint8 tile (covers the padded h1 columns)
+  constexpr int HC = HMC * 16;             // h1 row pitch (positions)
+  constexpr int IR = HR + 4, IC = HC + 4;  // input tile (covers the padded h1 columns)
+  constexpr int OMC = TX / 16;             // output m-blocks per row
   static_assert(TX % 16 == 0, "output m-blocks of 16 pixels");
-  __shared__ unsigned char xin[IR * IC];
+  static_assert(OMC == 4 && TY % 4 == 0, "wave w owns output m-block column w; rows in groups of four");
+  __shared__ __attribute__((aligned(16))) unsigned short xin[IR * IC];  // bf16 bits
   __shared__ __attribute__((aligned(16))) unsigned char h1[HR * HC * 16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, n16 = lane & 15;
   const int y0 = blockIdx.y * TY, x0 = blockIdx.x * TX, z = blockIdx.z;
   const gbyte* src = gin(in) + (int64_t)z * in_zs;
   const int hin_lim = Ho + 2 * crop + 6, win_lim = Wo + 2 * crop + 6;  // input dims implied by the output
-  for (int t = tid; t < IR * IC; t += 256) {
-    const int r = t / IC, c = t % IC;
-    const int y = min(y0 + crop + r, hin_lim - 1), x = min(x0 + crop + c, win_lim - 1);
-    xin[t] = src[(int64_t)y * in_rs + x];
+  {
+    // rows wave + 4k, columns lane + 64 m: all byte loads issued before any is used
+    constexpr int NK = (IR + 3) / 4, NM = (IC + 63) / 64;
+    unsigned int b[NK][NM];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const gbyte* row = src + (int64_t)min(y0 + crop + wave + 4 * k, hin_lim - 1) * in_rs;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) b[k][m] = row[min(x0 + crop + lane + 64 * m, win_lim - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+        if (wave + 4 * k < IR && lane + 64 * m < IC)
+          xin[(wave + 4 * k) * IC + lane + 64 * m] =
+              (unsigned short)(__builtin_bit_cast(unsigned int, (float)b[k][m]) >> 16);
   }
   // weight fragments: lane (g, c) holds output channel c's K elements 8g..8g+7
+  // (every load is unconditional, from a clamped index, and the padding is
+  // selected afterwards, so that all of them are in flight together)
   const bool realc = n16 < S_C;
-  bf16x8 w1f, w2f[3];
+  const int c8 = realc ? n16 : 0;
+  float w1v[8], w2v[3][8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int t = 8 * g + e;
-    w1f[e] = (__bf16)(realc && t < 25 ? ldf(ww, OFF_W1 + n16 * 25 + t) : 0.f);
-  }
+  for (int e = 0; e < 8; ++e) w1v[e] = ldf(ww, OFF_W1 + c8 * 25 + min(8 * g + e, 24));
 #pragma unroll
-  for (int s3 = 0; s3 < 3; ++s3) {
-    const int t = 4 * s3 + g;
+  for (int s3 = 0; s3 < 3; ++s3)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) w2f[s3][e] = (__bf16)(realc && t < 9 ? ldf(ww, OFF_W2 + (n16 * 8 + e) * 9 + t) : 0.f);
-  }
+    for (int e = 0; e < 8; ++e) w2v[s3][e] = ldf(ww, OFF_W2 + (c8 * 8 + e) * 9 + min(4 * s3 + g, 8));
   const bool realg = g < 2;  // this lane's rows are real channels 4g..4g+3
   float b1[4], b2[4], wh[4];
 #pragma unroll
@@ -156,63 +177,82 @@ __global__ __launch_bounds__(256) void student_mfma(const uint8_t* in, int64_t i
     const int co = realg ? 4 * g + k : 0;
     b1[k] = ldf(ww, OFF_B1 + co);
     b2[k] = ldf(ww, OFF_B2 + co);
-    wh[k] = realg ? ldf(ww, OFF_WH + co) : 0.f;
+    wh[k] = ldf(ww, OFF_WH + co);
+    wh[k] = realg ? wh[k] : 0.f;
   }
   const float bh = ldf(ww, OFF_BH);
-  // per-lane tap offsets in the uint8 tile (taps past 25 read byte 0: zero weights)
-  int toff[8];
+  bf16x8 w1f, w2f[3];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) w1f[e] = (__bf16)(realc && 8 * g + e < 25 ? w1v[e] : 0.f);
+#pragma unroll
+  for (int s3 = 0; s3 < 3; ++s3)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w2f[s3][e] = (__bf16)(realc && 4 * s3 + g < 9 ? w2v[s3][e] : 0.f);
+  // per-lane bases of the tap reads in the bf16 tile, at h1 row `wave`
+  // (taps past 25 read element 0 of that row: zero weights)
+  const unsigned short* xb[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int t = 8 * g + e;
-    toff[e] = t < 25 ? (t / 5) * IC + t % 5 : 0;
+    xb[e] = xin + wave * IC + n16 + (t < 25 ? (t / 5) * IC + t % 5 : 0);
   }
+  unsigned char* const h1w = h1 + ((wave * HC + n16) * 16 + g * 8);
   __syncthreads();
-  // ---- conv1
-  for (int mb = wave; mb < HR * HMC; mb += 4) {
-    const int r = mb / HMC, mc = mb % HMC;
-    const unsigned char* a0 = xin + r * IC + mc * 16 + n16;
-    unsigned int raw[8];
+  // ---- conv1: h1 rows wave + 4k
 #pragma unroll
-    for (int e = 0; e < 8; ++e) raw[e] = a0[toff[e]];
-    u4v pk;
+  for (int k = 0; k < (HR + 3) / 4; ++k) {
+    if (wave + 4 * k < HR) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e)  // uint8 -> bf16 exactly: the float's high half
-      pk[e] = __builtin_amdgcn_perm(__builtin_bit_cast(unsigned int, (float)raw[2 * e + 1]),
-                                    __builtin_bit_cast(unsigned int, (float)raw[2 * e]), 0x07060302u);
-    const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, pk), f4{0.f, 0.f, 0.f, 0.f},
-                                                         0, 0, 0);
-    if (realg) {
-      const __bf16 h0 = (__bf16)s_relu(d[0] + b1[0]), h1v = (__bf16)s_relu(d[1] + b1[1]);
-      const __bf16 h2 = (__bf16)s_relu(d[2] + b1[2]), h3 = (__bf16)s_relu(d[3] + b1[3]);
-      const u2v wv = {(unsigned)__builtin_bit_cast(unsigned short, h0) |
-                          ((unsigned)__builtin_bit_cast(unsigned short, h1v) << 16),
-                      (unsigned)__builtin_bit_cast(unsigned short, h2) |
-                          ((unsigned)__builtin_bit_cast(unsigned short, h3) << 16)};
-      st<u2v>(h1 + ((r * HC + mc * 16 + n16) * 16 + g * 8), wv);
+      for (int mc = 0; mc < HMC; ++mc) {
+        const int off = 4 * k * IC + mc * 16;  // compile-time
+        u4v pk;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          pk[e] = (unsigned)xb[2 * e][off] | ((unsigned)xb[2 * e + 1][off] << 16);
+        const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, pk),
+                                                             f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        if (realg) {
+          const __bf16 h0 = (__bf16)s_relu(d[0] + b1[0]), h1v = (__bf16)s_relu(d[1] + b1[1]);
+          const __bf16 h2 = (__bf16)s_relu(d[2] + b1[2]), h3 = (__bf16)s_relu(d[3] + b1[3]);
+          const u2v wv = {(unsigned)__builtin_bit_cast(unsigned short, h0) |
+                              ((unsigned)__builtin_bit_cast(unsigned short, h1v) << 16),
+                          (unsigned)__builtin_bit_cast(unsigned short, h2) |
+                              ((unsigned)__builtin_bit_cast(unsigned short, h3) << 16)};
+          st<u2v>(h1w + (4 * k * HC + mc * 16) * 16, wv);
+        }
+      }
     }
   }
   __syncthreads();
-  // ---- conv2 + head
+  // ---- conv2 + head: output rows 0..TY-1 of m-block column `wave`
   int hoff[3];
 #pragma unroll
   for (int s3 = 0; s3 < 3; ++s3) {
     const int t = 4 * s3 + g < 9 ? 4 * s3 + g : 0;  // padded taps: zero weights
     hoff[s3] = ((t / 3) * HC + t % 3) * 16;
   }
-  for (int mb = wave; mb < TY * (TX / 16); mb += 4) {
-    const int oy = mb / (TX / 16), omc = mb % (TX / 16);
-    const unsigned char* b0 = h1 + (oy * HC + omc * 16 + n16) * 16;
-    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  const unsigned char* const b0w = h1 + (wave * 16 + n16) * 16;
+  const int x = x0 + wave * 16 + n16;
 #pragma unroll
-    for (int s3 = 0; s3 < 3; ++s3)
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[s3], ld<bf16x8>(b0 + hoff[s3]), acc, 0, 0, 0);
-    float part = 0.f;
+  for (int grp = 0; grp < TY / 4; ++grp) {
+    float mine = 0.f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) part = fmaf(wh[k], s_relu(acc[k] + b2[k]), part);
-    part += __shfl(part, (lane + 16) & 63);  // lanes g = 0: channels 0..3 + 4..7
-    const int y = y0 + oy, x = x0 + omc * 16 + n16;
-    if (g == 0 && y < Ho && x < Wo) st<float>(gout(out) + ((int64_t)z * out_zs + (int64_t)y * out_rs + x) * 4,
-                                             s_sigmoid(part + bh));
+    for (int j = 0; j < 4; ++j) {
+      const unsigned char* b0 = b0w + (4 * grp + j) * HC * 16;
+      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s3 = 0; s3 < 3; ++s3)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[s3], ld<bf16x8>(b0 + hoff[s3]), acc, 0, 0, 0);
+      float part = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) part = fmaf(wh[k], s_relu(acc[k] + b2[k]), part);
+      // channels 0..3 (lane group 0) + 4..7 (lane group 1) of pixel n16
+      const float sum = __shfl(part, n16) + __shfl(part, n16 + 16);
+      mine = g == j ? sum : mine;
+    }
+    const int y = y0 + 4 * grp + g;
+    if (y < Ho && x < Wo) st<float>(gout(out) + ((int64_t)z * out_zs + (int64_t)y * out_rs + x) * 4,
+                                   s_sigmoid(mine + bh));
   }
 }
 
