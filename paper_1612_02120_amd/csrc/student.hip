@@ -387,36 +387,53 @@ __global__ void st_dh1(const float* __restrict__ dh2, const float* __restrict__ 
 // layer 1: dY = dh2 (P-6)^2 x 8, X = h1 (3x3, 8 channels)
 // layer 2: dY = dz  (P-6)^2 x 1, X = h2 (1x1, 8 channels)
 template <int LAYER>
-__global__ __launch_bounds__(256) void st_wgrad(const float* __restrict__ dY, const void* __restrict__ X, int B, int P,
-                                                int chunk, float* __restrict__ part) {
+__global__ __launch_bounds__(1024) void st_wgrad(const float* __restrict__ dY, const void* __restrict__ X, int B, int P,
+                                                 int chunk, float* __restrict__ part) {
   constexpr int K = LAYER == 0 ? 5 : LAYER == 1 ? 3 : 1;
   constexpr int CI = LAYER == 0 ? 1 : 8;
   constexpr int CO = LAYER == 2 ? 1 : 8;
   constexpr int NW = CO * CI * K * K;
   constexpr int NE = NW + CO;
+  constexpr int U = 8;  // positions whose loads are issued together
   const int Ho = LAYER == 0 ? P - 4 : P - 6;
   const int Hi = Ho + K - 1;
   const int64_t n = (int64_t)B * Ho * Ho;
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
   const int64_t p1 = min(n, p0 + chunk);
   for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    // element e: weight (co, ci, i, j), or the bias of co (then ci = i = j = 0
+    // and the input is not read)
+    const bool wt = e < NW;
+    const int co = wt ? e / (CI * K * K) : e - NW, r = wt ? e % (CI * K * K) : 0;
+    const int ci = r / (K * K), i = (r % (K * K)) / K, j = r % K;
+    // position p0 as (b, y, x), advanced one position at a time below (no
+    // division per position); the sum runs over p = p0 .. p1 - 1 in order
+    int b = (int)(p0 / ((int64_t)Ho * Ho));
+    const int rem = (int)(p0 % ((int64_t)Ho * Ho));
+    int y = rem / Ho, x = rem % Ho;
     float acc = 0.f;
-    if (e < NW) {
-      const int co = e / (CI * K * K), r = e % (CI * K * K);
-      const int ci = r / (K * K), i = (r % (K * K)) / K, j = r % K;
-      for (int64_t p = p0; p < p1; ++p) {
-        const int b = (int)(p / ((int64_t)Ho * Ho));
-        const int rem = (int)(p % ((int64_t)Ho * Ho));
-        const int y = rem / Ho, x = rem % Ho;
+    for (int64_t pb = p0; pb < p1; pb += U) {
+      float dv[U], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool live = pb + u < p1;
+        const int64_t pp = live ? pb + u : p0;
+        dv[u] = dY[pp * CO + co];
         const int64_t xi = ((int64_t)b * Hi + y + i) * Hi + x + j;
-        float xv;
-        if constexpr (LAYER == 0) xv = (float)reinterpret_cast<const uint8_t*>(X)[xi] * (1.0f / 255.0f);
-        else xv = reinterpret_cast<const float*>(X)[xi * CI + ci];
-        acc = fmaf(dY[p * CO + co], xv, acc);
+        if constexpr (LAYER == 0) xv[u] = (float)reinterpret_cast<const uint8_t*>(X)[live ? xi : 0] * (1.0f / 255.0f);
+        else xv[u] = reinterpret_cast<const float*>(X)[(live ? xi : 0) * CI + ci];
+        if (++x == Ho) {
+          x = 0;
+          if (++y == Ho) {
+            y = 0;
+            ++b;
+          }
+        }
       }
-    } else {
-      const int co = e - NW;
-      for (int64_t p = p0; p < p1; ++p) acc += dY[p * CO + co];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (pb + u < p1) acc = wt ? fmaf(dv[u], xv[u], acc) : acc + dv[u];
+      }
     }
     part[(int64_t)blockIdx.x * NE + e] = acc;
   }
@@ -669,9 +686,10 @@ static int grad_impl(Student* s, const uint8_t* patches, const float* teacher, i
   hipLaunchKernelGGL(st_conv1, dim3(blocks(n1)), dim3(256), 0, st, patches, B, P, s->ww, h1, bf);
   hipLaunchKernelGGL(st_conv2_loss, dim3(nloss), dim3(256), 0, st, h1, B, P, s->ww, teacher, h2, dz, dh2, lp, invN, bf);
   hipLaunchKernelGGL(st_dh1, dim3(blocks(n1)), dim3(256), 0, st, dh2, h1, B, P, s->ww, dh1, bf);
+  // one thread per gradient element of a chunk (8 x 25 + 8, 8 x 72 + 8, 8 + 1)
   hipLaunchKernelGGL(st_wgrad<0>, dim3(nc0), dim3(256), 0, st, dh1, (const void*)patches, B, P, chunk, p0);
-  hipLaunchKernelGGL(st_wgrad<1>, dim3(nc1), dim3(256), 0, st, dh2, (const void*)h1, B, P, chunk, p1);
-  hipLaunchKernelGGL(st_wgrad<2>, dim3(nc2), dim3(256), 0, st, dz, (const void*)h2, B, P, chunk, p2);
+  hipLaunchKernelGGL(st_wgrad<1>, dim3(nc1), dim3(640), 0, st, dh2, (const void*)h1, B, P, chunk, p1);
+  hipLaunchKernelGGL(st_wgrad<2>, dim3(nc2), dim3(64), 0, st, dz, (const void*)h2, B, P, chunk, p2);
   ReduceArgs a;
   std::memset(&a, 0, sizeof(a));
   a.part[0] = p0;
