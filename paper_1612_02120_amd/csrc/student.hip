@@ -394,7 +394,7 @@ __global__ __launch_bounds__(1024) void st_wgrad(const float* __restrict__ dY, c
   constexpr int CO = LAYER == 2 ? 1 : 8;
   constexpr int NW = CO * CI * K * K;
   constexpr int NE = NW + CO;
-  constexpr int U = 8;  // positions whose loads are issued together
+  constexpr int U = 32;  // positions whose loads are issued together
   const int Ho = LAYER == 0 ? P - 4 : P - 6;
   const int Hi = Ho + K - 1;
   const int64_t n = (int64_t)B * Ho * Ho;
